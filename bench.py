@@ -1,0 +1,189 @@
+#!/usr/bin/env python3
+"""Throughput of the Blahut-Arimoto iteration for the binary deletion channel at
+n = 20 on one MI355X; prints one JSON line.
+
+Workload: three instances n = 20, d in {0.64, 0.80, 0.95}, p_0 uniform, FP32
+log-domain iterates (FP64 certification reported after the timed steps).  One
+step = one BA iteration of all three instances: q = W^T p, D(x), the Blahut
+reductions and the update, over all 2*3^20 - 2^20 nonzeros of W per instance.
+
+metric: W-nonzero terms per second = iterations/s x nnz(W) x instances, and BA
+iterations per second.  The default engine evaluates the two products of each
+iteration stage by stage (BA_ENGINE_FACTORED); the per-nonzero engine of the
+paper's method (BA_ENGINE_STREAM) is measured on the same workload and reported
+beside it.  The FP64 plain iteration of one instance is reported too.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+N = 20
+DS = [0.64, 0.80, 0.95]
+
+
+def stage_sizes(n):
+    """Entries of the n+1 intermediate arrays of the factored products."""
+    return [((2 << i) - 1) << (n - i) for i in range(n + 1)]
+
+
+def factored_bytes_per_iteration(n, esz, nb):
+    """Algorithmic HBM bytes of one sweep (forward or backward): each stage reads
+    its source array once and writes its destination once."""
+    s = stage_sizes(n)
+    return sum(s[i] + s[i + 1] for i in range(n)) * esz * nb
+
+
+def cpu_baseline(target_s=10.0):
+    """The oracle (plain C, brute-force rows) doing both sweeps of the first BA
+    iteration on a bounded sample of n = 20 input rows, timed on this host."""
+    import numpy as np
+
+    import bdc_inputs as inp
+    import oracle.native as on
+    from oracle import bdc
+
+    on.lib()
+    p = np.full(1 << N, 2.0 ** -N)
+    w = bdc.length_weights(N, 0.8)[bdc.output_lengths(N)]
+    q_full = w * bdc.r_uniform(N)  # exact output law of the uniform input
+    probe = inp.sample_rows(N, 64, seed=21)
+    t0 = time.perf_counter()
+    on.sample_sweeps(N, 0.8, p, probe, q_full)
+    dt = time.perf_counter() - t0
+    count = int(min(1 << N, max(64, 64 * target_s / max(dt, 1e-6))))
+    xs = inp.sample_rows(N, count, seed=22)
+    t0 = time.perf_counter()
+    _, _, visited = on.sample_sweeps(N, 0.8, p, xs, q_full)
+    el = time.perf_counter() - t0
+    return {"value": visited / el, "unit": "W-nonzero terms/s", "cores": on.num_threads(),
+            "kind": "oracle",
+            "sample": "both sweeps of the first BA iteration (uniform p, d=0.8) on %d seeded rows "
+                      "of the n=20 channel (%d nonzeros, brute-force rows), %.1f s" % (len(xs), visited, el),
+            "cpu": platform.processor() or platform.machine()}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--stream-steps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-stream", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the BA instances of this workload fit one MI355X "
+              "(multi-GPU sharding is described in DESIGN.md, not implemented)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2604_05867_amd as ba
+
+    dev = torch.device("cuda:0")
+    nnz = ba.nnz(N)
+    nb = len(DS)
+    ctx = ba.Context([N] * nb, DS, prec=ba.PREC_FP32_LOG, engine=ba.ENGINE_FACTORED, cert_every=50,
+                     device=dev)
+    print("bench: warmup %d" % args.warmup, file=sys.stderr, flush=True)
+    ctx.step(args.warmup)
+    torch.cuda.synchronize()
+    print("bench: timing %d steps" % args.steps, file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    ctx.step(args.steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms_step = el / args.steps * 1e3
+    iters_s = args.steps / el
+    value = iters_s * nnz * nb
+
+    # per-kernel-class device time (HIP events on the bound stream) over the same number of steps
+    kt = ctx.time_kernels(args.steps)
+    dom = max(("sweep1", "sweep2"), key=lambda k: kt[k][0])
+    dom_ms, dom_launches = kt[dom]
+    per_launch_ms = dom_ms / max(dom_launches, 1)
+    bytes_iter = factored_bytes_per_iteration(N, 4, nb)
+    launches_per_iter = N
+    bytes_launch = bytes_iter / launches_per_iter
+    achieved = bytes_launch / (per_launch_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
+                "frac": round(achieved / 8000.0, 4), "traffic": None,
+                "kernel": "k_fwd_stage" if dom == "sweep1" else "k_bwd_stage",
+                "bytes_per_launch": int(bytes_launch), "avg_launch_us": round(per_launch_ms * 1e3, 2)}
+
+    lo, hi = ctx.bounds()
+    cert = {"lower_bits": lo, "upper_bits": hi, "gap_bits": [h - l for l, h in zip(lo, hi)],
+            "iterations": args.warmup + 2 * args.steps}
+    kernel_ms = {k: round(v[0] / args.steps, 4) for k, v in kt.items()}
+    ctx.close()
+
+    extra = {}
+    if not args.no_stream and args.stream_steps > 0:
+        print("bench: stream engine", file=sys.stderr, flush=True)
+        cs = ba.Context([N] * nb, DS, prec=ba.PREC_FP32_LOG, engine=ba.ENGINE_STREAM, device=dev)
+        cs.step(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cs.step(args.stream_steps)
+        torch.cuda.synchronize()
+        es = time.perf_counter() - t0
+        kts = cs.time_kernels(1)
+        extra["stream_engine"] = {"value": args.stream_steps / es * nnz * nb, "unit": "W-nonzero terms/s",
+                                  "ms_per_step": es / args.stream_steps * 1e3,
+                                  "kernel_ms_per_step": {k: round(v[0], 3) for k, v in kts.items()}}
+        cs.close()
+    print("bench: fp64 plain", file=sys.stderr, flush=True)
+    c64 = ba.Context(N, 0.80, prec=ba.PREC_FP64, engine=ba.ENGINE_FACTORED, device=dev)
+    c64.step(2)
+    torch.cuda.synchronize()
+    k64 = max(5, args.steps // 5)
+    t0 = time.perf_counter()
+    c64.step(k64)
+    torch.cuda.synchronize()
+    e64 = time.perf_counter() - t0
+    extra["fp64_single"] = {"iters_per_s": k64 / e64, "value": k64 / e64 * nnz, "unit": "W-nonzero terms/s",
+                            "ms_per_step": e64 / k64 * 1e3}
+    c64.close()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("bench: cpu baseline", file=sys.stderr, flush=True)
+        cpu = cpu_baseline()
+
+    line = {
+        "metric": "W-nonzero terms/s and BA iters/s at n=20",
+        "value": value,
+        "unit": "W-nonzero terms/s",
+        "iters_per_s": iters_s,
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "BA iteration, binary deletion channel n=20, d in {0.64,0.80,0.95} "
+                               "(3 instances), p0 uniform, FP32 log-domain iterates, factored engine",
+                   "n": N, "d": DS, "instances": nb, "nnz_per_instance": nnz},
+        "kernel_ms_per_step": kernel_ms,
+        "roofline": roofline,
+        "certified": cert,
+        "cpu_baseline": cpu,
+    }
+    line.update(extra)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,221 @@
+/*
+ * ba.h - C ABI of the MI355X (gfx950) Blahut-Arimoto engine for the
+ * finite-length binary deletion channel BDC_d.
+ *
+ * The method (Pinto & Ribeiro, "Improved Capacity Upper Bounds for the Deletion
+ * Channel using a Parallelized Blahut-Arimoto Algorithm"):
+ *   inputs  x in {0,1}^n, outputs y in {0,1}^{<=n} (Section 2.2);
+ *   W(y|x) = emb(y,x) d^(n-|y|) (1-d)^|y|, emb = number of embeddings of y in x
+ *   as a subsequence (Section 2.2, numerator of P_{n,k});
+ *   one BA iteration (Section 2.3, Algorithm 1):  q = W^T p,
+ *   D(x) = sum_y W(y|x) log(W(y|x)/q(y)),  p <- p e^D / Z,
+ *   with the Blahut bounds  L = log sum_x p(x) e^{D(x)} <= C_n(d) <= U = max_x D(x)
+ *   and the stopping quantity max_x log(p_{t+1}(x)/p_t(x)) = U - L (Section 2.3).
+ *
+ * Conventions used by every entry point
+ * -------------------------------------
+ *  - String order: x = (x_0..x_{n-1}) is the index sum_i x_i 2^(n-1-i); an output
+ *    y of length k has rank (2^k - 1) + sum_i y_i 2^(k-1-i).  Arrays over inputs
+ *    have 2^n entries; arrays over outputs have 2^(n+1) - 1 entries.
+ *  - Units: everything crossing this boundary is in bits (the paper's logarithm
+ *    base, Section 2.1), except log-probability arrays (logp, theta), which are
+ *    natural logarithms.
+ *  - Memory: a context owns host state only.  All device memory the library
+ *    uses is one caller-provided workspace (ba_workspace_bytes / ba_bind); the
+ *    library never allocates device memory itself.  Pointers named *_dev are
+ *    device pointers borrowed for the duration of the call; all other pointers
+ *    are host pointers.  Work is queued on the bound HIP stream.
+ *  - Errors: every int-returning call returns BA_OK (0) or a negative BA_E*
+ *    code; nothing aborts, throws or exits.  Outputs are written only on BA_OK.
+ *    ba_last_error() gives a message for the most recent failure on a context.
+ *  - Threads: a context may be used by one host thread at a time.  Calls that
+ *    overlap on one context race.
+ */
+#ifndef BA_H
+#define BA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ba_ctx ba_ctx;
+
+enum {
+  BA_OK = 0,
+  BA_EINVAL = -1,    /* an argument is out of range */
+  BA_ENOMEM = -2,    /* host allocation failed, or the bound workspace is too small */
+  BA_EDEVICE = -3,   /* a HIP call failed (message in ba_last_error) */
+  BA_ESTATE = -4,    /* call not valid in the context's state (e.g. before ba_bind) */
+  BA_ENUMERIC = -5   /* NaN or Inf found in a log-probability input or iterate */
+};
+
+/* Precision of the iteration.  Certification (ba_bounds, ba_run's checks,
+ * ba_eval, ba_grad) is always FP64. */
+enum {
+  BA_PREC_FP64 = 0,     /* FP64 iterates, log domain */
+  BA_PREC_FP32_LOG = 1  /* FP32 iterates in the log domain, FP64 certification */
+};
+
+/* How the two sweeps q = W^T p and W v are evaluated.  Both give the same
+ * values (up to rounding order).
+ *  BA_ENGINE_STREAM:   the paper's method (Sections 3-4): every nonzero W(y|x)
+ *                      is generated on the fly by an exact integer embedding-count
+ *                      DP over the subsequences of x and visited once per sweep
+ *                      (scatter into q, gather for D).
+ *  BA_ENGINE_FACTORED: the same two products evaluated position by position: the
+ *                      deletion channel acts on each input bit independently, so
+ *                      W^T p and W v factor into n sparse stages of width
+ *                      2^(n+1); the nonzeros are never enumerated. */
+enum {
+  BA_ENGINE_STREAM = 0,
+  BA_ENGINE_FACTORED = 1
+};
+
+/* ---- lifetime --------------------------------------------------------------- */
+
+/* One instance: 1 <= n <= 20, 0 <= d <= 1.  FP64 iteration, FACTORED engine,
+ * p_0 uniform (Section 2.3).  *out receives a new context (free with ba_free).
+ * BA_EINVAL if n or d is out of range or out is NULL. */
+int ba_init(int n, double d, ba_ctx **out);
+
+/* A batch of `count` independent instances (1 <= count <= 4096), instance i with
+ * length n[i] in [1, 20] and deletion probability d[i] in [0, 1].  Instances with
+ * the same n share the embedding-count tables and are advanced by the same kernel
+ * launches (Section 2.2: W depends on d only through the weights
+ * d^(n-k) (1-d)^k).  prec is BA_PREC_*; cert_every >= 1 is the number of
+ * iterations between FP64 certifications in ba_run.  Host arrays n and d are
+ * copied. */
+int ba_init_batch(int count, const int *n, const double *d, int prec, int cert_every,
+                  ba_ctx **out);
+
+/* Select BA_ENGINE_*.  Allowed at any time after init; takes effect at the next
+ * call that runs sweeps. */
+int ba_set_engine(ba_ctx *c, int engine);
+
+/* Free the host state.  The workspace stays owned by the caller.  NULL is a no-op. */
+void ba_free(ba_ctx *c);
+
+/* ---- memory and stream -------------------------------------------------------- */
+
+/* Bytes of device workspace the context needs (alignment 256). */
+int ba_workspace_bytes(const ba_ctx *c, size_t *bytes);
+
+/* Bind a caller-owned device workspace of at least ba_workspace_bytes bytes
+ * (256-byte aligned) and a HIP stream (hipStream_t, may be NULL for the null
+ * stream).  Builds the count tables and the per-instance constants on the
+ * stream and resets every instance to p_0 = uniform.  Can be called again to
+ * move the context to another workspace (state is reset).  BA_ENOMEM if bytes is
+ * too small, BA_EINVAL if the pointer is NULL or misaligned. */
+int ba_bind(ba_ctx *c, void *workspace_dev, size_t bytes, void *hip_stream);
+
+/* ---- iteration ---------------------------------------------------------------- */
+
+/* Queue `iters` >= 0 BA iterations (Section 2.3: output law, refined input law,
+ * normalisation) for every instance that has not converged.  Asynchronous: no
+ * host synchronisation.  An instance whose current-iterate gap U - L (in the
+ * iteration precision) falls below its tolerance (see ba_run) stops updating.
+ * BA_ESTATE before ba_bind. */
+int ba_step(ba_ctx *c, int iters);
+
+/* Iterate until the FP64-certified gap U - L is below gap_bits for every instance
+ * or until max_iters further iterations, certifying every cert_every iterations
+ * (1 for FP64 single-instance contexts).  Synchronises once per certification.
+ * *iters_done (host, may be NULL) receives the number of iterations performed by
+ * the slowest instance.  The stopping rule is that of Section 2.3 with the
+ * tolerance in bits. */
+int ba_run(ba_ctx *c, double gap_bits, int max_iters, int *iters_done);
+
+/* FP64 certification of the current iterate of every instance: lower and upper
+ * bounds on C_n(d) in bits (lower <= C_n(d) <= upper).  The iterate is first
+ * normalised and floored at (max log p - 700) so that every input keeps a
+ * representable probability; the bounds are valid for that full-support law.
+ * lower_bits/upper_bits are host arrays of length count.  Blocks. */
+int ba_bounds(ba_ctx *c, double *lower_bits, double *upper_bits);
+
+/* Best certified bounds seen so far by ba_run/ba_bounds (max lower, min upper),
+ * host arrays of length count; and completed iterations per instance (host int
+ * array of length count, may be NULL).  Blocks. */
+int ba_best_bounds(ba_ctx *c, double *lower_bits, double *upper_bits, int *iters);
+
+/* ---- single-instance evaluation hooks (count == 1 contexts, or instance 0) -------- */
+
+/* FP64 evaluation at an arbitrary log-probability vector logp_dev (2^n doubles,
+ * not necessarily normalised; normalised and floored as in ba_bounds).  Optional
+ * outputs (NULL to skip):
+ *   r_dev[2^(n+1)-1]  r(y) e^{-M} = sum_x p(x) emb(y,x) e^{-M}, M = max of the
+ *                     normalised floored log p (so q(y) = w_k r(y) e^M);
+ *   D_dev[2^n]        D(x) in nats;
+ *   out4 (host[4])    {L bits, U bits, I bits, M nats}.
+ * Does not change the iterate.  Blocks. */
+int ba_eval(ba_ctx *c, const double *logp_dev, double *r_dev, double *D_dev, double *out4);
+
+/* Mutual information and its gradients for p = softmax(theta), theta_dev[2^n]
+ * (FP64 device array): *I_bits = I(p; d); dI_dtheta_dev[2^n] (device, may be
+ * NULL) = p (D - I) / ln 2;  *dI_dd_bits (host, may be NULL) =
+ * sum_x p(x) sum_y s_k W(y|x) log(W(y|x)/q(y)) / ln 2 with
+ * s_k = (n-k)/d - k/(1-d).  BA_EINVAL for d in {0, 1} when dI_dd_bits is
+ * requested.  Does not change the iterate.  Blocks. */
+int ba_grad(ba_ctx *c, const double *theta_dev, double *I_bits, double *dI_dtheta_dev,
+            double *dI_dd_bits);
+
+/* Entropic mirror ascent on I(softmax(theta)): `steps` times
+ * theta <- theta + eta * D(theta), in place on theta_dev[2^n] (FP64).  eta = 1
+ * reproduces the BA update.  Asynchronous. */
+int ba_mirror_ascent(ba_ctx *c, double *theta_dev, double eta, int steps);
+
+/* Copy the current iterate (natural log of p, normalised) of every instance into
+ * logp_dev (device, FP64, instances concatenated in order, 2^n[i] each), or load
+ * it from there (not necessarily normalised; resets convergence flags).
+ * BA_ENUMERIC if the loaded values contain NaN or +Inf. */
+int ba_get_logp(ba_ctx *c, double *logp_dev);
+int ba_set_logp(ba_ctx *c, const double *logp_dev);
+
+/* ---- embedding counts (parity hooks for the count generator) ---------------- */
+
+/* Row x of the embedding-count matrix of instance 0's n, computed on the device
+ * by the same count generator the sweeps use: rank_dev[i], emb_dev[i] (device
+ * uint32 arrays of capacity cap) in increasing rank order, *nnz (host) = number
+ * of distinct subsequences of x.  BA_EINVAL if x >= 2^n or cap < nnz (then
+ * *nnz is still set and nothing is written).  Blocks. */
+int ba_row_counts(ba_ctx *c, uint32_t x, uint32_t *rank_dev, uint32_t *emb_dev, int cap,
+                  int *nnz);
+
+/* Whole-matrix check of the count generator for instance 0's n, on the device:
+ * stats (host uint64[6]) = {total nonzeros, rows whose length sums
+ * sum_{|y|=k} emb(y,x) differ from C(n,k) for some k, 0 (reserved), minimum row
+ * nnz, maximum row nnz, maximum emb}.  Expected: total = 2*3^n - 2^n, 0 failing
+ * rows, min nnz = n+1, max emb = C(n, floor(n/2)).  Blocks. */
+int ba_verify_counts(ba_ctx *c, uint64_t *stats);
+
+/* ---- introspection ------------------------------------------------------------ */
+
+int ba_instance_count(const ba_ctx *c);
+/* Nonzeros of W for length n: 2*3^n - 2^n. */
+uint64_t ba_nnz(int n);
+const char *ba_strerror(int code);
+const char *ba_last_error(const ba_ctx *c);
+
+/* ---- measurement ---------------------------------------------------------------- */
+
+/* Run `iters` iterations (like ba_step) with a HIP event pair around every kernel
+ * launch, on the bound stream, and report the summed device time per kernel
+ * class in ms (host double[BA_NKCLASS], indexed by BA_K_*) together with the
+ * number of launches per class (host int[BA_NKCLASS], may be NULL).  Blocks. */
+enum {
+  BA_K_SWEEP1 = 0,   /* q = W^T p  (stream: scatter kernel; factored: forward stages) */
+  BA_K_LOGR = 1,     /* v(y) = w_k log r(y) */
+  BA_K_SWEEP2 = 2,   /* W v        (stream: gather kernel; factored: backward stages) */
+  BA_K_REDUCE = 3,   /* D, partial maxima and log-sum-exp */
+  BA_K_UPDATE = 4,   /* normalisation and log p update */
+  BA_NKCLASS = 5
+};
+int ba_time_kernels(ba_ctx *c, int iters, double *ms, int *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BA_H */

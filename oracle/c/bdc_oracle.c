@@ -369,3 +369,52 @@ int bdc_num_threads(void) {
     return 1;
 #endif
 }
+
+/* ---- both sweeps of one BA iteration on a sample of input rows ----------- */
+
+/* For each sampled x: its row by brute force over position subsets, then
+ *   q_part(y) += p(x) W(y|x)                                 (Section 2.3 step 1)
+ *   D(x) = sum_y W(y|x) log(W(y|x) / q(y)), q given in q_full (step 2(a)).
+ * q_part has one slice of 2^(n+1)-1 doubles per OpenMP thread (the caller sums
+ * them).  Returns the number of nonzeros visited, or a negative error. */
+long long bdc_sample_sweeps(int n, double d, const double *p, const uint32_t *xs, int count,
+                            const double *q_full, double *q_part, double *D_out) {
+    if (n < 1 || n > 22) return -1;
+    double w[32];
+    weights(n, d, w);
+    const size_t Y = row_cap(n);
+    long long total = 0;
+    int err = 0;
+#pragma omp parallel reduction(+ : total)
+    {
+        int t = 0;
+#ifdef _OPENMP
+        t = omp_get_thread_num();
+#endif
+        double *qt = q_part + (size_t)t * Y;
+        uint32_t *dense = (uint32_t *)calloc(Y, sizeof(uint32_t));
+        uint32_t *touched = (uint32_t *)malloc(Y * sizeof(uint32_t));
+        uint32_t *rk = (uint32_t *)malloc(Y * sizeof(uint32_t));
+        uint32_t *em = (uint32_t *)malloc(Y * sizeof(uint32_t));
+        if (!dense || !touched || !rk || !em) {
+#pragma omp atomic write
+            err = -2;
+        } else {
+#pragma omp for schedule(dynamic, 1)
+            for (int i = 0; i < count; ++i) {
+                int nnz = row_into(n, xs[i], dense, touched, rk, em, (int)Y);
+                double acc = 0.0;
+                const double px = p[xs[i]];
+                for (int e = 0; e < nnz; ++e) {
+                    const double Wv = (double)em[e] * w[length_of_rank(rk[e])];
+                    qt[rk[e]] += px * Wv;
+                    if (Wv > 0.0) acc += Wv * log(Wv / q_full[rk[e]]);
+                }
+                D_out[i] = acc;
+                total += nnz;
+            }
+        }
+        free(dense); free(touched); free(rk); free(em);
+    }
+    return err ? err : total;
+}

@@ -51,6 +51,9 @@ def lib():
         L.bdc_product_D.argtypes = [ctypes.c_int, ctypes.c_double, f64p, u32p, ctypes.c_int,
                                     f64p, ctypes.c_void_p]
         L.bdc_num_threads.restype = ctypes.c_int
+        L.bdc_sample_sweeps.argtypes = [ctypes.c_int, ctypes.c_double, f64p, u32p, ctypes.c_int, f64p,
+                                        f64p, f64p]
+        L.bdc_sample_sweeps.restype = ctypes.c_longlong
         _lib = L
     return _lib
 
@@ -147,3 +150,18 @@ def product_D(n: int, d: float, pi1: np.ndarray, xs, want_Dd: bool = False):
     if rc:
         raise RuntimeError("bdc_product_D failed: %d" % rc)
     return (D, Dd) if want_Dd else D
+
+
+def sample_sweeps(n: int, d: float, p: np.ndarray, xs, q_full: np.ndarray):
+    """Both sweeps of one BA iteration on the sampled rows xs (brute-force rows).
+    Returns (q_part summed over threads, D at xs, nonzeros visited)."""
+    xs = np.ascontiguousarray(np.asarray(xs, dtype=np.uint32))
+    Y = (1 << (n + 1)) - 1
+    nt = num_threads()
+    q_part = np.zeros(nt * Y)
+    D = np.zeros(len(xs))
+    tot = lib().bdc_sample_sweeps(n, d, np.ascontiguousarray(p, dtype=np.float64), xs, len(xs),
+                                  np.ascontiguousarray(q_full, dtype=np.float64), q_part, D)
+    if tot < 0:
+        raise RuntimeError("bdc_sample_sweeps failed: %d" % tot)
+    return q_part.reshape(nt, Y).sum(axis=0), D, int(tot)

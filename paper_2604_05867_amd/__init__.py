@@ -1,0 +1,236 @@
+"""MI355X (gfx950) Blahut-Arimoto engine for the finite-length binary deletion
+channel: Python binding of ``libba.so`` (C ABI in ``include/ba.h``).
+
+This module only marshals arguments: every step of the computation runs in the
+HIP kernels of ``libba.so``.  PyTorch supplies device memory (one workspace
+tensor per context) and the HIP stream.  If the library is missing, importing
+works but every constructor raises: there is no CPU fallback.
+
+Quantities follow the paper (Pinto & Ribeiro, Sections 2.2-2.3): inputs
+x in {0,1}^n (x_0 most significant), outputs y of length k with rank
+2^k - 1 + bits(y); bounds and rates in bits; log-probabilities in nats.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libba.so")
+
+BA_OK, BA_EINVAL, BA_ENOMEM, BA_EDEVICE, BA_ESTATE, BA_ENUMERIC = 0, -1, -2, -3, -4, -5
+PREC_FP64, PREC_FP32_LOG = 0, 1
+ENGINE_STREAM, ENGINE_FACTORED = 0, 1
+KCLASS = ("sweep1", "logr", "sweep2", "reduce", "update")
+
+_lib = None
+
+
+class BAError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s (code %d)" % (msg, code))
+        self.code = code
+
+
+def lib():
+    """Load libba.so (built by ``paper_2604_05867_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libba.so is not built: run python -c 'import __graft_entry__ as g; g.build()'")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, f64, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    pi32, pf64 = ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)
+    L.ba_init.argtypes = [i32, f64, ctypes.POINTER(vp)]
+    L.ba_init_batch.argtypes = [i32, pi32, pf64, i32, i32, ctypes.POINTER(vp)]
+    L.ba_set_engine.argtypes = [vp, i32]
+    L.ba_free.argtypes = [vp]
+    L.ba_free.restype = None
+    L.ba_workspace_bytes.argtypes = [vp, ctypes.POINTER(sz)]
+    L.ba_bind.argtypes = [vp, vp, sz, vp]
+    L.ba_step.argtypes = [vp, i32]
+    L.ba_run.argtypes = [vp, f64, i32, pi32]
+    L.ba_bounds.argtypes = [vp, pf64, pf64]
+    L.ba_best_bounds.argtypes = [vp, pf64, pf64, pi32]
+    L.ba_eval.argtypes = [vp, vp, vp, vp, pf64]
+    L.ba_grad.argtypes = [vp, vp, pf64, vp, pf64]
+    L.ba_mirror_ascent.argtypes = [vp, vp, f64, i32]
+    L.ba_get_logp.argtypes = [vp, vp]
+    L.ba_set_logp.argtypes = [vp, vp]
+    L.ba_row_counts.argtypes = [vp, ctypes.c_uint32, vp, vp, i32, pi32]
+    L.ba_verify_counts.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64)]
+    L.ba_instance_count.argtypes = [vp]
+    L.ba_nnz.argtypes = [i32]
+    L.ba_nnz.restype = ctypes.c_uint64
+    L.ba_strerror.argtypes = [i32]
+    L.ba_strerror.restype = ctypes.c_char_p
+    L.ba_last_error.argtypes = [vp]
+    L.ba_last_error.restype = ctypes.c_char_p
+    L.ba_time_kernels.argtypes = [vp, i32, pf64, pi32]
+    _lib = L
+    return L
+
+
+def nnz(n: int) -> int:
+    """Nonzeros of W for input length n (2*3^n - 2^n)."""
+    return int(lib().ba_nnz(n))
+
+
+def _ptr(t: torch.Tensor | None):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Context:
+    """A batch of BA instances bound to a torch-owned workspace and stream.
+
+    ``n`` and ``d`` are sequences (or scalars for one instance)."""
+
+    def __init__(self, n, d, prec: int = PREC_FP64, engine: int = ENGINE_FACTORED,
+                 cert_every: int = 50, device: str | torch.device = "cuda:0",
+                 stream: torch.cuda.Stream | None = None):
+        L = lib()
+        ns = [int(n)] if isinstance(n, int) else [int(v) for v in n]
+        ds = [float(d)] if isinstance(d, (int, float)) else [float(v) for v in d]
+        if len(ds) == 1 and len(ns) > 1:
+            ds = ds * len(ns)
+        if len(ns) == 1 and len(ds) > 1:
+            ns = ns * len(ds)
+        self.n, self.d, self.prec = ns, ds, prec
+        self.count = len(ns)
+        self._h = ctypes.c_void_p()
+        arr_n = (ctypes.c_int * self.count)(*ns)
+        arr_d = (ctypes.c_double * self.count)(*ds)
+        self._check(L.ba_init_batch(self.count, arr_n, arr_d, prec, cert_every, ctypes.byref(self._h)),
+                    "ba_init_batch")
+        self.set_engine(engine)
+        self.device = torch.device(device)
+        nbytes = ctypes.c_size_t()
+        self._check(L.ba_workspace_bytes(self._h, ctypes.byref(nbytes)), "ba_workspace_bytes")
+        self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._check(L.ba_bind(self._h, _ptr(self.workspace), nbytes.value,
+                              ctypes.c_void_p(self.stream.cuda_stream)), "ba_bind")
+
+    # -- plumbing -----------------------------------------------------------
+    def _check(self, rc: int, what: str):
+        if rc != BA_OK:
+            msg = lib().ba_last_error(self._h).decode() if self._h else ""
+            raise BAError(rc, "%s: %s%s" % (what, lib().ba_strerror(rc).decode(), (" - " + msg) if msg else ""))
+
+    def close(self):
+        if self._h:
+            lib().ba_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_engine(self, engine: int):
+        self._check(lib().ba_set_engine(self._h, engine), "ba_set_engine")
+        self.engine = engine
+
+    # -- iteration ----------------------------------------------------------
+    def step(self, iters: int = 1):
+        self._check(lib().ba_step(self._h, iters), "ba_step")
+
+    def run(self, gap_bits: float, max_iters: int) -> int:
+        done = ctypes.c_int()
+        self._check(lib().ba_run(self._h, gap_bits, max_iters, ctypes.byref(done)), "ba_run")
+        return done.value
+
+    def bounds(self):
+        lo = (ctypes.c_double * self.count)()
+        hi = (ctypes.c_double * self.count)()
+        self._check(lib().ba_bounds(self._h, lo, hi), "ba_bounds")
+        return list(lo), list(hi)
+
+    def best_bounds(self):
+        lo = (ctypes.c_double * self.count)()
+        hi = (ctypes.c_double * self.count)()
+        it = (ctypes.c_int * self.count)()
+        self._check(lib().ba_best_bounds(self._h, lo, hi, it), "ba_best_bounds")
+        return list(lo), list(hi), list(it)
+
+    # -- evaluation hooks (instance 0) --------------------------------------
+    def eval(self, logp: torch.Tensor, want_r: bool = True, want_D: bool = True):
+        """FP64 evaluation at logp: returns dict(L, U, I bits, M nats, r, D)."""
+        n = self.n[0]
+        logp = logp.to(self.device, torch.float64).contiguous()
+        r = torch.empty((1 << (n + 1)) - 1, dtype=torch.float64, device=self.device) if want_r else None
+        D = torch.empty(1 << n, dtype=torch.float64, device=self.device) if want_D else None
+        out = (ctypes.c_double * 4)()
+        self._check(lib().ba_eval(self._h, _ptr(logp), _ptr(r), _ptr(D), out), "ba_eval")
+        return {"L": out[0], "U": out[1], "I": out[2], "M": out[3], "r": r, "D": D}
+
+    def grad(self, theta: torch.Tensor, want_dd: bool = True):
+        """I(softmax(theta)) in bits with dI/dtheta and dI/dd (bits)."""
+        theta = theta.to(self.device, torch.float64).contiguous()
+        g = torch.empty_like(theta)
+        I = ctypes.c_double()
+        dd = ctypes.c_double()
+        self._check(lib().ba_grad(self._h, _ptr(theta), ctypes.byref(I), _ptr(g),
+                                  ctypes.byref(dd) if want_dd else None), "ba_grad")
+        return I.value, g, (dd.value if want_dd else None)
+
+    def mirror_ascent(self, theta: torch.Tensor, eta: float, steps: int) -> torch.Tensor:
+        th = theta.to(self.device, torch.float64).clone().contiguous()
+        self._check(lib().ba_mirror_ascent(self._h, _ptr(th), eta, steps), "ba_mirror_ascent")
+        return th
+
+    def get_logp(self) -> torch.Tensor:
+        tot = sum(1 << n for n in self.n)
+        out = torch.empty(tot, dtype=torch.float64, device=self.device)
+        self._check(lib().ba_get_logp(self._h, _ptr(out)), "ba_get_logp")
+        return out
+
+    def set_logp(self, logp: torch.Tensor):
+        logp = logp.to(self.device, torch.float64).contiguous()
+        self._check(lib().ba_set_logp(self._h, _ptr(logp)), "ba_set_logp")
+
+    def row_counts(self, x: int, cap: int | None = None):
+        n = self.n[0]
+        if cap is None:
+            cap = min((1 << (n + 1)) - 1, 40000)
+        rk = torch.zeros(max(cap, 1), dtype=torch.int32, device=self.device)
+        em = torch.zeros(max(cap, 1), dtype=torch.int32, device=self.device)
+        nz = ctypes.c_int()
+        self._check(lib().ba_row_counts(self._h, x, _ptr(rk), _ptr(em), cap, ctypes.byref(nz)), "ba_row_counts")
+        return rk[:nz.value].cpu().numpy().view("uint32"), em[:nz.value].cpu().numpy().view("uint32")
+
+    def verify_counts(self):
+        st = (ctypes.c_uint64 * 6)()
+        self._check(lib().ba_verify_counts(self._h, st), "ba_verify_counts")
+        keys = ("total_nnz", "rows_failing", "reserved", "min_row_nnz", "max_row_nnz", "max_emb")
+        return dict(zip(keys, [int(v) for v in st]))
+
+    def time_kernels(self, iters: int):
+        ms = (ctypes.c_double * len(KCLASS))()
+        cnt = (ctypes.c_int * len(KCLASS))()
+        self._check(lib().ba_time_kernels(self._h, iters, ms, cnt), "ba_time_kernels")
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(KCLASS)}
+
+
+class BAInfo(torch.autograd.Function):
+    """I(p; d) in bits for p = softmax(theta), with the hand-written backward:
+    dI/dtheta = p (D - I) / ln 2 and dI/dd (see ba_grad in include/ba.h).
+
+    ``ctx_ba`` is a one-instance :class:`Context` built for the same d."""
+
+    @staticmethod
+    def forward(ctx, theta: torch.Tensor, d: torch.Tensor, ctx_ba: Context):
+        want_dd = 0.0 < ctx_ba.d[0] < 1.0
+        I, g_theta, g_d = ctx_ba.grad(theta.detach(), want_dd=want_dd)
+        ctx.save_for_backward(g_theta.to(device=theta.device, dtype=theta.dtype))
+        ctx.g_d = 0.0 if g_d is None else g_d
+        return theta.new_tensor(I)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (g_theta,) = ctx.saved_tensors
+        return grad_out * g_theta, grad_out * ctx.g_d, None

@@ -1,0 +1,758 @@
+// Host side of the C ABI declared in include/ba.h.
+//
+// A context holds host state only: instance parameters, the workspace layout
+// and the bound stream.  All device memory comes from the caller's workspace.
+// Every iteration step is a fixed sequence of kernel launches on the bound
+// stream with no host synchronisation; host round trips happen only in the
+// calls documented as blocking.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/ba.h"
+#include "ba_internal.h"
+
+using namespace ba;
+
+namespace {
+
+inline size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
+inline size_t pad64(size_t n) { return (n + 63) & ~size_t(63); }
+
+// Offsets of one group's arrays inside the workspace.
+struct GroupLayout {
+  size_t tables;
+  size_t lp, p, r, v, v2, g, gd, D, f0, f1;     // iteration arrays (precision T)
+  size_t h, hd, part, st, cs;
+  size_t c_lp, c_p, c_r, c_v, c_v2, c_g, c_gd, c_D, c_f0, c_f1, c_part, c_st;  // FP64 cert
+};
+
+struct GroupHost {
+  int n = 0;
+  std::vector<int> inst;      // global instance ids, increasing
+  GroupLayout L{};
+  Tables tb{};
+  Group<float> gf{};          // iteration group if FP32
+  Group<double> gd{};         // iteration group if FP64
+  Group<double> cert{};       // FP64 evaluation group
+  size_t xs = 0, ys = 0, v2s = 0, fs = 0, ps = 0;
+};
+
+}  // namespace
+
+struct ba_ctx {
+  int count = 0;
+  std::vector<int> n;
+  std::vector<double> d;
+  int prec = BA_PREC_FP64;
+  int cert_every = 1;
+  int engine = BA_ENGINE_FACTORED;
+  std::vector<GroupHost> groups;
+  std::vector<std::pair<int, int>> where;  // instance -> (group, slot)
+  size_t need = 0;
+  size_t misc = 0;       // misc area: stats[8] u64, nnz u32, out4 double, scratch State
+  size_t verify = 0;     // verify bins / dense row for group of instance 0
+  size_t verify_bytes = 0;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  hipStream_t stream = nullptr;
+  bool bound = false;
+  std::string err;
+  // timing hook
+  bool timing = false;
+  std::vector<hipEvent_t> ev;
+  std::vector<int> ev_class;    // class of the bracket opened by the event, -1 for a close
+  std::vector<int> ev_kernels;  // kernels launched inside the bracket
+};
+
+namespace {
+
+int fail(ba_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                    \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      return fail((ctx), BA_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));     \
+  } while (0)
+
+uint64_t ipow3(int e) {
+  uint64_t v = 1;
+  while (e-- > 0) v *= 3;
+  return v;
+}
+
+bool valid_d(double d) { return d >= 0.0 && d <= 1.0 && isfinite(d); }
+
+void make_consts(int n, double d, Consts* c) {
+  memset(c, 0, sizeof(*c));
+  for (int k = 0; k <= n; ++k) {
+    const double a = (n - k == 0) ? 1.0 : pow(d, double(n - k));
+    const double b = (k == 0) ? 1.0 : pow(1.0 - d, double(k));
+    c->w[k] = a * b;
+    c->sw[k] = (d > 0.0 && d < 1.0) ? ((n - k) / d - k / (1.0 - d)) * c->w[k] : 0.0;
+  }
+}
+
+size_t elem(const ba_ctx* c) { return c->prec == BA_PREC_FP32_LOG ? sizeof(float) : sizeof(double); }
+
+void plan(ba_ctx* c) {
+  // group instances by n (order of first appearance)
+  c->groups.clear();
+  c->where.assign(c->count, {0, 0});
+  for (int i = 0; i < c->count; ++i) {
+    int gi = -1;
+    for (size_t j = 0; j < c->groups.size(); ++j)
+      if (c->groups[j].n == c->n[i]) gi = int(j);
+    if (gi < 0) {
+      GroupHost g;
+      g.n = c->n[i];
+      c->groups.push_back(g);
+      gi = int(c->groups.size()) - 1;
+    }
+    c->where[i] = {gi, int(c->groups[gi].inst.size())};
+    c->groups[gi].inst.push_back(i);
+  }
+  const size_t T = elem(c);
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o += al256(bytes); return r; };
+  for (auto& g : c->groups) {
+    const int n = g.n, n1 = (n + 1) / 2, n2 = n / 2;
+    const size_t nb = g.inst.size();
+    g.xs = pad64(size_t(1) << n);
+    g.ys = pad64(out_count(n));
+    g.v2s = pad64(size_t(out_count(n1)) * out_count(n2));
+    g.fs = pad64(size_t(2) << n);
+    g.ps = size_t(2) * kMaxRedBlocks * kPartStride;
+    GroupLayout& L = g.L;
+    L.tables = take(table_bytes(n));
+    L.lp = take(nb * g.xs * T);
+    L.p = take(nb * g.xs * T);
+    L.r = take(nb * g.ys * T);
+    L.v = take(nb * g.ys * T);
+    L.v2 = take(nb * g.v2s * T);
+    L.g = take(nb * g.xs * T);
+    L.gd = take(nb * g.xs * T);
+    L.D = take(nb * g.xs * T);
+    L.f0 = take(nb * g.fs * T);
+    L.f1 = take(nb * g.fs * T);
+    L.h = take(nb * g.xs * 8);
+    L.hd = take(nb * g.xs * 8);
+    L.part = take(nb * g.ps * 8);
+    L.st = take(nb * sizeof(State));
+    L.cs = take(nb * sizeof(Consts));
+    L.c_lp = take(nb * g.xs * 8);
+    L.c_p = take(nb * g.xs * 8);
+    L.c_r = take(nb * g.ys * 8);
+    L.c_v = take(nb * g.ys * 8);
+    L.c_v2 = take(nb * g.v2s * 8);
+    L.c_g = take(nb * g.xs * 8);
+    L.c_gd = take(nb * g.xs * 8);
+    L.c_D = take(nb * g.xs * 8);
+    L.c_f0 = take(nb * g.fs * 8);
+    L.c_f1 = take(nb * g.fs * 8);
+    L.c_part = take(nb * g.ps * 8);
+    L.c_st = take(nb * sizeof(State));
+  }
+  // verify bins for instance 0's n (also the dense row buffer)
+  const int n0 = c->n[0];
+  c->verify_bytes = (size_t(1) << n0) * size_t(n0 + 2) * 4;
+  if (c->verify_bytes < size_t(out_count(n0)) * 4) c->verify_bytes = size_t(out_count(n0)) * 4;
+  c->verify = take(c->verify_bytes);
+  c->misc = take(4096);
+  c->need = o;
+}
+
+template <typename T>
+Group<T> make_group(char* ws, const GroupHost& g, bool cert) {
+  const GroupLayout& L = g.L;
+  Group<T> G{};
+  G.n = g.n;
+  G.nb = int(g.inst.size());
+  G.xs = g.xs;
+  G.ys = g.ys;
+  G.v2s = g.v2s;
+  G.fs = g.fs;
+  G.ps = g.ps;
+  G.lp = reinterpret_cast<T*>(ws + (cert ? L.c_lp : L.lp));
+  G.p = reinterpret_cast<T*>(ws + (cert ? L.c_p : L.p));
+  G.r = reinterpret_cast<T*>(ws + (cert ? L.c_r : L.r));
+  G.v = reinterpret_cast<T*>(ws + (cert ? L.c_v : L.v));
+  G.v2 = reinterpret_cast<T*>(ws + (cert ? L.c_v2 : L.v2));
+  G.g = reinterpret_cast<T*>(ws + (cert ? L.c_g : L.g));
+  G.gd = reinterpret_cast<T*>(ws + (cert ? L.c_gd : L.gd));
+  G.D = reinterpret_cast<T*>(ws + (cert ? L.c_D : L.D));
+  G.f0 = reinterpret_cast<T*>(ws + (cert ? L.c_f0 : L.f0));
+  G.f1 = reinterpret_cast<T*>(ws + (cert ? L.c_f1 : L.f1));
+  G.h = reinterpret_cast<const double*>(ws + L.h);
+  G.hd = reinterpret_cast<const double*>(ws + L.hd);
+  G.part = reinterpret_cast<double*>(ws + (cert ? L.c_part : L.part));
+  G.st = reinterpret_cast<State*>(ws + (cert ? L.c_st : L.st));
+  G.cs = reinterpret_cast<const Consts*>(ws + L.cs);
+  return G;
+}
+
+// Restrict a group view to one instance slot.
+template <typename T>
+Group<T> slot_view(Group<T> G, int j) {
+  G.nb = 1;
+  G.lp += size_t(j) * G.xs;
+  G.p += size_t(j) * G.xs;
+  G.r += size_t(j) * G.ys;
+  G.v += size_t(j) * G.ys;
+  G.v2 += size_t(j) * G.v2s;
+  G.g += size_t(j) * G.xs;
+  G.gd += size_t(j) * G.xs;
+  G.D += size_t(j) * G.xs;
+  G.f0 += size_t(j) * G.fs;
+  G.f1 += size_t(j) * G.fs;
+  G.h += size_t(j) * G.xs;
+  G.hd += size_t(j) * G.xs;
+  G.part += size_t(j) * G.ps;
+  G.st += j;
+  G.cs += j;
+  return G;
+}
+
+int k0_for(int n, int nbt, size_t esz) {
+  int k0 = 0;
+  while (k0 + 1 <= n && size_t((2u << (k0 + 1)) - 1u) * nbt * esz <= 65536) ++k0;
+  return k0;
+}
+
+// ---- timing hook: events around kernel classes ------------------------------
+struct Timer {
+  ba_ctx* c;
+  Timer(ba_ctx* c_, int cls, int kernels) : c(c_) { mark(cls, kernels); }
+  ~Timer() { mark(-1, 0); }
+  void mark(int cls, int kernels) {
+    if (!c->timing) return;
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    (void)hipEventRecord(e, c->stream);
+    c->ev.push_back(e);
+    c->ev_class.push_back(cls);
+    c->ev_kernels.push_back(kernels);
+  }
+};
+
+// One sweep pair + reductions on group G (iteration or certification group).
+template <typename T>
+int sweeps(ba_ctx* c, const GroupHost& gh, const Group<T>& G, int use_sw_g, T* g_out) {
+  hipStream_t s = c->stream;
+  const int n = gh.n, n1 = (n + 1) / 2, n2 = n / 2;
+  const StreamExtra ex{};
+  if (c->engine == BA_ENGINE_STREAM) {
+    const int nbt = G.nb < kTile ? G.nb : kTile;
+    const int k0 = k0_for(n, nbt, sizeof(T));
+    {
+      Timer t(c, BA_K_SWEEP1, 1);
+      HIPCHK(c, launch_fill_zero(G.r, size_t(G.nb) * G.ys * sizeof(T), s));
+      HIPCHK(c, launch_stream<T>(kOpScatter, gh.tb, G, k0, ex, s));
+    }
+    {
+      Timer t(c, BA_K_LOGR, 1);
+      HIPCHK(c, launch_logr<T>(G, use_sw_g, 1, n1, n2, s));
+    }
+    {
+      Timer t(c, BA_K_SWEEP2, 1);
+      Group<T> G2 = G;
+      G2.g = g_out;
+      HIPCHK(c, launch_fill_zero(g_out, size_t(G.nb) * G.xs * sizeof(T), s));
+      HIPCHK(c, launch_stream<T>(kOpGather, gh.tb, G2, k0, ex, s));
+    }
+  } else {
+    {
+      Timer t(c, BA_K_SWEEP1, n);
+      HIPCHK(c, launch_forward<T>(G, s, nullptr));
+    }
+    {
+      Timer t(c, BA_K_LOGR, 1);
+      HIPCHK(c, launch_logr<T>(G, use_sw_g, 0, n1, n2, s));
+    }
+    {
+      Timer t(c, BA_K_SWEEP2, n);
+      Group<T> G2 = G;
+      G2.g = g_out;
+      HIPCHK(c, launch_backward<T>(G2, s, nullptr));
+    }
+  }
+  return BA_OK;
+}
+
+template <typename T>
+int iterate_group(ba_ctx* c, const GroupHost& gh, const Group<T>& G) {
+  const int nblk = reduce_blocks(gh.n);
+  int rc = sweeps<T>(c, gh, G, 0, G.g);
+  if (rc) return rc;
+  {
+    Timer t(c, BA_K_REDUCE, 1);
+    HIPCHK(c, launch_dpart<T>(G, nblk, 0, nullptr, c->stream));
+  }
+  {
+    Timer t(c, BA_K_UPDATE, 1);
+    const double floor = (sizeof(T) == 4) ? kFloor32 : kFloor64;
+    HIPCHK(c, launch_update<T>(G, nblk, floor, c->prec == BA_PREC_FP64 ? 1 : 0, c->stream));
+  }
+  return BA_OK;
+}
+
+// FP64 evaluation of `src` (any precision) through the certification group; the
+// results land in cert.D / cert.r / cert.st and, via finish, in `out` states.
+template <typename T>
+int certify_group(ba_ctx* c, const GroupHost& gh, const Group<T>& src, const Group<double>& cert,
+                  State* out, int write_best) {
+  const int nblk = reduce_blocks(gh.n);
+  HIPCHK(c, launch_cert_prepare<T>(src, cert, nblk, kFloor64, c->stream));
+  int rc = sweeps<double>(c, gh, cert, 0, cert.g);
+  if (rc) return rc;
+  HIPCHK(c, launch_dpart<double>(cert, nblk, 0, nullptr, c->stream));
+  HIPCHK(c, launch_cert_finish(cert, nblk, out, write_best, c->stream));
+  return BA_OK;
+}
+
+int certify_all(ba_ctx* c, int write_best) {
+  for (auto& gh : c->groups) {
+    int rc;
+    if (c->prec == BA_PREC_FP32_LOG) rc = certify_group<float>(c, gh, gh.gf, gh.cert, gh.gf.st, write_best);
+    else rc = certify_group<double>(c, gh, gh.gd, gh.cert, gh.gd.st, write_best);
+    if (rc) return rc;
+  }
+  return BA_OK;
+}
+
+int read_states(ba_ctx* c, std::vector<State>& out) {
+  out.resize(c->count);
+  for (auto& gh : c->groups) {
+    std::vector<State> tmp(gh.inst.size());
+    const State* src = (c->prec == BA_PREC_FP32_LOG) ? gh.gf.st : gh.gd.st;
+    HIPCHK(c, hipMemcpyAsync(tmp.data(), src, tmp.size() * sizeof(State), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (size_t j = 0; j < gh.inst.size(); ++j) out[gh.inst[j]] = tmp[j];
+  }
+  return BA_OK;
+}
+
+int write_states(ba_ctx* c, const std::vector<State>& in) {
+  for (auto& gh : c->groups) {
+    std::vector<State> tmp(gh.inst.size());
+    for (size_t j = 0; j < gh.inst.size(); ++j) tmp[j] = in[gh.inst[j]];
+    State* dst = (c->prec == BA_PREC_FP32_LOG) ? gh.gf.st : gh.gd.st;
+    HIPCHK(c, hipMemcpyAsync(dst, tmp.data(), tmp.size() * sizeof(State), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  return BA_OK;
+}
+
+int check_ctx(ba_ctx* c) {
+  if (!c) return BA_EINVAL;
+  if (!c->bound) return fail(c, BA_ESTATE, "context is not bound to a workspace (call ba_bind)");
+  return BA_OK;
+}
+
+int new_ctx(int count, const int* n, const double* d, int prec, int cert_every, ba_ctx** out) {
+  if (!out || count < 1 || count > 4096 || !n || !d || cert_every < 1 ||
+      (prec != BA_PREC_FP64 && prec != BA_PREC_FP32_LOG))
+    return BA_EINVAL;
+  for (int i = 0; i < count; ++i)
+    if (n[i] < 1 || n[i] > kNMax || !valid_d(d[i])) return BA_EINVAL;
+  ba_ctx* c = new (std::nothrow) ba_ctx();
+  if (!c) return BA_ENOMEM;
+  c->count = count;
+  c->n.assign(n, n + count);
+  c->d.assign(d, d + count);
+  c->prec = prec;
+  c->cert_every = cert_every;
+  plan(c);
+  *out = c;
+  return BA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ba_init(int n, double d, ba_ctx** out) { return new_ctx(1, &n, &d, BA_PREC_FP64, 1, out); }
+
+int ba_init_batch(int count, const int* n, const double* d, int prec, int cert_every, ba_ctx** out) {
+  return new_ctx(count, n, d, prec, cert_every, out);
+}
+
+int ba_set_engine(ba_ctx* c, int engine) {
+  if (!c || (engine != BA_ENGINE_STREAM && engine != BA_ENGINE_FACTORED)) return BA_EINVAL;
+  c->engine = engine;
+  return BA_OK;
+}
+
+void ba_free(ba_ctx* c) {
+  if (!c) return;
+  for (auto e : c->ev) (void)hipEventDestroy(e);
+  delete c;
+}
+
+int ba_workspace_bytes(const ba_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return BA_EINVAL;
+  *bytes = c->need;
+  return BA_OK;
+}
+
+int ba_bind(ba_ctx* c, void* ws, size_t bytes, void* stream) {
+  if (!c || !ws || (reinterpret_cast<uintptr_t>(ws) & 255u)) return fail(c, BA_EINVAL, "workspace pointer NULL or not 256-byte aligned");
+  if (bytes < c->need) return fail(c, BA_ENOMEM, "workspace smaller than ba_workspace_bytes");
+  c->ws = static_cast<char*>(ws);
+  c->ws_bytes = bytes;
+  c->stream = static_cast<hipStream_t>(stream);
+  c->bound = false;
+  hipStream_t s = c->stream;
+  for (auto& gh : c->groups) {
+    gh.gf = make_group<float>(c->ws, gh, false);
+    gh.gd = make_group<double>(c->ws, gh, false);
+    gh.cert = make_group<double>(c->ws, gh, true);
+    HIPCHK(c, build_tables(gh.n, c->ws + gh.L.tables, s, &gh.tb));
+    // per-instance constants
+    std::vector<Consts> cs(gh.inst.size());
+    for (size_t j = 0; j < gh.inst.size(); ++j) make_consts(gh.n, c->d[gh.inst[j]], &cs[j]);
+    HIPCHK(c, hipMemcpyAsync(c->ws + gh.L.cs, cs.data(), cs.size() * sizeof(Consts), hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    // H and Hd: one pass of the count generator over all nonzeros (init op)
+    const size_t nb = gh.inst.size();
+    HIPCHK(c, launch_fill_zero(c->ws + gh.L.h, nb * gh.xs * 8, s));
+    HIPCHK(c, launch_fill_zero(c->ws + gh.L.hd, nb * gh.xs * 8, s));
+    StreamExtra ex{};
+    ex.h = reinterpret_cast<double*>(c->ws + gh.L.h);
+    ex.hd = reinterpret_cast<double*>(c->ws + gh.L.hd);
+    HIPCHK(c, launch_stream<double>(kOpInit, gh.tb, gh.cert, 0, ex, s));
+    // states
+    HIPCHK(c, launch_fill_zero(c->ws + gh.L.c_st, nb * sizeof(State), s));
+    if (c->prec == BA_PREC_FP32_LOG) HIPCHK(c, launch_reset<float>(gh.gf, s));
+    else HIPCHK(c, launch_reset<double>(gh.gd, s));
+  }
+  HIPCHK(c, hipStreamSynchronize(s));
+  c->bound = true;
+  return BA_OK;
+}
+
+int ba_step(ba_ctx* c, int iters) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (iters < 0) return fail(c, BA_EINVAL, "iters < 0");
+  for (int it = 0; it < iters; ++it)
+    for (auto& gh : c->groups) {
+      rc = (c->prec == BA_PREC_FP32_LOG) ? iterate_group<float>(c, gh, gh.gf) : iterate_group<double>(c, gh, gh.gd);
+      if (rc) return rc;
+    }
+  return BA_OK;
+}
+
+int ba_run(ba_ctx* c, double gap_bits, int max_iters, int* iters_done) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!(gap_bits > 0.0) || max_iters < 0) return fail(c, BA_EINVAL, "gap_bits must be > 0 and max_iters >= 0");
+  std::vector<State> st;
+  if ((rc = read_states(c, st))) return rc;
+  std::vector<int> start(c->count);
+  for (int i = 0; i < c->count; ++i) {
+    start[i] = st[i].iters;
+    st[i].tol = gap_bits * kLn2;
+    if (!st[i].bad) st[i].converged = 0;
+  }
+  if ((rc = write_states(c, st))) return rc;
+  // FP64 iterates: the update kernel tests the gap of every iterate and freezes the
+  // instance at the first one below tol; FP32: certify every cert_every iterations.
+  const int chunk = (c->prec == BA_PREC_FP64) ? 32 : c->cert_every;
+  int done = 0;
+  bool all = false;
+  while (done < max_iters) {
+    const int k = std::min(chunk, max_iters - done);
+    if ((rc = ba_step(c, k))) return rc;
+    done += k;
+    if (c->prec == BA_PREC_FP32_LOG && (rc = certify_all(c, 1))) return rc;
+    if ((rc = read_states(c, st))) return rc;
+    all = true;
+    for (int i = 0; i < c->count; ++i) {
+      if (st[i].bad) return fail(c, BA_ENUMERIC, "non-finite value in instance " + std::to_string(i));
+      if (!st[i].converged) all = false;
+    }
+    if (all) break;
+  }
+  // certify the final iterates (records best bounds)
+  if ((rc = certify_all(c, 1))) return rc;
+  if ((rc = read_states(c, st))) return rc;
+  int most = 0;
+  for (int i = 0; i < c->count; ++i) {
+    if (st[i].bad) return fail(c, BA_ENUMERIC, "non-finite value in instance " + std::to_string(i));
+    most = std::max(most, st[i].iters - start[i]);
+  }
+  if (iters_done) *iters_done = most;
+  return BA_OK;
+}
+
+int ba_bounds(ba_ctx* c, double* lower, double* upper) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!lower || !upper) return fail(c, BA_EINVAL, "NULL output");
+  if ((rc = certify_all(c, 1))) return rc;
+  std::vector<State> st;
+  if ((rc = read_states(c, st))) return rc;
+  for (int i = 0; i < c->count; ++i)
+    if (st[i].bad) return fail(c, BA_ENUMERIC, "non-finite value in instance " + std::to_string(i));
+  for (int i = 0; i < c->count; ++i) {
+    lower[i] = st[i].certL / kLn2;
+    upper[i] = st[i].certU / kLn2;
+  }
+  return BA_OK;
+}
+
+int ba_best_bounds(ba_ctx* c, double* lower, double* upper, int* iters) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!lower || !upper) return fail(c, BA_EINVAL, "NULL output");
+  std::vector<State> st;
+  if ((rc = read_states(c, st))) return rc;
+  for (int i = 0; i < c->count; ++i) {
+    lower[i] = st[i].bestL / kLn2;
+    upper[i] = st[i].bestU / kLn2;
+    if (iters) iters[i] = st[i].iters;
+  }
+  return BA_OK;
+}
+
+int ba_eval(ba_ctx* c, const double* logp_dev, double* r_dev, double* D_dev, double* out4) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!logp_dev) return fail(c, BA_EINVAL, "NULL logp");
+  const auto [gi, slot] = c->where[0];
+  GroupHost& gh = c->groups[gi];
+  Group<double> src = slot_view(gh.gd, 0);
+  src.lp = const_cast<double*>(logp_dev);
+  src.xs = size_t(1) << gh.n;
+  Group<double> cert = slot_view(gh.cert, slot);
+  State* scratch = reinterpret_cast<State*>(c->ws + c->misc + 256);
+  HIPCHK(c, launch_fill_zero(scratch, 256, c->stream));
+  if ((rc = certify_group<double>(c, gh, src, cert, scratch, 0))) return rc;
+  const size_t X = size_t(1) << gh.n;
+  if (r_dev) HIPCHK(c, launch_copy_f64(r_dev, cert.r, out_count(gh.n), c->stream));
+  if (D_dev) HIPCHK(c, launch_copy_f64(D_dev, cert.D, X, c->stream));
+  State h;
+  HIPCHK(c, hipMemcpyAsync(&h, scratch, sizeof(State), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (h.bad) return fail(c, BA_ENUMERIC, "non-finite value in logp");
+  if (out4) {
+    out4[0] = h.certL / kLn2;
+    out4[1] = h.certU / kLn2;
+    out4[2] = h.certI / kLn2;
+    out4[3] = h.certM;
+  }
+  return BA_OK;
+}
+
+int ba_grad(ba_ctx* c, const double* theta_dev, double* I_bits, double* dI_dtheta_dev, double* dI_dd_bits) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!theta_dev || !I_bits) return fail(c, BA_EINVAL, "NULL theta or I");
+  if (dI_dd_bits && !(c->d[0] > 0.0 && c->d[0] < 1.0))
+    return fail(c, BA_EINVAL, "dI/dd is undefined at d = 0 or d = 1");
+  const auto [gi, slot] = c->where[0];
+  GroupHost& gh = c->groups[gi];
+  hipStream_t s = c->stream;
+  const int nblk = reduce_blocks(gh.n);
+  Group<double> src = slot_view(gh.gd, 0);
+  src.lp = const_cast<double*>(theta_dev);
+  src.xs = size_t(1) << gh.n;
+  Group<double> cert = slot_view(gh.cert, slot);
+  HIPCHK(c, launch_cert_prepare<double>(src, cert, nblk, kFloor64, s));
+  if ((rc = sweeps<double>(c, gh, cert, 0, cert.g))) return rc;
+  // second gather with v = s_k w_k log r: Gd
+  const int n1 = (gh.n + 1) / 2, n2 = gh.n / 2;
+  {
+    Group<double> Gd = cert;
+    Gd.g = cert.gd;
+    HIPCHK(c, launch_logr<double>(cert, 1, c->engine == BA_ENGINE_STREAM, n1, n2, s));
+    if (c->engine == BA_ENGINE_STREAM) {
+      const StreamExtra ex{};
+      HIPCHK(c, launch_fill_zero(cert.gd, cert.xs * sizeof(double), s));
+      HIPCHK(c, launch_stream<double>(kOpGather, gh.tb, Gd, k0_for(gh.n, 1, 8), ex, s));
+    } else {
+      HIPCHK(c, launch_backward<double>(Gd, s, nullptr));
+    }
+  }
+  HIPCHK(c, launch_dpart<double>(cert, nblk, 1, cert.gd, s));
+  double* out4 = reinterpret_cast<double*>(c->ws + c->misc + 128);
+  HIPCHK(c, launch_grad_finish(cert, nblk, out4, dI_dtheta_dev, s));
+  double h[4];
+  HIPCHK(c, hipMemcpyAsync(h, out4, sizeof(h), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  if (!isfinite(h[0]) || !isfinite(h[1])) return fail(c, BA_ENUMERIC, "non-finite gradient");
+  *I_bits = h[0];
+  if (dI_dd_bits) *dI_dd_bits = h[1];
+  return BA_OK;
+}
+
+int ba_mirror_ascent(ba_ctx* c, double* theta_dev, double eta, int steps) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!theta_dev || steps < 0 || !isfinite(eta)) return fail(c, BA_EINVAL, "bad mirror-ascent arguments");
+  const auto [gi, slot] = c->where[0];
+  GroupHost& gh = c->groups[gi];
+  const int nblk = reduce_blocks(gh.n);
+  Group<double> src = slot_view(gh.gd, 0);
+  src.lp = theta_dev;
+  src.xs = size_t(1) << gh.n;
+  Group<double> cert = slot_view(gh.cert, slot);
+  for (int t = 0; t < steps; ++t) {
+    HIPCHK(c, launch_cert_prepare<double>(src, cert, nblk, kFloor64, c->stream));
+    if ((rc = sweeps<double>(c, gh, cert, 0, cert.g))) return rc;
+    HIPCHK(c, launch_dpart<double>(cert, nblk, 0, nullptr, c->stream));
+    HIPCHK(c, launch_mirror_update(gh.n, theta_dev, cert.D, eta, c->stream));
+  }
+  return BA_OK;
+}
+
+int ba_get_logp(ba_ctx* c, double* logp_dev) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!logp_dev) return fail(c, BA_EINVAL, "NULL logp");
+  size_t off = 0;
+  for (int i = 0; i < c->count; ++i) {
+    const auto [gi, slot] = c->where[i];
+    GroupHost& gh = c->groups[gi];
+    if (c->prec == BA_PREC_FP32_LOG) HIPCHK(c, launch_get_logp<float>(slot_view(gh.gf, slot), logp_dev + off, c->stream));
+    else HIPCHK(c, launch_get_logp<double>(slot_view(gh.gd, slot), logp_dev + off, c->stream));
+    off += size_t(1) << c->n[i];
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return BA_OK;
+}
+
+int ba_set_logp(ba_ctx* c, const double* logp_dev) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!logp_dev) return fail(c, BA_EINVAL, "NULL logp");
+  size_t off = 0;
+  for (int i = 0; i < c->count; ++i) {
+    const auto [gi, slot] = c->where[i];
+    GroupHost& gh = c->groups[gi];
+    const int nblk = reduce_blocks(gh.n);
+    const double floor = (c->prec == BA_PREC_FP32_LOG) ? kFloor32 : kFloor64;
+    if (c->prec == BA_PREC_FP32_LOG) HIPCHK(c, launch_set_logp<float>(slot_view(gh.gf, slot), logp_dev + off, nblk, floor, c->stream));
+    else HIPCHK(c, launch_set_logp<double>(slot_view(gh.gd, slot), logp_dev + off, nblk, floor, c->stream));
+    off += size_t(1) << c->n[i];
+  }
+  std::vector<State> st;
+  if ((rc = read_states(c, st))) return rc;
+  for (int i = 0; i < c->count; ++i)
+    if (st[i].bad) return fail(c, BA_ENUMERIC, "logp contains NaN or +Inf (instance " + std::to_string(i) + ")");
+  return BA_OK;
+}
+
+int ba_row_counts(ba_ctx* c, uint32_t x, uint32_t* rank_dev, uint32_t* emb_dev, int cap, int* nnz) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  const auto [gi, slot] = c->where[0];
+  GroupHost& gh = c->groups[gi];
+  if (!nnz || x >= (1u << gh.n) || cap < 0 || (cap > 0 && (!rank_dev || !emb_dev)))
+    return fail(c, BA_EINVAL, "bad row arguments");
+  hipStream_t s = c->stream;
+  uint32_t* dense = reinterpret_cast<uint32_t*>(c->ws + c->verify);
+  uint32_t* nnz_dev = reinterpret_cast<uint32_t*>(c->ws + c->misc + 64);
+  HIPCHK(c, launch_fill_zero(dense, al256(size_t(out_count(gh.n)) * 4), s));
+  StreamExtra ex{};
+  ex.target_x = x;
+  ex.row_dense = dense;
+  HIPCHK(c, launch_stream<double>(kOpRow, gh.tb, slot_view(gh.cert, slot), 0, ex, s));
+  HIPCHK(c, launch_row_compact(dense, gh.n, rank_dev, emb_dev, cap, nnz_dev, s));
+  uint32_t h = 0;
+  HIPCHK(c, hipMemcpyAsync(&h, nnz_dev, 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  *nnz = int(h);
+  if (int(h) > cap) return fail(c, BA_EINVAL, "cap smaller than the row's nonzero count");
+  return BA_OK;
+}
+
+int ba_verify_counts(ba_ctx* c, uint64_t* stats) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!stats) return fail(c, BA_EINVAL, "NULL stats");
+  const auto [gi, slot] = c->where[0];
+  GroupHost& gh = c->groups[gi];
+  hipStream_t s = c->stream;
+  uint32_t* bins = reinterpret_cast<uint32_t*>(c->ws + c->verify);
+  unsigned long long* st_dev = reinterpret_cast<unsigned long long*>(c->ws + c->misc);
+  HIPCHK(c, launch_fill_zero(bins, al256(c->verify_bytes), s));
+  unsigned long long init[8] = {0, 0, 0, ~0ull, 0, 0, 0, 0};
+  HIPCHK(c, hipMemcpyAsync(st_dev, init, sizeof(init), hipMemcpyHostToDevice, s));
+  StreamExtra ex{};
+  ex.bins = bins;
+  ex.stats = st_dev;
+  HIPCHK(c, launch_stream<double>(kOpVerify, gh.tb, slot_view(gh.cert, slot), 0, ex, s));
+  unsigned long long h[8];
+  HIPCHK(c, hipMemcpyAsync(h, st_dev, sizeof(h), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  for (int i = 0; i < 6; ++i) stats[i] = h[i];
+  stats[2] = 0;
+  return BA_OK;
+}
+
+int ba_time_kernels(ba_ctx* c, int iters, double* ms, int* launches) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!ms || iters < 0) return fail(c, BA_EINVAL, "bad timing arguments");
+  for (auto e : c->ev) (void)hipEventDestroy(e);
+  c->ev.clear();
+  c->ev_class.clear();
+  c->ev_kernels.clear();
+  c->timing = true;
+  rc = ba_step(c, iters);
+  c->timing = false;
+  if (rc) return rc;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int k = 0; k < BA_NKCLASS; ++k) {
+    ms[k] = 0.0;
+    if (launches) launches[k] = 0;
+  }
+  for (size_t i = 0; i + 1 < c->ev.size(); i += 2) {
+    float t = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&t, c->ev[i], c->ev[i + 1]));
+    const int k = c->ev_class[i];
+    if (k >= 0 && k < BA_NKCLASS) {
+      ms[k] += t;
+      if (launches) launches[k] += c->ev_kernels[i];
+    }
+  }
+  for (auto e : c->ev) (void)hipEventDestroy(e);
+  c->ev.clear();
+  c->ev_class.clear();
+  c->ev_kernels.clear();
+  return BA_OK;
+}
+
+int ba_instance_count(const ba_ctx* c) { return c ? c->count : 0; }
+
+uint64_t ba_nnz(int n) {
+  if (n < 0 || n > 40) return 0;
+  return 2 * ipow3(n) - (uint64_t(1) << n);
+}
+
+const char* ba_strerror(int code) {
+  switch (code) {
+    case BA_OK: return "ok";
+    case BA_EINVAL: return "invalid argument";
+    case BA_ENOMEM: return "out of memory or workspace too small";
+    case BA_EDEVICE: return "HIP device error";
+    case BA_ESTATE: return "invalid state";
+    case BA_ENUMERIC: return "non-finite value";
+  }
+  return "unknown error";
+}
+
+const char* ba_last_error(const ba_ctx* c) { return c ? c->err.c_str() : ""; }
+
+}  // extern "C"

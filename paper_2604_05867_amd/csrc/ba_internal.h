@@ -1,0 +1,185 @@
+// Internal declarations shared by the HIP sources of libba (not part of the ABI).
+//
+// Notation (paper, Sections 2.2-2.3): x in {0,1}^n is an input, y in {0,1}^{<=n}
+// an output, emb(y,x) the number of embeddings of y in x, w_k = d^(n-k)(1-d)^k,
+// W(y|x) = emb(y,x) w_|y|.  One BA iteration computes
+//   r(y) = sum_x p(x) emb(y,x)          (so q(y) = w_k r(y)),
+//   G(x) = sum_y emb(y,x) w_k log r(y),
+//   D(x) = H(x) - G(x),  H(x) = sum_y emb(y,x) w_k log emb(y,x),
+// because log(W/q) = log(emb/r): the weight w_k cancels.  Both sweeps work on
+// r scaled by e^{-M} (M = max log p); the shift is undone in the D kernel
+// (sum_y W(y|x) = 1).
+//
+// Instances that share n form a group; every per-instance array of a group is
+// one allocation with a fixed stride per instance (instance b at b*stride).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ba {
+
+constexpr int kNMax = 20;       // largest supported input length
+constexpr int kHalfMax = 10;    // largest half length ceil(20/2)
+constexpr int kWave = 64;       // CDNA wavefront
+constexpr int kBlock = 256;     // threads per block
+constexpr int kTile = 8;        // instances handled together by one stream-engine launch
+constexpr double kLn2 = 0.69314718055994530942;
+constexpr double kFloor64 = 700.0;  // floor on log p, nats below the max (FP64)
+constexpr double kFloor32 = 80.0;   // floor on log p, nats below the max (FP32 iterates)
+constexpr int kPartStride = 8;      // doubles per block record of a reduction
+constexpr int kMaxRedBlocks = 1024; // blocks per instance of a reduction
+
+inline __host__ __device__ uint32_t out_count(int n) { return (2u << n) - 1u; }  // 2^(n+1)-1
+
+// ---------------------------------------------------------------------------
+// Count tables for one input length n, split as x = x1 x2 with |x1| = n1 =
+// ceil(n/2) and |x2| = n2 = floor(n/2).
+//
+// Every distinct subsequence y of x factors uniquely as y = y1 y2 where y1 is
+// the longest prefix of y that is a subsequence of x1 (the greedy, NextPos-based
+// embedding of Section 4 uses x1 as far as it can) and y2 is a subsequence of x2;
+// conversely a pair (y1 <= x1, y2 <= x2) arises this way iff y2 is empty or y1
+// followed by the first bit of y2 is not a subsequence of x1.  The class of
+// (x1, y1) records which bits can still extend y1 inside x1.
+//
+// T1 entry (16 bytes), one per (x1, y1 distinct subsequence of x1):
+//   w.x = x1 | y1 << 10 | k1 << 20 | cls << 24
+//   bytes 4..15: byte u = emb(y1[0:k1-u], x1), u = 0..k1   (<= C(10,5) = 252)
+// classes, also the sort order of T1:
+//   0: only bit 1 extends y1 in x1 -> compatible y2 start with 0 (or are empty)
+//   1: no bit extends y1           -> every y2
+//   2: only bit 0 extends y1       -> y2 start with 1 (or are empty)
+//   3: both bits extend y1         -> only the empty y2
+// So y2 starting with 0 pair with T1[cg[0], cg[2]) and y2 starting with 1 with
+// T1[cg[1], cg[3]).  T1 is stored twice: sorted by (cls, x1, y1) for the scatter
+// sweep (distinct targets across lanes) and by (cls, y1, x1) for the gather sweep
+// (lanes sharing y1 read the same cache lines).
+//
+// T2 entry (16 bytes), one per (x2, y2 distinct subsequence of x2), grouped per
+// x2 as [empty][y2 starting with 0, by rank][y2 starting with 1, by rank]:
+//   w.x = y2 | k2 << 10 | jmax << 14
+//   bytes 4..15: E2s[j] = emb(y2, x2[j:n2]), j = 0..n2; jmax = last j with E2s > 0
+// ---------------------------------------------------------------------------
+struct Tables {
+  int n, n1, n2;
+  uint32_t m1;          // number of T1 entries = 2*3^n1 - 2^n1
+  uint32_t m2;          // number of T2 entries = 2*3^n2 - 2^n2
+  uint32_t cg[5];       // class boundaries in T1
+  const uint4* t1s;     // sorted (cls, x1, y1)
+  const uint4* t1g;     // sorted (cls, y1, x1)
+  const uint4* t2;      // grouped per x2
+  const uint32_t* off2; // [2^n2 + 1] start of x2's group in t2
+  const uint32_t* n0_2; // [2^n2] number of y2 starting with 0 for x2
+};
+
+// Per-instance constants, FP64: w[k] = d^(n-k)(1-d)^k, sw[k] = s_k w_k with
+// s_k = (n-k)/d - k/(1-d) (zero when d is 0 or 1).
+struct Consts {
+  double w[kNMax + 1];
+  double sw[kNMax + 1];
+  double pad[2];
+};
+
+// Per-instance scalar state (device, FP64, nats).
+struct State {
+  double M;           // max log p of the current iterate
+  double L, U, I;     // bounds and rate at the last evaluated iterate
+  double certL, certU, certI, certM;  // last FP64 evaluation
+  double bestL, bestU;                // best certified bounds
+  double tol;         // freeze when U - L < tol (nats); < 0 disables
+  double lse;         // scratch: log-sum-exp of the last normalisation
+  int iters;          // completed updates
+  int converged;      // 1: frozen (kernels skip the instance)
+  int bad;            // non-finite value seen
+  int pad;
+};
+
+// One group of nb instances with length n, arrays at fixed strides.
+template <typename T>
+struct Group {
+  int n, nb;
+  size_t xs, ys;      // strides: inputs (2^n) and outputs (2^(n+1)-1 rounded up)
+  T* lp;              // log p
+  T* p;               // p e^{-M}
+  T* r;               // r(y) e^{-M}
+  T* v;               // v(y) = w_k log(r(y) e^{-M})  (or s_k w_k log ... )
+  T* v2;              // stream engine: v in split layout, stride v2s
+  size_t v2s;
+  T* g;               // G(x)
+  T* gd;              // Gd(x) (gradient evaluations only)
+  T* D;               // D(x)
+  T* f0;              // factored engine ping-pong, stride fs
+  T* f1;
+  size_t fs;
+  const double* h;    // H(x) (FP64 always)
+  const double* hd;   // Hd(x)
+  double* part;       // per-block partials, stride ps
+  size_t ps;
+  State* st;          // [nb]
+  const Consts* cs;   // [nb]
+};
+
+enum StreamOp { kOpScatter = 0, kOpGather = 1, kOpInit = 2, kOpRow = 3, kOpVerify = 4 };
+
+// Extra arguments of the non-iteration stream ops.
+struct StreamExtra {
+  double* h;                  // init: H(x), stride xs
+  double* hd;                 // init: Hd(x)
+  uint32_t target_x;          // row
+  uint32_t* row_dense;        // row: dense counts by rank
+  uint32_t* bins;             // verify: [2^n][n+2] length sums and nonzero counts
+  unsigned long long* stats;  // verify: [6]
+};
+
+// ---- launch wrappers (defined in the .hip files) ---------------------------
+
+// ba_tables.hip
+size_t table_bytes(int n);
+hipError_t build_tables(int n, void* mem, hipStream_t s, Tables* out_host);
+
+// ba_stream.hip
+template <typename T>
+hipError_t launch_stream(StreamOp op, const Tables& tb, const Group<T>& g, int k0,
+                         const StreamExtra& ex, hipStream_t s);
+hipError_t launch_row_compact(const uint32_t* dense, int n, uint32_t* rank_out,
+                              uint32_t* emb_out, int cap, uint32_t* nnz_dev, hipStream_t s);
+
+// ba_factored.hip: the two products stage by stage.
+template <typename T>
+hipError_t launch_forward(const Group<T>& g, hipStream_t s, int* launches);  // p -> r
+template <typename T>
+hipError_t launch_backward(const Group<T>& g, hipStream_t s, int* launches); // v -> G
+
+// ba_reduce.hip
+template <typename T>
+hipError_t launch_logr(const Group<T>& g, int use_sw, int want_v2, int n1, int n2, hipStream_t s);
+template <typename T>
+hipError_t launch_dpart(const Group<T>& g, int nblk, int use_hd, const T* gd, hipStream_t s);
+template <typename T>
+hipError_t launch_update(const Group<T>& g, int nblk, double floor, int check_tol, hipStream_t s);
+int reduce_blocks(int n);
+
+// Certification: FP64 evaluation of the current iterate of a group (any T).
+// Step 1 (two partial passes) normalises, floors and renormalises log p into the
+// FP64 group's lp/p; step 2 finishes after the FP64 sweeps and D.
+template <typename T>
+hipError_t launch_cert_prepare(const Group<T>& src, const Group<double>& dst, int nblk,
+                               double floor, hipStream_t s);
+hipError_t launch_cert_finish(const Group<double>& g, int nblk, State* out, int write_best,
+                              hipStream_t s);
+hipError_t launch_grad_finish(const Group<double>& g, int nblk, double* out4,
+                              double* grad_theta, hipStream_t s);
+hipError_t launch_mirror_update(int n, double* theta, const double* D, double eta,
+                                hipStream_t s);
+template <typename T>
+hipError_t launch_get_logp(const Group<T>& g, double* dst, hipStream_t s);
+template <typename T>
+hipError_t launch_set_logp(const Group<T>& g, const double* src, int nblk, double floor,
+                           hipStream_t s);
+template <typename T>
+hipError_t launch_reset(const Group<T>& g, hipStream_t s);
+hipError_t launch_fill_zero(void* ptr, size_t bytes, hipStream_t s);
+hipError_t launch_copy_f64(double* dst, const double* src, size_t count, hipStream_t s);
+
+}  // namespace ba

@@ -1,0 +1,352 @@
+// Stream engine: the per-nonzero sweeps of the paper's method (Sections 3-4).
+//
+// Every nonzero W(y|x) is generated on the fly with its exact integer embedding
+// count and visited once per sweep.  Work decomposition (MI355X-specific, see
+// ba_internal.h for the tables): a block owns one right half x2 and a range of
+// 64-entry chunks of T1; each wavefront takes one chunk, so lane l owns the pair
+// (x1, y1) of entry chunk*64+l, i.e. the input x = x1 x2 and the prefix y1 of
+// its outputs.  The lane runs the embedding-count DP of y1 over the positions of
+// x2 once per chunk (in registers):
+//   c[u]  = number of embeddings of y1[0:k1-u] in x1 x2[0:j]   (u = 0..k1)
+//   l[0]  = emb(y1, x1),  l[j+1] = embeddings of y1 in x1 x2[0:j+1] whose last
+//           bit sits at position j of x2,
+// and then the wavefront walks the compatible suffixes y2 of x2 in lockstep
+// (scalar loads of T2); the embedding count of y = y1 y2 is
+//   emb(y, x) = sum_j l[j] * emb(y2, x2[j:n2])      (at most 11 integer MACs),
+// because y2's first bit cannot be matched in x1 after y1's embedding (class
+// rule), so y2 lies entirely in x2 to the right of y1's last bit.
+//
+// Ops: scatter  r(y) += p(x) emb(y,x)   (outputs with |y| <= k0 in LDS first)
+//      gather   G(x) += emb(y,x) v(y)    (v in split layout V2[rank(y2)][rank(y1)])
+//      init     H(x) += w_k emb log emb, Hd(x) += s_k w_k emb log emb
+//      row      dense row of one x (parity hook)
+//      verify   per-row length sums and nonzero counts
+#include "ba_internal.h"
+
+namespace ba {
+namespace {
+
+__device__ __forceinline__ uint32_t byte_of(const uint4& t, int j) {
+  const uint32_t w = (j < 4) ? t.y : ((j < 8) ? t.z : t.w);
+  return (w >> (8 * (j & 3))) & 0xffu;
+}
+
+template <typename T>
+__device__ __forceinline__ void atomic_add(T* p, T v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void lds_add(T* p, T v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+constexpr uint32_t binom_dev(int n, int k) {
+  uint32_t r = 1;
+  for (int i = 1; i <= k; ++i) r = r * uint32_t(n - k + i) / uint32_t(i);
+  return r;
+}
+
+template <typename T, int OP>
+__global__ __launch_bounds__(kBlock) void k_stream(Tables tb, Group<T> g, int k0, int parts,
+                                                   StreamExtra ex) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int n1 = tb.n1, n2 = tb.n2;
+  const uint32_t x2 = blockIdx.x / parts;
+  const uint32_t part = blockIdx.x % parts;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x / kWave;
+  const uint32_t S1 = out_count(n1);
+  const uint32_t X1 = 1u << n1;
+
+  // Instances of this launch's tile and which of them are still iterating.
+  int b0 = 0, nbt = 1;
+  uint32_t live = 1;
+  if (OP == kOpScatter || OP == kOpGather || OP == kOpInit) {
+    b0 = blockIdx.y * kTile;
+    nbt = min(kTile, g.nb - b0);
+    live = 0;
+    for (int b = 0; b < nbt; ++b)
+      if (OP == kOpInit || !g.st[b0 + b].converged) live |= 1u << b;
+    if (live == 0) return;  // uniform across the block
+  }
+  if (OP == kOpRow && x2 != (ex.target_x & ((1u << n2) - 1u))) return;
+
+  const uint32_t nshort = (2u << k0) - 1u;
+  T* rs = reinterpret_cast<T*>(smem);  // scatter: [nbt][nshort]
+  T* gs = reinterpret_cast<T*>(smem);  // gather:  [nbt][X1]
+  if (OP == kOpScatter) {
+    for (uint32_t i = threadIdx.x; i < nshort * nbt; i += kBlock) rs[i] = T(0);
+  } else if (OP == kOpGather) {
+    for (uint32_t i = threadIdx.x; i < X1 * nbt; i += kBlock) gs[i] = T(0);
+  }
+  __syncthreads();
+
+  const uint4* __restrict__ t1 = (OP == kOpGather) ? tb.t1g : tb.t1s;
+  const uint32_t o2 = tb.off2[x2];
+  const uint32_t c2 = tb.off2[x2 + 1] - o2;
+  const uint32_t z0 = tb.n0_2[x2];
+  const uint32_t nchunk = (tb.m1 + kWave - 1) / kWave;
+  const uint32_t cpp = (nchunk + parts - 1) / parts;
+  const uint32_t cb = part * cpp;
+  const uint32_t ce = min(nchunk, cb + cpp);
+
+  double wk[kNMax + 1], swk[kNMax + 1];
+  if (OP == kOpInit) {
+    // only used for single-instance init launches (nbt == 1 enforced by the host)
+    for (int k = 0; k <= kNMax; ++k) { wk[k] = g.cs[b0].w[k]; swk[k] = g.cs[b0].sw[k]; }
+  }
+
+  for (uint32_t ch = cb + wave; ch < ce; ch += kBlock / kWave) {
+    const uint32_t e = ch * kWave + lane;
+    const bool valid = e < tb.m1;
+    const uint4 ent = valid ? t1[e] : make_uint4(0u, 0u, 0u, 0u);
+    const uint32_t x1 = ent.x & 1023u;
+    const uint32_t y1 = (ent.x >> 10) & 1023u;
+    const int k1 = (ent.x >> 20) & 15;
+    const uint32_t x = (x1 << n2) | x2;
+    if (OP == kOpRow) {
+      if (__ballot(valid && x == ex.target_x) == 0) continue;
+    }
+
+    // Embedding-count DP of y1 across x2 (c[u] for prefix length k1-u).
+    uint32_t c[kHalfMax + 1];
+#pragma unroll
+    for (int u = 0; u <= kHalfMax; ++u) c[u] = byte_of(ent, u);
+    const uint32_t kmask = (1u << k1) - 1u;
+    const uint32_t m1 = y1 & kmask, m0 = ~y1 & kmask;
+    uint32_t l[kHalfMax + 1];
+    l[0] = c[0];
+#pragma unroll
+    for (int j = 0; j < kHalfMax; ++j) {
+      if (j < n2) {
+        const uint32_t mb = ((x2 >> (n2 - 1 - j)) & 1u) ? m1 : m0;
+        const uint32_t before = c[0];
+#pragma unroll
+        for (int u = 0; u < kHalfMax; ++u) c[u] += ((mb >> u) & 1u) * c[u + 1];
+        l[j + 1] = c[0] - before;
+      } else {
+        l[j + 1] = 0u;
+      }
+    }
+
+    // Per-lane state of the op.
+    T pl[kTile];
+    T acc[kTile];
+    double ah = 0.0, ahd = 0.0;
+    const uint32_t A1 = y1 | (1u << k1);
+    const uint32_t R1 = A1 - 1u;  // rank of y1
+    if (OP == kOpScatter) {
+#pragma unroll
+      for (int b = 0; b < kTile; ++b)
+        pl[b] = (b < nbt && valid) ? g.p[(size_t)(b0 + b) * g.xs + x] : T(0);
+    }
+    if (OP == kOpGather) {
+#pragma unroll
+      for (int b = 0; b < kTile; ++b) acc[b] = T(0);
+    }
+
+    // Three groups of y2: empty (all lanes), starting with 0, starting with 1.
+#pragma unroll 1
+    for (int grp = 0; grp < 3; ++grp) {
+      uint32_t qb, qe, lo, hi;
+      if (grp == 0) { qb = o2; qe = o2 + 1; lo = 0; hi = tb.m1; }
+      else if (grp == 1) { qb = o2 + 1; qe = o2 + 1 + z0; lo = tb.cg[0]; hi = tb.cg[2]; }
+      else { qb = o2 + 1 + z0; qe = o2 + c2; lo = tb.cg[1]; hi = tb.cg[3]; }
+      const uint32_t cs0 = ch * kWave, ce0 = cs0 + kWave;
+      if (qb >= qe || ce0 <= lo || cs0 >= hi) continue;  // uniform
+      const bool ok = valid && e >= lo && e < hi;
+#pragma unroll 1
+      for (uint32_t q = qb; q < qe; ++q) {
+        const uint4 t = tb.t2[q];  // uniform: scalar load
+        const uint32_t y2 = t.x & 1023u;
+        const int k2 = (t.x >> 10) & 15;
+        const int jmax = (t.x >> 14) & 15;
+        uint32_t emb = 0;
+#pragma unroll
+        for (int j = 0; j <= kHalfMax; ++j)
+          if (j <= jmax) emb = __umul24(l[j], byte_of(t, j)) + emb;
+        if (!ok) continue;
+        const int k = k1 + k2;
+        if (OP == kOpScatter) {
+          const uint32_t rank = (A1 << k2) + y2 - 1u;
+          const T fe = T(emb);
+          if (k <= k0) {
+#pragma unroll
+            for (int b = 0; b < kTile; ++b)
+              if (b < nbt && ((live >> b) & 1u)) lds_add(&rs[b * nshort + rank], pl[b] * fe);
+          } else {
+#pragma unroll
+            for (int b = 0; b < kTile; ++b)
+              if (b < nbt && ((live >> b) & 1u)) atomic_add(&g.r[(size_t)(b0 + b) * g.ys + rank], pl[b] * fe);
+          }
+        } else if (OP == kOpGather) {
+          const size_t idx = size_t((1u << k2) - 1u + y2) * S1 + R1;
+          const T fe = T(emb);
+#pragma unroll
+          for (int b = 0; b < kTile; ++b)
+            if (b < nbt && ((live >> b) & 1u)) acc[b] += fe * g.v2[(size_t)(b0 + b) * g.v2s + idx];
+        } else if (OP == kOpInit) {
+          const double le = log(double(emb));
+          const double t0 = double(emb) * le;
+          ah += wk[k] * t0;
+          ahd += swk[k] * t0;
+        } else if (OP == kOpRow) {
+          if (x == ex.target_x) ex.row_dense[(A1 << k2) + y2 - 1u] = emb;
+        } else if (OP == kOpVerify) {
+          atomicAdd(&ex.bins[(size_t)x * (tb.n + 2) + k], emb);
+          atomicAdd(&ex.bins[(size_t)x * (tb.n + 2) + tb.n + 1], 1u);
+          atomicMax(&ex.stats[5], (unsigned long long)emb);
+        }
+      }
+    }
+    if (OP == kOpGather && valid) {
+#pragma unroll
+      for (int b = 0; b < kTile; ++b)
+        if (b < nbt && ((live >> b) & 1u)) lds_add(&gs[b * X1 + x1], acc[b]);
+    }
+    if (OP == kOpInit && valid) {
+      atomic_add(&ex.h[(size_t)b0 * g.xs + x], ah);
+      atomic_add(&ex.hd[(size_t)b0 * g.xs + x], ahd);
+    }
+  }
+
+  if (OP == kOpScatter) {
+    __syncthreads();
+    for (int b = 0; b < nbt; ++b) {
+      if (!((live >> b) & 1u)) continue;
+      for (uint32_t i = threadIdx.x; i < nshort; i += kBlock) {
+        const T v = rs[b * nshort + i];
+        if (v != T(0)) atomic_add(&g.r[(size_t)(b0 + b) * g.ys + i], v);
+      }
+    }
+  } else if (OP == kOpGather) {
+    __syncthreads();
+    for (int b = 0; b < nbt; ++b) {
+      if (!((live >> b) & 1u)) continue;
+      for (uint32_t i = threadIdx.x; i < X1; i += kBlock) {
+        const T v = gs[b * X1 + i];
+        if (v != T(0)) atomic_add(&g.g[(size_t)(b0 + b) * g.xs + ((i << n2) | x2)], v);
+      }
+    }
+  }
+}
+
+// Verify finish: one thread per row checks sum_{|y|=k} emb = C(n,k) and records
+// nnz statistics.  stats = {total nnz, rows failing, 0, min nnz, max nnz, max emb}.
+__global__ void k_verify_finish(int n, const unsigned int* bins, unsigned long long* stats) {
+  const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= (1u << n)) return;
+  const unsigned int* b = bins + (size_t)x * (n + 2);
+  bool ok = true;
+  for (int k = 0; k <= n; ++k) ok = ok && (b[k] == binom_dev(n, k));
+  const unsigned long long nnz = b[n + 1];
+  atomicAdd(&stats[0], nnz);
+  if (!ok) atomicAdd(&stats[1], 1ull);
+  atomicMin(&stats[3], nnz);
+  atomicMax(&stats[4], nnz);
+}
+
+// Row compaction: dense counts by rank -> (rank, emb) in increasing rank.
+// One block; ballot-free two-level scan per 1024-rank window.
+__global__ __launch_bounds__(1024) void k_row_compact(const uint32_t* dense, uint32_t total,
+                                                      uint32_t* rank_out, uint32_t* emb_out,
+                                                      int cap, uint32_t* nnz_dev) {
+  __shared__ uint32_t sc[1024];
+  __shared__ uint32_t base;
+  if (threadIdx.x == 0) base = 0;
+  __syncthreads();
+  for (uint32_t w0 = 0; w0 < total; w0 += 1024) {
+    const uint32_t r = w0 + threadIdx.x;
+    const uint32_t v = (r < total) ? dense[r] : 0u;
+    const uint32_t f = v != 0u;
+    sc[threadIdx.x] = f;
+    __syncthreads();
+    for (uint32_t off = 1; off < 1024; off <<= 1) {
+      const uint32_t t = (threadIdx.x >= off) ? sc[threadIdx.x - off] : 0u;
+      __syncthreads();
+      sc[threadIdx.x] += t;
+      __syncthreads();
+    }
+    const uint32_t pos = base + sc[threadIdx.x] - f;
+    if (f && pos < (uint32_t)cap) {
+      rank_out[pos] = r;
+      emb_out[pos] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 1023) base += sc[1023];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *nnz_dev = base;
+}
+
+template <typename T, int OP>
+hipError_t launch_op(const Tables& tb, const Group<T>& g, int k0, const StreamExtra& ex, hipStream_t s) {
+  const uint32_t X2 = 1u << tb.n2;
+  const uint32_t nchunk = (tb.m1 + kWave - 1) / kWave;
+  // Spread each x2 over several blocks so that the grid holds >= ~2048 blocks.
+  int parts = 1;
+  if (OP != kOpRow) {
+    while ((uint64_t)X2 * parts < 2048 && (uint32_t)parts * 8 < nchunk) parts *= 2;
+  }
+  const int tiles = (OP == kOpScatter || OP == kOpGather) ? (g.nb + kTile - 1) / kTile
+                    : (OP == kOpInit ? g.nb : 1);
+  const int nbt = (OP == kOpScatter || OP == kOpGather) ? (g.nb < kTile ? g.nb : kTile) : 1;
+  size_t lds = 0;
+  if (OP == kOpScatter) lds = size_t((2u << k0) - 1u) * nbt * sizeof(T);
+  if (OP == kOpGather) lds = size_t(1u << tb.n1) * nbt * sizeof(T);
+  if (OP == kOpInit) {
+    // one instance per launch grid row: blockIdx.y selects the instance tile of size 1
+    Group<T> g1 = g;
+    for (int b = 0; b < g.nb; ++b) {
+      Group<T> gb = g1;
+      gb.nb = 1;
+      gb.st = g.st + b;
+      gb.cs = g.cs + b;
+      StreamExtra eb = ex;
+      eb.h = ex.h + (size_t)b * g.xs;
+      eb.hd = ex.hd + (size_t)b * g.xs;
+      hipLaunchKernelGGL((k_stream<T, OP>), dim3(X2 * parts, 1), dim3(kBlock), 0, s, tb, gb, k0,
+                         parts, eb);
+    }
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL((k_stream<T, OP>), dim3(X2 * parts, tiles), dim3(kBlock), lds, s, tb, g, k0,
+                     parts, ex);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_stream(StreamOp op, const Tables& tb, const Group<T>& g, int k0,
+                         const StreamExtra& ex, hipStream_t s) {
+  switch (op) {
+    case kOpScatter: return launch_op<T, kOpScatter>(tb, g, k0, ex, s);
+    case kOpGather: return launch_op<T, kOpGather>(tb, g, k0, ex, s);
+    case kOpInit: return launch_op<T, kOpInit>(tb, g, k0, ex, s);
+    case kOpRow: return launch_op<T, kOpRow>(tb, g, k0, ex, s);
+    case kOpVerify: {
+      hipError_t e = launch_op<T, kOpVerify>(tb, g, k0, ex, s);
+      if (e != hipSuccess) return e;
+      const uint32_t X = 1u << tb.n;
+      hipLaunchKernelGGL(k_verify_finish, dim3((X + 255) / 256), dim3(256), 0, s, tb.n, ex.bins,
+                         ex.stats);
+      return hipGetLastError();
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+template hipError_t launch_stream<float>(StreamOp, const Tables&, const Group<float>&, int,
+                                         const StreamExtra&, hipStream_t);
+template hipError_t launch_stream<double>(StreamOp, const Tables&, const Group<double>&, int,
+                                          const StreamExtra&, hipStream_t);
+
+hipError_t launch_row_compact(const uint32_t* dense, int n, uint32_t* rank_out, uint32_t* emb_out,
+                              int cap, uint32_t* nnz_dev, hipStream_t s) {
+  hipLaunchKernelGGL(k_row_compact, dim3(1), dim3(1024), 0, s, dense, out_count(n), rank_out,
+                     emb_out, cap, nnz_dev);
+  return hipGetLastError();
+}
+
+}  // namespace ba

@@ -1,0 +1,329 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs.
+
+Bars (written in each test): embedding counts bit-exact; FP64 evaluations and
+bounds within 1e-9 bits (in practice ~1e-12); FP32-iterated runs certified in
+FP64 within 1e-6 bits of the oracle's FP64 capacity bracket.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import bdc_inputs as inp
+from oracle import bdc
+
+pytestmark = pytest.mark.gpu
+LN2 = math.log(2.0)
+ENGINES = ("factored", "stream")
+
+
+@pytest.fixture(scope="module")
+def ba():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2604_05867_amd as m
+    m.lib()  # fails loudly if the library is missing
+    return m
+
+
+def engine_id(ba, name):
+    return ba.ENGINE_FACTORED if name == "factored" else ba.ENGINE_STREAM
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+# ---------------------------------------------------------------------------
+# counts
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 8, 11, 12, 16, 20])
+def test_row_counts_bit_exact(ba, oracle_native, n):
+    say("row counts n=%d" % n)
+    ctx = ba.Context(n, 0.5)
+    xs = inp.sample_rows(n, 64 if n >= 16 else 32, seed=n)
+    want = oracle_native.rows(n, xs)
+    for x, (rk_o, em_o) in zip(xs, want):
+        rk, em = ctx.row_counts(int(x))
+        assert np.array_equal(rk, rk_o), (n, int(x))
+        assert np.array_equal(em, em_o), (n, int(x))
+    ctx.close()
+
+
+def test_row_counts_cap_error(ba):
+    ctx = ba.Context(10, 0.5)
+    with pytest.raises(ba.BAError) as e:
+        ctx.row_counts(0b1010101010, cap=5)
+    assert e.value.code == ba.BA_EINVAL
+    with pytest.raises(ba.BAError):
+        ctx.row_counts(1 << 10)
+    ctx.close()
+
+
+@pytest.mark.parametrize("n", [1, 4, 9, 12, 16, 20])
+def test_verify_all_rows(ba, oracle_native, n):
+    """Every row: sum_{|y|=k} emb = C(n,k); total nnz = 2*3^n - 2^n; min row nnz
+    = n+1 (constant string); max emb = C(n, floor(n/2))."""
+    say("verify n=%d" % n)
+    ctx = ba.Context(n, 0.5)
+    st = ctx.verify_counts()
+    assert st["total_nnz"] == 2 * 3 ** n - 2 ** n
+    assert st["rows_failing"] == 0
+    assert st["min_row_nnz"] == n + 1
+    assert st["max_emb"] == math.comb(n, n // 2)
+    if n <= 12:
+        csr = oracle_native.CSR(n)
+        assert st["max_row_nnz"] == int(np.diff(csr.indptr).max())
+    ctx.close()
+
+
+# ---------------------------------------------------------------------------
+# one FP64 evaluation at a shared law (sweeps, log r, D, reductions)
+# ---------------------------------------------------------------------------
+
+def oracle_eval(oracle_native, n, d, lp):
+    if n <= 10:
+        W = bdc.channel_dense(n, d)
+        ev = bdc.evaluate(W, bdc.floor_logp(bdc.normalise_logp(lp), 700.0))
+        return ev.D, ev.L, ev.U, ev.I, ev.q_scaled, float(bdc.floor_logp(bdc.normalise_logp(lp), 700.0).max())
+    csr = oracle_native.CSR(n)
+    D, L, U, I, q = csr.evaluate(d, lp, floor_nats=700.0, want_q=True)
+    lpf = bdc.floor_logp(bdc.normalise_logp(lp), 700.0)
+    return D, L, U, I, q, float(bdc.normalise_logp(lpf).max())
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+@pytest.mark.parametrize("n,d,kind", [(1, 0.3, "random"), (3, 0.5, "random"), (6, 0.0, "random"),
+                                      (6, 1.0, "product"), (8, 0.5, "random"), (10, 0.77, "product"),
+                                      (12, 0.64, "random"), (14, 0.9, "random")])
+def test_eval_matches_oracle(ba, oracle_native, engine, n, d, kind):
+    say("eval n=%d d=%.2f %s %s" % (n, d, kind, engine))
+    lp = inp.random_logp(n, seed=n, spread=2.0) if kind == "random" else \
+        inp.product_logp(n, inp.product_bit_probs(n, seed=n))
+    D_o, L_o, U_o, I_o, q_o, M_o = oracle_eval(oracle_native, n, d, lp)
+    ctx = ba.Context(n, d, engine=engine_id(ba, engine))
+    got = ctx.eval(torch.from_numpy(lp))
+    assert abs(got["L"] - L_o / LN2) < 1e-10
+    assert abs(got["U"] - U_o / LN2) < 1e-10
+    assert abs(got["I"] - I_o / LN2) < 1e-10
+    assert np.allclose(got["D"].cpu().numpy(), D_o, atol=1e-10, rtol=0)
+    if 0.0 < d < 1.0:
+        k = bdc.output_lengths(n)
+        w = bdc.length_weights(n, d)[k]
+        r_o = q_o * np.exp(M_o) / w
+        r_g = got["r"].cpu().numpy() * math.exp(got["M"])
+        assert np.allclose(r_g, r_o, rtol=1e-11, atol=0)
+    ctx.close()
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+def test_eval_uniform_closed_form_n20(ba, engine):
+    """At the uniform law r(y) = C(n,k) 2^-k for every y (any n)."""
+    n = 20
+    say("uniform closed form n=20 %s" % engine)
+    ctx = ba.Context(n, 0.8, engine=engine_id(ba, engine))
+    got = ctx.eval(torch.full((1 << n,), -n * LN2, dtype=torch.float64))
+    r = got["r"].cpu().numpy() * math.exp(got["M"])
+    want = bdc.r_uniform(n)
+    assert np.allclose(r, want, rtol=1e-12, atol=0)
+    assert got["L"] <= got["U"] + 1e-12
+    ctx.close()
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+def test_eval_product_law_sampled_n20(ba, oracle_native, engine):
+    """Full size n = 20 at a product input law: r at sampled outputs and D at
+    sampled inputs against the oracle's closed forms (one by one)."""
+    n, d = 20, 0.8
+    say("product law n=20 %s" % engine)
+    pi1 = inp.product_bit_probs(n, seed=17)
+    lp = inp.product_logp(n, pi1)
+    ctx = ba.Context(n, d, engine=engine_id(ba, engine))
+    got = ctx.eval(torch.from_numpy(lp))
+    M = got["M"]
+    ys = inp.sample_outputs(n, 4000, seed=5)
+    r_g = got["r"].cpu().numpy()[ys] * math.exp(M)
+    r_o = oracle_native.product_r(n, pi1, ys)
+    assert np.allclose(r_g, r_o, rtol=1e-11, atol=0)
+    xs = inp.sample_rows(n, 48, seed=6)
+    D_o = oracle_native.product_D(n, d, pi1, xs)
+    D_g = got["D"].cpu().numpy()[xs]
+    assert np.allclose(D_g, D_o, atol=1e-9, rtol=0)
+    # property: the upper bound is the max of D, the lower bound below it
+    assert got["U"] >= float(D_o.max()) / LN2 - 1e-9
+    assert got["L"] <= got["U"]
+    ctx.close()
+
+
+# ---------------------------------------------------------------------------
+# iterations
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("engine", ENGINES)
+@pytest.mark.parametrize("n,d,iters", [(2, 0.5, 40), (8, 0.5, 25), (11, 0.7, 10)])
+def test_fp64_iterates_match_oracle(ba, engine, n, d, iters):
+    say("iterates n=%d %s" % (n, engine))
+    W = bdc.channel_dense(n, d)
+    ctx = ba.Context(n, d, engine=engine_id(ba, engine))
+    ctx.step(iters)
+    lp_g = ctx.get_logp().cpu().numpy()
+    lp_o = bdc.ba_iterate(W, bdc.uniform_logp(n), iters)
+    assert np.max(np.abs(lp_g - lp_o)) < 1e-10
+    lo, hi = ctx.bounds()
+    L_o, U_o = bdc.certify(W, lp_o)
+    assert abs(lo[0] - L_o) < 1e-10 and abs(hi[0] - U_o) < 1e-10
+    ctx.close()
+
+
+def test_config1_n8_to_1e9(ba):
+    """n = 8, d = 0.5, FP64 until the gap is below 1e-9 bits, against the oracle's
+    BA with the same stopping rule (Section 2.3)."""
+    n, d = 8, 0.5
+    W = bdc.channel_dense(n, d)
+    res = bdc.ba(W, n, tol_bits=1e-9, max_iters=20000)
+    ctx = ba.Context(n, d)
+    done = ctx.run(1e-9, 20000)
+    lo, hi, its = ctx.best_bounds()
+    say("C1: gpu iters=%d oracle iters=%d" % (its[0], res.iters))
+    assert its[0] == res.iters
+    assert abs(lo[0] - res.lower_bits) < 1e-9 and abs(hi[0] - res.upper_bits) < 1e-9
+    assert hi[0] - lo[0] < 1e-9
+    assert done >= res.iters
+    ctx.close()
+
+
+def oracle_ba_csr(csr, d, tol_bits, max_iters):
+    """The BA loop of Section 2.3 on the C oracle's sparse channel, with log p
+    floored at 700 nats below its max (the optimum has zero-probability inputs,
+    so unfloored iterates underflow FP64 after a few thousand iterations)."""
+    lp = bdc.uniform_logp(csr.n)
+    for t in range(max_iters + 1):
+        D, L, U, I, _ = csr.evaluate(d, lp, floor_nats=700.0)
+        if (U - L) / LN2 < tol_bits or t == max_iters:
+            return L / LN2, U / LN2, t
+        lp = bdc.floor_logp(bdc.normalise_logp(lp) + D - L, 700.0)
+
+
+def test_fp32_log_domain_certified(ba, oracle_native):
+    """FP32 iterates, FP64 certification: certified gap < 1e-6 bits and the
+    certified bracket intersects the oracle's FP64 bracket."""
+    n, d = 10, 0.8
+    L_o, U_o, t_o = oracle_ba_csr(oracle_native.CSR(n), d, 1e-8, 100000)
+    ctx = ba.Context(n, d, prec=ba.PREC_FP32_LOG, cert_every=50)
+    done = ctx.run(1e-6, 60000)
+    lo, hi, its = ctx.best_bounds()
+    say("fp32: iters=%d L=%.12f U=%.12f ref=[%.12f, %.12f] (%d)" % (done, lo[0], hi[0], L_o, U_o, t_o))
+    assert hi[0] - lo[0] < 1e-6
+    assert lo[0] <= U_o + 1e-12 and L_o <= hi[0] + 1e-12
+    assert abs(lo[0] - L_o) < 1e-6
+    ctx.close()
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+def test_batch_equals_singles(ba, engine):
+    ns = [6, 8, 6, 7, 8]
+    ds = [0.3, 0.5, 0.9, 0.64, 0.96]
+    ctx = ba.Context(ns, ds, prec=ba.PREC_FP64, engine=engine_id(ba, engine))
+    ctx.step(15)
+    lo, hi = ctx.bounds()
+    lp_all = ctx.get_logp().cpu().numpy()
+    off = 0
+    for i, (n, d) in enumerate(zip(ns, ds)):
+        s = ba.Context(n, d, engine=engine_id(ba, engine))
+        s.step(15)
+        l1, h1 = s.bounds()
+        assert abs(l1[0] - lo[i]) < 1e-12 and abs(h1[0] - hi[i]) < 1e-12
+        assert np.allclose(s.get_logp().cpu().numpy(), lp_all[off:off + (1 << n)], atol=1e-12)
+        off += 1 << n
+        s.close()
+    ctx.close()
+
+
+def test_engines_agree_fp32_batch(ba):
+    ns = [10, 12]
+    ds = [0.64, 0.96]
+    out = []
+    for eng in (ba.ENGINE_FACTORED, ba.ENGINE_STREAM):
+        c = ba.Context(ns, ds, prec=ba.PREC_FP32_LOG, engine=eng)
+        c.step(20)
+        out.append(c.get_logp().cpu().numpy())
+        c.close()
+    assert np.max(np.abs(out[0] - out[1])) < 1e-3
+
+
+def test_symmetry_of_iterates_n16(ba):
+    """Theorem 4: from uniform, p(cpl x) = p(x) = p(rev x) at every iteration."""
+    n = 16
+    ctx = ba.Context(n, 0.7)
+    ctx.step(30)
+    lp = ctx.get_logp().cpu().numpy()
+    x = np.arange(1 << n)
+    cp = x ^ ((1 << n) - 1)
+    rv = np.zeros_like(x)
+    for i in range(n):
+        rv |= ((x >> i) & 1) << (n - 1 - i)
+    assert np.max(np.abs(lp[cp] - lp)) < 1e-9
+    assert np.max(np.abs(lp[rv] - lp)) < 1e-9
+    ctx.close()
+
+
+def test_set_get_logp_and_numeric_errors(ba):
+    n = 6
+    ctx = ba.Context(n, 0.5)
+    lp = torch.from_numpy(inp.random_logp(n, seed=3))
+    ctx.set_logp(lp)
+    back = ctx.get_logp().cpu().numpy()
+    assert np.allclose(back, bdc.normalise_logp(lp.numpy()), atol=1e-13)
+    bad = lp.clone()
+    bad[5] = float("nan")
+    with pytest.raises(ba.BAError) as e:
+        ctx.set_logp(bad)
+    assert e.value.code == ba.BA_ENUMERIC
+    ctx.close()
+
+
+# ---------------------------------------------------------------------------
+# gradients and mirror ascent
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("engine", ENGINES)
+def test_gradients_match_oracle(ba, engine):
+    n, d = 8, 0.8
+    theta = inp.theta_normal(n, seed=0, sigma=0.1)
+    I_o, g_o, gd_o = bdc.info_and_grads(n, d, theta)
+    ctx = ba.Context(n, d, engine=engine_id(ba, engine))
+    I, g, gd = ctx.grad(torch.from_numpy(theta))
+    assert abs(I - I_o) < 1e-11
+    assert np.allclose(g.cpu().numpy(), g_o, atol=1e-12)
+    assert abs(gd - gd_o) < 1e-10
+    ctx.close()
+
+
+def test_autograd_function(ba):
+    n, d = 6, 0.6
+    ctx = ba.Context(n, d)
+    theta = torch.from_numpy(inp.theta_normal(n, seed=1, sigma=0.2)).requires_grad_(True)
+    dd = torch.tensor(d, dtype=torch.float64, requires_grad=True)
+    I = ba.BAInfo.apply(theta, dd, ctx)
+    I.backward()
+    I_o, g_o, gd_o = bdc.info_and_grads(n, d, theta.detach().numpy())
+    assert abs(I.item() - I_o) < 1e-11
+    assert np.allclose(theta.grad.numpy(), g_o, atol=1e-12)
+    assert abs(dd.grad.item() - gd_o) < 1e-10
+    ctx.close()
+
+
+def test_mirror_ascent_unit_step_is_ba(ba):
+    n, d = 7, 0.65
+    theta = inp.theta_normal(n, seed=2, sigma=0.3)
+    ctx = ba.Context(n, d)
+    th = ctx.mirror_ascent(torch.from_numpy(theta), 1.0, 12).cpu().numpy()
+    th_o = bdc.mirror_ascent(n, d, theta, 1.0, 12)
+    assert np.allclose(bdc.normalise_logp(th), bdc.normalise_logp(th_o), atol=1e-11)
+    th2 = ctx.mirror_ascent(torch.from_numpy(theta), 2.0, 5).cpu().numpy()
+    th2_o = bdc.mirror_ascent(n, d, theta, 2.0, 5)
+    assert np.allclose(bdc.normalise_logp(th2), bdc.normalise_logp(th2_o), atol=1e-11)
+    ctx.close()

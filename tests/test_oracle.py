@@ -424,3 +424,19 @@ def test_csr_matches_dense(oracle_native, n, d):
     a = csr.iterate(d, lp, 20)
     b = bdc.ba_iterate(W, bdc.normalise_logp(lp), 20)
     assert np.allclose(bdc.normalise_logp(a), b, atol=1e-11)
+
+
+def test_sample_sweeps_match_dense(oracle_native):
+    """The bounded-sample sweeps (used for the CPU baseline) against the dense
+    evaluation: q restricted to the sampled rows and D at those rows."""
+    n, d = 7, 0.55
+    W = bdc.channel_dense(n, d)
+    lp = bdc.normalise_logp(inp.random_logp(n, seed=8))
+    p = np.exp(lp)
+    q_full = p @ W
+    xs = inp.sample_rows(n, 20, seed=3)
+    q_part, D, tot = oracle_native.sample_sweeps(n, d, p, xs, q_full)
+    assert np.allclose(q_part, p[xs] @ W[xs], rtol=1e-13, atol=1e-300)
+    ev = bdc.evaluate(W, lp)
+    assert np.allclose(D, ev.D[xs], atol=1e-12)
+    assert tot == int((W[xs] > 0).sum())
