@@ -95,6 +95,20 @@ int ba_init_batch(int count, const int *n, const double *d, int prec, int cert_e
  * call that runs sweeps. */
 int ba_set_engine(ba_ctx *c, int engine);
 
+/* Run ba_run's iteration chunks as one captured HIP graph (replayed until the
+ * stopping rule holds) instead of individual launches.  Needs a non-null bound
+ * stream (capture is not allowed on the legacy null stream): BA_ESTATE otherwise,
+ * reported by ba_run.  The graph is rebuilt after ba_bind, ba_set_engine or a
+ * change of chunk length. */
+int ba_set_graphs(ba_ctx *c, int enable);
+
+/* Tuning knobs (they never change results beyond rounding order).
+ *  BA_TUNE_SCATTER_LDS_KB: LDS budget (1..160 KB, default 64) of the stream
+ *  engine's scatter; outputs short enough for the budget are accumulated in LDS
+ *  before going to device memory.  Capped by the device's per-block limit. */
+enum { BA_TUNE_SCATTER_LDS_KB = 0 };
+int ba_set_tuning(ba_ctx *c, int key, int value);
+
 /* Free the host state.  The workspace stays owned by the caller.  NULL is a no-op. */
 void ba_free(ba_ctx *c);
 

@@ -24,6 +24,7 @@ BA_OK, BA_EINVAL, BA_ENOMEM, BA_EDEVICE, BA_ESTATE, BA_ENUMERIC = 0, -1, -2, -3,
 PREC_FP64, PREC_FP32_LOG = 0, 1
 ENGINE_STREAM, ENGINE_FACTORED = 0, 1
 KCLASS = ("sweep1", "logr", "sweep2", "reduce", "update")
+TUNE_SCATTER_LDS_KB = 0
 
 _lib = None
 
@@ -70,6 +71,8 @@ def lib():
     L.ba_last_error.argtypes = [vp]
     L.ba_last_error.restype = ctypes.c_char_p
     L.ba_time_kernels.argtypes = [vp, i32, pf64, pi32]
+    L.ba_set_graphs.argtypes = [vp, i32]
+    L.ba_set_tuning.argtypes = [vp, i32, i32]
     _lib = L
     return L
 
@@ -130,6 +133,13 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def set_graphs(self, enable: bool = True):
+        """Replay ba_run's chunks as a captured HIP graph (needs a non-null stream)."""
+        self._check(lib().ba_set_graphs(self._h, 1 if enable else 0), "ba_set_graphs")
+
+    def set_tuning(self, key: int, value: int):
+        self._check(lib().ba_set_tuning(self._h, key, value), "ba_set_tuning")
 
     def set_engine(self, engine: int):
         self._check(lib().ba_set_engine(self._h, engine), "ba_set_engine")

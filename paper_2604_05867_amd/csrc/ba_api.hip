@@ -63,6 +63,13 @@ struct ba_ctx {
   hipStream_t stream = nullptr;
   bool bound = false;
   std::string err;
+  // tuning
+  int scatter_lds_kb = 64;
+  // graph replay of ba_run chunks
+  bool use_graph = false;
+  hipGraphExec_t gexec = nullptr;
+  int gchunk = -1;
+  int gengine = -1;
   // timing hook
   bool timing = false;
   std::vector<hipEvent_t> ev;
@@ -222,9 +229,10 @@ Group<T> slot_view(Group<T> G, int j) {
   return G;
 }
 
-int k0_for(int n, int nbt, size_t esz) {
+// Longest output length accumulated in LDS by the scatter, for an LDS budget.
+int k0_for(int n, int nbt, size_t esz, size_t budget) {
   int k0 = 0;
-  while (k0 + 1 <= n && size_t((2u << (k0 + 1)) - 1u) * nbt * esz <= 65536) ++k0;
+  while (k0 + 1 <= n && size_t((2u << (k0 + 1)) - 1u) * nbt * esz <= budget) ++k0;
   return k0;
 }
 
@@ -252,11 +260,14 @@ int sweeps(ba_ctx* c, const GroupHost& gh, const Group<T>& G, int use_sw_g, T* g
   const StreamExtra ex{};
   if (c->engine == BA_ENGINE_STREAM) {
     const int nbt = G.nb < kTile ? G.nb : kTile;
-    const int k0 = k0_for(n, nbt, sizeof(T));
+    const size_t budget = std::min<size_t>(size_t(c->scatter_lds_kb) * 1024, size_t(stream_lds_limit()));
+    const int k0 = k0_for(n, nbt, sizeof(T), budget);
     {
       Timer t(c, BA_K_SWEEP1, 1);
       HIPCHK(c, launch_fill_zero(G.r, size_t(G.nb) * G.ys * sizeof(T), s));
+      HIPCHK(c, launch_fill_zero(G.v2, size_t(G.nb) * G.v2s * sizeof(T), s));
       HIPCHK(c, launch_stream<T>(kOpScatter, gh.tb, G, k0, ex, s));
+      HIPCHK(c, launch_combine_r<T>(G, n1, n2, k0, s));
     }
     {
       Timer t(c, BA_K_LOGR, 1);
@@ -352,6 +363,13 @@ int write_states(ba_ctx* c, const std::vector<State>& in) {
   return BA_OK;
 }
 
+void drop_graph(ba_ctx* c) {
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  c->gexec = nullptr;
+  c->gchunk = -1;
+  c->gengine = -1;
+}
+
 int check_ctx(ba_ctx* c) {
   if (!c) return BA_EINVAL;
   if (!c->bound) return fail(c, BA_ESTATE, "context is not bound to a workspace (call ba_bind)");
@@ -388,12 +406,32 @@ int ba_init_batch(int count, const int* n, const double* d, int prec, int cert_e
 
 int ba_set_engine(ba_ctx* c, int engine) {
   if (!c || (engine != BA_ENGINE_STREAM && engine != BA_ENGINE_FACTORED)) return BA_EINVAL;
+  if (engine != c->engine) drop_graph(c);
   c->engine = engine;
+  return BA_OK;
+}
+
+int ba_set_tuning(ba_ctx* c, int key, int value) {
+  if (!c) return BA_EINVAL;
+  if (key == BA_TUNE_SCATTER_LDS_KB) {
+    if (value < 1 || value > 160) return fail(c, BA_EINVAL, "scatter LDS budget must be 1..160 KB");
+    c->scatter_lds_kb = value;
+    drop_graph(c);
+    return BA_OK;
+  }
+  return fail(c, BA_EINVAL, "unknown tuning key");
+}
+
+int ba_set_graphs(ba_ctx* c, int enable) {
+  if (!c) return BA_EINVAL;
+  c->use_graph = enable != 0;
+  if (!c->use_graph) drop_graph(c);
   return BA_OK;
 }
 
 void ba_free(ba_ctx* c) {
   if (!c) return;
+  drop_graph(c);
   for (auto e : c->ev) (void)hipEventDestroy(e);
   delete c;
 }
@@ -407,6 +445,7 @@ int ba_workspace_bytes(const ba_ctx* c, size_t* bytes) {
 int ba_bind(ba_ctx* c, void* ws, size_t bytes, void* stream) {
   if (!c || !ws || (reinterpret_cast<uintptr_t>(ws) & 255u)) return fail(c, BA_EINVAL, "workspace pointer NULL or not 256-byte aligned");
   if (bytes < c->need) return fail(c, BA_ENOMEM, "workspace smaller than ba_workspace_bytes");
+  drop_graph(c);
   c->ws = static_cast<char*>(ws);
   c->ws_bytes = bytes;
   c->stream = static_cast<hipStream_t>(stream);
@@ -470,11 +509,32 @@ int ba_run(ba_ctx* c, double gap_bits, int max_iters, int* iters_done) {
   const int chunk = (c->prec == BA_PREC_FP64) ? 32 : c->cert_every;
   int done = 0;
   bool all = false;
+  if (c->use_graph && !c->stream)
+    return fail(c, BA_ESTATE, "graph capture needs a non-null stream (bind one)");
   while (done < max_iters) {
     const int k = std::min(chunk, max_iters - done);
-    if ((rc = ba_step(c, k))) return rc;
+    if (c->use_graph && k == chunk) {
+      if (!c->gexec || c->gchunk != chunk || c->gengine != c->engine) {
+        drop_graph(c);
+        hipGraph_t graph = nullptr;
+        HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        int rc2 = ba_step(c, k);
+        if (!rc2 && c->prec == BA_PREC_FP32_LOG) rc2 = certify_all(c, 1);
+        hipError_t ec = hipStreamEndCapture(c->stream, &graph);
+        if (rc2) { if (graph) (void)hipGraphDestroy(graph); return rc2; }
+        HIPCHK(c, ec);
+        hipError_t ei = hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        HIPCHK(c, ei);
+        c->gchunk = chunk;
+        c->gengine = c->engine;
+      }
+      HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
+    } else {
+      if ((rc = ba_step(c, k))) return rc;
+      if (c->prec == BA_PREC_FP32_LOG && (rc = certify_all(c, 1))) return rc;
+    }
     done += k;
-    if (c->prec == BA_PREC_FP32_LOG && (rc = certify_all(c, 1))) return rc;
     if ((rc = read_states(c, st))) return rc;
     all = true;
     for (int i = 0; i < c->count; ++i) {
@@ -579,7 +639,7 @@ int ba_grad(ba_ctx* c, const double* theta_dev, double* I_bits, double* dI_dthet
     if (c->engine == BA_ENGINE_STREAM) {
       const StreamExtra ex{};
       HIPCHK(c, launch_fill_zero(cert.gd, cert.xs * sizeof(double), s));
-      HIPCHK(c, launch_stream<double>(kOpGather, gh.tb, Gd, k0_for(gh.n, 1, 8), ex, s));
+      HIPCHK(c, launch_stream<double>(kOpGather, gh.tb, Gd, 0, ex, s));
     } else {
       HIPCHK(c, launch_backward<double>(Gd, s, nullptr));
     }

@@ -142,6 +142,9 @@ hipError_t build_tables(int n, void* mem, hipStream_t s, Tables* out_host);
 template <typename T>
 hipError_t launch_stream(StreamOp op, const Tables& tb, const Group<T>& g, int k0,
                          const StreamExtra& ex, hipStream_t s);
+template <typename T>
+hipError_t launch_combine_r(const Group<T>& g, int n1, int n2, int k0, hipStream_t s);
+int stream_lds_limit();  // largest dynamic LDS a block may request on this device
 hipError_t launch_row_compact(const uint32_t* dense, int n, uint32_t* rank_out,
                               uint32_t* emb_out, int cap, uint32_t* nnz_dev, hipStream_t s);
 

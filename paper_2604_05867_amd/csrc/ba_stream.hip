@@ -40,6 +40,36 @@ __device__ __forceinline__ void lds_add(T* p, T v) {
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// DPP row shifts (within 16-lane rows; lanes without a source read 0).
+template <int D>
+__device__ __forceinline__ int dpp_row_shr(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x110 + D, 0xf, 0xf, true);
+}
+__device__ __forceinline__ int dpp_row_shl1(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x101, 0xf, 0xf, true);
+}
+template <int D>
+__device__ __forceinline__ float shr_t(float v) {
+  return __int_as_float(dpp_row_shr<D>(__float_as_int(v)));
+}
+template <int D>
+__device__ __forceinline__ double shr_t(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = dpp_row_shr<D>(int(b & 0xffffffffll));
+  const int hi = dpp_row_shr<D>(int(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+// Segmented inclusive sum over lanes of a 16-lane row: m_d = 1 when lane-d is in
+// the same segment.  Afterwards the last lane of each segment holds its sum.
+template <typename T>
+__device__ __forceinline__ T seg_row_sum(T v, T m1, T m2, T m4, T m8) {
+  v = fma(shr_t<1>(v), m1, v);
+  v = fma(shr_t<2>(v), m2, v);
+  v = fma(shr_t<4>(v), m4, v);
+  v = fma(shr_t<8>(v), m8, v);
+  return v;
+}
+
 constexpr uint32_t binom_dev(int n, int k) {
   uint32_t r = 1;
   for (int i = 1; i <= k; ++i) r = r * uint32_t(n - k + i) / uint32_t(i);
@@ -81,7 +111,7 @@ __global__ __launch_bounds__(kBlock) void k_stream(Tables tb, Group<T> g, int k0
   }
   __syncthreads();
 
-  const uint4* __restrict__ t1 = (OP == kOpGather) ? tb.t1g : tb.t1s;
+  const uint4* __restrict__ t1 = (OP == kOpGather || OP == kOpScatter) ? tb.t1g : tb.t1s;
   const uint32_t o2 = tb.off2[x2];
   const uint32_t c2 = tb.off2[x2 + 1] - o2;
   const uint32_t z0 = tb.n0_2[x2];
@@ -135,10 +165,27 @@ __global__ __launch_bounds__(kBlock) void k_stream(Tables tb, Group<T> g, int k0
     double ah = 0.0, ahd = 0.0;
     const uint32_t A1 = y1 | (1u << k1);
     const uint32_t R1 = A1 - 1u;  // rank of y1
+    // Scatter: lanes are sorted by (class, y1, x1), so lanes with the same y1 form
+    // contiguous runs that, for a given y2, add into the same output.  Per run and
+    // 16-lane row a segmented Hillis-Steele scan over DPP row shifts leaves the run's
+    // sum in its last lane (sm_d = 1 when lane-d is in the same run and row).
+    T sm1 = T(0), sm2 = T(0), sm4 = T(0), sm8 = T(0);
+    bool emit = false;
     if (OP == kOpScatter) {
 #pragma unroll
       for (int b = 0; b < kTile; ++b)
         pl[b] = (b < nbt && valid) ? g.p[(size_t)(b0 + b) * g.xs + x] : T(0);
+      const int key = valid ? int(((ent.x >> 24) & 3u) << 12 | R1) : -1;
+      const int rl = lane & 15;
+      // The DPP reads run with every lane active (a disabled source lane reads 0).
+      const int kd1 = dpp_row_shr<1>(key), kd2 = dpp_row_shr<2>(key);
+      const int kd4 = dpp_row_shr<4>(key), kd8 = dpp_row_shr<8>(key);
+      const int ku1 = dpp_row_shl1(key);
+      sm1 = (rl >= 1 && kd1 == key) ? T(1) : T(0);
+      sm2 = (rl >= 2 && kd2 == key) ? T(1) : T(0);
+      sm4 = (rl >= 4 && kd4 == key) ? T(1) : T(0);
+      sm8 = (rl >= 8 && kd8 == key) ? T(1) : T(0);
+      emit = (rl == 15) || (ku1 != key);
     }
     if (OP == kOpGather) {
 #pragma unroll
@@ -165,21 +212,26 @@ __global__ __launch_bounds__(kBlock) void k_stream(Tables tb, Group<T> g, int k0
 #pragma unroll
         for (int j = 0; j <= kHalfMax; ++j)
           if (j <= jmax) emb = __umul24(l[j], byte_of(t, j)) + emb;
-        if (!ok) continue;
         const int k = k1 + k2;
         if (OP == kOpScatter) {
+          // All lanes take part in the run reduction (inactive lanes add 0), then
+          // the last lane of each run (per 16-lane row) issues one atomic.
+          const T fe = ok ? T(emb) : T(0);
           const uint32_t rank = (A1 << k2) + y2 - 1u;
-          const T fe = T(emb);
-          if (k <= k0) {
+          const size_t i2 = size_t((1u << k2) - 1u + y2) * S1 + R1;
 #pragma unroll
-            for (int b = 0; b < kTile; ++b)
-              if (b < nbt && ((live >> b) & 1u)) lds_add(&rs[b * nshort + rank], pl[b] * fe);
-          } else {
-#pragma unroll
-            for (int b = 0; b < kTile; ++b)
-              if (b < nbt && ((live >> b) & 1u)) atomic_add(&g.r[(size_t)(b0 + b) * g.ys + rank], pl[b] * fe);
+          for (int b = 0; b < kTile; ++b) {
+            if (b >= nbt || !((live >> b) & 1u)) continue;  // uniform
+            const T cv = seg_row_sum(pl[b] * fe, sm1, sm2, sm4, sm8);
+            if (emit && ok && cv != T(0)) {
+              if (k <= k0) lds_add(&rs[b * nshort + rank], cv);
+              else atomic_add(&g.v2[(size_t)(b0 + b) * g.v2s + i2], cv);
+            }
           }
-        } else if (OP == kOpGather) {
+          continue;
+        }
+        if (!ok) continue;
+        if (OP == kOpGather) {
           const size_t idx = size_t((1u << k2) - 1u + y2) * S1 + R1;
           const T fe = T(emb);
 #pragma unroll
@@ -246,6 +298,32 @@ __global__ void k_verify_finish(int n, const unsigned int* bins, unsigned long l
   atomicMax(&stats[4], nnz);
 }
 
+// r(y) for |y| > k0 from the split layout of the scatter: the sum over the splits
+// y = y1 y2 (|y1| <= n1, |y2| <= n2) of R2[rank(y2)][rank(y1)].  Outputs with
+// |y| <= k0 already hold their LDS-accumulated values.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_combine_r(Group<T> g, int n1, int n2, int k0) {
+  const int b = blockIdx.y;
+  if (g.st[b].converged) return;
+  const uint32_t Y = out_count(g.n);
+  const uint32_t S1 = out_count(n1);
+  const T* r2 = g.v2 + (size_t)b * g.v2s;
+  T* r = g.r + (size_t)b * g.ys;
+  for (uint32_t y = blockIdx.x * blockDim.x + threadIdx.x; y < Y; y += gridDim.x * blockDim.x) {
+    const int k = 31 - __clz(y + 1u);
+    if (k <= k0) continue;
+    const uint32_t yb = y + 1u - (1u << k);
+    T acc = T(0);
+    const int lo = k > n2 ? k - n2 : 0, hi = k < n1 ? k : n1;
+    for (int k1 = lo; k1 <= hi; ++k1) {
+      const int k2 = k - k1;
+      const uint32_t y1 = yb >> k2, y2 = yb & ((1u << k2) - 1u);
+      acc += r2[size_t((1u << k2) - 1u + y2) * S1 + ((1u << k1) - 1u + y1)];
+    }
+    r[y] = acc;
+  }
+}
+
 // Row compaction: dense counts by rank -> (rank, emb) in increasing rank.
 // One block; ballot-free two-level scan per 1024-rank window.
 __global__ __launch_bounds__(1024) void k_row_compact(const uint32_t* dense, uint32_t total,
@@ -310,6 +388,11 @@ hipError_t launch_op(const Tables& tb, const Group<T>& g, int k0, const StreamEx
     }
     return hipGetLastError();
   }
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stream<T, OP>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL((k_stream<T, OP>), dim3(X2 * parts, tiles), dim3(kBlock), lds, s, tb, g, k0,
                      parts, ex);
   return hipGetLastError();
@@ -341,6 +424,30 @@ template hipError_t launch_stream<float>(StreamOp, const Tables&, const Group<fl
                                          const StreamExtra&, hipStream_t);
 template hipError_t launch_stream<double>(StreamOp, const Tables&, const Group<double>&, int,
                                           const StreamExtra&, hipStream_t);
+
+template <typename T>
+hipError_t launch_combine_r(const Group<T>& g, int n1, int n2, int k0, hipStream_t s) {
+  uint32_t grid = (out_count(g.n) + kBlock - 1) / kBlock;
+  if (grid > 4096u) grid = 4096u;
+  hipLaunchKernelGGL(k_combine_r<T>, dim3(grid, g.nb), dim3(kBlock), 0, s, g, n1, n2, k0);
+  return hipGetLastError();
+}
+template hipError_t launch_combine_r<float>(const Group<float>&, int, int, int, hipStream_t);
+template hipError_t launch_combine_r<double>(const Group<double>&, int, int, int, hipStream_t);
+
+int stream_lds_limit() {
+  static int cached = 0;
+  if (cached) return cached;
+  int dev = 0, v = 0;
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&v, hipDeviceAttributeSharedMemPerBlockOptin, dev) == hipSuccess && v > 0)
+    cached = v;
+  else if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
+    cached = v;
+  else
+    cached = 65536;
+  return cached;
+}
 
 hipError_t launch_row_compact(const uint32_t* dense, int n, uint32_t* rank_out, uint32_t* emb_out,
                               int cap, uint32_t* nnz_dev, hipStream_t s) {

@@ -327,3 +327,42 @@ def test_mirror_ascent_unit_step_is_ba(ba):
     th2_o = bdc.mirror_ascent(n, d, theta, 2.0, 5)
     assert np.allclose(bdc.normalise_logp(th2), bdc.normalise_logp(th2_o), atol=1e-11)
     ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_graph_replay_matches_eager(ba, prec):
+    """ba_run replaying a captured graph (many replays with host reads between
+    them) gives the same iterates as eager launches; the factored engine has no
+    atomics, so the results are bitwise equal."""
+    ns = [8, 10, 8]
+    ds = [0.5, 0.7, 0.9]
+    p = ba.PREC_FP64 if prec == "fp64" else ba.PREC_FP32_LOG
+    out = []
+    s = torch.cuda.Stream()
+    c = ba.Context(ns, ds, prec=p, cert_every=20, stream=s)
+    start = torch.cat([torch.full((1 << n,), 0.0, dtype=torch.float64) for n in ns])
+    for graphs in (False, True):
+        # same context (H(x) is accumulated with atomics once per context) and the
+        # same starting state for both runs
+        c.set_graphs(graphs)
+        with torch.cuda.stream(s):
+            c.set_logp(start)
+            done = c.run(1e-7, 400)
+            lo, hi, its = c.best_bounds()
+            lp = c.get_logp().cpu().numpy()
+        s.synchronize()
+        out.append((done, lo, hi, its, lp))
+    c.close()
+    assert out[0][0] == out[1][0] and out[0][3] == out[1][3]
+    assert out[0][1] == out[1][1] and out[0][2] == out[1][2]
+    assert np.array_equal(out[0][4], out[1][4])
+
+
+def test_graph_needs_a_stream(ba):
+    c = ba.Context(6, 0.5)
+    c.set_graphs(True)
+    if c.stream.cuda_stream == 0:
+        with pytest.raises(ba.BAError) as e:
+            c.run(1e-6, 10)
+        assert e.value.code == ba.BA_ESTATE
+    c.close()
