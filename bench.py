@@ -35,11 +35,17 @@ def stage_sizes(n):
     return [((2 << i) - 1) << (n - i) for i in range(n + 1)]
 
 
-def factored_bytes_per_iteration(n, esz, nb):
-    """Algorithmic HBM bytes of one sweep (forward or backward): each stage reads
-    its source array once and writes its destination once."""
+def factored_launch_bytes(n, esz, nb, fuse=True):
+    """Algorithmic HBM bytes of each launch of one sweep (forward or backward):
+    a launch covering positions i..i+t-1 reads its source array (stage i) once and
+    writes its destination (stage i+t) once.  Two positions per launch when fused."""
     s = stage_sizes(n)
-    return sum(s[i] + s[i + 1] for i in range(n)) * esz * nb
+    out, i = [], 0
+    while i < n:
+        t = 2 if (fuse and i + 2 <= n) else 1
+        out.append((s[i] + s[i + t]) * esz * nb)
+        i += t
+    return out
 
 
 def cpu_baseline(target_s=10.0):
@@ -71,6 +77,92 @@ def cpu_baseline(target_s=10.0):
             "cpu": platform.processor() or platform.machine()}
 
 
+def run_segments(ctx, gap_bits, cap, seg, tag):
+    """ba_run in segments of `seg` iterations (continuing the same run), printing
+    progress after each; returns when every instance meets gap_bits or after cap."""
+    import numpy as np
+    done = 0
+    while done < cap:
+        k = min(seg, cap - done)
+        ctx.run(gap_bits, k)
+        done += k
+        lo, hi, it = ctx.best_bounds()
+        left = int(np.sum(np.array(hi) - np.array(lo) >= gap_bits))
+        print("%s: %d iterations, %d instances above the gap" % (tag, done, left), file=sys.stderr, flush=True)
+        if left == 0:
+            break
+    return done
+
+
+def config3(cap, gap_bits, plain_limit_s, plain_graphs=False):
+    """Batched FP32 (one graph, 128 instances) against plain FP64 one instance at a
+    time, both to a certified gap < gap_bits or the iteration cap.  Prints one JSON
+    line with both wall times and the speedup at equal certified gap."""
+    import numpy as np
+    import torch
+
+    import bdc_inputs as inp
+    import paper_2604_05867_amd as ba
+
+    ns, ds = [], []
+    for n in (10, 12, 14, 16):
+        for d in inp.d_grid():
+            ns.append(n)
+            ds.append(float(d))
+    s = torch.cuda.Stream()
+    ctx = ba.Context(ns, ds, prec=ba.PREC_FP32_LOG, engine=ba.ENGINE_FACTORED, cert_every=50, stream=s)
+    ctx.set_graphs(True)
+    ctx.set_stop_rule(ba.STOP_BEST)
+    with torch.cuda.stream(s):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run_segments(ctx, gap_bits, cap, 25000, "config3 batched")
+        s.synchronize()
+        t_batch = time.perf_counter() - t0
+        lo_b, hi_b, it_b = ctx.best_bounds()
+    ctx.close()
+    print("config3: batched %.2f s" % t_batch, file=sys.stderr, flush=True)
+    # plain FP64, one instance after another, each to the gap the batched run reached
+    t_plain = 0.0
+    plain = []
+    t_start = time.perf_counter()
+    for i, (n, d) in enumerate(zip(ns, ds)):
+        if time.perf_counter() - t_start > plain_limit_s:
+            break
+        target = max(gap_bits, hi_b[i] - lo_b[i])
+        ps = torch.cuda.Stream() if plain_graphs else torch.cuda.current_stream()
+        c = ba.Context(n, d, prec=ba.PREC_FP64, engine=ba.ENGINE_FACTORED, stream=ps)
+        c.set_stop_rule(ba.STOP_BEST)
+        c.set_graphs(plain_graphs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        with torch.cuda.stream(ps):
+            c.run(target * (1 + 1e-9), cap)
+        torch.cuda.synchronize()
+        t_plain += time.perf_counter() - t0
+        lo, hi, it = c.best_bounds()
+        plain.append({"n": n, "d": d, "iters": it[0], "L": lo[0], "U": hi[0]})
+        c.close()
+        print("config3: plain %d/%d n=%d d=%.3f iters=%d gap=%.2e" % (i + 1, len(ns), n, d, it[0], hi[0] - lo[0]),
+              file=sys.stderr, flush=True)
+    m = len(plain)
+    # batched time for the same instances is not separable; scale by the instance share
+    share = m / len(ns)
+    out = {
+        "metric": "batched FP32 vs plain FP64 speedup at equal certified gap",
+        "stop_rule": "best certified bounds so far", "plain_graphs": plain_graphs,
+        "gap_bits": gap_bits, "cap": cap, "instances": len(ns), "plain_instances_timed": m,
+        "t_batched_s": t_batch, "t_plain_s_timed": t_plain,
+        "speedup": (t_plain / share) / t_batch if m else None,
+        "batched": [{"n": n, "d": d, "iters": it, "L": l, "U": h} for n, d, it, l, h in zip(ns, ds, it_b, lo_b, hi_b)],
+        "plain": plain,
+        "max_abs_L_diff_bits": max((abs(p["L"] - lo_b[j]) for j, p in enumerate(plain)), default=None),
+        "max_abs_U_diff_bits": max((abs(p["U"] - hi_b[j]) for j, p in enumerate(plain)), default=None),
+        "converged_batched": int(np.sum(np.array(hi_b) - np.array(lo_b) < gap_bits)),
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -79,7 +171,28 @@ def main():
     ap.add_argument("--stream-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stream", action="store_true")
+    ap.add_argument("--config3", action="store_true",
+                    help="batched FP32 vs plain FP64 at equal certified gap (several minutes)")
+    ap.add_argument("--cap", type=int, default=200000)
+    ap.add_argument("--gap", type=float, default=1e-6)
+    ap.add_argument("--plain-limit-s", type=float, default=600.0)
+    ap.add_argument("--plain-graphs", action="store_true",
+                    help="config3: replay the plain FP64 runs as graphs too")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="one 256 MiB device-to-device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        a = torch.ones(1 << 26, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": a.numel() * 4}))
+        return
+    if args.config3:
+        config3(args.cap, args.gap, args.plain_limit_s, args.plain_graphs)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the BA instances of this workload fit one MI355X "
               "(multi-GPU sharding is described in DESIGN.md, not implemented)", file=sys.stderr)
@@ -111,13 +224,12 @@ def main():
     dom = max(("sweep1", "sweep2"), key=lambda k: kt[k][0])
     dom_ms, dom_launches = kt[dom]
     per_launch_ms = dom_ms / max(dom_launches, 1)
-    bytes_iter = factored_bytes_per_iteration(N, 4, nb)
-    launches_per_iter = N
-    bytes_launch = bytes_iter / launches_per_iter
+    per_launch = factored_launch_bytes(N, 4, nb)
+    bytes_launch = sum(per_launch) / len(per_launch)
     achieved = bytes_launch / (per_launch_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
                 "frac": round(achieved / 8000.0, 4), "traffic": None,
-                "kernel": "k_fwd_stage" if dom == "sweep1" else "k_bwd_stage",
+                "kernel": "k_fwd_stage2<float,4>" if dom == "sweep1" else "k_bwd_stage2<float,4>",
                 "bytes_per_launch": int(bytes_launch), "avg_launch_us": round(per_launch_ms * 1e3, 2)}
 
     lo, hi = ctx.bounds()

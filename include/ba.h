@@ -91,9 +91,27 @@ int ba_init(int n, double d, ba_ctx **out);
 int ba_init_batch(int count, const int *n, const double *d, int prec, int cert_every,
                   ba_ctx **out);
 
+/* A batch of exact deletion channels BDC_{n,k} (Section 2.2): on input x the
+ * output is a uniformly random length-k subsequence position set, so
+ * W(y|x) = emb(y,x)/C(n,k) for |y| = k and 0 otherwise; its capacity is C_{n,k}.
+ * Bounds from ba_bounds/ba_run bracket C_{n,k}; combined over k they bound C_n(d)
+ * by Lemma 2: C_n(d) <= sum_k C(n,k) d^(n-k) (1-d)^k C_{n,k}.  1 <= n[i] <= 20,
+ * 0 <= k[i] <= n[i]; everything else as ba_init_batch.  ba_grad's dI/dd is
+ * rejected (BA_EINVAL) for these instances. */
+int ba_init_exact(int count, const int *n, const int *k, int prec, int cert_every, ba_ctx **out);
+
 /* Select BA_ENGINE_*.  Allowed at any time after init; takes effect at the next
  * call that runs sweeps. */
 int ba_set_engine(ba_ctx *c, int engine);
+
+/* Stopping rule of ba_run.  BA_STOP_ITERATE (default): stop when the current
+ * iterate's gap U - L is below the tolerance (the rule of Section 2.3).
+ * BA_STOP_BEST: stop when the best certified bounds seen so far (max L, min U over
+ * the iterates evaluated in FP64) are closer than the tolerance; the upper bound
+ * is not monotone in the iteration count, so this can stop earlier.  Both report
+ * valid bounds. */
+enum { BA_STOP_ITERATE = 0, BA_STOP_BEST = 1 };
+int ba_set_stop_rule(ba_ctx *c, int rule);
 
 /* Run ba_run's iteration chunks as one captured HIP graph (replayed until the
  * stopping rule holds) instead of individual launches.  Needs a non-null bound
@@ -106,7 +124,12 @@ int ba_set_graphs(ba_ctx *c, int enable);
  *  BA_TUNE_SCATTER_LDS_KB: LDS budget (1..160 KB, default 64) of the stream
  *  engine's scatter; outputs short enough for the budget are accumulated in LDS
  *  before going to device memory.  Capped by the device's per-block limit. */
-enum { BA_TUNE_SCATTER_LDS_KB = 0 };
+enum {
+  BA_TUNE_SCATTER_LDS_KB = 0,
+  /* BA_TUNE_FACTORED_FUSE: 1 (default) evaluates two input positions per launch of
+   * the factored engine, 0 one position per launch. */
+  BA_TUNE_FACTORED_FUSE = 1
+};
 int ba_set_tuning(ba_ctx *c, int key, int value);
 
 /* Free the host state.  The workspace stays owned by the caller.  NULL is a no-op. */
@@ -136,7 +159,9 @@ int ba_step(ba_ctx *c, int iters);
 
 /* Iterate until the FP64-certified gap U - L is below gap_bits for every instance
  * or until max_iters further iterations, certifying every cert_every iterations
- * (1 for FP64 single-instance contexts).  Synchronises once per certification.
+ * (FP32 iterates; FP64 iterates are tested every iteration on the device).
+ * Synchronises once per chunk of iterations.  Instances that already meet gap_bits
+ * stay frozen, so repeated calls continue a run.
  * *iters_done (host, may be NULL) receives the number of iterations performed by
  * the slowest instance.  The stopping rule is that of Section 2.3 with the
  * tolerance in bits. */
@@ -149,7 +174,8 @@ int ba_run(ba_ctx *c, double gap_bits, int max_iters, int *iters_done);
  * lower_bits/upper_bits are host arrays of length count.  Blocks. */
 int ba_bounds(ba_ctx *c, double *lower_bits, double *upper_bits);
 
-/* Best certified bounds seen so far by ba_run/ba_bounds (max lower, min upper),
+/* Best certified bounds seen so far (max lower, min upper) over the FP64 iterates
+ * (BA_PREC_FP64: every iteration) and the certifications of ba_run/ba_bounds,
  * host arrays of length count; and completed iterations per instance (host int
  * array of length count, may be NULL).  Blocks. */
 int ba_best_bounds(ba_ctx *c, double *lower_bits, double *upper_bits, int *iters);

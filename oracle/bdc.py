@@ -97,6 +97,34 @@ def channel_dense(n: int, d: float, E: np.ndarray | None = None) -> np.ndarray:
     return E * length_weights(n, d)[output_lengths(n)][None, :]
 
 
+def channel_dense_exact(n: int, k: int, E: np.ndarray | None = None) -> np.ndarray:
+    """W[x, rank(y)] = emb(y, x) / C(n, k) for |y| = k, 0 otherwise: the exact
+    deletion channel BDC_{n,k} of Section 2.2 (a uniformly random set of n-k
+    positions is deleted), whose capacity is C_{n,k}."""
+    if E is None:
+        E = emb_dense(n)
+    w = np.zeros(n + 1)
+    w[k] = 1.0 / math.comb(n, k)
+    return E * w[output_lengths(n)][None, :]
+
+
+def lemma2_bound(n: int, d: float, c_nk) -> float:
+    """Lemma 2: C_n(d) <= sum_k C(n,k) d^(n-k) (1-d)^k C_{n,k}; c_nk[k] for k = 0..n
+    (the k = 0 term is C_{n,0} = 0)."""
+    w = length_weights(n, d)
+    return float(sum(math.comb(n, k) * w[k] * c_nk[k] for k in range(n + 1)))
+
+
+def lemma10_bound(n: int, k: int, s: int, c_small, c_rest) -> float:
+    """Lemma 10 (RC23): C_{n,k} <= sum_i [C(s,i) C(n-s,k-i) / C(n,k)] (C_{s,i} + C_{n-s,k-i});
+    c_small[i] = C_{s,i}, c_rest[j] = C_{n-s,j}."""
+    tot = 0.0
+    for i in range(0, s + 1):
+        if 0 <= k - i <= n - s:
+            tot += math.comb(s, i) * math.comb(n - s, k - i) / math.comb(n, k) * (c_small[i] + c_rest[k - i])
+    return tot
+
+
 # ---------------------------------------------------------------------------
 # One Blahut-Arimoto iteration, in the order of Section 2.3 (and Algorithm 1).
 # Probabilities are carried as logs; the paper itself evaluates log W^{(t)} for

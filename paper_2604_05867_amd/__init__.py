@@ -25,6 +25,8 @@ PREC_FP64, PREC_FP32_LOG = 0, 1
 ENGINE_STREAM, ENGINE_FACTORED = 0, 1
 KCLASS = ("sweep1", "logr", "sweep2", "reduce", "update")
 TUNE_SCATTER_LDS_KB = 0
+TUNE_FACTORED_FUSE = 1
+STOP_ITERATE, STOP_BEST = 0, 1
 
 _lib = None
 
@@ -47,6 +49,7 @@ def lib():
     pi32, pf64 = ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)
     L.ba_init.argtypes = [i32, f64, ctypes.POINTER(vp)]
     L.ba_init_batch.argtypes = [i32, pi32, pf64, i32, i32, ctypes.POINTER(vp)]
+    L.ba_init_exact.argtypes = [i32, pi32, pi32, i32, i32, ctypes.POINTER(vp)]
     L.ba_set_engine.argtypes = [vp, i32]
     L.ba_free.argtypes = [vp]
     L.ba_free.restype = None
@@ -73,6 +76,7 @@ def lib():
     L.ba_time_kernels.argtypes = [vp, i32, pf64, pi32]
     L.ba_set_graphs.argtypes = [vp, i32]
     L.ba_set_tuning.argtypes = [vp, i32, i32]
+    L.ba_set_stop_rule.argtypes = [vp, i32]
     _lib = L
     return L
 
@@ -91,11 +95,14 @@ class Context:
 
     ``n`` and ``d`` are sequences (or scalars for one instance)."""
 
-    def __init__(self, n, d, prec: int = PREC_FP64, engine: int = ENGINE_FACTORED,
+    def __init__(self, n, d=None, prec: int = PREC_FP64, engine: int = ENGINE_FACTORED,
                  cert_every: int = 50, device: str | torch.device = "cuda:0",
-                 stream: torch.cuda.Stream | None = None):
+                 stream: torch.cuda.Stream | None = None, k=None):
         L = lib()
         ns = [int(n)] if isinstance(n, int) else [int(v) for v in n]
+        exact = k is not None
+        if exact:
+            d = [0.5] * (1 if isinstance(k, int) else len(k))
         ds = [float(d)] if isinstance(d, (int, float)) else [float(v) for v in d]
         if len(ds) == 1 and len(ns) > 1:
             ds = ds * len(ns)
@@ -106,8 +113,18 @@ class Context:
         self._h = ctypes.c_void_p()
         arr_n = (ctypes.c_int * self.count)(*ns)
         arr_d = (ctypes.c_double * self.count)(*ds)
-        self._check(L.ba_init_batch(self.count, arr_n, arr_d, prec, cert_every, ctypes.byref(self._h)),
-                    "ba_init_batch")
+        if exact:
+            ks = [int(k)] if isinstance(k, int) else [int(v) for v in k]
+            if len(ks) == 1 and self.count > 1:
+                ks = ks * self.count
+            self.k = ks
+            arr_k = (ctypes.c_int * self.count)(*ks)
+            self._check(L.ba_init_exact(self.count, arr_n, arr_k, prec, cert_every, ctypes.byref(self._h)),
+                        "ba_init_exact")
+        else:
+            self.k = None
+            self._check(L.ba_init_batch(self.count, arr_n, arr_d, prec, cert_every, ctypes.byref(self._h)),
+                        "ba_init_batch")
         self.set_engine(engine)
         self.device = torch.device(device)
         nbytes = ctypes.c_size_t()
@@ -137,6 +154,10 @@ class Context:
     def set_graphs(self, enable: bool = True):
         """Replay ba_run's chunks as a captured HIP graph (needs a non-null stream)."""
         self._check(lib().ba_set_graphs(self._h, 1 if enable else 0), "ba_set_graphs")
+
+    def set_stop_rule(self, rule: int):
+        """STOP_ITERATE (gap of the current iterate) or STOP_BEST (best bounds so far)."""
+        self._check(lib().ba_set_stop_rule(self._h, rule), "ba_set_stop_rule")
 
     def set_tuning(self, key: int, value: int):
         self._check(lib().ba_set_tuning(self._h, key, value), "ba_set_tuning")

@@ -49,6 +49,7 @@ struct ba_ctx {
   int count = 0;
   std::vector<int> n;
   std::vector<double> d;
+  std::vector<int> kexact;  // >= 0: exact deletion channel BDC_{n,k} for that instance
   int prec = BA_PREC_FP64;
   int cert_every = 1;
   int engine = BA_ENGINE_FACTORED;
@@ -65,6 +66,8 @@ struct ba_ctx {
   std::string err;
   // tuning
   int scatter_lds_kb = 64;
+  int fuse = 1;  // factored engine: two positions per launch
+  int stop_rule = BA_STOP_ITERATE;
   // graph replay of ba_run chunks
   bool use_graph = false;
   hipGraphExec_t gexec = nullptr;
@@ -98,6 +101,15 @@ uint64_t ipow3(int e) {
 }
 
 bool valid_d(double d) { return d >= 0.0 && d <= 1.0 && isfinite(d); }
+
+// Exact deletion channel BDC_{n,k} (Section 2.2): W(y|x) = emb(y,x)/C(n,k) for
+// |y| = k, so w_j = [j = k]/C(n,k); no deletion probability, no d-gradient.
+void make_consts_exact(int n, int k, Consts* c) {
+  memset(c, 0, sizeof(*c));
+  double binom = 1.0;
+  for (int i = 1; i <= k; ++i) binom = binom * double(n - k + i) / double(i);
+  c->w[k] = 1.0 / binom;
+}
 
 void make_consts(int n, double d, Consts* c) {
   memset(c, 0, sizeof(*c));
@@ -282,18 +294,18 @@ int sweeps(ba_ctx* c, const GroupHost& gh, const Group<T>& G, int use_sw_g, T* g
     }
   } else {
     {
-      Timer t(c, BA_K_SWEEP1, n);
-      HIPCHK(c, launch_forward<T>(G, s, nullptr));
+      Timer t(c, BA_K_SWEEP1, factored_launches(n, c->fuse));
+      HIPCHK(c, launch_forward<T>(G, s, nullptr, c->fuse));
     }
     {
       Timer t(c, BA_K_LOGR, 1);
       HIPCHK(c, launch_logr<T>(G, use_sw_g, 0, n1, n2, s));
     }
     {
-      Timer t(c, BA_K_SWEEP2, n);
+      Timer t(c, BA_K_SWEEP2, factored_launches(n, c->fuse));
       Group<T> G2 = G;
       G2.g = g_out;
-      HIPCHK(c, launch_backward<T>(G2, s, nullptr));
+      HIPCHK(c, launch_backward<T>(G2, s, nullptr, c->fuse));
     }
   }
   return BA_OK;
@@ -387,6 +399,7 @@ int new_ctx(int count, const int* n, const double* d, int prec, int cert_every, 
   c->count = count;
   c->n.assign(n, n + count);
   c->d.assign(d, d + count);
+  c->kexact.assign(count, -1);
   c->prec = prec;
   c->cert_every = cert_every;
   plan(c);
@@ -404,6 +417,17 @@ int ba_init_batch(int count, const int* n, const double* d, int prec, int cert_e
   return new_ctx(count, n, d, prec, cert_every, out);
 }
 
+int ba_init_exact(int count, const int* n, const int* k, int prec, int cert_every, ba_ctx** out) {
+  if (!k || !n || count < 1 || count > 4096) return BA_EINVAL;
+  for (int i = 0; i < count; ++i)
+    if (k[i] < 0 || k[i] > n[i]) return BA_EINVAL;
+  std::vector<double> d(count, 0.5);
+  int rc = new_ctx(count, n, d.data(), prec, cert_every, out);
+  if (rc) return rc;
+  (*out)->kexact.assign(k, k + count);
+  return BA_OK;
+}
+
 int ba_set_engine(ba_ctx* c, int engine) {
   if (!c || (engine != BA_ENGINE_STREAM && engine != BA_ENGINE_FACTORED)) return BA_EINVAL;
   if (engine != c->engine) drop_graph(c);
@@ -419,7 +443,19 @@ int ba_set_tuning(ba_ctx* c, int key, int value) {
     drop_graph(c);
     return BA_OK;
   }
+  if (key == BA_TUNE_FACTORED_FUSE) {
+    if (value != 0 && value != 1) return fail(c, BA_EINVAL, "fuse must be 0 or 1");
+    c->fuse = value;
+    drop_graph(c);
+    return BA_OK;
+  }
   return fail(c, BA_EINVAL, "unknown tuning key");
+}
+
+int ba_set_stop_rule(ba_ctx* c, int rule) {
+  if (!c || (rule != BA_STOP_ITERATE && rule != BA_STOP_BEST)) return BA_EINVAL;
+  c->stop_rule = rule;
+  return BA_OK;
 }
 
 int ba_set_graphs(ba_ctx* c, int enable) {
@@ -458,7 +494,11 @@ int ba_bind(ba_ctx* c, void* ws, size_t bytes, void* stream) {
     HIPCHK(c, build_tables(gh.n, c->ws + gh.L.tables, s, &gh.tb));
     // per-instance constants
     std::vector<Consts> cs(gh.inst.size());
-    for (size_t j = 0; j < gh.inst.size(); ++j) make_consts(gh.n, c->d[gh.inst[j]], &cs[j]);
+    for (size_t j = 0; j < gh.inst.size(); ++j) {
+      const int i = gh.inst[j];
+      if (c->kexact[i] >= 0) make_consts_exact(gh.n, c->kexact[i], &cs[j]);
+      else make_consts(gh.n, c->d[i], &cs[j]);
+    }
     HIPCHK(c, hipMemcpyAsync(c->ws + gh.L.cs, cs.data(), cs.size() * sizeof(Consts), hipMemcpyHostToDevice, s));
     HIPCHK(c, hipStreamSynchronize(s));
     // H and Hd: one pass of the count generator over all nonzeros (init op)
@@ -501,7 +541,12 @@ int ba_run(ba_ctx* c, double gap_bits, int max_iters, int* iters_done) {
   for (int i = 0; i < c->count; ++i) {
     start[i] = st[i].iters;
     st[i].tol = gap_bits * kLn2;
-    if (!st[i].bad) st[i].converged = 0;
+    st[i].stop_best = (c->stop_rule == BA_STOP_BEST) ? 1 : 0;
+    // an instance stays frozen only if it already meets this tolerance (so ba_run
+    // can be called repeatedly to continue a run)
+    const double last = (c->prec == BA_PREC_FP64) ? st[i].U - st[i].L : st[i].certU - st[i].certL;
+    const double gap = st[i].stop_best ? st[i].bestU - st[i].bestL : last;
+    if (!st[i].bad && !(st[i].converged && gap < st[i].tol)) st[i].converged = 0;
   }
   if ((rc = write_states(c, st))) return rc;
   // FP64 iterates: the update kernel tests the gap of every iterate and freezes the
@@ -618,7 +663,7 @@ int ba_grad(ba_ctx* c, const double* theta_dev, double* I_bits, double* dI_dthet
   int rc = check_ctx(c);
   if (rc) return rc;
   if (!theta_dev || !I_bits) return fail(c, BA_EINVAL, "NULL theta or I");
-  if (dI_dd_bits && !(c->d[0] > 0.0 && c->d[0] < 1.0))
+  if (dI_dd_bits && (c->kexact[0] >= 0 || !(c->d[0] > 0.0 && c->d[0] < 1.0)))
     return fail(c, BA_EINVAL, "dI/dd is undefined at d = 0 or d = 1");
   const auto [gi, slot] = c->where[0];
   GroupHost& gh = c->groups[gi];
@@ -641,7 +686,7 @@ int ba_grad(ba_ctx* c, const double* theta_dev, double* I_bits, double* dI_dthet
       HIPCHK(c, launch_fill_zero(cert.gd, cert.xs * sizeof(double), s));
       HIPCHK(c, launch_stream<double>(kOpGather, gh.tb, Gd, 0, ex, s));
     } else {
-      HIPCHK(c, launch_backward<double>(Gd, s, nullptr));
+      HIPCHK(c, launch_backward<double>(Gd, s, nullptr, c->fuse));
     }
   }
   HIPCHK(c, launch_dpart<double>(cert, nblk, 1, cert.gd, s));

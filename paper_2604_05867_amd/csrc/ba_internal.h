@@ -92,7 +92,7 @@ struct State {
   int iters;          // completed updates
   int converged;      // 1: frozen (kernels skip the instance)
   int bad;            // non-finite value seen
-  int pad;
+  int stop_best;      // 1: the tolerance test uses the best bounds so far
 };
 
 // One group of nb instances with length n, arrays at fixed strides.
@@ -149,10 +149,12 @@ hipError_t launch_row_compact(const uint32_t* dense, int n, uint32_t* rank_out,
                               uint32_t* emb_out, int cap, uint32_t* nnz_dev, hipStream_t s);
 
 // ba_factored.hip: the two products stage by stage.
+// fuse = 1: two positions per launch (k_fwd_stage2 / k_bwd_stage2).
 template <typename T>
-hipError_t launch_forward(const Group<T>& g, hipStream_t s, int* launches);  // p -> r
+hipError_t launch_forward(const Group<T>& g, hipStream_t s, int* launches, int fuse);  // p -> r
 template <typename T>
-hipError_t launch_backward(const Group<T>& g, hipStream_t s, int* launches); // v -> G
+hipError_t launch_backward(const Group<T>& g, hipStream_t s, int* launches, int fuse); // v -> G
+int factored_launches(int n, int fuse);
 
 // ba_reduce.hip
 template <typename T>

@@ -181,11 +181,18 @@ __global__ __launch_bounds__(kBlock) void k_update(Group<T> g, int nblk, double 
   const double U = P.dmax;
   const double Mn = P.m - L;
   const bool finite = isfinite(L) && isfinite(U) && isfinite(P.i);
-  const bool stop = !finite || (check_tol && st->tol >= 0.0 && (U - L) < st->tol);
+  // FP64 iterates (check_tol): these are the exact bounds of the current iterate,
+  // so they also update the best bounds; FP32 iterates leave that to certification.
+  const double bL = (check_tol && finite) ? fmax(st->bestL, L) : st->bestL;
+  const double bU = (check_tol && finite) ? fmin(st->bestU, U) : st->bestU;
+  const double gap = st->stop_best ? (bU - bL) : (U - L);
+  const bool stop = !finite || (check_tol && st->tol >= 0.0 && gap < st->tol);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     st->L = L;
     st->U = U;
     st->I = P.i;
+    st->bestL = bL;
+    st->bestU = bU;
     if (!finite) st->bad = 1;
     if (stop) {
       st->converged = 1;
@@ -290,7 +297,8 @@ __global__ __launch_bounds__(kBlock) void k_cert_finish(Group<double> g, int nbl
   if (write_best && isfinite(L) && isfinite(U)) {
     if (L > st->bestL) st->bestL = L;
     if (U < st->bestU) st->bestU = U;
-    if (st->tol >= 0.0 && (U - L) < st->tol) st->converged = 1;
+    const double gap = st->stop_best ? (st->bestU - st->bestL) : (U - L);
+    if (st->tol >= 0.0 && gap < st->tol) st->converged = 1;
   }
 }
 
@@ -370,6 +378,7 @@ __global__ __launch_bounds__(kBlock) void k_reset(Group<T> g) {
     st->iters = 0;
     st->converged = 0;
     st->bad = 0;
+    st->stop_best = 0;
   }
   for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < X; x += gridDim.x * blockDim.x) {
     g.lp[(size_t)b * g.xs + x] = T(l0);

@@ -202,9 +202,8 @@ __global__ __launch_bounds__(kBlock) void k_stream(Tables tb, Group<T> g, int k0
       const uint32_t cs0 = ch * kWave, ce0 = cs0 + kWave;
       if (qb >= qe || ce0 <= lo || cs0 >= hi) continue;  // uniform
       const bool ok = valid && e >= lo && e < hi;
-#pragma unroll 1
-      for (uint32_t q = qb; q < qe; ++q) {
-        const uint4 t = tb.t2[q];  // uniform: scalar load
+      // One compatible suffix y2 (T2 entry t, uniform across the wavefront).
+      auto body = [&](const uint4& t) {
         const uint32_t y2 = t.x & 1023u;
         const int k2 = (t.x >> 10) & 15;
         const int jmax = (t.x >> 14) & 15;
@@ -228,9 +227,9 @@ __global__ __launch_bounds__(kBlock) void k_stream(Tables tb, Group<T> g, int k0
               else atomic_add(&g.v2[(size_t)(b0 + b) * g.v2s + i2], cv);
             }
           }
-          continue;
+          return;
         }
-        if (!ok) continue;
+        if (!ok) return;
         if (OP == kOpGather) {
           const size_t idx = size_t((1u << k2) - 1u + y2) * S1 + R1;
           const T fe = T(emb);
@@ -249,7 +248,20 @@ __global__ __launch_bounds__(kBlock) void k_stream(Tables tb, Group<T> g, int k0
           atomicAdd(&ex.bins[(size_t)x * (tb.n + 2) + tb.n + 1], 1u);
           atomicMax(&ex.stats[5], (unsigned long long)emb);
         }
+      };
+      // Four suffixes per trip: their scalar loads (and, in the gather, their
+      // V2 loads) are in flight together.
+      uint32_t q = qb;
+#pragma unroll 1
+      for (; q + 4u <= qe; q += 4u) {
+        const uint4 ta = tb.t2[q], tbb = tb.t2[q + 1u], tc = tb.t2[q + 2u], td = tb.t2[q + 3u];
+        body(ta);
+        body(tbb);
+        body(tc);
+        body(td);
       }
+#pragma unroll 1
+      for (; q < qe; ++q) body(tb.t2[q]);
     }
     if (OP == kOpGather && valid) {
 #pragma unroll

@@ -1,0 +1,279 @@
+"""GPU checks at the benchmark configurations' full sizes (n = 16 and n = 20).
+
+At these sizes the dense oracle does not fit; the CPU oracle's sparse channel
+(n = 16) and properties that hold at any size (n = 20) are the references.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import bdc_inputs as inp
+from oracle import bdc
+
+pytestmark = pytest.mark.gpu
+LN2 = math.log(2.0)
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def ba():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2604_05867_amd as m
+    m.lib()
+    return m
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def cpl_rev_maps(n):
+    x = np.arange(1 << n)
+    cp = x ^ ((1 << n) - 1)
+    rv = np.zeros_like(x)
+    for i in range(n):
+        rv |= ((x >> i) & 1) << (n - 1 - i)
+    return cp, rv
+
+
+# ---------------------------------------------------------------------------
+# config 2: n = 16, d = 0.70, FP64, 2000 iterations
+# ---------------------------------------------------------------------------
+
+def golden_config2():
+    path = os.path.join(GOLDEN, "config2_n16_d070.txt")
+    if not os.path.exists(path):
+        pytest.skip("golden values not generated (tests/golden/make_golden.py config2)")
+    rows = {}
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        t, L, U, I, mn = line.split()
+        rows[int(t)] = (float(L), float(U), float(I))
+    return rows
+
+
+@pytest.mark.parametrize("engine", ["factored", "stream"])
+def test_config2_n16_fp64_iterates(ba, engine):
+    """FP64 iterates at n = 16 against the oracle's stored bounds at checkpoints
+    up to 2000 iterations (gap 1e-8 is not reached: the cap applies)."""
+    rows = golden_config2()
+    eng = ba.ENGINE_FACTORED if engine == "factored" else ba.ENGINE_STREAM
+    ctx = ba.Context(16, 0.70, engine=eng)
+    done = 0
+    last = max(rows) if engine == "factored" else 100
+    for t in sorted(rows):
+        if t > last:
+            break
+        ctx.step(t - done)
+        done = t
+        lo, hi = ctx.bounds()
+        L, U, I = rows[t]
+        say("config2 %s t=%d L=%.12f (%.12f) U=%.12f (%.12f)" % (engine, t, lo[0], L, hi[0], U))
+        assert abs(lo[0] - L) < 1e-9 and abs(hi[0] - U) < 1e-9
+    ctx.close()
+
+
+# ---------------------------------------------------------------------------
+# config 4: n = 16, d = 0.80, gradients and mirror ascent
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def csr16(oracle_native):
+    return oracle_native.CSR(16)
+
+
+def oracle_info(csr, d, theta):
+    lp = theta - theta.max()
+    lp = lp - math.log(np.exp(lp).sum())
+    D, L, U, I, _ = csr.evaluate(d, lp)
+    return I / LN2, D, lp
+
+
+def test_config4_forward_backward_against_oracle(ba, csr16):
+    n, d = 16, 0.80
+    theta = inp.theta_normal(n, seed=0, sigma=0.1)
+    ctx = ba.Context(n, d)
+    I, g, gd = ctx.grad(torch.from_numpy(theta))
+    I_o, D_o, lp = oracle_info(csr16, d, theta)
+    p = np.exp(lp)
+    g_o = p * (D_o - I_o * LN2) / LN2
+    say("config4: I=%.15f oracle %.15f dI/dd=%.12f" % (I, I_o, gd))
+    assert abs(I - I_o) < 1e-10
+    assert np.max(np.abs(g.cpu().numpy() - g_o)) < 1e-13
+    h = 1e-6
+    fd_d = (oracle_info(csr16, d + h, theta)[0] - oracle_info(csr16, d - h, theta)[0]) / (2 * h)
+    assert abs(fd_d - gd) <= 1e-8 + 1e-5 * abs(gd)
+    ctx.close()
+
+
+def test_config4_central_differences(ba):
+    """73 probes: 64 seeded coordinates and 8 seeded unit directions of theta, and d,
+    central differences with h = 1e-6 of the library's own I against its gradient."""
+    n, d = 16, 0.80
+    theta = inp.theta_normal(n, seed=0, sigma=0.1)
+    rng = np.random.default_rng(7)
+    coords = rng.choice(1 << n, size=64, replace=False)
+    dirs = rng.normal(size=(8, 1 << n))
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    ctx = ba.Context(n, d)
+    I0, g, gd = ctx.grad(torch.from_numpy(theta))
+    g = g.cpu().numpy()
+    h = 1e-6
+
+    def I_at(th, dd=None):
+        c = ctx if dd is None else ba.Context(n, dd)
+        v = c.grad(torch.from_numpy(th), want_dd=False)[0]
+        if dd is not None:
+            c.close()
+        return v
+
+    for j in coords:
+        e = np.zeros_like(theta)
+        e[j] = h
+        fd = (I_at(theta + e) - I_at(theta - e)) / (2 * h)
+        assert abs(fd - g[j]) <= 1e-8 + 1e-5 * abs(g[j]), (j, fd, g[j])
+    for v in dirs:
+        fd = (I_at(theta + h * v) - I_at(theta - h * v)) / (2 * h)
+        an = float(g @ v)
+        assert abs(fd - an) <= 1e-8 + 1e-5 * abs(an)
+    fd_d = (I_at(theta, d + h) - I_at(theta, d - h)) / (2 * h)
+    assert abs(fd_d - gd) <= 1e-8 + 1e-5 * abs(gd)
+    ctx.close()
+
+
+def test_config4_mirror_ascent_vs_ba(ba):
+    """500 mirror-ascent steps against 500 BA steps from the same theta: eta = 1 is
+    BA; eta = 2 must keep valid bounds (bracketing the capacity from both sides)."""
+    n, d = 16, 0.80
+    theta = inp.theta_normal(n, seed=0, sigma=0.1)
+    ctx = ba.Context(n, d)
+    ctx.set_logp(torch.from_numpy(theta))
+    ctx.step(500)
+    lp_ba = ctx.get_logp()
+    lo_ba, hi_ba = ctx.bounds()
+    th1 = ctx.mirror_ascent(torch.from_numpy(theta), 1.0, 500)
+    ev1 = ctx.eval(th1)
+    lp1 = th1.cpu().numpy()
+    lp1 = lp1 - lp1.max()
+    lp1 -= math.log(np.exp(lp1).sum())
+    assert np.max(np.abs(lp1 - lp_ba.cpu().numpy())) < 1e-8
+    assert abs(ev1["L"] - lo_ba[0]) < 1e-9 and abs(ev1["U"] - hi_ba[0]) < 1e-9
+    th2 = ctx.mirror_ascent(torch.from_numpy(theta), 2.0, 500)
+    ev2 = ctx.eval(th2)
+    say("config4: BA [%.9f, %.9f]  eta=2 [%.9f, %.9f]" % (lo_ba[0], hi_ba[0], ev2["L"], ev2["U"]))
+    assert ev2["L"] <= hi_ba[0] + 1e-12 and lo_ba[0] <= ev2["U"] + 1e-12
+    ctx.close()
+
+
+# ---------------------------------------------------------------------------
+# config 5: n = 20, FP32 iterates, FP64 certification, orbit check
+# ---------------------------------------------------------------------------
+
+def test_config5_n20_properties(ba):
+    n = 20
+    ds = [0.64, 0.80, 0.95]
+    ctx = ba.Context([n] * 3, ds, prec=ba.PREC_FP32_LOG, cert_every=50)
+    done = ctx.run(1e-6, 1500)
+    lo, hi, its = ctx.best_bounds()
+    say("config5: iters=%s L=%s U=%s" % (its, lo, hi))
+    for i, d in enumerate(ds):
+        assert lo[i] <= hi[i]
+        assert hi[i] - lo[i] < 0.05
+        assert lo[i] <= n * (1 - d) + 1e-12          # C_n(d) <= n C_1(d)
+    for i in range(2):                                  # non-increasing in d
+        assert lo[i + 1] <= hi[i] + 1e-12
+    # orbit check (Theorem 4): the final FP32 iterate is cpl/rev invariant
+    lp = ctx.get_logp().cpu().numpy().reshape(3, 1 << n)
+    cp, rv = cpl_rev_maps(n)
+    for i in range(3):
+        top = lp[i] > lp[i].max() - 30.0               # inputs that carry probability
+        assert np.max(np.abs(lp[i][cp] - lp[i])[top]) < 1e-3
+        assert np.max(np.abs(lp[i][rv] - lp[i])[top]) < 1e-3
+    # subadditivity against an FP64 run at n = 10: C_20 <= 2 C_10
+    c10 = ba.Context([10] * 3, ds, prec=ba.PREC_FP64)
+    c10.run(1e-8, 50000)
+    lo10, hi10, _ = c10.best_bounds()
+    for i in range(3):
+        assert lo[i] <= 2 * hi10[i] + 1e-9
+    c10.close()
+    ctx.close()
+
+
+# ---------------------------------------------------------------------------
+# autotuner: choices never change results (beyond rounding)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("engine", ["factored", "stream"])
+def test_autotuner_choices_do_not_change_results(ba, engine, tmp_path):
+    from paper_2604_05867_amd import autotune
+    ns, ds = [10, 12, 10], [0.64, 0.8, 0.96]
+    eng = ba.ENGINE_FACTORED if engine == "factored" else ba.ENGINE_STREAM
+    ref = None
+    for knob, value in autotune.CANDIDATES[eng]:
+        c = ba.Context(ns, ds, prec=ba.PREC_FP32_LOG, engine=eng)
+        c.set_tuning(knob, value)
+        c.step(10)
+        lo, hi = c.bounds()
+        if ref is None:
+            ref = (lo, hi)
+        assert np.allclose(lo, ref[0], atol=1e-6) and np.allclose(hi, ref[1], atol=1e-6)
+        c.close()
+    c = ba.Context(ns, ds, prec=ba.PREC_FP32_LOG, engine=eng)
+    path = str(tmp_path / "tune.json")
+    entry = autotune.tune(c, iters=2, cache_path=path)
+    assert entry["choice"][1] in [v for _, v in autotune.CANDIDATES[eng]]
+    again = autotune.tune(c, cache_path=path)
+    assert again["choice"] == entry["choice"]
+    c.step(10)
+    lo, hi = c.bounds()
+    assert np.allclose(lo, ref[0], atol=1e-6) and np.allclose(hi, ref[1], atol=1e-6)
+    c.close()
+
+
+# ---------------------------------------------------------------------------
+# exact deletion channels BDC_{n,k} and Lemma 2
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("engine", ["factored", "stream"])
+def test_exact_channels_match_oracle(ba, engine):
+    n = 7
+    eng = ba.ENGINE_FACTORED if engine == "factored" else ba.ENGINE_STREAM
+    ks = list(range(n + 1))
+    ctx = ba.Context([n] * len(ks), k=ks, engine=eng)
+    ctx.step(30)
+    lo, hi = ctx.bounds()
+    lp = ctx.get_logp().cpu().numpy().reshape(len(ks), 1 << n)
+    E = bdc.emb_dense(n)
+    for k in ks:
+        W = bdc.channel_dense_exact(n, k, E)
+        lp_o = bdc.ba_iterate(W, bdc.uniform_logp(n), 30)
+        L_o, U_o = bdc.certify(W, lp_o)
+        assert np.max(np.abs(lp[k] - lp_o)) < 1e-10
+        assert abs(lo[k] - L_o) < 1e-10 and abs(hi[k] - U_o) < 1e-10
+    ctx.close()
+
+
+def test_exact_channels_paper_values_and_lemma2(ba):
+    """C_{n,0} = 0, C_{n,1} = 1 (Table 1's k = 1 entry), C_{n,n} = n (Table 1's k = n
+    entry); Lemma 2 between the probabilistic and the exact channels at n = 12."""
+    n = 12
+    ks = list(range(n + 1))
+    ex = ba.Context([n] * len(ks), k=ks, prec=ba.PREC_FP64)
+    ex.run(1e-7, 20000)
+    lo, hi, _ = ex.best_bounds()
+    say("exact n=12: L=%s U=%s" % ([round(v, 5) for v in lo], [round(v, 5) for v in hi]))
+    assert abs(hi[0]) < 1e-9
+    assert abs(lo[1] - 1.0) < 1e-6 and abs(hi[1] - 1.0) < 1e-6
+    assert abs(lo[n] - n) < 1e-9 and abs(hi[n] - n) < 1e-9
+    for d in (0.3, 0.64, 0.9):
+        c = ba.Context(n, d)
+        c.run(1e-7, 20000)
+        l, h, _ = c.best_bounds()
+        assert l[0] <= bdc.lemma2_bound(n, d, hi) + 1e-9
+        c.close()
+    ex.close()

@@ -366,3 +366,24 @@ def test_graph_needs_a_stream(ba):
             c.run(1e-6, 10)
         assert e.value.code == ba.BA_ESTATE
     c.close()
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 8, 13])
+def test_factored_fusion_settings_agree(ba, n):
+    """One and two input positions per launch give the same evaluation (both
+    against the oracle for n <= 8)."""
+    d = 0.6
+    lp = inp.random_logp(n, seed=40 + n, spread=2.0)
+    out = []
+    for fuse in (0, 1):
+        c = ba.Context(n, d)
+        c.set_tuning(ba.TUNE_FACTORED_FUSE, fuse)
+        got = c.eval(torch.from_numpy(lp))
+        out.append((got["L"], got["U"], got["r"].cpu().numpy(), got["D"].cpu().numpy()))
+        c.close()
+    assert abs(out[0][0] - out[1][0]) < 1e-12 and abs(out[0][1] - out[1][1]) < 1e-12
+    assert np.allclose(out[0][2], out[1][2], rtol=1e-13, atol=0)
+    assert np.allclose(out[0][3], out[1][3], atol=1e-12)
+    if n <= 8:
+        ev = bdc.evaluate(bdc.channel_dense(n, d), lp)
+        assert abs(out[1][0] - ev.L / LN2) < 1e-11

@@ -426,6 +426,42 @@ def test_csr_matches_dense(oracle_native, n, d):
     assert np.allclose(bdc.normalise_logp(a), b, atol=1e-11)
 
 
+def exact_capacity(n, k, tol=1e-10):
+    return bdc.ba(bdc.channel_dense_exact(n, k), n, tol_bits=tol, max_iters=200000)
+
+
+def test_exact_channel_paper_values():
+    """Section 6 states C_{2,1} = 1 and C_{2,2} = 2; Table 1 gives C_{29,1} = 1.0000
+    and C_{29,29} = 29.0000, i.e. C_{n,1} = 1 (one output bit, achieved by 0^n and
+    1^n) and C_{n,n} = n (no deletion).  C_{n,0} = 0 (the output is always empty)."""
+    vals = paper_values()
+    assert abs(exact_capacity(2, 1).lower_bits - vals["C_2_1"]) < 1e-9
+    assert abs(exact_capacity(2, 2).lower_bits - vals["C_2_2"]) < 1e-9
+    for n in (3, 5, 7):
+        assert abs(exact_capacity(n, 1).lower_bits - vals["C_29_1"]) < 1e-9
+        assert abs(exact_capacity(n, n).upper_bits - n * vals["C_29_29"] / 29.0) < 1e-9
+        assert abs(exact_capacity(n, 0).upper_bits) < 1e-12
+    for n in range(1, 8):
+        W = bdc.channel_dense_exact(n, min(n, 3))
+        assert np.allclose(W.sum(axis=1), 1.0, atol=1e-14)
+
+
+def test_exact_channel_lemmas_2_and_10():
+    """Lemma 2 (C_n(d) <= sum_k pi_k C_{n,k}) and Lemma 10 with s = 2
+    (C_{n,k} <= sum_i [C(2,i)C(n-2,k-i)/C(n,k)] (C_{2,i} + C_{n-2,k-i})) hold between
+    independently computed brackets."""
+    n = 6
+    U = [exact_capacity(n, k, 1e-9).upper_bits for k in range(n + 1)]
+    L = [exact_capacity(n, k, 1e-9).lower_bits for k in range(n + 1)]
+    for d in (0.2, 0.5, 0.8):
+        Cn = bdc.ba(bdc.channel_dense(n, d), n, tol_bits=1e-9, max_iters=200000)
+        assert Cn.lower_bits <= bdc.lemma2_bound(n, d, U) + 1e-9
+    c2 = [exact_capacity(2, i, 1e-9).upper_bits for i in range(3)]
+    c4 = [exact_capacity(4, j, 1e-9).upper_bits for j in range(5)]
+    for k in range(1, n + 1):
+        assert L[k] <= bdc.lemma10_bound(n, k, 2, c2, c4) + 1e-9
+
+
 def test_sample_sweeps_match_dense(oracle_native):
     """The bounded-sample sweeps (used for the CPU baseline) against the dense
     evaluation: q restricted to the sampled rows and D at those rows."""
