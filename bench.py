@@ -271,6 +271,23 @@ def main():
     ctx.close()
 
     extra = {}
+    # the same workload with the complement-symmetric kernels (valid from p0 uniform)
+    print("bench: symmetric kernels", file=sys.stderr, flush=True)
+    csym = ba.Context([N] * nb, DS, prec=ba.PREC_FP32_LOG, engine=ba.ENGINE_FACTORED, cert_every=50, device=dev)
+    csym.set_symmetry(True)
+    csym.step(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    csym.step(args.steps)
+    torch.cuda.synchronize()
+    esym = time.perf_counter() - t0
+    ktsym = csym.time_kernels(args.steps)
+    lo_s, hi_s = csym.bounds()
+    extra["symmetric"] = {"value": args.steps / esym * nnz * nb, "unit": "W-nonzero terms/s",
+                          "iters_per_s": args.steps / esym, "ms_per_step": esym / args.steps * 1e3,
+                          "kernel_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in ktsym.items()},
+                          "certified_lower_bits": lo_s, "certified_upper_bits": hi_s}
+    csym.close()
     if not args.no_stream and args.stream_steps > 0:
         print("bench: stream engine", file=sys.stderr, flush=True)
         cs = ba.Context([N] * nb, DS, prec=ba.PREC_FP32_LOG, engine=ba.ENGINE_STREAM, device=dev)

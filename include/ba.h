@@ -113,6 +113,21 @@ int ba_set_engine(ba_ctx *c, int engine);
 enum { BA_STOP_ITERATE = 0, BA_STOP_BEST = 1 };
 int ba_set_stop_rule(ba_ctx *c, int rule);
 
+/* Complement-symmetric iteration (Appendix A, Theorem 4: from the uniform law
+ * every BA iterate of BDC_d and of BDC_{n,k} satisfies p(cpl x) = p(x), cpl = bitwise
+ * complement).  enable = 1: the iterations of the factored engine evaluate only
+ * the inputs x < 2^(n-1) and the stage entries whose first column bit is 0, reading
+ * the other half from the complement (about half the memory traffic; same results
+ * up to rounding).  Applies to groups with even n >= 4 and two positions per launch
+ * (BA_TUNE_FACTORED_FUSE = 1); other groups, the stream engine, certification,
+ * ba_eval and ba_grad run the full kernels.  Enabling it on a bound context checks
+ * that every iterate is invariant under complement (max |log p(x) - log p(cpl x)|
+ * <= 1e-9 nats for FP64, 1e-4 for FP32 iterates) and then makes it exactly so;
+ * BA_EINVAL (mode left off) if not.  While enabled, ba_set_logp applies the same
+ * check after setting the law and switches the mode off (BA_EINVAL) if it fails.
+ * enable = 0 switches back to the full kernels.  Off by default. */
+int ba_set_symmetry(ba_ctx *c, int enable);
+
 /* Run ba_run's iteration chunks as one captured HIP graph (replayed until the
  * stopping rule holds) instead of individual launches.  Needs a non-null bound
  * stream (capture is not allowed on the legacy null stream): BA_ESTATE otherwise,

@@ -77,6 +77,7 @@ def lib():
     L.ba_set_graphs.argtypes = [vp, i32]
     L.ba_set_tuning.argtypes = [vp, i32, i32]
     L.ba_set_stop_rule.argtypes = [vp, i32]
+    L.ba_set_symmetry.argtypes = [vp, i32]
     _lib = L
     return L
 
@@ -158,6 +159,11 @@ class Context:
     def set_stop_rule(self, rule: int):
         """STOP_ITERATE (gap of the current iterate) or STOP_BEST (best bounds so far)."""
         self._check(lib().ba_set_stop_rule(self._h, rule), "ba_set_stop_rule")
+
+    def set_symmetry(self, enable: bool = True):
+        """Complement-symmetric iteration (iterates invariant under bitwise
+        complement, as from the uniform start); see ba_set_symmetry."""
+        self._check(lib().ba_set_symmetry(self._h, 1 if enable else 0), "ba_set_symmetry")
 
     def set_tuning(self, key: int, value: int):
         self._check(lib().ba_set_tuning(self._h, key, value), "ba_set_tuning")

@@ -28,7 +28,7 @@ inline size_t pad64(size_t n) { return (n + 63) & ~size_t(63); }
 struct GroupLayout {
   size_t tables;
   size_t lp, p, r, v, v2, g, gd, D, f0, f1;     // iteration arrays (precision T)
-  size_t h, hd, part, st, cs;
+  size_t h, hd, hf, part, st, cs;
   size_t c_lp, c_p, c_r, c_v, c_v2, c_g, c_gd, c_D, c_f0, c_f1, c_part, c_st;  // FP64 cert
 };
 
@@ -57,6 +57,7 @@ struct ba_ctx {
   std::vector<std::pair<int, int>> where;  // instance -> (group, slot)
   size_t need = 0;
   size_t misc = 0;       // misc area: stats[8] u64, nnz u32, out4 double, scratch State
+  size_t symdev = 0;     // one double per instance: symmetry deviation
   size_t verify = 0;     // verify bins / dense row for group of instance 0
   size_t verify_bytes = 0;
   char* ws = nullptr;
@@ -68,6 +69,7 @@ struct ba_ctx {
   int scatter_lds_kb = 64;
   int fuse = 1;  // factored engine: two positions per launch
   int stop_rule = BA_STOP_ITERATE;
+  int sym = 0;   // complement-symmetric iteration requested
   // graph replay of ba_run chunks
   bool use_graph = false;
   hipGraphExec_t gexec = nullptr;
@@ -150,7 +152,7 @@ void plan(ba_ctx* c) {
     g.ys = pad64(out_count(n));
     g.v2s = pad64(size_t(out_count(n1)) * out_count(n2));
     g.fs = pad64(size_t(2) << n);
-    g.ps = size_t(2) * kMaxRedBlocks * kPartStride;
+    g.ps = size_t(kPartDoubles);
     GroupLayout& L = g.L;
     L.tables = take(table_bytes(n));
     L.lp = take(nb * g.xs * T);
@@ -165,6 +167,7 @@ void plan(ba_ctx* c) {
     L.f1 = take(nb * g.fs * T);
     L.h = take(nb * g.xs * 8);
     L.hd = take(nb * g.xs * 8);
+    L.hf = take(nb * g.xs * T);
     L.part = take(nb * g.ps * 8);
     L.st = take(nb * sizeof(State));
     L.cs = take(nb * sizeof(Consts));
@@ -187,6 +190,7 @@ void plan(ba_ctx* c) {
   if (c->verify_bytes < size_t(out_count(n0)) * 4) c->verify_bytes = size_t(out_count(n0)) * 4;
   c->verify = take(c->verify_bytes);
   c->misc = take(4096);
+  c->symdev = take(size_t(c->count) * 8);
   c->need = o;
 }
 
@@ -213,6 +217,9 @@ Group<T> make_group(char* ws, const GroupHost& g, bool cert) {
   G.f1 = reinterpret_cast<T*>(ws + (cert ? L.c_f1 : L.f1));
   G.h = reinterpret_cast<const double*>(ws + L.h);
   G.hd = reinterpret_cast<const double*>(ws + L.hd);
+  // H in the iteration precision (a rounded copy for FP32, H itself for FP64)
+  G.hf = (sizeof(T) == sizeof(double) || cert) ? reinterpret_cast<const T*>(ws + L.h)
+                                               : reinterpret_cast<const T*>(ws + L.hf);
   G.part = reinterpret_cast<double*>(ws + (cert ? L.c_part : L.part));
   G.st = reinterpret_cast<State*>(ws + (cert ? L.c_st : L.st));
   G.cs = reinterpret_cast<const Consts*>(ws + L.cs);
@@ -235,6 +242,7 @@ Group<T> slot_view(Group<T> G, int j) {
   G.f1 += size_t(j) * G.fs;
   G.h += size_t(j) * G.xs;
   G.hd += size_t(j) * G.xs;
+  G.hf += size_t(j) * G.xs;
   G.part += size_t(j) * G.ps;
   G.st += j;
   G.cs += j;
@@ -265,8 +273,19 @@ struct Timer {
 };
 
 // One sweep pair + reductions on group G (iteration or certification group).
+// The complement-symmetric kernels run for this group's iterations.
+bool sym_active(const ba_ctx* c, int n) {
+  return c->sym && c->engine == BA_ENGINE_FACTORED && symmetric_supported(n, c->fuse);
+}
+
+// tail = 1 (factored engine, iteration only): the last forward launch writes v
+// and the last backward launch forms D and its block records; *tail_done is the
+// number of those records, 0 if the backward part was not fused (then the caller
+// launches k_dpart).
 template <typename T>
-int sweeps(ba_ctx* c, const GroupHost& gh, const Group<T>& G, int use_sw_g, T* g_out) {
+int sweeps(ba_ctx* c, const GroupHost& gh, const Group<T>& G, int use_sw_g, T* g_out, int tail = 0,
+           int* tail_done = nullptr) {
+  if (tail_done) *tail_done = 0;
   hipStream_t s = c->stream;
   const int n = gh.n, n1 = (n + 1) / 2, n2 = n / 2;
   const StreamExtra ex{};
@@ -292,12 +311,24 @@ int sweeps(ba_ctx* c, const GroupHost& gh, const Group<T>& G, int use_sw_g, T* g
       HIPCHK(c, launch_fill_zero(g_out, size_t(G.nb) * G.xs * sizeof(T), s));
       HIPCHK(c, launch_stream<T>(kOpGather, gh.tb, G2, k0, ex, s));
     }
-  } else {
+  } else if (tail && !use_sw_g && sym_active(c, n)) {
     {
-      Timer t(c, BA_K_SWEEP1, factored_launches(n, c->fuse));
-      HIPCHK(c, launch_forward<T>(G, s, nullptr, c->fuse));
+      Timer t(c, BA_K_SWEEP1, factored_launches(n, 1));
+      HIPCHK(c, launch_forward_sym<T>(G, s, nullptr));
     }
     {
+      Timer t(c, BA_K_SWEEP2, factored_launches(n, 1));
+      Group<T> G2 = G;
+      G2.g = g_out;
+      HIPCHK(c, launch_backward_sym<T>(G2, s, nullptr, tail_done));
+    }
+  } else {
+    const int fuse_tail = (tail && !use_sw_g) ? 1 : 0;
+    {
+      Timer t(c, BA_K_SWEEP1, factored_launches(n, c->fuse));
+      HIPCHK(c, launch_forward<T>(G, s, nullptr, c->fuse, fuse_tail));
+    }
+    if (!fuse_tail) {
       Timer t(c, BA_K_LOGR, 1);
       HIPCHK(c, launch_logr<T>(G, use_sw_g, 0, n1, n2, s));
     }
@@ -305,7 +336,7 @@ int sweeps(ba_ctx* c, const GroupHost& gh, const Group<T>& G, int use_sw_g, T* g
       Timer t(c, BA_K_SWEEP2, factored_launches(n, c->fuse));
       Group<T> G2 = G;
       G2.g = g_out;
-      HIPCHK(c, launch_backward<T>(G2, s, nullptr, c->fuse));
+      HIPCHK(c, launch_backward<T>(G2, s, nullptr, c->fuse, fuse_tail, tail_done));
     }
   }
   return BA_OK;
@@ -313,17 +344,22 @@ int sweeps(ba_ctx* c, const GroupHost& gh, const Group<T>& G, int use_sw_g, T* g
 
 template <typename T>
 int iterate_group(ba_ctx* c, const GroupHost& gh, const Group<T>& G) {
-  const int nblk = reduce_blocks(gh.n);
-  int rc = sweeps<T>(c, gh, G, 0, G.g);
+  int nblk = 0;  // block records written by the fused D launch, if any
+  int rc = sweeps<T>(c, gh, G, 0, G.g, 1, &nblk);
   if (rc) return rc;
   {
-    Timer t(c, BA_K_REDUCE, 1);
-    HIPCHK(c, launch_dpart<T>(G, nblk, 0, nullptr, c->stream));
+    Timer t(c, BA_K_REDUCE, nblk ? 1 : 2);
+    if (!nblk) {
+      nblk = reduce_blocks(gh.n);
+      HIPCHK(c, launch_dpart<T>(G, nblk, 0, nullptr, c->stream));
+    }
+    HIPCHK(c, launch_final_parts<T>(G, nblk, c->stream));
   }
   {
     Timer t(c, BA_K_UPDATE, 1);
     const double floor = (sizeof(T) == 4) ? kFloor32 : kFloor64;
-    HIPCHK(c, launch_update<T>(G, nblk, floor, c->prec == BA_PREC_FP64 ? 1 : 0, c->stream));
+    HIPCHK(c, launch_update<T>(G, reduce_blocks(gh.n), floor, c->prec == BA_PREC_FP64 ? 1 : 0,
+                               sym_active(c, gh.n) ? 1 : 0, c->stream));
   }
   return BA_OK;
 }
@@ -509,6 +545,9 @@ int ba_bind(ba_ctx* c, void* ws, size_t bytes, void* stream) {
     ex.h = reinterpret_cast<double*>(c->ws + gh.L.h);
     ex.hd = reinterpret_cast<double*>(c->ws + gh.L.hd);
     HIPCHK(c, launch_stream<double>(kOpInit, gh.tb, gh.cert, 0, ex, s));
+    if (c->prec == BA_PREC_FP32_LOG)
+      HIPCHK(c, launch_to_float(reinterpret_cast<const double*>(c->ws + gh.L.h),
+                                reinterpret_cast<float*>(c->ws + gh.L.hf), nb * gh.xs, s));
     // states
     HIPCHK(c, launch_fill_zero(c->ws + gh.L.c_st, nb * sizeof(State), s));
     if (c->prec == BA_PREC_FP32_LOG) HIPCHK(c, launch_reset<float>(gh.gf, s));
@@ -686,7 +725,7 @@ int ba_grad(ba_ctx* c, const double* theta_dev, double* I_bits, double* dI_dthet
       HIPCHK(c, launch_fill_zero(cert.gd, cert.xs * sizeof(double), s));
       HIPCHK(c, launch_stream<double>(kOpGather, gh.tb, Gd, 0, ex, s));
     } else {
-      HIPCHK(c, launch_backward<double>(Gd, s, nullptr, c->fuse));
+      HIPCHK(c, launch_backward<double>(Gd, s, nullptr, c->fuse, 0, nullptr));
     }
   }
   HIPCHK(c, launch_dpart<double>(cert, nblk, 1, cert.gd, s));
@@ -737,6 +776,39 @@ int ba_get_logp(ba_ctx* c, double* logp_dev) {
   return BA_OK;
 }
 
+// Symmetric mode: check that every instance's iterate is invariant under
+// complement (within a rounding tolerance of its precision), then make it exactly
+// so by copying the half x < 2^(n-1) onto the complements.
+int sym_check_and_fix(ba_ctx* c) {
+  hipStream_t s = c->stream;
+  double* dev = reinterpret_cast<double*>(c->ws + c->symdev);
+  std::vector<double> host(c->count);
+  size_t k = 0;
+  std::vector<std::pair<size_t, size_t>> span;  // per group: first slot in dev, count
+  for (auto& gh : c->groups) {
+    if (c->prec == BA_PREC_FP32_LOG) HIPCHK(c, launch_sym_check<float>(gh.gf, dev + k, s));
+    else HIPCHK(c, launch_sym_check<double>(gh.gd, dev + k, s));
+    span.push_back({k, gh.inst.size()});
+    k += gh.inst.size();
+  }
+  HIPCHK(c, hipMemcpyAsync(host.data(), dev, k * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  const double tol = (c->prec == BA_PREC_FP32_LOG) ? 1e-4 : 1e-9;
+  for (size_t gi = 0; gi < c->groups.size(); ++gi)
+    for (size_t j = 0; j < span[gi].second; ++j) {
+      const double dv = host[span[gi].first + j];
+      if (!(dv <= tol))
+        return fail(c, BA_EINVAL, "iterate of instance " + std::to_string(c->groups[gi].inst[j]) +
+                                      " is not complement-symmetric (max |log p(x) - log p(cpl x)| = " +
+                                      std::to_string(dv) + ")");
+    }
+  for (auto& gh : c->groups) {
+    if (c->prec == BA_PREC_FP32_LOG) HIPCHK(c, launch_symmetrize<float>(gh.gf, s));
+    else HIPCHK(c, launch_symmetrize<double>(gh.gd, s));
+  }
+  return BA_OK;
+}
+
 int ba_set_logp(ba_ctx* c, const double* logp_dev) {
   int rc = check_ctx(c);
   if (rc) return rc;
@@ -755,6 +827,26 @@ int ba_set_logp(ba_ctx* c, const double* logp_dev) {
   if ((rc = read_states(c, st))) return rc;
   for (int i = 0; i < c->count; ++i)
     if (st[i].bad) return fail(c, BA_ENUMERIC, "logp contains NaN or +Inf (instance " + std::to_string(i) + ")");
+  if (c->sym && (rc = sym_check_and_fix(c))) {
+    c->sym = 0;
+    drop_graph(c);
+    return rc;
+  }
+  return BA_OK;
+}
+
+int ba_set_symmetry(ba_ctx* c, int enable) {
+  if (!c || (enable != 0 && enable != 1)) return c ? fail(c, BA_EINVAL, "enable must be 0 or 1") : BA_EINVAL;
+  if (enable && c->bound) {
+    c->sym = 1;
+    const int rc = sym_check_and_fix(c);
+    if (rc) {
+      c->sym = 0;
+      return rc;
+    }
+  }
+  c->sym = enable;
+  drop_graph(c);
   return BA_OK;
 }
 

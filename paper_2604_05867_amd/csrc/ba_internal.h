@@ -29,6 +29,10 @@ constexpr double kFloor64 = 700.0;  // floor on log p, nats below the max (FP64)
 constexpr double kFloor32 = 80.0;   // floor on log p, nats below the max (FP32 iterates)
 constexpr int kPartStride = 8;      // doubles per block record of a reduction
 constexpr int kMaxRedBlocks = 1024; // blocks per instance of a reduction
+// per-instance record buffer: block records [0, kMaxRedBlocks), a second set used
+// by the normalisation passes, then the final (combined) record
+constexpr int kFinalRec = 2 * kMaxRedBlocks * kPartStride;
+constexpr int kPartDoubles = kFinalRec + kPartStride;
 
 inline __host__ __device__ uint32_t out_count(int n) { return (2u << n) - 1u; }  // 2^(n+1)-1
 
@@ -114,6 +118,7 @@ struct Group {
   size_t fs;
   const double* h;    // H(x) (FP64 always)
   const double* hd;   // Hd(x)
+  const T* hf;        // H(x) rounded to T (the same array as h when T is double)
   double* part;       // per-block partials, stride ps
   size_t ps;
   State* st;          // [nb]
@@ -150,19 +155,44 @@ hipError_t launch_row_compact(const uint32_t* dense, int n, uint32_t* rank_out,
 
 // ba_factored.hip: the two products stage by stage.
 // fuse = 1: two positions per launch (k_fwd_stage2 / k_bwd_stage2).
+// logv = 1: the last forward launch writes v = w_k log r instead of r.
+// dpart = 1: the last backward launch also forms D = H - G - M and the block
+// records of k_dpart, writing D instead of G; *dpart_blocks returns the number of
+// records it wrote, or 0 if it could not fuse (smallest n), in which case the
+// caller launches k_dpart itself.
 template <typename T>
-hipError_t launch_forward(const Group<T>& g, hipStream_t s, int* launches, int fuse);  // p -> r
+hipError_t launch_forward(const Group<T>& g, hipStream_t s, int* launches, int fuse, int logv);  // p -> r
 template <typename T>
-hipError_t launch_backward(const Group<T>& g, hipStream_t s, int* launches, int fuse); // v -> G
+hipError_t launch_backward(const Group<T>& g, hipStream_t s, int* launches, int fuse, int dpart,
+                           int* dpart_blocks);                                                   // v -> G
 int factored_launches(int n, int fuse);
+// Complement-symmetric iteration (iterate invariant under complement): the two
+// products on the canonical half, v and D fused as above; v is stored at compact
+// indices (2^n entries) and D, G for x < 2^(n-1).  Supported for even n >= 4 with
+// two positions per launch.
+bool symmetric_supported(int n, int fuse);
+template <typename T>
+hipError_t launch_forward_sym(const Group<T>& g, hipStream_t s, int* launches);
+template <typename T>
+hipError_t launch_backward_sym(const Group<T>& g, hipStream_t s, int* launches, int* dpart_blocks);
 
 // ba_reduce.hip
 template <typename T>
 hipError_t launch_logr(const Group<T>& g, int use_sw, int want_v2, int n1, int n2, hipStream_t s);
 template <typename T>
 hipError_t launch_dpart(const Group<T>& g, int nblk, int use_hd, const T* gd, hipStream_t s);
+// Combine the nblk block records of every instance into its final record.
 template <typename T>
-hipError_t launch_update(const Group<T>& g, int nblk, double floor, int check_tol, hipStream_t s);
+hipError_t launch_final_parts(const Group<T>& g, int nblk, hipStream_t s);
+// sym: D holds x < 2^(n-1) only (complement-symmetric iteration); the update
+// writes each value to x and cpl x.
+template <typename T>
+hipError_t launch_update(const Group<T>& g, int nblk, double floor, int check_tol, int sym, hipStream_t s);
+// out[b] = max_x |log p(x) - log p(cpl x)| (device, one double per instance).
+template <typename T>
+hipError_t launch_sym_check(const Group<T>& g, double* out, hipStream_t s);
+template <typename T>
+hipError_t launch_symmetrize(const Group<T>& g, hipStream_t s);
 int reduce_blocks(int n);
 
 // Certification: FP64 evaluation of the current iterate of a group (any T).
@@ -186,5 +216,6 @@ template <typename T>
 hipError_t launch_reset(const Group<T>& g, hipStream_t s);
 hipError_t launch_fill_zero(void* ptr, size_t bytes, hipStream_t s);
 hipError_t launch_copy_f64(double* dst, const double* src, size_t count, hipStream_t s);
+hipError_t launch_to_float(const double* src, float* dst, size_t count, hipStream_t s);
 
 }  // namespace ba

@@ -1,0 +1,116 @@
+// Device-side reduction records of one BA iteration (Section 2.3): for the
+// current iterate, U = max_x D(x), L = log sum_x p(x) e^{D(x)} (online
+// log-sum-exp of a = log p + D), I = sum_x p(x) D(x) and, for the derivative in
+// d, sum_x p(x) Dd(x).  A kernel accumulates one record per thread, reduces it
+// per block and stores one record per block; a one-block-per-instance kernel
+// combines them into the final record that the update kernel reads.  Included by
+// the .hip sources only.
+#pragma once
+
+#include <math.h>
+
+#include "ba_internal.h"
+
+namespace ba {
+
+struct Part {
+  double m;     // max of a = log p + D
+  double s;     // sum exp(a - m)
+  double dmax;  // max D
+  double i;     // sum p D
+  double id;    // sum p Dd
+};
+
+__device__ __forceinline__ Part part_empty() { return Part{-INFINITY, 0.0, -INFINITY, 0.0, 0.0}; }
+
+__device__ __forceinline__ double lse_merge_s(double m1, double s1, double m2, double s2, double m) {
+  double r = 0.0;
+  if (s1 != 0.0) r += s1 * exp(m1 - m);
+  if (s2 != 0.0) r += s2 * exp(m2 - m);
+  return r;
+}
+
+__device__ __forceinline__ Part combine(const Part& a, const Part& b) {
+  Part c;
+  c.m = fmax(a.m, b.m);
+  c.s = (c.m == -INFINITY) ? 0.0 : lse_merge_s(a.m, a.s, b.m, b.s, c.m);
+  c.dmax = fmax(a.dmax, b.dmax);
+  c.i = a.i + b.i;
+  c.id = a.id + b.id;
+  return c;
+}
+
+__device__ __forceinline__ double exp_in(double v, double) { return exp(v); }
+__device__ __forceinline__ double exp_in(double v, float) { return double(expf(float(v))); }
+
+// Add one input with a = log p + D, D, p and p*Dd to a thread's record; the
+// exponential of the running log-sum-exp is taken in precision E (the iterate's).
+// wt: the number of inputs this value stands for (2 when only one of each
+// complement pair x, cpl(x) is evaluated).
+template <typename E>
+__device__ __forceinline__ void part_add(Part& p, double a, double dv, double px, double pdd, double wt = 1.0) {
+  if (a > p.m) {
+    p.s = p.s * exp_in(p.m - a, E()) + wt;
+    p.m = a;
+  } else {
+    p.s += wt * exp_in(a - p.m, E());
+  }
+  p.dmax = fmax(p.dmax, dv);
+  p.i += wt * px * dv;
+  p.id += wt * pdd;
+}
+
+// Reduction of one record per lane: max first, then every lane rescales its sum
+// to the common max (one exponential per lane) and the rest are plain sums/maxes.
+__device__ __forceinline__ Part wave_reduce(Part p) {
+  double m = p.m, dmax = p.dmax;
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    m = fmax(m, __shfl_xor(m, off));
+    dmax = fmax(dmax, __shfl_xor(dmax, off));
+  }
+  double s = (p.s != 0.0) ? p.s * exp(p.m - m) : 0.0;
+  double i = p.i, id = p.id;
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    s += __shfl_xor(s, off);
+    i += __shfl_xor(i, off);
+    id += __shfl_xor(id, off);
+  }
+  return Part{m, s, dmax, i, id};
+}
+
+// Block reduction (blockDim.x == kBlock); the result is valid in every thread.
+__device__ __forceinline__ Part block_reduce(Part p) {
+  __shared__ Part sp[kBlock / kWave];
+  p = wave_reduce(p);
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  __syncthreads();
+  if (lane == 0) sp[wave] = p;
+  __syncthreads();
+  Part r = sp[0];
+  for (int w = 1; w < kBlock / kWave; ++w) r = combine(r, sp[w]);
+  return r;
+}
+
+__device__ __forceinline__ void store_part(double* dst, const Part& p) {
+  dst[0] = p.m; dst[1] = p.s; dst[2] = p.dmax; dst[3] = p.i; dst[4] = p.id;
+}
+
+// A record written by an earlier kernel on the stream.
+__device__ __forceinline__ Part load_part(const double* q) { return Part{q[0], q[1], q[2], q[3], q[4]}; }
+
+// Combine the nblk records at src (every block that calls this does it in full).
+__device__ __forceinline__ Part gather_parts(const double* src, int nblk) {
+  Part p = part_empty();
+  for (int j = threadIdx.x; j < nblk; j += kBlock) p = combine(p, load_part(src + (size_t)j * kPartStride));
+  return block_reduce(p);
+}
+
+// Store this block's record (index rec) of an instance whose records start at
+// `part` (thread 0 writes).
+__device__ __forceinline__ void store_block_part(double* part, int rec, const Part& blk) {
+  if (threadIdx.x == 0) store_part(part + (size_t)rec * kPartStride, blk);
+}
+
+}  // namespace ba

@@ -4,84 +4,17 @@
 // and the update log p <- log p + D - L (normalisation of W^{(t)}).
 //
 // Reductions are two-level: a partial kernel writes one record per block
-// (wavefront shuffles, then LDS across the 4 wavefronts), and the consumer kernel
-// combines the <= 1024 records of its instance redundantly in every block, so no
-// separate combine launch and no host round trip is needed.  Partials are FP64
-// for both iteration precisions.
+// (wavefront shuffles, then LDS across the 4 wavefronts), a one-block-per-instance
+// kernel combines them into the final record, and the update kernel reads that
+// one record; there is no host round trip.  Records are FP64 for both iteration
+// precisions.
 #include <math.h>
 
 #include "ba_internal.h"
+#include "ba_part.h"
 
 namespace ba {
 namespace {
-
-struct Part {
-  double m;     // max of a = log p + D
-  double s;     // sum exp(a - m)
-  double dmax;  // max D
-  double i;     // sum p D
-  double id;    // sum p Dd
-};
-
-__device__ __forceinline__ Part part_empty() { return Part{-INFINITY, 0.0, -INFINITY, 0.0, 0.0}; }
-
-__device__ __forceinline__ double lse_merge_s(double m1, double s1, double m2, double s2, double m) {
-  double r = 0.0;
-  if (s1 != 0.0) r += s1 * exp(m1 - m);
-  if (s2 != 0.0) r += s2 * exp(m2 - m);
-  return r;
-}
-
-__device__ __forceinline__ Part combine(const Part& a, const Part& b) {
-  Part c;
-  c.m = fmax(a.m, b.m);
-  c.s = (c.m == -INFINITY) ? 0.0 : lse_merge_s(a.m, a.s, b.m, b.s, c.m);
-  c.dmax = fmax(a.dmax, b.dmax);
-  c.i = a.i + b.i;
-  c.id = a.id + b.id;
-  return c;
-}
-
-__device__ Part wave_reduce(Part p) {
-#pragma unroll
-  for (int off = kWave / 2; off > 0; off >>= 1) {
-    Part o;
-    o.m = __shfl_xor(p.m, off);
-    o.s = __shfl_xor(p.s, off);
-    o.dmax = __shfl_xor(p.dmax, off);
-    o.i = __shfl_xor(p.i, off);
-    o.id = __shfl_xor(p.id, off);
-    p = combine(p, o);
-  }
-  return p;
-}
-
-// Block reduction; the result is valid in every thread.
-__device__ Part block_reduce(Part p) {
-  __shared__ Part sp[kBlock / kWave];
-  p = wave_reduce(p);
-  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  __syncthreads();
-  if (lane == 0) sp[wave] = p;
-  __syncthreads();
-  Part r = sp[0];
-  for (int w = 1; w < kBlock / kWave; ++w) r = combine(r, sp[w]);
-  return r;
-}
-
-__device__ void store_part(double* dst, const Part& p) {
-  dst[0] = p.m; dst[1] = p.s; dst[2] = p.dmax; dst[3] = p.i; dst[4] = p.id;
-}
-
-// Combine the nblk records at src (every block does this redundantly).
-__device__ Part gather_parts(const double* src, int nblk) {
-  Part p = part_empty();
-  for (int j = threadIdx.x; j < nblk; j += kBlock) {
-    const double* q = src + (size_t)j * kPartStride;
-    p = combine(p, Part{q[0], q[1], q[2], q[3], q[4]});
-  }
-  return block_reduce(p);
-}
 
 __device__ __forceinline__ int length_of_rank(uint32_t r) { return 31 - __clz(r + 1u); }
 
@@ -145,38 +78,39 @@ __global__ __launch_bounds__(kBlock) void k_dpart(Group<T> g, int nblk, int use_
   const double M = g.st[b].M;
   const T* lp = g.lp + (size_t)b * g.xs;
   const T* gg = g.g + (size_t)b * g.xs;
-  const double* h = g.h + (size_t)b * g.xs;
+  const T* h = g.hf + (size_t)b * g.xs;
   T* D = g.D + (size_t)b * g.xs;
   Part p = part_empty();
   for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < X; x += gridDim.x * blockDim.x) {
-    const T dv = T(h[x]) - gg[x] - T(M);
+    const T dv = h[x] - gg[x] - T(M);
     D[x] = dv;
-    const double a = double(lp[x]) + double(dv);
-    if (a > p.m) {
-      p.s = p.s * exp(p.m - a) + 1.0;
-      p.m = a;
-    } else {
-      p.s += exp(a - p.m);
-    }
-    p.dmax = fmax(p.dmax, double(dv));
-    const double px = exp(double(lp[x]));
-    p.i += px * double(dv);
-    if (use_hd) {
-      const double ddv = g.hd[(size_t)b * g.xs + x] - double(gd[(size_t)b * g.xs + x]);
-      p.id += px * ddv;
-    }
+    const double l = double(lp[x]);
+    const double px = exp_in(l, T());
+    const double pdd = use_hd ? px * (g.hd[(size_t)b * g.xs + x] - double(gd[(size_t)b * g.xs + x])) : 0.0;
+    part_add<T>(p, l + double(dv), double(dv), px, pdd);
   }
   p = block_reduce(p);
-  if (threadIdx.x == 0) store_part(g.part + (size_t)b * g.ps + (size_t)blockIdx.x * kPartStride, p);
+  store_block_part(g.part + (size_t)b * g.ps, blockIdx.x, p);
 }
 
-// log p <- max(log p + D - L, M' - floor),  p <- e^{log p - M'}, M' = max(log p + D) - L.
+// Final record of every instance from its nblk block records (one block per instance).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_update(Group<T> g, int nblk, double floor, int check_tol) {
+__global__ __launch_bounds__(kBlock) void k_final_parts(Group<T> g, int nblk) {
+  const int b = blockIdx.x;
+  if (g.st[b].converged) return;
+  double* part = g.part + (size_t)b * g.ps;
+  const Part P = gather_parts(part, nblk);
+  if (threadIdx.x == 0) store_part(part + kFinalRec, P);
+}
+
+// log p <- max(log p + D - L, M' - floor),  p <- e^{log p - M'}, M' = max(log p + D) - L,
+// from the final record of the D kernel.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_update(Group<T> g, int nblk, double floor, int check_tol, int sym) {
   const int b = blockIdx.y;
   State* st = g.st + b;
   if (st->converged) return;
-  const Part P = gather_parts(g.part + (size_t)b * g.ps, nblk);
+  const Part P = load_part(g.part + (size_t)b * g.ps + kFinalRec);
   const double L = P.m + log(P.s);
   const double U = P.dmax;
   const double Mn = P.m - L;
@@ -207,11 +141,55 @@ __global__ __launch_bounds__(kBlock) void k_update(Group<T> g, int nblk, double 
   T* p = g.p + (size_t)b * g.xs;
   const T* D = g.D + (size_t)b * g.xs;
   const T lo = T(Mn - floor);
-  for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < X; x += gridDim.x * blockDim.x) {
+  // sym: D holds the inputs x < 2^(n-1) only; their complements get the same values
+  const uint32_t count = sym ? X / 2u : X;
+  for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < count; x += gridDim.x * blockDim.x) {
     T nl = lp[x] + D[x] - T(L);
     nl = nl > lo ? nl : lo;
+    const T px = exp_t<T>(nl - T(Mn));
     lp[x] = nl;
-    p[x] = exp_t<T>(nl - T(Mn));
+    p[x] = px;
+    if (sym) {
+      lp[X - 1u - x] = nl;
+      p[X - 1u - x] = px;
+    }
+  }
+}
+
+// Largest |log p(x) - log p(cpl x)| of every instance (one block per instance).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_sym_check(Group<T> g, double* out) {
+  const int b = blockIdx.x;
+  const uint32_t X = 1u << g.n;
+  const T* lp = g.lp + (size_t)b * g.xs;
+  double m = 0.0;
+  for (uint32_t x = threadIdx.x; x < X / 2u; x += blockDim.x) {
+    const double dv = fabs(double(lp[x]) - double(lp[X - 1u - x]));
+    m = (dv > m || dv != dv) ? dv : m;  // NaN propagates
+  }
+  __shared__ double sm[kBlock];
+  sm[threadIdx.x] = m;
+  __syncthreads();
+  for (int off = kBlock / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) {
+      const double o = sm[threadIdx.x + off];
+      if (o > sm[threadIdx.x] || o != o) sm[threadIdx.x] = o;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[b] = sm[0];
+}
+
+// Copy the half x < 2^(n-1) onto the complements (log p and p).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_symmetrize(Group<T> g) {
+  const int b = blockIdx.y;
+  const uint32_t X = 1u << g.n;
+  T* lp = g.lp + (size_t)b * g.xs;
+  T* p = g.p + (size_t)b * g.xs;
+  for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < X / 2u; x += gridDim.x * blockDim.x) {
+    lp[X - 1u - x] = lp[x];
+    p[X - 1u - x] = p[x];
   }
 }
 
@@ -391,6 +369,11 @@ __global__ void k_fill_zero(uint4* p, size_t n16) {
     p[i] = make_uint4(0u, 0u, 0u, 0u);
 }
 
+__global__ void k_to_float(const double* src, float* dst, size_t count) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = float(src[i]);
+}
+
 __global__ void k_copy_f64(double* dst, const double* src, size_t count) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
     dst[i] = src[i];
@@ -428,17 +411,35 @@ hipError_t launch_dpart(const Group<T>& g, int nblk, int use_hd, const T* gd, hi
 }
 
 template <typename T>
-hipError_t launch_update(const Group<T>& g, int nblk, double floor, int check_tol, hipStream_t s) {
-  hipLaunchKernelGGL(k_update<T>, dim3(nblk, g.nb), dim3(kBlock), 0, s, g, nblk, floor, check_tol);
+hipError_t launch_final_parts(const Group<T>& g, int nblk, hipStream_t s) {
+  hipLaunchKernelGGL(k_final_parts<T>, dim3(g.nb), dim3(kBlock), 0, s, g, nblk);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_update(const Group<T>& g, int nblk, double floor, int check_tol, int sym, hipStream_t s) {
+  hipLaunchKernelGGL(k_update<T>, dim3(nblk, g.nb), dim3(kBlock), 0, s, g, nblk, floor, check_tol, sym);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_sym_check(const Group<T>& g, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sym_check<T>, dim3(g.nb), dim3(kBlock), 0, s, g, out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_symmetrize(const Group<T>& g, hipStream_t s) {
+  hipLaunchKernelGGL(k_symmetrize<T>, dim3(grid_for(1u << (g.n - 1)), g.nb), dim3(kBlock), 0, s, g);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_cert_prepare(const Group<T>& src, const Group<double>& dst, int nblk, double floor,
                                hipStream_t s) {
-  // partials live in the destination group's partial buffer: A at +0, B at +ps/2
+  // partials live in the destination group's record buffer: A at +0, B after the first set
   double* partA = dst.part;
-  double* partB = dst.part + dst.ps / 2;
+  double* partB = dst.part + size_t(kMaxRedBlocks) * kPartStride;
   hipLaunchKernelGGL(k_lse_a<T>, dim3(nblk, src.nb), dim3(kBlock), 0, s, src.lp, src.xs, src.n, partA, dst.ps);
   hipLaunchKernelGGL(k_lse_b<T>, dim3(nblk, src.nb), dim3(kBlock), 0, s, src.lp, src.xs, src.n, partA, partB,
                      dst.ps, nblk, floor);
@@ -472,7 +473,7 @@ hipError_t launch_get_logp(const Group<T>& g, double* dst, hipStream_t s) {
 template <typename T>
 hipError_t launch_set_logp(const Group<T>& g, const double* src, int nblk, double floor, hipStream_t s) {
   double* partA = g.part;
-  double* partB = g.part + g.ps / 2;
+  double* partB = g.part + size_t(kMaxRedBlocks) * kPartStride;
   const size_t X = size_t(1) << g.n;
   hipLaunchKernelGGL(k_lse_a<double>, dim3(nblk, g.nb), dim3(kBlock), 0, s, src, X, g.n, partA, g.ps);
   hipLaunchKernelGGL(k_lse_b<double>, dim3(nblk, g.nb), dim3(kBlock), 0, s, src, X, g.n, partA, partB, g.ps,
@@ -495,6 +496,11 @@ hipError_t launch_fill_zero(void* ptr, size_t bytes, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_to_float(const double* src, float* dst, size_t count, hipStream_t s) {
+  hipLaunchKernelGGL(k_to_float, dim3(grid_for(count)), dim3(kBlock), 0, s, src, dst, count);
+  return hipGetLastError();
+}
+
 hipError_t launch_copy_f64(double* dst, const double* src, size_t count, hipStream_t s) {
   hipLaunchKernelGGL(k_copy_f64, dim3(grid_for(count)), dim3(kBlock), 0, s, dst, src, count);
   return hipGetLastError();
@@ -503,7 +509,10 @@ hipError_t launch_copy_f64(double* dst, const double* src, size_t count, hipStre
 #define BA_INST(T)                                                                               \
   template hipError_t launch_logr<T>(const Group<T>&, int, int, int, int, hipStream_t);          \
   template hipError_t launch_dpart<T>(const Group<T>&, int, int, const T*, hipStream_t);         \
-  template hipError_t launch_update<T>(const Group<T>&, int, double, int, hipStream_t);          \
+  template hipError_t launch_update<T>(const Group<T>&, int, double, int, int, hipStream_t);     \
+  template hipError_t launch_sym_check<T>(const Group<T>&, double*, hipStream_t);               \
+  template hipError_t launch_symmetrize<T>(const Group<T>&, hipStream_t);                       \
+  template hipError_t launch_final_parts<T>(const Group<T>&, int, hipStream_t);                 \
   template hipError_t launch_cert_prepare<T>(const Group<T>&, const Group<double>&, int, double, \
                                              hipStream_t);                                       \
   template hipError_t launch_get_logp<T>(const Group<T>&, double*, hipStream_t);                \

@@ -1,0 +1,162 @@
+"""GPU: complement-symmetric iteration (Appendix A, Theorem 4).
+
+From the uniform law every BA iterate satisfies p(cpl x) = p(x), so the factored
+products can be evaluated on the canonical half.  The symmetric mode must give the
+iterates and bounds of the full kernels (FP64: within 1e-12; FP32: same rounding
+class) and of the oracle's BA, and refuse laws that are not complement-symmetric.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import bdc_inputs as inp
+from oracle import bdc
+
+pytestmark = pytest.mark.gpu
+LN2 = math.log(2.0)
+
+
+@pytest.fixture(scope="module")
+def ba():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2604_05867_amd as m
+    m.lib()
+    return m
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def run_pair(ba, ns, ds, prec, iters, exact_k=None):
+    """(logp, bounds) after `iters` iterations with the full and the symmetric kernels."""
+    out = []
+    for sym in (False, True):
+        if exact_k is not None:
+            c = ba.Context(ns, None, prec=prec, k=exact_k)
+        else:
+            c = ba.Context(ns, ds, prec=prec)
+        if sym:
+            c.set_symmetry(True)
+        c.step(iters)
+        lo, hi = c.bounds()
+        out.append((c.get_logp().cpu().numpy(), np.array(lo), np.array(hi)))
+        c.close()
+    return out
+
+
+@pytest.mark.parametrize("n", [4, 6, 8, 10, 12, 16])
+def test_symmetric_fp64_equals_full(ba, n):
+    say("symmetric fp64 n=%d" % n)
+    (lp_f, lo_f, hi_f), (lp_s, lo_s, hi_s) = run_pair(ba, n, 0.7, ba.PREC_FP64, 30)
+    assert np.max(np.abs(lp_f - lp_s)) < 1e-12
+    assert np.max(np.abs(lo_f - lo_s)) < 1e-12 and np.max(np.abs(hi_f - hi_s)) < 1e-12
+    # the symmetric iterate is exactly invariant under complement
+    assert np.array_equal(lp_s, lp_s[::-1])
+
+
+@pytest.mark.parametrize("n", [8, 14])
+def test_symmetric_fp64_matches_oracle(ba, n):
+    """Against the oracle's dense or sparse BA from the uniform law (Section 2.3)."""
+    d, iters = 0.6, 12
+    if n <= 8:
+        W = bdc.channel_dense(n, d)
+        lp_o = bdc.ba_iterate(W, bdc.uniform_logp(n), iters)
+        L_o, U_o = bdc.certify(W, lp_o)
+    else:
+        import oracle.native as on
+        csr = on.CSR(n)
+        lp_o = bdc.uniform_logp(n)
+        for _ in range(iters):
+            D, L, U, I, _ = csr.evaluate(d, lp_o, floor_nats=700.0)
+            lp_o = bdc.floor_logp(bdc.normalise_logp(lp_o) + D - L, 700.0)
+        _, L, U, _, _ = csr.evaluate(d, lp_o, floor_nats=700.0)
+        L_o, U_o = L / LN2, U / LN2
+    c = ba.Context(n, d)
+    c.set_symmetry(True)
+    c.step(iters)
+    lp = c.get_logp().cpu().numpy()
+    lo, hi = c.bounds()
+    c.close()
+    assert np.max(np.abs(lp - lp_o)) < 1e-10
+    assert abs(lo[0] - L_o) < 1e-10 and abs(hi[0] - U_o) < 1e-10
+
+
+def test_symmetric_fp32_batch_mixed_n(ba):
+    """A batch with odd n (full kernels) and even n (symmetric kernels), FP32
+    iterates: same iterates as the full kernels up to FP32 rounding, certified
+    bounds within 1e-6 bits."""
+    ns = [7, 8, 10, 12, 10]
+    ds = [0.64, 0.7, 0.8, 0.9, 0.96]
+    (lp_f, lo_f, hi_f), (lp_s, lo_s, hi_s) = run_pair(ba, ns, ds, ba.PREC_FP32_LOG, 200)
+    assert np.max(np.abs(lp_f - lp_s)) < 1e-2
+    assert np.max(np.abs(lo_f - lo_s)) < 1e-6 and np.max(np.abs(hi_f - hi_s)) < 1e-6
+
+
+def test_symmetric_exact_channel(ba):
+    """Exact channels BDC_{n,k} are complement-invariant too (Section 2.2)."""
+    (lp_f, lo_f, hi_f), (lp_s, lo_s, hi_s) = run_pair(ba, [10, 12], None, ba.PREC_FP64, 25, exact_k=[5, 4])
+    assert np.max(np.abs(lp_f - lp_s)) < 1e-12
+    assert np.max(np.abs(lo_f - lo_s)) < 1e-12 and np.max(np.abs(hi_f - hi_s)) < 1e-12
+
+
+def test_symmetric_n20_fp32(ba):
+    """The benchmark shape: n = 20, three instances, FP32 iterates."""
+    ds = [0.64, 0.8, 0.95]
+    (lp_f, lo_f, hi_f), (lp_s, lo_s, hi_s) = run_pair(ba, [20] * 3, ds, ba.PREC_FP32_LOG, 6)
+    assert np.max(np.abs(lp_f - lp_s)) < 1e-4
+    assert np.max(np.abs(lo_f - lo_s)) < 1e-7 and np.max(np.abs(hi_f - hi_s)) < 1e-7
+    X = 1 << 20
+    for b in range(3):
+        seg = lp_s[b * X:(b + 1) * X]
+        assert np.array_equal(seg, seg[::-1])
+
+
+def test_symmetric_rejects_asymmetric_law(ba):
+    n = 10
+    c = ba.Context(n, 0.7)
+    lp = inp.random_logp(n, seed=5, spread=2.0)
+    c.set_logp(torch.from_numpy(lp))
+    with pytest.raises(ba.BAError) as e:
+        c.set_symmetry(True)
+    assert e.value.code == ba.BA_EINVAL
+    # a complement-symmetric law is accepted and iterates like the full kernels
+    sym = 0.5 * (lp + lp[::-1])
+    c.set_logp(torch.from_numpy(np.ascontiguousarray(sym)))
+    c.set_symmetry(True)
+    c.step(10)
+    lp_s = c.get_logp().cpu().numpy()
+    # setting an asymmetric law while the mode is on switches it off with an error
+    with pytest.raises(ba.BAError):
+        c.set_logp(torch.from_numpy(lp))
+    c.close()
+    f = ba.Context(n, 0.7)
+    f.set_logp(torch.from_numpy(np.ascontiguousarray(sym)))
+    f.step(10)
+    assert np.max(np.abs(f.get_logp().cpu().numpy() - lp_s)) < 1e-12
+    f.close()
+
+
+def test_symmetric_graph_replay(ba):
+    """ba_run's captured graph with the symmetric kernels equals eager launches."""
+    s = torch.cuda.Stream()
+    c = ba.Context([8, 10], [0.6, 0.9], prec=ba.PREC_FP32_LOG, cert_every=20, stream=s)
+    c.set_symmetry(True)
+    start = torch.zeros((1 << 8) + (1 << 10), dtype=torch.float64)
+    out = []
+    for graphs in (False, True):
+        c.set_graphs(graphs)
+        with torch.cuda.stream(s):
+            c.set_logp(start)
+            done = c.run(1e-7, 300)
+            lo, hi, its = c.best_bounds()
+            lp = c.get_logp().cpu().numpy()
+        s.synchronize()
+        out.append((done, lo, hi, its, lp))
+    c.close()
+    assert out[0][0] == out[1][0] and out[0][3] == out[1][3]
+    assert out[0][1] == out[1][1] and out[0][2] == out[1][2]
+    assert np.array_equal(out[0][4], out[1][4])
