@@ -194,6 +194,39 @@ def config3(cap, gap_bits, plain_limit_s, plain_graphs=False):
     print(json.dumps(out))
 
 
+def step_compare(cap, gap_bits, etas):
+    """Iterations and time to a certified gap with the update step eta (1 = BA) on a
+    batch of slow instances (FP32 iterates, one graph-replayed context per eta)."""
+    import torch
+
+    import paper_2604_05867_amd as ba
+
+    ns, ds = [], []
+    for n in (10, 12, 14, 16):
+        for d in (0.64, 0.80, 0.96):
+            ns.append(n)
+            ds.append(d)
+    res = {}
+    for eta in etas:
+        s = torch.cuda.Stream()
+        ctx = ba.Context(ns, ds, prec=ba.PREC_FP32_LOG, engine=ba.ENGINE_FACTORED, cert_every=50, stream=s)
+        ctx.set_graphs(True)
+        ctx.set_stop_rule(ba.STOP_BEST)
+        ctx.set_step(eta)
+        with torch.cuda.stream(s):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            run_segments(ctx, gap_bits, cap, 25000, "step %.2f" % eta)
+            s.synchronize()
+            el = time.perf_counter() - t0
+            lo, hi, its = ctx.best_bounds()
+        ctx.close()
+        res[str(eta)] = {"seconds": el, "iters": its, "gap_bits": [h - l for l, h in zip(lo, hi)],
+                         "lower_bits": lo, "converged": int(sum(1 for l, h in zip(lo, hi) if h - l < gap_bits))}
+    print(json.dumps({"metric": "iterations to a certified gap vs update step", "gap_bits": gap_bits, "cap": cap,
+                      "instances": [{"n": n, "d": d} for n, d in zip(ns, ds)], "results": res}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -207,6 +240,8 @@ def main():
     ap.add_argument("--cap", type=int, default=200000)
     ap.add_argument("--gap", type=float, default=1e-6)
     ap.add_argument("--plain-limit-s", type=float, default=600.0)
+    ap.add_argument("--step-compare", action="store_true",
+                    help="iterations to the gap for update steps 1, 1.5, 2 (several minutes)")
     ap.add_argument("--plain-graphs", action="store_true",
                     help="config3: replay the plain FP64 runs as graphs too")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -223,6 +258,9 @@ def main():
         return
     if args.config3:
         config3(args.cap, args.gap, args.plain_limit_s, args.plain_graphs)
+        return
+    if args.step_compare:
+        step_compare(args.cap, args.gap, (1.0, 1.5, 2.0))
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the BA instances of this workload fit one MI355X "

@@ -68,10 +68,16 @@ enum {
  *  BA_ENGINE_FACTORED: the same two products evaluated position by position: the
  *                      deletion channel acts on each input bit independently, so
  *                      W^T p and W v factor into n sparse stages of width
- *                      2^(n+1); the nonzeros are never enumerated. */
+ *                      2^(n+1); the nonzeros are never enumerated.
+ *  BA_ENGINE_PULL:     q = W^T p in pull form (Section 5): every output y sums
+ *                      over its length-n supersequences, enumerated by
+ *                      Algorithms 5-6, with an embedding-count DP per pair; no
+ *                      atomics and a fixed summation order (deterministic).  W v
+ *                      as in BA_ENGINE_STREAM. */
 enum {
   BA_ENGINE_STREAM = 0,
-  BA_ENGINE_FACTORED = 1
+  BA_ENGINE_FACTORED = 1,
+  BA_ENGINE_PULL = 2
 };
 
 /* ---- lifetime --------------------------------------------------------------- */
@@ -127,6 +133,15 @@ int ba_set_stop_rule(ba_ctx *c, int rule);
  * check after setting the law and switches the mode off (BA_EINVAL) if it fails.
  * enable = 0 switches back to the full kernels.  Off by default. */
 int ba_set_symmetry(ba_ctx *c, int enable);
+
+/* Update step of the iterations (ba_step, ba_run): log p <- log p + eta D - log
+ * sum_x p e^{eta D}, i.e. p <- p e^{eta D} / Z, entropic mirror ascent on I(p) with
+ * step eta; eta = 1 (default) is the BA update of Section 2.3 exactly.  The
+ * reported and certified bounds L = log sum p e^D <= C <= max D stay valid for any
+ * iterate; eta > 1 is not monotone in I and can oscillate for large eta (eta = 2
+ * roughly halves the iterations the lower bound needs on the cases measured;
+ * eta = 3 oscillated at n = 10, d = 0.67).  0 < eta <= 8, else BA_EINVAL. */
+int ba_set_step(ba_ctx *c, double eta);
 
 /* Run ba_run's iteration chunks as one captured HIP graph (replayed until the
  * stopping rule holds) instead of individual launches.  Needs a non-null bound

@@ -308,6 +308,80 @@ def mirror_ascent(n: int, d: float, theta: np.ndarray, eta: float, steps: int,
 
 
 # ---------------------------------------------------------------------------
+# Supersequence enumeration (Section 5): the pull form of step 1 of Section 2.3,
+# r(y) = sum over the length-n supersequences x of y of p(x) emb(y, x).
+# ---------------------------------------------------------------------------
+
+def binom_le(n: int, t: int) -> int:
+    """sum_{j <= t} C(n, j), 0 for t < 0 (Section 5.1's notation)."""
+    return sum(math.comb(n, j) for j in range(0, t + 1)) if t >= 0 else 0
+
+
+def subset_unrank(n: int, w: int, j: int) -> list[int]:
+    """Algorithm 5 (Section 5.1): the j-th w-subset of {0..n-1}.  Scanning t = 0, 1, ...
+    the subsets that contain t (C(n-t-1, w-1) of them, the rest chosen after t) come
+    before those that do not."""
+    assert 0 <= j < math.comb(n, w)
+    out = []
+    for t in range(n):
+        if w == 0:
+            break
+        c = math.comb(n - t - 1, w - 1)
+        if j < c:
+            out.append(t)
+            w -= 1
+        else:
+            j -= c
+    return out
+
+
+def supersequence(i: int, n: int, y: list[int], fixed: bool = True) -> int:
+    """Algorithm 6 (Section 5.2): the i-th length-n supersequence of y, as an input
+    index.  S (from Algorithm 5) holds the positions not used by the leftmost
+    embedding of y: before y is complete they get the complement of the next symbol
+    of y, the other positions copy y in order.  After y is complete, positions in S
+    get 1 - y_{k-1}; the printed algorithm sets the positions outside S to 0, which
+    is not one-to-one when y ends in 1 (both choices give 0).  We read it as setting
+    them to y_{k-1}, so S is recoverable from the tail (fixed=True; fixed=False is
+    the printed rule).  For the empty y (k = 0) the positions in S are 1, the
+    others 0."""
+    k = len(y)
+    w = 0
+    while not (binom_le(n, w - 1) <= i < binom_le(n, w)):
+        w += 1
+    assert w <= n - k
+    S = set(subset_unrank(n, w, i - binom_le(n, w - 1)))
+    last = y[k - 1] if k > 0 else 0
+    x, r = [], 0
+    for pos in range(n):
+        if pos in S:
+            x.append(1 - y[r] if r < k else 1 - last)
+        elif r < k:
+            x.append(y[r])
+            r += 1
+        else:
+            x.append(last if fixed else 0)
+    return sum(b << (n - 1 - q) for q, b in enumerate(x))
+
+
+def supersequence_count(n: int, k: int) -> int:
+    """Lemma 7 (Section 5): a length-k string has sum_{i <= n-k} C(n, i) length-n
+    supersequences."""
+    return binom_le(n, n - k)
+
+
+def r_pull(n: int, lp: np.ndarray, y_bits: int, k: int) -> float:
+    """r(y) = sum_x p(x) emb(y, x) with p = exp(lp), summed over the supersequences
+    of y enumerated by Algorithm 6 (Section 5)."""
+    y = [(y_bits >> (k - 1 - q)) & 1 for q in range(k)]
+    tot = 0.0
+    for i in range(supersequence_count(n, k)):
+        x = supersequence(i, n, y)
+        tot += math.exp(lp[x]) * emb_brute(y, string_bits(x, n))
+    return tot
+
+
+# ---------------------------------------------------------------------------
 # Closed forms of the output law for special inputs.
 # ---------------------------------------------------------------------------
 

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(HERE, "libba.so")
 
 BA_OK, BA_EINVAL, BA_ENOMEM, BA_EDEVICE, BA_ESTATE, BA_ENUMERIC = 0, -1, -2, -3, -4, -5
 PREC_FP64, PREC_FP32_LOG = 0, 1
-ENGINE_STREAM, ENGINE_FACTORED = 0, 1
+ENGINE_STREAM, ENGINE_FACTORED, ENGINE_PULL = 0, 1, 2
 KCLASS = ("sweep1", "logr", "sweep2", "reduce", "update")
 TUNE_SCATTER_LDS_KB = 0
 TUNE_FACTORED_FUSE = 1
@@ -78,6 +78,7 @@ def lib():
     L.ba_set_tuning.argtypes = [vp, i32, i32]
     L.ba_set_stop_rule.argtypes = [vp, i32]
     L.ba_set_symmetry.argtypes = [vp, i32]
+    L.ba_set_step.argtypes = [vp, ctypes.c_double]
     _lib = L
     return L
 
@@ -164,6 +165,10 @@ class Context:
         """Complement-symmetric iteration (iterates invariant under bitwise
         complement, as from the uniform start); see ba_set_symmetry."""
         self._check(lib().ba_set_symmetry(self._h, 1 if enable else 0), "ba_set_symmetry")
+
+    def set_step(self, eta: float):
+        """Update step eta of the iterations (1 = BA; see ba_set_step)."""
+        self._check(lib().ba_set_step(self._h, float(eta)), "ba_set_step")
 
     def set_tuning(self, key: int, value: int):
         self._check(lib().ba_set_tuning(self._h, key, value), "ba_set_tuning")

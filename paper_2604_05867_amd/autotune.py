@@ -38,6 +38,8 @@ def tune(ctx: Context, iters: int = 3, cache_path: str | None = None, force: boo
     Returns {"key", "choice": (knob, value), "ms_per_iter": {value: ms}}.  The
     timing runs ``iters`` iterations per candidate on the context itself and then
     restores the starting iterate."""
+    if ctx.engine not in CANDIDATES:
+        return {"key": None, "choice": None, "ms_per_iter": {}}
     key = _key(ctx.n, ctx.prec, ctx.engine)
     cache = {}
     if cache_path and os.path.exists(cache_path):

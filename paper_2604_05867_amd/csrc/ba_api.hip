@@ -30,6 +30,7 @@ struct GroupLayout {
   size_t lp, p, r, v, v2, g, gd, D, f0, f1;     // iteration arrays (precision T)
   size_t h, hd, hf, part, st, cs;
   size_t c_lp, c_p, c_r, c_v, c_v2, c_g, c_gd, c_D, c_f0, c_f1, c_part, c_st;  // FP64 cert
+  size_t pull;                                  // pull-sweep partials (FP64-sized)
 };
 
 struct GroupHost {
@@ -70,6 +71,7 @@ struct ba_ctx {
   int fuse = 1;  // factored engine: two positions per launch
   int stop_rule = BA_STOP_ITERATE;
   int sym = 0;   // complement-symmetric iteration requested
+  double eta = 1.0;  // update step (1 = BA)
   // graph replay of ba_run chunks
   bool use_graph = false;
   hipGraphExec_t gexec = nullptr;
@@ -183,6 +185,7 @@ void plan(ba_ctx* c) {
     L.c_f1 = take(nb * g.fs * 8);
     L.c_part = take(nb * g.ps * 8);
     L.c_st = take(nb * sizeof(State));
+    L.pull = take(pull_partial_bytes(n, int(nb), 8));
   }
   // verify bins for instance 0's n (also the dense row buffer)
   const int n0 = c->n[0];
@@ -223,6 +226,7 @@ Group<T> make_group(char* ws, const GroupHost& g, bool cert) {
   G.part = reinterpret_cast<double*>(ws + (cert ? L.c_part : L.part));
   G.st = reinterpret_cast<State*>(ws + (cert ? L.c_st : L.st));
   G.cs = reinterpret_cast<const Consts*>(ws + L.cs);
+  G.eta = 1.0;
   return G;
 }
 
@@ -289,7 +293,23 @@ int sweeps(ba_ctx* c, const GroupHost& gh, const Group<T>& G, int use_sw_g, T* g
   hipStream_t s = c->stream;
   const int n = gh.n, n1 = (n + 1) / 2, n2 = n / 2;
   const StreamExtra ex{};
-  if (c->engine == BA_ENGINE_STREAM) {
+  if (c->engine == BA_ENGINE_PULL) {
+    {
+      Timer t(c, BA_K_SWEEP1, 2 * ((G.nb + kTile - 1) / kTile));
+      HIPCHK(c, launch_pull<T>(G, reinterpret_cast<T*>(c->ws + gh.L.pull), s));
+    }
+    {
+      Timer t(c, BA_K_LOGR, 1);
+      HIPCHK(c, launch_logr<T>(G, use_sw_g, 1, n1, n2, s));
+    }
+    {
+      Timer t(c, BA_K_SWEEP2, 1);
+      Group<T> G2 = G;
+      G2.g = g_out;
+      HIPCHK(c, launch_fill_zero(g_out, size_t(G.nb) * G.xs * sizeof(T), s));
+      HIPCHK(c, launch_stream<T>(kOpGather, gh.tb, G2, 0, ex, s));
+    }
+  } else if (c->engine == BA_ENGINE_STREAM) {
     const int nbt = G.nb < kTile ? G.nb : kTile;
     const size_t budget = std::min<size_t>(size_t(c->scatter_lds_kb) * 1024, size_t(stream_lds_limit()));
     const int k0 = k0_for(n, nbt, sizeof(T), budget);
@@ -343,7 +363,9 @@ int sweeps(ba_ctx* c, const GroupHost& gh, const Group<T>& G, int use_sw_g, T* g
 }
 
 template <typename T>
-int iterate_group(ba_ctx* c, const GroupHost& gh, const Group<T>& G) {
+int iterate_group(ba_ctx* c, const GroupHost& gh, const Group<T>& G0) {
+  Group<T> G = G0;
+  G.eta = c->eta;
   int nblk = 0;  // block records written by the fused D launch, if any
   int rc = sweeps<T>(c, gh, G, 0, G.g, 1, &nblk);
   if (rc) return rc;
@@ -465,7 +487,8 @@ int ba_init_exact(int count, const int* n, const int* k, int prec, int cert_ever
 }
 
 int ba_set_engine(ba_ctx* c, int engine) {
-  if (!c || (engine != BA_ENGINE_STREAM && engine != BA_ENGINE_FACTORED)) return BA_EINVAL;
+  if (!c || (engine != BA_ENGINE_STREAM && engine != BA_ENGINE_FACTORED && engine != BA_ENGINE_PULL))
+    return BA_EINVAL;
   if (engine != c->engine) drop_graph(c);
   c->engine = engine;
   return BA_OK;
@@ -719,8 +742,9 @@ int ba_grad(ba_ctx* c, const double* theta_dev, double* I_bits, double* dI_dthet
   {
     Group<double> Gd = cert;
     Gd.g = cert.gd;
-    HIPCHK(c, launch_logr<double>(cert, 1, c->engine == BA_ENGINE_STREAM, n1, n2, s));
-    if (c->engine == BA_ENGINE_STREAM) {
+    const bool split = c->engine != BA_ENGINE_FACTORED;  // stream gather for W v
+    HIPCHK(c, launch_logr<double>(cert, 1, split, n1, n2, s));
+    if (split) {
       const StreamExtra ex{};
       HIPCHK(c, launch_fill_zero(cert.gd, cert.xs * sizeof(double), s));
       HIPCHK(c, launch_stream<double>(kOpGather, gh.tb, Gd, 0, ex, s));
@@ -832,6 +856,14 @@ int ba_set_logp(ba_ctx* c, const double* logp_dev) {
     drop_graph(c);
     return rc;
   }
+  return BA_OK;
+}
+
+int ba_set_step(ba_ctx* c, double eta) {
+  if (!c) return BA_EINVAL;
+  if (!(eta > 0.0 && eta <= 8.0)) return fail(c, BA_EINVAL, "step must be in (0, 8]");
+  c->eta = eta;
+  drop_graph(c);
   return BA_OK;
 }
 

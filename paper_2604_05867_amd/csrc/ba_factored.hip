@@ -166,7 +166,8 @@ __device__ __forceinline__ void d_epilogue(const Group<T>& g, int b, double M, u
   for (int k = 0; k < V; ++k) {
     d.v[k] = h.v[k] - G.v[k] - T(M);
     const double lk = double(l.v[k]);
-    part_add<T>(p, lk + double(d.v[k]), double(d.v[k]), exp_in(lk, T()), 0.0, wt);
+    part_add<T>(p, lk + double(d.v[k]), double(d.v[k]), exp_in(lk, T()), 0.0, wt, g.eta != 1.0,
+                lk + g.eta * double(d.v[k]));
   }
   stv<T, V>(g.D + (size_t)b * g.xs + x, d);
 }

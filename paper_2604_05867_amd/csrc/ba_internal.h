@@ -123,6 +123,7 @@ struct Group {
   size_t ps;
   State* st;          // [nb]
   const Consts* cs;   // [nb]
+  double eta;         // update step: log p <- log p + eta D - log sum p e^{eta D} (1 = BA)
 };
 
 enum StreamOp { kOpScatter = 0, kOpGather = 1, kOpInit = 2, kOpRow = 3, kOpVerify = 4 };
@@ -152,6 +153,13 @@ hipError_t launch_combine_r(const Group<T>& g, int n1, int n2, int k0, hipStream
 int stream_lds_limit();  // largest dynamic LDS a block may request on this device
 hipError_t launch_row_compact(const uint32_t* dense, int n, uint32_t* rank_out,
                               uint32_t* emb_out, int cap, uint32_t* nnz_dev, hipStream_t s);
+
+// ba_pull.hip: r in pull form over the supersequences of every output (Section 5),
+// through a partial buffer of pull_partial_bytes (written, then summed per output
+// in a fixed order).
+size_t pull_partial_bytes(int n, int nb, size_t esz);
+template <typename T>
+hipError_t launch_pull(const Group<T>& g, T* partial, hipStream_t s);
 
 // ba_factored.hip: the two products stage by stage.
 // fuse = 1: two positions per launch (k_fwd_stage2 / k_bwd_stage2).

@@ -1,7 +1,7 @@
 // Device-side reduction records of one BA iteration (Section 2.3): for the
 // current iterate, U = max_x D(x), L = log sum_x p(x) e^{D(x)} (online
-// log-sum-exp of a = log p + D), I = sum_x p(x) D(x) and, for the derivative in
-// d, sum_x p(x) Dd(x).  A kernel accumulates one record per thread, reduces it
+// log-sum-exp of a = log p + D), I = sum_x p(x) D(x), for the derivative in d
+// sum_x p(x) Dd(x), and for a step eta != 1 the normaliser log sum_x p e^{eta D}.  A kernel accumulates one record per thread, reduces it
 // per block and stores one record per block; a one-block-per-instance kernel
 // combines them into the final record that the update kernel reads.  Included by
 // the .hip sources only.
@@ -19,9 +19,13 @@ struct Part {
   double dmax;  // max D
   double i;     // sum p D
   double id;    // sum p Dd
+  double m2;    // max of a2 = log p + eta D (step eta != 1 only)
+  double s2;    // sum exp(a2 - m2)
 };
 
-__device__ __forceinline__ Part part_empty() { return Part{-INFINITY, 0.0, -INFINITY, 0.0, 0.0}; }
+__device__ __forceinline__ Part part_empty() {
+  return Part{-INFINITY, 0.0, -INFINITY, 0.0, 0.0, -INFINITY, 0.0};
+}
 
 __device__ __forceinline__ double lse_merge_s(double m1, double s1, double m2, double s2, double m) {
   double r = 0.0;
@@ -37,6 +41,8 @@ __device__ __forceinline__ Part combine(const Part& a, const Part& b) {
   c.dmax = fmax(a.dmax, b.dmax);
   c.i = a.i + b.i;
   c.id = a.id + b.id;
+  c.m2 = fmax(a.m2, b.m2);
+  c.s2 = (c.m2 == -INFINITY) ? 0.0 : lse_merge_s(a.m2, a.s2, b.m2, b.s2, c.m2);
   return c;
 }
 
@@ -47,14 +53,29 @@ __device__ __forceinline__ double exp_in(double v, float) { return double(expf(f
 // exponential of the running log-sum-exp is taken in precision E (the iterate's).
 // wt: the number of inputs this value stands for (2 when only one of each
 // complement pair x, cpl(x) is evaluated).
-template <typename E>
-__device__ __forceinline__ void part_add(Part& p, double a, double dv, double px, double pdd, double wt = 1.0) {
-  if (a > p.m) {
-    p.s = p.s * exp_in(p.m - a, E()) + wt;
-    p.m = a;
+__device__ __forceinline__ void lse_add(double& m, double& s, double a, double wt, double) {
+  if (a > m) {
+    s = s * exp(m - a) + wt;
+    m = a;
   } else {
-    p.s += wt * exp_in(a - p.m, E());
+    s += wt * exp(a - m);
   }
+}
+__device__ __forceinline__ void lse_add(double& m, double& s, double a, double wt, float) {
+  if (a > m) {
+    s = s * double(expf(float(m - a))) + wt;
+    m = a;
+  } else {
+    s += wt * double(expf(float(a - m)));
+  }
+}
+
+// a = log p + D, a2 = log p + eta D (used when eta != 1).
+template <typename E>
+__device__ __forceinline__ void part_add(Part& p, double a, double dv, double px, double pdd, double wt = 1.0,
+                                         bool step = false, double a2 = 0.0) {
+  lse_add(p.m, p.s, a, wt, E());
+  if (step) lse_add(p.m2, p.s2, a2, wt, E());
   p.dmax = fmax(p.dmax, dv);
   p.i += wt * px * dv;
   p.id += wt * pdd;
@@ -77,7 +98,18 @@ __device__ __forceinline__ Part wave_reduce(Part p) {
     i += __shfl_xor(i, off);
     id += __shfl_xor(id, off);
   }
-  return Part{m, s, dmax, i, id};
+  // second log-sum-exp only where some lane has one (eta != 1)
+  double m2 = p.m2, s2 = 0.0;
+  if (__any(p.s2 != 0.0)) {
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) m2 = fmax(m2, __shfl_xor(m2, off));
+    s2 = (p.s2 != 0.0) ? p.s2 * exp(p.m2 - m2) : 0.0;
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) s2 += __shfl_xor(s2, off);
+  } else {
+    m2 = -INFINITY;
+  }
+  return Part{m, s, dmax, i, id, m2, s2};
 }
 
 // Block reduction (blockDim.x == kBlock); the result is valid in every thread.
@@ -94,11 +126,13 @@ __device__ __forceinline__ Part block_reduce(Part p) {
 }
 
 __device__ __forceinline__ void store_part(double* dst, const Part& p) {
-  dst[0] = p.m; dst[1] = p.s; dst[2] = p.dmax; dst[3] = p.i; dst[4] = p.id;
+  dst[0] = p.m; dst[1] = p.s; dst[2] = p.dmax; dst[3] = p.i; dst[4] = p.id; dst[5] = p.m2; dst[6] = p.s2;
 }
 
 // A record written by an earlier kernel on the stream.
-__device__ __forceinline__ Part load_part(const double* q) { return Part{q[0], q[1], q[2], q[3], q[4]}; }
+__device__ __forceinline__ Part load_part(const double* q) {
+  return Part{q[0], q[1], q[2], q[3], q[4], q[5], q[6]};
+}
 
 // Combine the nblk records at src (every block that calls this does it in full).
 __device__ __forceinline__ Part gather_parts(const double* src, int nblk) {

@@ -87,7 +87,7 @@ __global__ __launch_bounds__(kBlock) void k_dpart(Group<T> g, int nblk, int use_
     const double l = double(lp[x]);
     const double px = exp_in(l, T());
     const double pdd = use_hd ? px * (g.hd[(size_t)b * g.xs + x] - double(gd[(size_t)b * g.xs + x])) : 0.0;
-    part_add<T>(p, l + double(dv), double(dv), px, pdd);
+    part_add<T>(p, l + double(dv), double(dv), px, pdd, 1.0, g.eta != 1.0, l + g.eta * double(dv));
   }
   p = block_reduce(p);
   store_block_part(g.part + (size_t)b * g.ps, blockIdx.x, p);
@@ -104,7 +104,8 @@ __global__ __launch_bounds__(kBlock) void k_final_parts(Group<T> g, int nblk) {
 }
 
 // log p <- max(log p + D - L, M' - floor),  p <- e^{log p - M'}, M' = max(log p + D) - L,
-// from the final record of the D kernel.
+// from the final record of the D kernel (with a step eta != 1: log p + eta D minus
+// its log-sum-exp, entropic mirror ascent on the iterate).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_update(Group<T> g, int nblk, double floor, int check_tol, int sym) {
   const int b = blockIdx.y;
@@ -113,8 +114,11 @@ __global__ __launch_bounds__(kBlock) void k_update(Group<T> g, int nblk, double 
   const Part P = load_part(g.part + (size_t)b * g.ps + kFinalRec);
   const double L = P.m + log(P.s);
   const double U = P.dmax;
-  const double Mn = P.m - L;
-  const bool finite = isfinite(L) && isfinite(U) && isfinite(P.i);
+  // normaliser of the step: L itself for eta = 1 (BA)
+  const bool step = g.eta != 1.0;
+  const double Le = step ? P.m2 + log(P.s2) : L;
+  const double Mn = (step ? P.m2 : P.m) - Le;
+  const bool finite = isfinite(L) && isfinite(U) && isfinite(P.i) && isfinite(Le);
   // FP64 iterates (check_tol): these are the exact bounds of the current iterate,
   // so they also update the best bounds; FP32 iterates leave that to certification.
   const double bL = (check_tol && finite) ? fmax(st->bestL, L) : st->bestL;
@@ -144,7 +148,7 @@ __global__ __launch_bounds__(kBlock) void k_update(Group<T> g, int nblk, double 
   // sym: D holds the inputs x < 2^(n-1) only; their complements get the same values
   const uint32_t count = sym ? X / 2u : X;
   for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < count; x += gridDim.x * blockDim.x) {
-    T nl = lp[x] + D[x] - T(L);
+    T nl = step ? lp[x] + T(g.eta) * D[x] - T(Le) : lp[x] + D[x] - T(L);
     nl = nl > lo ? nl : lo;
     const T px = exp_t<T>(nl - T(Mn));
     lp[x] = nl;

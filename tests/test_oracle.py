@@ -476,3 +476,56 @@ def test_sample_sweeps_match_dense(oracle_native):
     ev = bdc.evaluate(W, lp)
     assert np.allclose(D, ev.D[xs], atol=1e-12)
     assert tot == int((W[xs] > 0).sum())
+
+
+# ---------------------------------------------------------------------------
+# supersequence enumeration (Section 5)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 5, 7])
+def test_subset_unrank_lists_every_subset_once_in_order(n):
+    """Algorithm 5: j -> the j-th w-subset is a bijection onto the w-subsets, and
+    the order puts subsets containing the smaller element first (lexicographic
+    order of the characteristic vectors, largest first)."""
+    for w in range(n + 1):
+        subs = [tuple(bdc.subset_unrank(n, w, j)) for j in range(math.comb(n, w))]
+        assert len(set(subs)) == math.comb(n, w)
+        assert all(len(s) == w and all(0 <= t < n for t in s) for s in subs)
+        vec = [sum(1 << (n - 1 - t) for t in s) for s in subs]
+        assert vec == sorted(vec, reverse=True)
+
+
+@pytest.mark.parametrize("n", [1, 2, 4, 6, 8])
+def test_supersequence_enumeration_is_a_bijection(n):
+    """Algorithm 6 (with the tail read as y_{k-1}) and Lemma 7: for every y the
+    indices 0 .. sum_{i<=n-k} C(n,i)-1 map one-to-one onto the supersequences,
+    found by brute force."""
+    for k in range(n + 1):
+        assert bdc.supersequence_count(n, k) == sum(math.comb(n, i) for i in range(n - k + 1))
+        for yb in range(1 << k):
+            y = [(yb >> (k - 1 - q)) & 1 for q in range(k)]
+            xs = [bdc.supersequence(i, n, y) for i in range(bdc.supersequence_count(n, k))]
+            sup = [x for x in range(1 << n) if bdc.emb_brute(y, bdc.string_bits(x, n)) > 0]
+            assert sorted(xs) == sup, (n, yb, k)
+
+
+def test_printed_supersequence_rule_is_not_one_to_one():
+    """The printed tail rule (0 outside S) repeats supersequences exactly when y
+    ends in 1 and S has positions after the embedding; n = 3, y = 1 is one case."""
+    y = [1]
+    xs = [bdc.supersequence(i, 3, y, fixed=False) for i in range(bdc.supersequence_count(3, 1))]
+    assert len(set(xs)) < len(xs)
+    y0 = [0]
+    xs0 = [bdc.supersequence(i, 3, y0, fixed=False) for i in range(bdc.supersequence_count(3, 1))]
+    assert len(set(xs0)) == len(xs0)
+
+
+@pytest.mark.parametrize("n", [3, 6])
+def test_pull_sum_matches_push(n):
+    """r(y) summed over supersequences equals column y of E^T p (dense)."""
+    lp = inp.random_logp(n, seed=70 + n, spread=2.0)
+    E = bdc.emb_dense(n)
+    r = np.exp(lp) @ E
+    for R in range((2 << n) - 1):
+        yb, k = bdc.unrank(R)
+        assert abs(bdc.r_pull(n, lp, yb, k) - r[R]) <= 1e-12 * max(1.0, abs(r[R]))
