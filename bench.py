@@ -340,6 +340,20 @@ def main():
                                   "ms_per_step": es / args.stream_steps * 1e3,
                                   "kernel_ms_per_step": {k: round(v[0], 3) for k, v in kts.items()}}
         cs.close()
+    if not args.no_stream and args.stream_steps > 0:
+        # sweep 1 in pull form (supersequence enumeration), sweep 2 as the stream engine
+        print("bench: pull engine", file=sys.stderr, flush=True)
+        cp = ba.Context([N] * nb, DS, prec=ba.PREC_FP32_LOG, engine=ba.ENGINE_PULL, device=dev)
+        cp.step(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cp.step(1)
+        torch.cuda.synchronize()
+        ep = time.perf_counter() - t0
+        ktp = cp.time_kernels(1)
+        extra["pull_engine"] = {"value": nnz * nb / ep, "unit": "W-nonzero terms/s", "ms_per_step": ep * 1e3,
+                                "kernel_ms_per_step": {k: round(v[0], 3) for k, v in ktp.items()}}
+        cp.close()
     print("bench: fp64 plain", file=sys.stderr, flush=True)
     c64 = ba.Context(N, 0.80, prec=ba.PREC_FP64, engine=ba.ENGINE_FACTORED, device=dev)
     c64.step(2)
