@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 
 N = 20
 DS = [0.64, 0.80, 0.95]
+FUSE = 2  # the library default: four positions per launch of the factored engine
 
 
 # HBM bytes per forward-sweep launch of this workload, from rocprofv3 FETCH_SIZE and
@@ -36,18 +37,22 @@ DS = [0.64, 0.80, 0.95]
 # measured on (summary: profiles/k_fwd_stage2_n20_fp32_x3.md).
 MEASURED_TRAFFIC = {
     "source": "paper_2604_05867_amd/csrc/ba_factored.hip",
-    "sha256": "1ead7816b7aef463e659cbe339f79d3634a673b2caede31240394438e37d3b72",
-    "bytes_per_launch": int((9 * 24314.2 + 33997.8) / 10 * 2.0 * 1024 + (9 * 24211.0 + 24959.9) / 10 * 1024),
+    "sha256": None,   # no PMC figures taken on the current kernels yet
+    "sweep1": None,
+    "sweep2": None,
 }
 
 
-def measured_traffic():
-    """The PMC traffic figure if the kernel source is unchanged since it was taken."""
+def measured_traffic(sweep):
+    """The PMC traffic figure of a sweep if the kernel source is unchanged since it
+    was taken, else None."""
     import hashlib
+    if MEASURED_TRAFFIC["sha256"] is None:
+        return None
     with open(os.path.join(ROOT, MEASURED_TRAFFIC["source"]), "rb") as f:
         if hashlib.sha256(f.read()).hexdigest() != MEASURED_TRAFFIC["sha256"]:
             return None
-    return MEASURED_TRAFFIC["bytes_per_launch"]
+    return MEASURED_TRAFFIC[sweep]
 
 
 def stage_sizes(n):
@@ -55,16 +60,33 @@ def stage_sizes(n):
     return [((2 << i) - 1) << (n - i) for i in range(n + 1)]
 
 
-def factored_launch_bytes(n, esz, nb, fuse=True):
-    """Algorithmic HBM bytes of each launch of one sweep (forward or backward):
-    a launch covering positions i..i+t-1 reads its source array (stage i) once and
-    writes its destination (stage i+t) once.  Two positions per launch when fused."""
+def sweep_launch_bytes(n, esz, nb, fuse, backward):
+    """Algorithmic HBM bytes of each launch of one sweep of the factored engine, in
+    launch order: a launch covering positions i..i+t-1 reads its source stage once
+    and writes its destination stage once; the last backward launch also reads
+    H and log p (D is formed there).  Launch sequence as in the library: fuse 2 =
+    four positions per launch (forward: the last 1-4 positions two at a time;
+    backward: the first n mod 4 positions two or one at a time), fuse 1 = two."""
     s = stage_sizes(n)
-    out, i = [], 0
-    while i < n:
-        t = 2 if (fuse and i + 2 <= n) else 1
-        out.append((s[i] + s[i + t]) * esz * nb)
-        i += t
+    steps = []
+    if not backward:
+        i = 0
+        while i < n:
+            t = 4 if (fuse == 2 and i + 4 < n) else (2 if (fuse and i + 2 <= n) else 1)
+            steps.append((i, i + t))
+            i += t
+    else:
+        top, lead = n, (n % 4 if (fuse == 2 and n >= 4) else -1)
+        while top > 0:
+            if lead >= 0 and n - top >= lead:
+                t = 4
+            else:
+                t = 2 if (fuse and top >= 2 and not (lead >= 0 and n - top + 2 > lead)) else 1
+            steps.append((top, top - t))
+            top -= t
+    out = [(s[a] + s[b]) * esz * nb for a, b in steps]
+    if backward:
+        out[-1] += 2 * (1 << n) * esz * nb
     return out
 
 
@@ -293,13 +315,15 @@ def main():
     dom = max(("sweep1", "sweep2"), key=lambda k: kt[k][0])
     dom_ms, dom_launches = kt[dom]
     per_launch_ms = dom_ms / max(dom_launches, 1)
-    per_launch = factored_launch_bytes(N, 4, nb)
+    per_launch = sweep_launch_bytes(N, 4, nb, FUSE, backward=(dom == "sweep2"))
+    assert len(per_launch) == dom_launches // args.steps, (len(per_launch), dom_launches)
     bytes_launch = sum(per_launch) / len(per_launch)
     achieved = bytes_launch / (per_launch_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
                 "frac": round(achieved / 8000.0, 4),
-                "traffic": measured_traffic() if dom == "sweep1" else None,
-                "kernel": "forward sweep (k_fwd_stage2)" if dom == "sweep1" else "backward sweep (k_bwd_stage2)",
+                "traffic": measured_traffic(dom),
+                "kernel": ("forward sweep (k_fwd_stage4 x4, k_fwd_stage2, k_fwd_stage2_w1)" if dom == "sweep1"
+                           else "backward sweep (k_bwd_stage4 x5, D fused into the last)"),
                 "bytes_per_launch": int(bytes_launch), "avg_launch_us": round(per_launch_ms * 1e3, 2)}
 
     lo, hi = ctx.bounds()

@@ -124,8 +124,8 @@ int ba_set_stop_rule(ba_ctx *c, int rule);
  * complement).  enable = 1: the iterations of the factored engine evaluate only
  * the inputs x < 2^(n-1) and the stage entries whose first column bit is 0, reading
  * the other half from the complement (about half the memory traffic; same results
- * up to rounding).  Applies to groups with even n >= 4 and two positions per launch
- * (BA_TUNE_FACTORED_FUSE = 1); other groups, the stream engine, certification,
+ * up to rounding).  Applies to groups with even n >= 4 and BA_TUNE_FACTORED_FUSE
+ * >= 1 (its kernels take two positions per launch); other groups, the stream engine, certification,
  * ba_eval and ba_grad run the full kernels.  Enabling it on a bound context checks
  * that every iterate is invariant under complement (max |log p(x) - log p(cpl x)|
  * <= 1e-9 nats for FP64, 1e-4 for FP32 iterates) and then makes it exactly so;
@@ -156,8 +156,9 @@ int ba_set_graphs(ba_ctx *c, int enable);
  *  before going to device memory.  Capped by the device's per-block limit. */
 enum {
   BA_TUNE_SCATTER_LDS_KB = 0,
-  /* BA_TUNE_FACTORED_FUSE: 1 (default) evaluates two input positions per launch of
-   * the factored engine, 0 one position per launch. */
+  /* BA_TUNE_FACTORED_FUSE: positions per launch of the factored engine: 2 (default)
+   * four (the forward's last 1-4 positions and the backward's first n mod 4 two or
+   * one at a time), 1 two, 0 one. */
   BA_TUNE_FACTORED_FUSE = 1
 };
 int ba_set_tuning(ba_ctx *c, int key, int value);

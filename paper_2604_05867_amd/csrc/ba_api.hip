@@ -68,7 +68,7 @@ struct ba_ctx {
   std::string err;
   // tuning
   int scatter_lds_kb = 64;
-  int fuse = 1;  // factored engine: two positions per launch
+  int fuse = 2;  // factored engine: four positions per launch (1: two, 0: one)
   int stop_rule = BA_STOP_ITERATE;
   int sym = 0;   // complement-symmetric iteration requested
   double eta = 1.0;  // update step (1 = BA)
@@ -333,19 +333,19 @@ int sweeps(ba_ctx* c, const GroupHost& gh, const Group<T>& G, int use_sw_g, T* g
     }
   } else if (tail && !use_sw_g && sym_active(c, n)) {
     {
-      Timer t(c, BA_K_SWEEP1, factored_launches(n, 1));
-      HIPCHK(c, launch_forward_sym<T>(G, s, nullptr));
+      Timer t(c, BA_K_SWEEP1, forward_launches(n, c->fuse));
+      HIPCHK(c, launch_forward_sym<T>(G, s, nullptr, c->fuse));
     }
     {
-      Timer t(c, BA_K_SWEEP2, factored_launches(n, 1));
+      Timer t(c, BA_K_SWEEP2, backward_launches(n, c->fuse));
       Group<T> G2 = G;
       G2.g = g_out;
-      HIPCHK(c, launch_backward_sym<T>(G2, s, nullptr, tail_done));
+      HIPCHK(c, launch_backward_sym<T>(G2, s, nullptr, tail_done, c->fuse));
     }
   } else {
     const int fuse_tail = (tail && !use_sw_g) ? 1 : 0;
     {
-      Timer t(c, BA_K_SWEEP1, factored_launches(n, c->fuse));
+      Timer t(c, BA_K_SWEEP1, forward_launches(n, c->fuse));
       HIPCHK(c, launch_forward<T>(G, s, nullptr, c->fuse, fuse_tail));
     }
     if (!fuse_tail) {
@@ -353,7 +353,7 @@ int sweeps(ba_ctx* c, const GroupHost& gh, const Group<T>& G, int use_sw_g, T* g
       HIPCHK(c, launch_logr<T>(G, use_sw_g, 0, n1, n2, s));
     }
     {
-      Timer t(c, BA_K_SWEEP2, factored_launches(n, c->fuse));
+      Timer t(c, BA_K_SWEEP2, backward_launches(n, c->fuse));
       Group<T> G2 = G;
       G2.g = g_out;
       HIPCHK(c, launch_backward<T>(G2, s, nullptr, c->fuse, fuse_tail, tail_done));
@@ -503,7 +503,7 @@ int ba_set_tuning(ba_ctx* c, int key, int value) {
     return BA_OK;
   }
   if (key == BA_TUNE_FACTORED_FUSE) {
-    if (value != 0 && value != 1) return fail(c, BA_EINVAL, "fuse must be 0 or 1");
+    if (value < 0 || value > 2) return fail(c, BA_EINVAL, "fuse must be 0, 1 or 2");
     c->fuse = value;
     drop_graph(c);
     return BA_OK;

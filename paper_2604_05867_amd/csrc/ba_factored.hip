@@ -213,6 +213,152 @@ __global__ __launch_bounds__(kBlock) void k_fwd_stage(int n, int i, const T* __r
   }
 }
 
+
+// Four forward stages at once (positions i .. i+3).  One thread per (source row y
+// of F_i, column s of the output width S4): it loads F_i of y and of its 4
+// ancestors P_1..P_4 (16 column groups u s each; absent rows are zero) and runs
+// the single stage
+//   F_{k+1}[z][g] = F_k[z][0g] + F_k[z][1g] (if z is a row of F_k) + F_k[parent z][last(z) g]
+// in registers on the rows that reach the outputs: the path P_0 = y .. P_{4-k} and,
+// when y has length i (a leaf of F_i), its subtree down to depth k.  It writes the
+// output row y and, for a leaf, the 30 rows below it (all rows of F_{i+4} of
+// length >= i are below exactly one leaf).  LOGV: last stage, write v = w_k log r.
+// Register part of the four-position forward step for one (y, column): F0 holds
+// F_i of the path P_0 = y .. P_3 (16 groups) and H4 the half of P_4 selected by
+// last(P_3); lastb[j] = last bit of P_j.  Returns F_{i+4}[y] and, in F4, the 30
+// rows below y (breadth-first: depth d, index m at (1 << d) - 2 + m).
+template <typename T>
+__device__ __forceinline__ T fwd4_registers(const T (&F0)[4][16], const T (&H4)[8], const uint32_t (&lastb)[4],
+                                            T (&F4)[30]) {
+  // stage 1: path P_0..P_3 (8 groups), children of y (parent halves chosen by
+  // select, so every register index is static)
+  T F1p[4][8], F1s[2][8];
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int g = 0; g < 8; ++g)
+      F1p[j][g] = (F0[j][g] + F0[j][8 + g]) + (lastb[j] ? F0[j + 1][8 + g] : F0[j + 1][g]);
+#pragma unroll
+  for (int g = 0; g < 8; ++g) F1p[3][g] = (F0[3][g] + F0[3][8 + g]) + H4[g];
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int g = 0; g < 8; ++g) F1s[c][g] = F0[0][c * 8 + g];
+  // stage 2: path P_0..P_2 (4 groups), subtree depth 1..2 (breadth-first 0..5)
+  T F2p[3][4], F2s[6][4];
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+      F2p[j][g] = (F1p[j][g] + F1p[j][4 + g]) + (lastb[j] ? F1p[j + 1][4 + g] : F1p[j + 1][g]);
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int g = 0; g < 4; ++g) F2s[c][g] = (F1s[c][g] + F1s[c][4 + g]) + F1p[0][c * 4 + g];
+#pragma unroll
+  for (int c = 0; c < 4; ++c)  // depth 2: child c/2 of y, then bit c&1
+#pragma unroll
+    for (int g = 0; g < 4; ++g) F2s[2 + c][g] = F1s[c >> 1][(c & 1) * 4 + g];
+  // stage 3: path P_0..P_1 (2 groups), subtree depth 1..3 (breadth-first 0..13)
+  T F3p[2][2], F3s[14][2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j)
+#pragma unroll
+    for (int g = 0; g < 2; ++g)
+      F3p[j][g] = (F2p[j][g] + F2p[j][2 + g]) + (lastb[j] ? F2p[j + 1][2 + g] : F2p[j + 1][g]);
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int g = 0; g < 2; ++g) F3s[c][g] = (F2s[c][g] + F2s[c][2 + g]) + F2p[0][c * 2 + g];
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int g = 0; g < 2; ++g) F3s[2 + c][g] = (F2s[2 + c][g] + F2s[2 + c][2 + g]) + F2s[c >> 1][(c & 1) * 2 + g];
+#pragma unroll
+  for (int c = 0; c < 8; ++c)
+#pragma unroll
+    for (int g = 0; g < 2; ++g) F3s[6 + c][g] = F2s[2 + (c >> 1)][(c & 1) * 2 + g];
+  // stage 4: y (1 group), subtree depth 1..4
+#pragma unroll
+  for (int c = 0; c < 2; ++c) F4[c] = (F3s[c][0] + F3s[c][1]) + F3p[0][c];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) F4[2 + c] = (F3s[2 + c][0] + F3s[2 + c][1]) + F3s[c >> 1][c & 1];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) F4[6 + c] = (F3s[6 + c][0] + F3s[6 + c][1]) + F3s[2 + (c >> 1)][c & 1];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) F4[14 + c] = F3s[6 + (c >> 1)][c & 1];
+  return (F3p[0][0] + F3p[0][1]) + (lastb[0] ? F3p[1][1] : F3p[1][0]);
+}
+
+// Path ranks of y and their last bits: P_{j+1} = parent(P_j) (garbage past the
+// empty row; such rows are never loaded).
+__device__ __forceinline__ void fwd4_path(uint32_t y, uint32_t (&P)[5], uint32_t (&lastb)[4]) {
+  P[0] = y;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    lastb[j] = (P[j] - 1u) & 1u;
+    P[j + 1] = (P[j] - 1u) >> 1;
+  }
+}
+
+// Four forward stages at once (positions i .. i+3).  One thread per (source row y
+// of F_i, column s of the output width S4): it loads F_i of y and of its 4
+// ancestors P_1..P_4 (16 column groups u s each; absent rows are zero) and runs
+// the single stage
+//   F_{k+1}[z][g] = F_k[z][0g] + F_k[z][1g] (if z is a row of F_k) + F_k[parent z][last(z) g]
+// in registers on the rows that reach the outputs: the path P_0 = y .. P_{4-k} and,
+// when y has length i (a leaf of F_i), its subtree down to depth k.  It writes the
+// output row y and, for a leaf, the 30 rows below it (all rows of F_{i+4} of
+// length >= i are below exactly one leaf).  LOGV: last stage, write v = w_k log r.
+template <typename T, bool LOGV>
+__global__ __launch_bounds__(kBlock) void k_fwd_stage4(int n, int i, const T* __restrict__ src, size_t sstride,
+                                                       T* __restrict__ dst, size_t dstride, const State* st,
+                                                       const Consts* cs, Order o) {
+  const int b = blockIdx.y;
+  if (st[b].converged) return;
+  uint32_t y, s;
+  if (!order_slot(o, y, s)) return;
+  src += (size_t)b * sstride;
+  dst += (size_t)b * dstride;
+  const int sh = n - i - 4;                  // log2 of the output width S4
+  const int ly = length_of_rank(y);
+  uint32_t P[5], lastb[4];
+  fwd4_path(y, P, lastb);
+  T F0[4][16], H4[8];
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int u = 0; u < 16; ++u) F0[j][u] = T(0);
+#pragma unroll
+  for (int u = 0; u < 8; ++u) H4[u] = T(0);
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    if (j <= ly) {
+      const T* row = src + ((size_t)P[j] << (sh + 4)) + s;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) F0[j][u] = row[uint32_t(u) << sh];
+    }
+  if (4 <= ly) {
+    const T* row = src + ((size_t)P[4] << (sh + 4)) + (lastb[3] << (sh + 3)) + s;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) H4[u] = row[uint32_t(u) << sh];
+  }
+  T F4[30];
+  T vy = fwd4_registers<T>(F0, H4, lastb, F4);
+  if constexpr (LOGV) vy = log_weighted<T>(cs[b], y, vy);
+  dst[((size_t)y << sh) + s] = vy;
+  if (ly != i) return;
+#pragma unroll
+  for (int d = 1; d <= 4; ++d)
+#pragma unroll
+    for (int m = 0; m < (1 << d); ++m) {
+      const uint32_t rk = ((y + 1u) << d) - 1u + uint32_t(m);
+      T v = F4[(1 << d) - 2 + m];
+      if constexpr (LOGV) v = log_weighted<T>(cs[b], rk, v);
+      dst[((size_t)rk << sh) + s] = v;
+    }
+}
+
 // One backward stage; each thread produces V consecutive columns of one row
 // (V divides the source row width S = 2^(n-i-1)).  DP: stage 0, write D and the
 // reduction records instead of G.
@@ -401,6 +547,90 @@ __global__ __launch_bounds__(kBlock) void k_bwd_stage2(int n, int i, const T* __
       stv<T, V>(op + S, o01);
       stv<T, V>(op + 2 * S, o10);
       stv<T, V>(op + 3 * S, o11);
+    }
+  }
+  if constexpr (DP) {
+    p = block_reduce(p);
+    store_block_part(g.part + (size_t)b * g.ps, blockIdx.x, p);
+  }
+}
+
+
+// Four backward stages at once (positions i .. i+3): for a row y of B_i and
+// columns (u, s), u = 4 bits,
+//   B_i[y][u s] = sum over the subsets K of the 4 positions of B_{i+4}[y u_K][s]
+// (u_K = the bits of u at the kept positions).  One thread per (y, column s):
+// it loads the 31 rows of y's depth-4 subtree (breadth-first index t, children
+// 2t+1 and 2t+2, the same as ranks) and applies the 4 single stages
+// B_k[z][b g] = B_{k+1}[z][g] + B_{k+1}[z b][g] in registers.  DP: stage 0 (one
+// row), write D and the reduction records instead of G.
+template <typename T, bool DP>
+__global__ __launch_bounds__(kBlock) void k_bwd_stage4(int n, int i, const T* __restrict__ src, size_t sstride,
+                                                       T* __restrict__ dst, size_t dstride, Group<T> g, Order o) {
+  const int b = blockIdx.y;
+  if (g.st[b].converged) return;
+  uint32_t y, s;
+  const bool valid = order_slot(o, y, s);
+  if (!DP && !valid) return;
+  src += (size_t)b * sstride;
+  dst += (size_t)b * dstride;
+  const int sh = n - i - 4;                  // log2 of the source width S4
+  Part p = part_empty();
+  if (valid) {
+    T S[31];
+#pragma unroll
+    for (int d = 0; d <= 4; ++d)
+#pragma unroll
+      for (int m = 0; m < (1 << d); ++m)
+        S[(1 << d) - 1 + m] = src[((((y + 1u) << d) - 1u + uint32_t(m)) << sh) + s];
+    T A[15][2];
+#pragma unroll
+    for (int t = 0; t < 15; ++t) {
+      A[t][0] = S[t] + S[2 * t + 1];
+      A[t][1] = S[t] + S[2 * t + 2];
+    }
+    T B[7][4];
+#pragma unroll
+    for (int t = 0; t < 7; ++t)
+#pragma unroll
+      for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) B[t][bb * 2 + q] = A[t][q] + A[2 * t + 1 + bb][q];
+    T C[3][8];
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+#pragma unroll
+      for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) C[t][bb * 4 + q] = B[t][q] + B[2 * t + 1 + bb][q];
+    T Dv[16];
+#pragma unroll
+    for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) Dv[bb * 8 + q] = C[0][q] + C[1 + bb][q];
+    const uint32_t S4 = 1u << sh;
+    if constexpr (DP) {
+      const double M = g.st[b].M;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        Vec<T, 1> gv;
+        gv.v[0] = Dv[u];
+        d_epilogue<T, 1>(g, b, M, uint32_t(u) * S4 + s, gv, p);
+      }
+    } else {
+      T* op = dst + (y << (sh + 4)) + s;
+      if (sh == 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          Vec<T, 4> w;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) w.v[k] = Dv[4 * q + k];
+          stv<T, 4>(op + 4 * q, w);
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) op[uint32_t(u) * S4] = Dv[u];
+      }
     }
   }
   if constexpr (DP) {
@@ -661,6 +891,150 @@ __global__ __launch_bounds__(kBlock) void k_bwd_stage2_sym(int n, int i, const T
   }
 }
 
+
+// Four forward stages, canonical half: as k_fwd_stage4 for the output columns
+// s < S4/2 (stride S4/2), with F_i stored as its groups u < 8 (first bit 0, stride
+// 8 S4); group u >= 8 of row z is group 15 - u of cpl z at column S4 - 1 - s.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fwd_stage4_sym(int n, int i, const T* __restrict__ src,
+                                                           size_t sstride, T* __restrict__ dst, size_t dstride,
+                                                           const State* st, Order o) {
+  const int b = blockIdx.y;
+  if (st[b].converged) return;
+  uint32_t y, s;
+  if (!order_slot(o, y, s)) return;
+  src += (size_t)b * sstride;
+  dst += (size_t)b * dstride;
+  const int sh = n - i - 4;                  // log2 of the full output width S4 (>= 1)
+  const uint32_t S4 = 1u << sh, sm = S4 - 1u - s;
+  const int ly = length_of_rank(y);
+  uint32_t P[5], lastb[4];
+  fwd4_path(y, P, lastb);
+  T F0[4][16], H4[8];
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int u = 0; u < 16; ++u) F0[j][u] = T(0);
+#pragma unroll
+  for (int u = 0; u < 8; ++u) H4[u] = T(0);
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    if (j <= ly) {
+      const T* row = src + ((size_t)P[j] << (sh + 3));
+      const T* rowm = src + ((size_t)mirror_rank(P[j]) << (sh + 3));
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        F0[j][u] = row[(uint32_t(u) << sh) + s];
+        F0[j][8 + u] = rowm[(uint32_t(7 - u) << sh) + sm];
+      }
+    }
+  if (4 <= ly) {
+    if (lastb[3]) {
+      const T* rowm = src + ((size_t)mirror_rank(P[4]) << (sh + 3));
+#pragma unroll
+      for (int u = 0; u < 8; ++u) H4[u] = rowm[(uint32_t(7 - u) << sh) + sm];
+    } else {
+      const T* row = src + ((size_t)P[4] << (sh + 3));
+#pragma unroll
+      for (int u = 0; u < 8; ++u) H4[u] = row[(uint32_t(u) << sh) + s];
+    }
+  }
+  T F4[30];
+  const T vy = fwd4_registers<T>(F0, H4, lastb, F4);
+  const int ho = sh - 1;                     // log2 of the stored output width
+  dst[((size_t)y << ho) + s] = vy;
+  if (ly != i) return;
+#pragma unroll
+  for (int d = 1; d <= 4; ++d)
+#pragma unroll
+    for (int m = 0; m < (1 << d); ++m) {
+      const uint32_t rk = ((y + 1u) << d) - 1u + uint32_t(m);
+      dst[((size_t)rk << ho) + s] = F4[(1 << d) - 2 + m];
+    }
+}
+
+// Four backward stages, canonical half: B_i[y][u s] for u < 8 (stride 8 S4) and
+// every s, from B_{i+4} stored as its columns s < S4/2 (stride S4/2), or, VC, from
+// the compact v (i + 4 = n).  A column in the upper half reads the subtree of
+// cpl y with complemented paths at the mirrored column.  DP: stage 0, D for
+// x < 2^(n-1) with weight 2.
+template <typename T, bool DP, bool VC>
+__global__ __launch_bounds__(kBlock) void k_bwd_stage4_sym(int n, int i, const T* __restrict__ src,
+                                                           size_t sstride, T* __restrict__ dst, size_t dstride,
+                                                           Group<T> g, Order o) {
+  const int b = blockIdx.y;
+  if (g.st[b].converged) return;
+  uint32_t y, s;
+  const bool valid = order_slot(o, y, s);
+  if (!DP && !valid) return;
+  src += (size_t)b * sstride;
+  dst += (size_t)b * dstride;
+  const int sh = n - i - 4;                  // log2 of the full source width S4
+  const uint32_t S4 = 1u << sh;
+  Part p = part_empty();
+  if (valid) {
+    T S[31];
+    if constexpr (VC) {
+#pragma unroll
+      for (int d = 0; d <= 4; ++d)
+#pragma unroll
+        for (int m = 0; m < (1 << d); ++m)
+          S[(1 << d) - 1 + m] = v_sym(src, ((y + 1u) << d) - 1u + uint32_t(m));
+    } else {
+      const bool up = s >= S4 / 2u;
+      const uint32_t yy = up ? mirror_rank(y) : y, col = up ? S4 - 1u - s : s;
+      const int hs = sh - 1;                 // log2 of the stored width
+#pragma unroll
+      for (int d = 0; d <= 4; ++d)
+#pragma unroll
+        for (int m = 0; m < (1 << d); ++m) {
+          const uint32_t mm = up ? (1u << d) - 1u - uint32_t(m) : uint32_t(m);
+          S[(1 << d) - 1 + m] = src[((((yy + 1u) << d) - 1u + mm) << hs) + col];
+        }
+    }
+    T A[15][2];
+#pragma unroll
+    for (int t = 0; t < 15; ++t) {
+      A[t][0] = S[t] + S[2 * t + 1];
+      A[t][1] = S[t] + S[2 * t + 2];
+    }
+    T B[7][4];
+#pragma unroll
+    for (int t = 0; t < 7; ++t)
+#pragma unroll
+      for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) B[t][bb * 2 + q] = A[t][q] + A[2 * t + 1 + bb][q];
+    T C[3][8];
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+#pragma unroll
+      for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) C[t][bb * 4 + q] = B[t][q] + B[2 * t + 1 + bb][q];
+    T Dv[8];  // first bit 0 only
+#pragma unroll
+    for (int q = 0; q < 8; ++q) Dv[q] = C[0][q] + C[1][q];
+    if constexpr (DP) {
+      const double M = g.st[b].M;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        Vec<T, 1> gv;
+        gv.v[0] = Dv[u];
+        d_epilogue<T, 1>(g, b, M, uint32_t(u) * S4 + s, gv, p, 2.0);
+      }
+    } else {
+      T* op = dst + (y << (sh + 3)) + s;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) op[uint32_t(u) * S4] = Dv[u];
+    }
+  }
+  if constexpr (DP) {
+    p = block_reduce(p);
+    store_block_part(g.part + (size_t)b * g.ps, blockIdx.x, p);
+  }
+}
+
 inline uint32_t grid_for(uint32_t total) {
   uint32_t g = (total + kBlock - 1) / kBlock;
   return g > 8192u ? 8192u : (g == 0 ? 1u : g);
@@ -685,6 +1059,27 @@ hipError_t launch_forward(const Group<T>& g, hipStream_t s, int* launches, int f
   size_t ss = g.xs;
   int k = 0;
   for (int i = 0; i < n; k++) {
+    // four positions per launch except the last four or fewer, whose outputs (one
+    // value per row) are written by the width-1 two-position kernel
+    if (fuse == 2 && i + 4 < n) {
+      const bool last = (i + 4 == n);
+      const bool lv = last && logv;
+      T* dst = last ? (lv ? g.v : g.r) : ((k & 1) ? g.f1 : g.f0);
+      const size_t ds = last ? g.ys : g.fs;
+      const uint32_t S4 = 1u << (n - i - 4);
+      const Order o = make_order(i + 1, ilog2(S4), sizeof(T));
+      const dim3 grid(blocks_for(order_threads(o)), g.nb);
+      if (lv)
+        hipLaunchKernelGGL((k_fwd_stage4<T, true>), grid, dim3(kBlock), 0, s, n, i, src, ss, dst, ds, g.st, g.cs, o);
+      else
+        hipLaunchKernelGGL((k_fwd_stage4<T, false>), grid, dim3(kBlock), 0, s, n, i, src, ss, dst, ds, g.st, g.cs,
+                           o);
+      if (launches) ++*launches;
+      src = dst;
+      ss = ds;
+      i += 4;
+      continue;
+    }
     const int step = (fuse && i + 2 <= n) ? 2 : 1;
     const bool last = (i + step == n);
     const bool lv = last && logv;
@@ -742,8 +1137,33 @@ hipError_t launch_backward(const Group<T>& g, hipStream_t s, int* launches, int 
   size_t ss = g.ys;
   int k = 0;
   if (dpart_blocks) *dpart_blocks = 0;
+  // fuse = 2: four positions per launch, the n mod 4 leftover positions first
+  const int lead = (fuse == 2 && n >= 4) ? n % 4 : -1;
   for (int top = n; top > 0; k++) {           // B_top -> B_{top-step}
-    const int step = (fuse && top >= 2) ? 2 : 1;
+    if (lead >= 0 && n - top >= lead) {
+      const int i = top - 4;
+      const bool last = (i == 0);
+      T* dst = last ? g.g : ((k & 1) ? g.f1 : g.f0);
+      const size_t ds = last ? g.xs : g.fs;
+      const uint32_t S4 = 1u << (n - i - 4);
+      const Order o = make_order(i + 1, ilog2(S4), sizeof(T));
+      const uint32_t nbk = blocks_for(order_threads(o));
+      const bool dp = last && dpart && nbk <= uint32_t(kMaxRedBlocks);
+      if (dp) {
+        hipLaunchKernelGGL((k_bwd_stage4<T, true>), dim3(nbk, g.nb), dim3(kBlock), 0, s, n, i, src, ss, dst, ds, g,
+                           o);
+        if (dpart_blocks) *dpart_blocks = int(nbk);
+      } else {
+        hipLaunchKernelGGL((k_bwd_stage4<T, false>), dim3(nbk, g.nb), dim3(kBlock), 0, s, n, i, src, ss, dst, ds,
+                           g, o);
+      }
+      if (launches) ++*launches;
+      src = dst;
+      ss = ds;
+      top = i;
+      continue;
+    }
+    const int step = (fuse && top >= 2 && !(lead >= 0 && n - top + 2 > lead)) ? 2 : 1;
     const int i = top - step;
     const bool last = (i == 0);
     T* dst;
@@ -808,13 +1228,24 @@ hipError_t launch_backward(const Group<T>& g, hipStream_t s, int* launches, int 
 bool symmetric_supported(int n, int fuse) { return fuse && n >= 4 && (n % 2) == 0; }
 
 template <typename T>
-hipError_t launch_forward_sym(const Group<T>& g, hipStream_t s, int* launches) {
+hipError_t launch_forward_sym(const Group<T>& g, hipStream_t s, int* launches, int fuse) {
   const int n = g.n;
   constexpr int V = 16 / sizeof(T);
   const T* src = g.p;
   size_t ss = g.xs;
   int k = 0;
-  for (int i = 0; i < n; i += 2, k++) {
+  int i0 = 0;
+  for (; fuse == 2 && i0 + 4 < n; i0 += 4, k++) {
+    T* dst = (k & 1) ? g.f1 : g.f0;
+    const uint32_t S4 = 1u << (n - i0 - 4);
+    const Order o = make_order(i0 + 1, ilog2(S4 / 2u), sizeof(T));
+    hipLaunchKernelGGL((k_fwd_stage4_sym<T>), dim3(blocks_for(order_threads(o)), g.nb), dim3(kBlock), 0, s, n, i0,
+                       src, ss, dst, g.fs, g.st, o);
+    if (launches) ++*launches;
+    src = dst;
+    ss = g.fs;
+  }
+  for (int i = i0; i < n; i += 2, k++) {
     const bool last = (i + 2 == n);
     T* dst = last ? g.v : ((k & 1) ? g.f1 : g.f0);
     const size_t ds = last ? g.ys : g.fs;
@@ -843,14 +1274,44 @@ hipError_t launch_forward_sym(const Group<T>& g, hipStream_t s, int* launches) {
 }
 
 template <typename T>
-hipError_t launch_backward_sym(const Group<T>& g, hipStream_t s, int* launches, int* dpart_blocks) {
+hipError_t launch_backward_sym(const Group<T>& g, hipStream_t s, int* launches, int* dpart_blocks, int fuse) {
   const int n = g.n;
   constexpr int V = 16 / sizeof(T);
   const T* src = g.v;
   size_t ss = g.ys;
   int k = 0;
   if (dpart_blocks) *dpart_blocks = 0;
-  for (int top = n; top > 0; top -= 2, k++) {
+  const int lead = (fuse == 2) ? n % 4 : -1;  // even n: 0 or 2
+  for (int top = n; top > 0; k++) {
+    if (lead >= 0 && n - top >= lead) {
+      const int i = top - 4;
+      const bool last = (i == 0), vc = (top == n);
+      T* dst = last ? g.g : ((k & 1) ? g.f1 : g.f0);
+      const size_t ds = last ? g.xs : g.fs;
+      const uint32_t S4 = 1u << (n - i - 4);
+      const Order o = make_order(i + 1, ilog2(S4), sizeof(T));
+      const uint32_t nbk = blocks_for(order_threads(o));
+      const dim3 grid(nbk, g.nb);
+      if (last) {
+        if (nbk > uint32_t(kMaxRedBlocks)) return hipErrorInvalidValue;
+        if (vc)
+          hipLaunchKernelGGL((k_bwd_stage4_sym<T, true, true>), grid, dim3(kBlock), 0, s, n, i, src, ss, dst, ds, g, o);
+        else
+          hipLaunchKernelGGL((k_bwd_stage4_sym<T, true, false>), grid, dim3(kBlock), 0, s, n, i, src, ss, dst, ds, g,
+                             o);
+        if (dpart_blocks) *dpart_blocks = int(nbk);
+      } else if (vc) {
+        hipLaunchKernelGGL((k_bwd_stage4_sym<T, false, true>), grid, dim3(kBlock), 0, s, n, i, src, ss, dst, ds, g, o);
+      } else {
+        hipLaunchKernelGGL((k_bwd_stage4_sym<T, false, false>), grid, dim3(kBlock), 0, s, n, i, src, ss, dst, ds, g,
+                           o);
+      }
+      if (launches) ++*launches;
+      src = dst;
+      ss = ds;
+      top = i;
+      continue;
+    }
     const int i = top - 2;
     const bool last = (i == 0);
     T* dst = last ? g.g : ((k & 1) ? g.f1 : g.f0);
@@ -880,19 +1341,33 @@ hipError_t launch_backward_sym(const Group<T>& g, hipStream_t s, int* launches, 
     if (launches) ++*launches;
     src = dst;
     ss = ds;
+    top = i;
   }
   return hipGetLastError();
 }
 
 int factored_launches(int n, int fuse) { return fuse ? (n + 1) / 2 : n; }
 
+int backward_launches(int n, int fuse) {
+  if (fuse == 2 && n >= 4) return n / 4 + (n % 4 + 1) / 2;
+  return factored_launches(n, fuse);
+}
+
+int forward_launches(int n, int fuse) {
+  if (fuse == 2 && n > 4) {
+    const int four = (n - 1) / 4;  // launches of four positions; the rest two at a time
+    return four + (n - 4 * four + 1) / 2;
+  }
+  return factored_launches(n, fuse);
+}
+
 template hipError_t launch_forward<float>(const Group<float>&, hipStream_t, int*, int, int);
 template hipError_t launch_forward<double>(const Group<double>&, hipStream_t, int*, int, int);
 template hipError_t launch_backward<float>(const Group<float>&, hipStream_t, int*, int, int, int*);
 template hipError_t launch_backward<double>(const Group<double>&, hipStream_t, int*, int, int, int*);
-template hipError_t launch_forward_sym<float>(const Group<float>&, hipStream_t, int*);
-template hipError_t launch_forward_sym<double>(const Group<double>&, hipStream_t, int*);
-template hipError_t launch_backward_sym<float>(const Group<float>&, hipStream_t, int*, int*);
-template hipError_t launch_backward_sym<double>(const Group<double>&, hipStream_t, int*, int*);
+template hipError_t launch_forward_sym<float>(const Group<float>&, hipStream_t, int*, int);
+template hipError_t launch_forward_sym<double>(const Group<double>&, hipStream_t, int*, int);
+template hipError_t launch_backward_sym<float>(const Group<float>&, hipStream_t, int*, int*, int);
+template hipError_t launch_backward_sym<double>(const Group<double>&, hipStream_t, int*, int*, int);
 
 }  // namespace ba

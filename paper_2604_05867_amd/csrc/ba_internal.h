@@ -162,7 +162,10 @@ template <typename T>
 hipError_t launch_pull(const Group<T>& g, T* partial, hipStream_t s);
 
 // ba_factored.hip: the two products stage by stage.
-// fuse = 1: two positions per launch (k_fwd_stage2 / k_bwd_stage2).
+// fuse = 1: two positions per launch (k_fwd_stage2 / k_bwd_stage2); fuse = 2: four
+// positions per launch (k_fwd_stage4 / k_bwd_stage4) with the leftover positions
+// two (or one) at a time: the last 1-4 in the forward, the first n mod 4 in the
+// backward.
 // logv = 1: the last forward launch writes v = w_k log r instead of r.
 // dpart = 1: the last backward launch also forms D = H - G - M and the block
 // records of k_dpart, writing D instead of G; *dpart_blocks returns the number of
@@ -173,16 +176,18 @@ hipError_t launch_forward(const Group<T>& g, hipStream_t s, int* launches, int f
 template <typename T>
 hipError_t launch_backward(const Group<T>& g, hipStream_t s, int* launches, int fuse, int dpart,
                            int* dpart_blocks);                                                   // v -> G
-int factored_launches(int n, int fuse);
+int factored_launches(int n, int fuse);   // forward launches (two positions each when fuse != 0)
+int backward_launches(int n, int fuse);   // fuse = 2: four positions per backward launch
+int forward_launches(int n, int fuse);    // fuse = 2: four positions per forward launch
 // Complement-symmetric iteration (iterate invariant under complement): the two
 // products on the canonical half, v and D fused as above; v is stored at compact
 // indices (2^n entries) and D, G for x < 2^(n-1).  Supported for even n >= 4 with
 // two positions per launch.
 bool symmetric_supported(int n, int fuse);
 template <typename T>
-hipError_t launch_forward_sym(const Group<T>& g, hipStream_t s, int* launches);
+hipError_t launch_forward_sym(const Group<T>& g, hipStream_t s, int* launches, int fuse);
 template <typename T>
-hipError_t launch_backward_sym(const Group<T>& g, hipStream_t s, int* launches, int* dpart_blocks);
+hipError_t launch_backward_sym(const Group<T>& g, hipStream_t s, int* launches, int* dpart_blocks, int fuse);
 
 // ba_reduce.hip
 template <typename T>

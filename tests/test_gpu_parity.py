@@ -368,22 +368,54 @@ def test_graph_needs_a_stream(ba):
     c.close()
 
 
-@pytest.mark.parametrize("n", [1, 2, 3, 7, 8, 13])
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6, 7, 8, 13, 16])
 def test_factored_fusion_settings_agree(ba, n):
-    """One and two input positions per launch give the same evaluation (both
+    """One, two and four input positions per launch give the same evaluation (all
     against the oracle for n <= 8)."""
     d = 0.6
     lp = inp.random_logp(n, seed=40 + n, spread=2.0)
     out = []
-    for fuse in (0, 1):
+    for fuse in (0, 1, 2):
         c = ba.Context(n, d)
         c.set_tuning(ba.TUNE_FACTORED_FUSE, fuse)
         got = c.eval(torch.from_numpy(lp))
         out.append((got["L"], got["U"], got["r"].cpu().numpy(), got["D"].cpu().numpy()))
         c.close()
-    assert abs(out[0][0] - out[1][0]) < 1e-12 and abs(out[0][1] - out[1][1]) < 1e-12
-    assert np.allclose(out[0][2], out[1][2], rtol=1e-13, atol=0)
-    assert np.allclose(out[0][3], out[1][3], atol=1e-12)
+    for o in out[1:]:
+        assert abs(out[0][0] - o[0]) < 1e-12 and abs(out[0][1] - o[1]) < 1e-12
+        assert np.allclose(out[0][2], o[2], rtol=1e-13, atol=0)
+        assert np.allclose(out[0][3], o[3], atol=1e-12)
     if n <= 8:
         ev = bdc.evaluate(bdc.channel_dense(n, d), lp)
         assert abs(out[1][0] - ev.L / LN2) < 1e-11
+
+
+@pytest.mark.parametrize("n", [4, 5, 6, 7, 8, 11, 16])
+def test_four_position_backward_iterates(ba, n):
+    """Iterations with four positions per backward launch (D fused into the last
+    one) equal those with two, FP64."""
+    out = []
+    for fuse in (1, 2):
+        c = ba.Context(n, 0.65)
+        c.set_tuning(ba.TUNE_FACTORED_FUSE, fuse)
+        c.step(20)
+        out.append((c.get_logp().cpu().numpy(), c.bounds()))
+        c.close()
+    assert np.max(np.abs(out[0][0] - out[1][0])) < 1e-12
+    assert abs(out[0][1][0][0] - out[1][1][0][0]) < 1e-12 and abs(out[0][1][1][0] - out[1][1][1][0]) < 1e-12
+
+
+def test_four_position_backward_n20_fp32(ba):
+    ds = [0.64, 0.8, 0.95]
+    out = []
+    for fuse in (1, 2):
+        c = ba.Context([20] * 3, ds, prec=ba.PREC_FP32_LOG)
+        c.set_tuning(ba.TUNE_FACTORED_FUSE, fuse)
+        c.step(5)
+        out.append((c.get_logp().cpu().numpy(), c.bounds()))
+        c.close()
+    # FP32 iterates of two summation orders: the laws differ by FP32 rounding
+    # (~1e-6 nats in log p), which moves the FP64-certified bounds by ~1e-6 bits
+    assert np.max(np.abs(out[0][0] - out[1][0])) < 1e-4
+    assert np.max(np.abs(np.array(out[0][1][0]) - np.array(out[1][1][0]))) < 5e-6
+    assert np.max(np.abs(np.array(out[0][1][1]) - np.array(out[1][1][1]))) < 5e-6

@@ -31,7 +31,7 @@ def say(*a):
     print(*a, flush=True)
 
 
-def run_pair(ba, ns, ds, prec, iters, exact_k=None):
+def run_pair(ba, ns, ds, prec, iters, exact_k=None, fuse=None):
     """(logp, bounds) after `iters` iterations with the full and the symmetric kernels."""
     out = []
     for sym in (False, True):
@@ -39,6 +39,8 @@ def run_pair(ba, ns, ds, prec, iters, exact_k=None):
             c = ba.Context(ns, None, prec=prec, k=exact_k)
         else:
             c = ba.Context(ns, ds, prec=prec)
+        if fuse is not None:
+            c.set_tuning(ba.TUNE_FACTORED_FUSE, fuse)
         if sym:
             c.set_symmetry(True)
         c.step(iters)
@@ -48,10 +50,11 @@ def run_pair(ba, ns, ds, prec, iters, exact_k=None):
     return out
 
 
-@pytest.mark.parametrize("n", [4, 6, 8, 10, 12, 16])
-def test_symmetric_fp64_equals_full(ba, n):
-    say("symmetric fp64 n=%d" % n)
-    (lp_f, lo_f, hi_f), (lp_s, lo_s, hi_s) = run_pair(ba, n, 0.7, ba.PREC_FP64, 30)
+@pytest.mark.parametrize("fuse", [1, 2])
+@pytest.mark.parametrize("n", [4, 6, 8, 10, 12, 14, 16])
+def test_symmetric_fp64_equals_full(ba, n, fuse):
+    say("symmetric fp64 n=%d fuse=%d" % (n, fuse))
+    (lp_f, lo_f, hi_f), (lp_s, lo_s, hi_s) = run_pair(ba, n, 0.7, ba.PREC_FP64, 30, fuse=fuse)
     assert np.max(np.abs(lp_f - lp_s)) < 1e-12
     assert np.max(np.abs(lo_f - lo_s)) < 1e-12 and np.max(np.abs(hi_f - hi_s)) < 1e-12
     # the symmetric iterate is exactly invariant under complement
