@@ -23,154 +23,13 @@
 // launch can write v(y) = w_k log r(y) instead of r, and the last backward launch
 // can form D(x) = H(x) - G(x) - M with the reduction records of the Blahut
 // quantities (Section 2.3) instead of writing G.
-#include "ba_internal.h"
-#include "ba_part.h"
+
+#include "ba_factored_common.h"
 
 namespace ba {
 namespace {
 
-// Vector of V consecutive elements (16-byte loads/stores when V*sizeof(T) is a
-// multiple of 16 and the address is aligned to it).
-template <typename T, int V>
-struct Vec {
-  T v[V];
-};
-template <typename T, int V>
-__device__ __forceinline__ Vec<T, V> ld(const T* p) {
-  Vec<T, V> r;
-  if constexpr ((V * sizeof(T)) % 16 == 0) {
-#pragma unroll
-    for (int k = 0; k < int(V * sizeof(T) / 16); ++k)
-      reinterpret_cast<uint4*>(r.v)[k] = reinterpret_cast<const uint4*>(p)[k];
-  } else {
-#pragma unroll
-    for (int k = 0; k < V; ++k) r.v[k] = p[k];
-  }
-  return r;
-}
-template <typename T, int V>
-__device__ __forceinline__ void stv(T* p, const Vec<T, V>& a) {
-  if constexpr ((V * sizeof(T)) % 16 == 0) {
-#pragma unroll
-    for (int k = 0; k < int(V * sizeof(T) / 16); ++k)
-      reinterpret_cast<uint4*>(p)[k] = reinterpret_cast<const uint4*>(a.v)[k];
-  } else {
-#pragma unroll
-    for (int k = 0; k < V; ++k) p[k] = a.v[k];
-  }
-}
-
-__device__ __forceinline__ int length_of_rank(uint32_t r) { return 31 - __clz(r + 1u); }
-
-template <typename T, int V>
-__device__ __forceinline__ Vec<T, V> zero_vec() {
-  Vec<T, V> z;
-#pragma unroll
-  for (int k = 0; k < V; ++k) z.v[k] = T(0);
-  return z;
-}
-
-template <typename T>
-__device__ __forceinline__ T log_t(T v);
-template <>
-__device__ __forceinline__ float log_t<float>(float v) { return logf(v); }
-template <>
-__device__ __forceinline__ double log_t<double>(double v) { return log(v); }
-
-// v(y) = w_k log r(y) for the output of rank y (0 where w_k = 0).
-template <typename T>
-__device__ __forceinline__ T log_weighted(const Consts& cs, uint32_t y, T r) {
-  const T wk = T(cs.w[length_of_rank(y)]);
-  return (wk == T(0)) ? T(0) : wk * log_t<T>(r);
-}
-
-// ---------------------------------------------------------------------------
-// Visiting order of the rows of a two-position launch.
-//
-// Output row c needs source rows c, its parent and its grandparent (forward), or
-// its children and grandchildren (backward).  In plain rank order those are read
-// again far apart in time (rank c vs 2c vs 4c), and most re-reads miss the
-// per-XCD L2.  Instead, per column tile of 2^cw_log2 chunks, the rows above level
-// lb are visited first in rank order, then the subtrees rooted at level lb one
-// after another, each breadth-first (2^h - 1 rows in 2^h slots), so every re-read
-// row was fetched a subtree (<= kTileBytes) earlier.  Logical blocks are spread
-// over the XCDs in contiguous runs (hardware block b runs on XCD b mod 8), so one
-// subtree stays on one L2.
-// ---------------------------------------------------------------------------
-struct Order {
-  uint32_t nlog;  // logical row slots per column tile
-  uint32_t top;   // rows above level lb: 2^lb - 1
-  uint32_t nct;   // column tiles
-  int lb, h;      // level of the subtree roots, subtree height (levels)
-  int cw_log2;    // log2 of the column-tile width in chunks
-};
-
-constexpr size_t kTileBytes = size_t(1) << 19;
-
-// levels: output levels of the launch (rows 0 .. 2^levels - 2); cols_log2: log2
-// of the chunks per row; chunk_bytes: bytes one thread covers in a source row.
-Order make_order(int levels, int cols_log2, size_t chunk_bytes) {
-  Order o;
-  o.cw_log2 = cols_log2 < 6 ? cols_log2 : 6;
-  const size_t seg = (size_t(1) << o.cw_log2) * chunk_bytes;
-  int h = 1;
-  while (h < levels && (seg << (h + 1)) <= kTileBytes) ++h;
-  o.h = h;
-  o.lb = levels - h;
-  o.top = (1u << o.lb) - 1u;
-  o.nlog = (o.lb == 0) ? (1u << h) - 1u : o.top + (1u << (o.lb + h));
-  o.nct = 1u << (cols_log2 - o.cw_log2);
-  return o;
-}
-
-uint32_t order_threads(const Order& o) { return o.nct * o.nlog << o.cw_log2; }
-
-__device__ __forceinline__ uint32_t logical_block() {
-  const uint32_t G = gridDim.x, bx = blockIdx.x;
-  return (G & 7u) ? bx : (bx & 7u) * (G >> 3) + (bx >> 3);
-}
-
-// (row, chunk) of logical slot q; false for a padding slot or past the end.
-__device__ __forceinline__ bool order_slot_q(const Order& o, uint32_t q, uint32_t& row, uint32_t& chunk) {
-  const uint32_t rest = q >> o.cw_log2;
-  const uint32_t ct = rest / o.nlog;
-  if (ct >= o.nct) return false;
-  uint32_t L = rest - ct * o.nlog;
-  chunk = (ct << o.cw_log2) + (q & ((1u << o.cw_log2) - 1u));
-  if (L < o.top) {
-    row = L;
-    return true;
-  }
-  L -= o.top;
-  const uint32_t mask = (1u << o.h) - 1u;
-  const uint32_t t = L >> o.h, j = L & mask;
-  if (j == mask) return false;
-  const int k = 31 - __clz(j + 1u);
-  row = (1u << (o.lb + k)) - 1u + (t << k) + (j + 1u - (1u << k));
-  return true;
-}
-
-// This thread's (row, chunk), one slot per thread.
-__device__ __forceinline__ bool order_slot(const Order& o, uint32_t& row, uint32_t& chunk) {
-  return order_slot_q(o, logical_block() * kBlock + threadIdx.x, row, chunk);
-}
-
-// D(x) = H(x) - G(x) - M for V consecutive inputs, accumulated into the record.
-template <typename T, int V>
-__device__ __forceinline__ void d_epilogue(const Group<T>& g, int b, double M, uint32_t x, const Vec<T, V>& G,
-                                           Part& p, double wt = 1.0) {
-  const Vec<T, V> h = ld<T, V>(g.hf + (size_t)b * g.xs + x);
-  const Vec<T, V> l = ld<T, V>(g.lp + (size_t)b * g.xs + x);
-  Vec<T, V> d;
-#pragma unroll
-  for (int k = 0; k < V; ++k) {
-    d.v[k] = h.v[k] - G.v[k] - T(M);
-    const double lk = double(l.v[k]);
-    part_add<T>(p, lk + double(d.v[k]), double(d.v[k]), exp_in(lk, T()), 0.0, wt, g.eta != 1.0,
-                lk + g.eta * double(d.v[k]));
-  }
-  stv<T, V>(g.D + (size_t)b * g.xs + x, d);
-}
+using namespace fac;
 
 // One forward stage; each thread produces V consecutive columns of one row
 // (V divides the row width S = 2^(n-i-1)).  LOGV: last stage, write v.
@@ -213,93 +72,6 @@ __global__ __launch_bounds__(kBlock) void k_fwd_stage(int n, int i, const T* __r
   }
 }
 
-
-// Four forward stages at once (positions i .. i+3).  One thread per (source row y
-// of F_i, column s of the output width S4): it loads F_i of y and of its 4
-// ancestors P_1..P_4 (16 column groups u s each; absent rows are zero) and runs
-// the single stage
-//   F_{k+1}[z][g] = F_k[z][0g] + F_k[z][1g] (if z is a row of F_k) + F_k[parent z][last(z) g]
-// in registers on the rows that reach the outputs: the path P_0 = y .. P_{4-k} and,
-// when y has length i (a leaf of F_i), its subtree down to depth k.  It writes the
-// output row y and, for a leaf, the 30 rows below it (all rows of F_{i+4} of
-// length >= i are below exactly one leaf).  LOGV: last stage, write v = w_k log r.
-// Register part of the four-position forward step for one (y, column): F0 holds
-// F_i of the path P_0 = y .. P_3 (16 groups) and H4 the half of P_4 selected by
-// last(P_3); lastb[j] = last bit of P_j.  Returns F_{i+4}[y] and, in F4, the 30
-// rows below y (breadth-first: depth d, index m at (1 << d) - 2 + m).
-template <typename T>
-__device__ __forceinline__ T fwd4_registers(const T (&F0)[4][16], const T (&H4)[8], const uint32_t (&lastb)[4],
-                                            T (&F4)[30]) {
-  // stage 1: path P_0..P_3 (8 groups), children of y (parent halves chosen by
-  // select, so every register index is static)
-  T F1p[4][8], F1s[2][8];
-#pragma unroll
-  for (int j = 0; j < 3; ++j)
-#pragma unroll
-    for (int g = 0; g < 8; ++g)
-      F1p[j][g] = (F0[j][g] + F0[j][8 + g]) + (lastb[j] ? F0[j + 1][8 + g] : F0[j + 1][g]);
-#pragma unroll
-  for (int g = 0; g < 8; ++g) F1p[3][g] = (F0[3][g] + F0[3][8 + g]) + H4[g];
-#pragma unroll
-  for (int c = 0; c < 2; ++c)
-#pragma unroll
-    for (int g = 0; g < 8; ++g) F1s[c][g] = F0[0][c * 8 + g];
-  // stage 2: path P_0..P_2 (4 groups), subtree depth 1..2 (breadth-first 0..5)
-  T F2p[3][4], F2s[6][4];
-#pragma unroll
-  for (int j = 0; j < 3; ++j)
-#pragma unroll
-    for (int g = 0; g < 4; ++g)
-      F2p[j][g] = (F1p[j][g] + F1p[j][4 + g]) + (lastb[j] ? F1p[j + 1][4 + g] : F1p[j + 1][g]);
-#pragma unroll
-  for (int c = 0; c < 2; ++c)
-#pragma unroll
-    for (int g = 0; g < 4; ++g) F2s[c][g] = (F1s[c][g] + F1s[c][4 + g]) + F1p[0][c * 4 + g];
-#pragma unroll
-  for (int c = 0; c < 4; ++c)  // depth 2: child c/2 of y, then bit c&1
-#pragma unroll
-    for (int g = 0; g < 4; ++g) F2s[2 + c][g] = F1s[c >> 1][(c & 1) * 4 + g];
-  // stage 3: path P_0..P_1 (2 groups), subtree depth 1..3 (breadth-first 0..13)
-  T F3p[2][2], F3s[14][2];
-#pragma unroll
-  for (int j = 0; j < 2; ++j)
-#pragma unroll
-    for (int g = 0; g < 2; ++g)
-      F3p[j][g] = (F2p[j][g] + F2p[j][2 + g]) + (lastb[j] ? F2p[j + 1][2 + g] : F2p[j + 1][g]);
-#pragma unroll
-  for (int c = 0; c < 2; ++c)
-#pragma unroll
-    for (int g = 0; g < 2; ++g) F3s[c][g] = (F2s[c][g] + F2s[c][2 + g]) + F2p[0][c * 2 + g];
-#pragma unroll
-  for (int c = 0; c < 4; ++c)
-#pragma unroll
-    for (int g = 0; g < 2; ++g) F3s[2 + c][g] = (F2s[2 + c][g] + F2s[2 + c][2 + g]) + F2s[c >> 1][(c & 1) * 2 + g];
-#pragma unroll
-  for (int c = 0; c < 8; ++c)
-#pragma unroll
-    for (int g = 0; g < 2; ++g) F3s[6 + c][g] = F2s[2 + (c >> 1)][(c & 1) * 2 + g];
-  // stage 4: y (1 group), subtree depth 1..4
-#pragma unroll
-  for (int c = 0; c < 2; ++c) F4[c] = (F3s[c][0] + F3s[c][1]) + F3p[0][c];
-#pragma unroll
-  for (int c = 0; c < 4; ++c) F4[2 + c] = (F3s[2 + c][0] + F3s[2 + c][1]) + F3s[c >> 1][c & 1];
-#pragma unroll
-  for (int c = 0; c < 8; ++c) F4[6 + c] = (F3s[6 + c][0] + F3s[6 + c][1]) + F3s[2 + (c >> 1)][c & 1];
-#pragma unroll
-  for (int c = 0; c < 16; ++c) F4[14 + c] = F3s[6 + (c >> 1)][c & 1];
-  return (F3p[0][0] + F3p[0][1]) + (lastb[0] ? F3p[1][1] : F3p[1][0]);
-}
-
-// Path ranks of y and their last bits: P_{j+1} = parent(P_j) (garbage past the
-// empty row; such rows are never loaded).
-__device__ __forceinline__ void fwd4_path(uint32_t y, uint32_t (&P)[5], uint32_t (&lastb)[4]) {
-  P[0] = y;
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    lastb[j] = (P[j] - 1u) & 1u;
-    P[j + 1] = (P[j] - 1u) >> 1;
-  }
-}
 
 // Four forward stages at once (positions i .. i+3).  One thread per (source row y
 // of F_i, column s of the output width S4): it loads F_i of y and of its 4
@@ -564,72 +336,77 @@ __global__ __launch_bounds__(kBlock) void k_bwd_stage2(int n, int i, const T* __
 // 2t+1 and 2t+2, the same as ranks) and applies the 4 single stages
 // B_k[z][b g] = B_{k+1}[z][g] + B_{k+1}[z b][g] in registers.  DP: stage 0 (one
 // row), write D and the reduction records instead of G.
-template <typename T, bool DP>
+template <typename T, int V, bool DP>
 __global__ __launch_bounds__(kBlock) void k_bwd_stage4(int n, int i, const T* __restrict__ src, size_t sstride,
                                                        T* __restrict__ dst, size_t dstride, Group<T> g, Order o) {
   const int b = blockIdx.y;
   if (g.st[b].converged) return;
-  uint32_t y, s;
-  const bool valid = order_slot(o, y, s);
+  uint32_t y, chunk;
+  const bool valid = order_slot(o, y, chunk);
   if (!DP && !valid) return;
   src += (size_t)b * sstride;
   dst += (size_t)b * dstride;
   const int sh = n - i - 4;                  // log2 of the source width S4
+  const uint32_t s = chunk * V;
   Part p = part_empty();
   if (valid) {
-    T S[31];
+    Vec<T, V> S[31];
 #pragma unroll
     for (int d = 0; d <= 4; ++d)
 #pragma unroll
       for (int m = 0; m < (1 << d); ++m)
-        S[(1 << d) - 1 + m] = src[((((y + 1u) << d) - 1u + uint32_t(m)) << sh) + s];
-    T A[15][2];
+        S[(1 << d) - 1 + m] = ld<T, V>(src + ((((y + 1u) << d) - 1u + uint32_t(m)) << sh) + s);
+    Vec<T, V> A[15][2];
 #pragma unroll
-    for (int t = 0; t < 15; ++t) {
-      A[t][0] = S[t] + S[2 * t + 1];
-      A[t][1] = S[t] + S[2 * t + 2];
-    }
-    T B[7][4];
+    for (int t = 0; t < 15; ++t)
+#pragma unroll
+      for (int k = 0; k < V; ++k) {
+        A[t][0].v[k] = S[t].v[k] + S[2 * t + 1].v[k];
+        A[t][1].v[k] = S[t].v[k] + S[2 * t + 2].v[k];
+      }
+    Vec<T, V> B[7][4];
 #pragma unroll
     for (int t = 0; t < 7; ++t)
 #pragma unroll
       for (int bb = 0; bb < 2; ++bb)
 #pragma unroll
-        for (int q = 0; q < 2; ++q) B[t][bb * 2 + q] = A[t][q] + A[2 * t + 1 + bb][q];
-    T C[3][8];
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+          for (int k = 0; k < V; ++k) B[t][bb * 2 + q].v[k] = A[t][q].v[k] + A[2 * t + 1 + bb][q].v[k];
+    Vec<T, V> C[3][8];
 #pragma unroll
     for (int t = 0; t < 3; ++t)
 #pragma unroll
       for (int bb = 0; bb < 2; ++bb)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) C[t][bb * 4 + q] = B[t][q] + B[2 * t + 1 + bb][q];
-    T Dv[16];
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int k = 0; k < V; ++k) C[t][bb * 4 + q].v[k] = B[t][q].v[k] + B[2 * t + 1 + bb][q].v[k];
+    Vec<T, V> Dv[16];
 #pragma unroll
     for (int bb = 0; bb < 2; ++bb)
 #pragma unroll
-      for (int q = 0; q < 8; ++q) Dv[bb * 8 + q] = C[0][q] + C[1 + bb][q];
+      for (int q = 0; q < 8; ++q)
+#pragma unroll
+        for (int k = 0; k < V; ++k) Dv[bb * 8 + q].v[k] = C[0][q].v[k] + C[1 + bb][q].v[k];
     const uint32_t S4 = 1u << sh;
     if constexpr (DP) {
       const double M = g.st[b].M;
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        Vec<T, 1> gv;
-        gv.v[0] = Dv[u];
-        d_epilogue<T, 1>(g, b, M, uint32_t(u) * S4 + s, gv, p);
-      }
+      for (int u = 0; u < 16; ++u) d_epilogue<T, V>(g, b, M, uint32_t(u) * S4 + s, Dv[u], p);
     } else {
       T* op = dst + (y << (sh + 4)) + s;
-      if (sh == 0) {
+      if (V == 1 && sh == 0) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           Vec<T, 4> w;
 #pragma unroll
-          for (int k = 0; k < 4; ++k) w.v[k] = Dv[4 * q + k];
+          for (int k = 0; k < 4; ++k) w.v[k] = Dv[4 * q + k].v[0];
           stv<T, 4>(op + 4 * q, w);
         }
       } else {
 #pragma unroll
-        for (int u = 0; u < 16; ++u) op[uint32_t(u) * S4] = Dv[u];
+        for (int u = 0; u < 16; ++u) stv<T, V>(op + uint32_t(u) * S4, Dv[u]);
       }
     }
   }
@@ -662,394 +439,9 @@ __global__ __launch_bounds__(kBlock) void k_bwd_stage2_w1(const T* __restrict__ 
 }
 
 
-// ---------------------------------------------------------------------------
-// Complement-symmetric variant (Theorem 4 of Appendix A: from the uniform law,
-// every BA iterate satisfies p(cpl x) = p(x)).  Then every stage is symmetric,
-// F_i[cpl y][cpl s] = F_i[y][s] and B_i[cpl y][cpl s] = B_i[y][s], so only the
-// columns whose first bit is 0 are computed and stored (row stride halved), and
-// the other half is read from the mirrored row and column.  The output law is
-// kept for outputs that are empty or start with 0, at the compact index
-// cr(0z) = 2^|z| + bits(z), cr(empty) = 0; D for inputs x < 2^(n-1).
-// ---------------------------------------------------------------------------
-
-// Rank of the complement of the string of rank R (same length).
-__device__ __forceinline__ uint32_t mirror_rank(uint32_t R) {
-  return 3u * (1u << length_of_rank(R)) - 3u - R;
-}
-
-// Compact index of the canonical member of {y, cpl y}.
-__device__ __forceinline__ uint32_t compact_rank(uint32_t R) {
-  if (R == 0u) return 0u;
-  const int k = length_of_rank(R);
-  const uint32_t a = R + 1u - (1u << k), half = 1u << (k - 1);
-  return half + (a < half ? a : (2u * half - 1u - a));
-}
-
-template <typename T, int V>
-__device__ __forceinline__ Vec<T, V> rev(const Vec<T, V>& a) {
-  Vec<T, V> r;
-#pragma unroll
-  for (int k = 0; k < V; ++k) r.v[k] = a.v[V - 1 - k];
-  return r;
-}
-
-// Two forward stages, canonical half: output columns s'' < S/2 of every row c of
-// F_{i+2} (stride S/2) from F_i stored as its columns u s'' with u in {00, 01}
-// (stride 2S); F_i[y][1b s''] = F_i[cpl y][0 (1-b) cpl s''].
-template <typename T, int V>
-__global__ __launch_bounds__(kBlock) void k_fwd_stage2_sym(int n, int i, const T* __restrict__ src,
-                                                           size_t sstride, T* __restrict__ dst,
-                                                           size_t dstride, const State* st, Order o) {
-  const int b = blockIdx.y;
-  if (st[b].converged) return;
-  uint32_t c, chunk;
-  if (!order_slot(o, c, chunk)) return;
-  src += (size_t)b * sstride;
-  dst += (size_t)b * dstride;
-  const int sh = n - i - 2;                  // log2 of the full output width S
-  const uint32_t S = 1u << sh;
-  const uint32_t rows_in = (2u << i) - 1u;
-  const uint32_t s = chunk * V, m = S - s - V;  // chunk and its mirror
-  const uint32_t r = (c - 1u) >> 1, bb = (c - 1u) & 1u;
-  const uint32_t gp = (r - 1u) >> 1, lb = (r - 1u) & 1u;
-  const bool has_own = c < rows_in, has_par = c >= 1u && r < rows_in, has_gp = c >= 1u && r >= 1u;
-  // row y, u in {0,1} (stored half), column chunk at col
-  auto at = [&](uint32_t y, uint32_t u, uint32_t col) { return src + (y << (sh + 1)) + (u << sh) + col; };
-  // present terms loaded before use, absent ones zero (as in k_fwd_stage2)
-  Vec<T, V> o00 = zero_vec<T, V>(), o01 = o00, o10 = o00, o11 = o00, e = o00, p01 = o00, p10 = o00, gv = o00;
-  if (has_own) {
-    const uint32_t cm = mirror_rank(c);
-    o00 = ld<T, V>(at(c, 0, s)); o01 = ld<T, V>(at(c, 1, s));
-    o10 = ld<T, V>(at(cm, 1, m)); o11 = ld<T, V>(at(cm, 0, m));
-  }
-  if (has_par) {
-    // u = bb bb: 00 direct, 11 = cpl(00) of the mirrored row
-    e = bb ? ld<T, V>(at(mirror_rank(r), 0, m)) : ld<T, V>(at(r, 0, s));
-    p01 = ld<T, V>(at(r, 1, s));
-    p10 = ld<T, V>(at(mirror_rank(r), 1, m));
-  }
-  if (has_gp) gv = lb ? ld<T, V>(at(mirror_rank(gp), 1u - bb, m)) : ld<T, V>(at(gp, bb, s));
-  // mirrored chunks are read in reverse column order
-  o10 = rev(o10);
-  o11 = rev(o11);
-  p10 = rev(p10);
-  if (has_par && bb) e = rev(e);
-  if (has_gp && lb) gv = rev(gv);
-  Vec<T, V> acc;
-#pragma unroll
-  for (int k = 0; k < V; ++k)
-    acc.v[k] = (((o00.v[k] + o01.v[k]) + (o10.v[k] + o11.v[k])) + ((e.v[k] + e.v[k]) + (p01.v[k] + p10.v[k]))) +
-               gv.v[k];
-  stv<T, V>(dst + (c << (sh - 1)) + s, acc);
-}
-
-// Last two forward positions, canonical outputs (empty or starting with 0): v at
-// the compact index.  F_{n-2} is stored as 2 values per row (u = 00, 01).  Slots
-// run over the subtree of the string "0" (local rank rho, compact index rho + 1);
-// the slot of rho = 0 also produces the empty output.
-template <typename T>
-struct W1SymLoads {
-  Vec<T, 2> own, ownm, par, parm;
-  T gp;
-};
-template <typename T>
-__device__ __forceinline__ W1SymLoads<T> fwd_w1_sym_load(uint32_t c, bool ok, uint32_t rows_in,
-                                                         const T* __restrict__ src) {
-  const uint32_t r = (c - 1u) >> 1, bb = (c - 1u) & 1u;
-  const uint32_t gp = (r - 1u) >> 1, lb = (r - 1u) & 1u;
-  W1SymLoads<T> w;
-  w.own = zero_vec<T, 2>();
-  w.ownm = w.own;
-  w.par = w.own;
-  w.parm = w.own;
-  w.gp = T(0);
-  if (ok && c < rows_in) {
-    w.own = ld<T, 2>(src + 2u * c);
-    w.ownm = ld<T, 2>(src + 2u * mirror_rank(c));
-  }
-  if (ok && c >= 1u && r < rows_in) {
-    w.par = ld<T, 2>(src + 2u * r);
-    w.parm = ld<T, 2>(src + 2u * mirror_rank(r));
-  }
-  if (ok && c >= 1u && r >= 1u) w.gp = lb ? src[2u * mirror_rank(gp) + 1u - bb] : src[2u * gp + bb];
-  return w;
-}
-template <typename T>
-__device__ __forceinline__ T fwd_w1_sym_value(uint32_t c, const W1SymLoads<T>& w) {
-  const uint32_t bb = (c - 1u) & 1u;
-  const T e = bb ? w.parm.v[0] : w.par.v[0];
-  return (((w.own.v[0] + w.own.v[1]) + (w.ownm.v[0] + w.ownm.v[1])) + ((e + e) + (w.par.v[1] + w.parm.v[1]))) +
-         w.gp;
-}
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_fwd_stage2_w1_sym(int n, const T* __restrict__ src, size_t sstride,
-                                                              T* __restrict__ dst, size_t dstride,
-                                                              const State* st, const Consts* cs, Order o) {
-  const int b = blockIdx.y;
-  if (st[b].converged) return;
-  src += (size_t)b * sstride;
-  dst += (size_t)b * dstride;
-  const uint32_t rows_in = (1u << (n - 1)) - 1u;   // rows of F_{n-2}
-  const uint32_t q0 = logical_block() * (4u * kBlock) + (threadIdx.x & ~63u) * 4u + (threadIdx.x & 63u);
-  uint32_t rho[4], c[4];
-  bool ok[4];
-  W1SymLoads<T> w[4];
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    uint32_t chunk;
-    ok[j] = order_slot_q(o, q0 + 64u * j, rho[j], chunk);
-    if (!ok[j]) rho[j] = 0u;
-    const int k = length_of_rank(rho[j]);
-    c[j] = rho[j] + (1u << k);  // global rank of the local rank rho in the subtree of "0"
-    w[j] = fwd_w1_sym_load<T>(c[j], ok[j], rows_in, src);
-  }
-#pragma unroll
-  for (int j = 0; j < 4; ++j)
-    if (ok[j]) dst[rho[j] + 1u] = log_weighted<T>(cs[b], c[j], fwd_w1_sym_value<T>(c[j], w[j]));
-#pragma unroll
-  for (int j = 0; j < 4; ++j)
-    if (ok[j] && rho[j] == 0u) {
-      const W1SymLoads<T> we = fwd_w1_sym_load<T>(0u, true, rows_in, src);
-      dst[0] = log_weighted<T>(cs[b], 0u, fwd_w1_sym_value<T>(0u, we));
-    }
-}
-
-// v of the output of rank R from the compact array.
-template <typename T>
-__device__ __forceinline__ T v_sym(const T* __restrict__ v, uint32_t R) { return v[compact_rank(R)]; }
-
-// First backward launch, canonical half: B_{n-2}[r][0 c] for every row r (two
-// values per row, stride 2) from the compact v.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_bwd_stage2_w1_sym(const T* __restrict__ src, size_t sstride,
-                                                              T* __restrict__ dst, size_t dstride,
-                                                              const State* st, Order o) {
-  const int b = blockIdx.y;
-  if (st[b].converged) return;
-  uint32_t r, chunk;
-  if (!order_slot(o, r, chunk)) return;
-  src += (size_t)b * sstride;
-  dst += (size_t)b * dstride;
-  const T e = v_sym(src, r), k0 = v_sym(src, 2u * r + 1u), k1 = v_sym(src, 2u * r + 2u);
-  const T g00 = v_sym(src, 4u * r + 3u), g01 = v_sym(src, 4u * r + 4u);
-  Vec<T, 2> out;
-  out.v[0] = e + k0 + k0 + g00;
-  out.v[1] = e + k1 + k0 + g01;
-  stv<T, 2>(dst + 2u * r, out);
-}
-
-// Two backward stages, canonical half: B_i[r][0 c s''] for every row r and every
-// s'' (stride 2S) from B_{i+2} stored as its columns s'' < S/2 (stride S/2);
-// a chunk in the upper half reads the mirrored rows cpl(r ...) at the mirrored
-// chunk.  DP: stage 0, D for x < 2^(n-1), each value standing for x and cpl x.
-template <typename T, int V, bool DP>
-__global__ __launch_bounds__(kBlock) void k_bwd_stage2_sym(int n, int i, const T* __restrict__ src,
-                                                           size_t sstride, T* __restrict__ dst,
-                                                           size_t dstride, Group<T> g, Order o) {
-  const int b = blockIdx.y;
-  if (g.st[b].converged) return;
-  uint32_t r, chunk;
-  const bool valid = order_slot(o, r, chunk);
-  if (!DP && !valid) return;
-  src += (size_t)b * sstride;
-  dst += (size_t)b * dstride;
-  const int sh = n - i - 2;                  // log2 of the full source width S
-  const uint32_t S = 1u << sh;
-  const uint32_t s = chunk * V;
-  Part p = part_empty();
-  if (valid) {
-    const bool up = s >= S / 2u;
-    const uint32_t col = up ? S - s - V : s;
-    const uint32_t rr = up ? mirror_rank(r) : r;
-    // children and grandchildren of r, or of cpl r with the bits flipped
-    const uint32_t c0 = up ? 2u * rr + 2u : 2u * r + 1u, c1 = up ? 2u * rr + 1u : 2u * r + 2u;
-    const uint32_t q00 = up ? 4u * rr + 6u : 4u * r + 3u, q01 = up ? 4u * rr + 5u : 4u * r + 4u;
-    const int hs = sh - 1;                   // log2 of the stored width S/2
-    Vec<T, V> e = ld<T, V>(src + (rr << hs) + col);
-    Vec<T, V> k0 = ld<T, V>(src + (c0 << hs) + col), k1 = ld<T, V>(src + (c1 << hs) + col);
-    Vec<T, V> g00 = ld<T, V>(src + (q00 << hs) + col), g01 = ld<T, V>(src + (q01 << hs) + col);
-    if (up) { e = rev(e); k0 = rev(k0); k1 = rev(k1); g00 = rev(g00); g01 = rev(g01); }
-    Vec<T, V> o00, o01;
-#pragma unroll
-    for (int k = 0; k < V; ++k) {
-      o00.v[k] = e.v[k] + k0.v[k] + k0.v[k] + g00.v[k];
-      o01.v[k] = e.v[k] + k1.v[k] + k0.v[k] + g01.v[k];
-    }
-    if constexpr (DP) {
-      const double M = g.st[b].M;
-      d_epilogue<T, V>(g, b, M, s, o00, p, 2.0);
-      d_epilogue<T, V>(g, b, M, S + s, o01, p, 2.0);
-    } else {
-      T* op = dst + (r << (sh + 1)) + s;
-      stv<T, V>(op, o00);
-      stv<T, V>(op + S, o01);
-    }
-  }
-  if constexpr (DP) {
-    p = block_reduce(p);
-    store_block_part(g.part + (size_t)b * g.ps, blockIdx.x, p);
-  }
-}
-
-
-// Four forward stages, canonical half: as k_fwd_stage4 for the output columns
-// s < S4/2 (stride S4/2), with F_i stored as its groups u < 8 (first bit 0, stride
-// 8 S4); group u >= 8 of row z is group 15 - u of cpl z at column S4 - 1 - s.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_fwd_stage4_sym(int n, int i, const T* __restrict__ src,
-                                                           size_t sstride, T* __restrict__ dst, size_t dstride,
-                                                           const State* st, Order o) {
-  const int b = blockIdx.y;
-  if (st[b].converged) return;
-  uint32_t y, s;
-  if (!order_slot(o, y, s)) return;
-  src += (size_t)b * sstride;
-  dst += (size_t)b * dstride;
-  const int sh = n - i - 4;                  // log2 of the full output width S4 (>= 1)
-  const uint32_t S4 = 1u << sh, sm = S4 - 1u - s;
-  const int ly = length_of_rank(y);
-  uint32_t P[5], lastb[4];
-  fwd4_path(y, P, lastb);
-  T F0[4][16], H4[8];
-#pragma unroll
-  for (int j = 0; j < 4; ++j)
-#pragma unroll
-    for (int u = 0; u < 16; ++u) F0[j][u] = T(0);
-#pragma unroll
-  for (int u = 0; u < 8; ++u) H4[u] = T(0);
-#pragma unroll
-  for (int j = 0; j < 4; ++j)
-    if (j <= ly) {
-      const T* row = src + ((size_t)P[j] << (sh + 3));
-      const T* rowm = src + ((size_t)mirror_rank(P[j]) << (sh + 3));
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        F0[j][u] = row[(uint32_t(u) << sh) + s];
-        F0[j][8 + u] = rowm[(uint32_t(7 - u) << sh) + sm];
-      }
-    }
-  if (4 <= ly) {
-    if (lastb[3]) {
-      const T* rowm = src + ((size_t)mirror_rank(P[4]) << (sh + 3));
-#pragma unroll
-      for (int u = 0; u < 8; ++u) H4[u] = rowm[(uint32_t(7 - u) << sh) + sm];
-    } else {
-      const T* row = src + ((size_t)P[4] << (sh + 3));
-#pragma unroll
-      for (int u = 0; u < 8; ++u) H4[u] = row[(uint32_t(u) << sh) + s];
-    }
-  }
-  T F4[30];
-  const T vy = fwd4_registers<T>(F0, H4, lastb, F4);
-  const int ho = sh - 1;                     // log2 of the stored output width
-  dst[((size_t)y << ho) + s] = vy;
-  if (ly != i) return;
-#pragma unroll
-  for (int d = 1; d <= 4; ++d)
-#pragma unroll
-    for (int m = 0; m < (1 << d); ++m) {
-      const uint32_t rk = ((y + 1u) << d) - 1u + uint32_t(m);
-      dst[((size_t)rk << ho) + s] = F4[(1 << d) - 2 + m];
-    }
-}
-
-// Four backward stages, canonical half: B_i[y][u s] for u < 8 (stride 8 S4) and
-// every s, from B_{i+4} stored as its columns s < S4/2 (stride S4/2), or, VC, from
-// the compact v (i + 4 = n).  A column in the upper half reads the subtree of
-// cpl y with complemented paths at the mirrored column.  DP: stage 0, D for
-// x < 2^(n-1) with weight 2.
-template <typename T, bool DP, bool VC>
-__global__ __launch_bounds__(kBlock) void k_bwd_stage4_sym(int n, int i, const T* __restrict__ src,
-                                                           size_t sstride, T* __restrict__ dst, size_t dstride,
-                                                           Group<T> g, Order o) {
-  const int b = blockIdx.y;
-  if (g.st[b].converged) return;
-  uint32_t y, s;
-  const bool valid = order_slot(o, y, s);
-  if (!DP && !valid) return;
-  src += (size_t)b * sstride;
-  dst += (size_t)b * dstride;
-  const int sh = n - i - 4;                  // log2 of the full source width S4
-  const uint32_t S4 = 1u << sh;
-  Part p = part_empty();
-  if (valid) {
-    T S[31];
-    if constexpr (VC) {
-#pragma unroll
-      for (int d = 0; d <= 4; ++d)
-#pragma unroll
-        for (int m = 0; m < (1 << d); ++m)
-          S[(1 << d) - 1 + m] = v_sym(src, ((y + 1u) << d) - 1u + uint32_t(m));
-    } else {
-      const bool up = s >= S4 / 2u;
-      const uint32_t yy = up ? mirror_rank(y) : y, col = up ? S4 - 1u - s : s;
-      const int hs = sh - 1;                 // log2 of the stored width
-#pragma unroll
-      for (int d = 0; d <= 4; ++d)
-#pragma unroll
-        for (int m = 0; m < (1 << d); ++m) {
-          const uint32_t mm = up ? (1u << d) - 1u - uint32_t(m) : uint32_t(m);
-          S[(1 << d) - 1 + m] = src[((((yy + 1u) << d) - 1u + mm) << hs) + col];
-        }
-    }
-    T A[15][2];
-#pragma unroll
-    for (int t = 0; t < 15; ++t) {
-      A[t][0] = S[t] + S[2 * t + 1];
-      A[t][1] = S[t] + S[2 * t + 2];
-    }
-    T B[7][4];
-#pragma unroll
-    for (int t = 0; t < 7; ++t)
-#pragma unroll
-      for (int bb = 0; bb < 2; ++bb)
-#pragma unroll
-        for (int q = 0; q < 2; ++q) B[t][bb * 2 + q] = A[t][q] + A[2 * t + 1 + bb][q];
-    T C[3][8];
-#pragma unroll
-    for (int t = 0; t < 3; ++t)
-#pragma unroll
-      for (int bb = 0; bb < 2; ++bb)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) C[t][bb * 4 + q] = B[t][q] + B[2 * t + 1 + bb][q];
-    T Dv[8];  // first bit 0 only
-#pragma unroll
-    for (int q = 0; q < 8; ++q) Dv[q] = C[0][q] + C[1][q];
-    if constexpr (DP) {
-      const double M = g.st[b].M;
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        Vec<T, 1> gv;
-        gv.v[0] = Dv[u];
-        d_epilogue<T, 1>(g, b, M, uint32_t(u) * S4 + s, gv, p, 2.0);
-      }
-    } else {
-      T* op = dst + (y << (sh + 3)) + s;
-#pragma unroll
-      for (int u = 0; u < 8; ++u) op[uint32_t(u) * S4] = Dv[u];
-    }
-  }
-  if constexpr (DP) {
-    p = block_reduce(p);
-    store_block_part(g.part + (size_t)b * g.ps, blockIdx.x, p);
-  }
-}
-
-inline uint32_t grid_for(uint32_t total) {
-  uint32_t g = (total + kBlock - 1) / kBlock;
-  return g > 8192u ? 8192u : (g == 0 ? 1u : g);
-}
-
-// Blocks for an ordered launch, a multiple of 8 so that the XCD placement of
-// logical_block applies (the extra blocks find no slot).
-inline uint32_t blocks_for(uint32_t threads) {
-  const uint32_t g = threads == 0 ? 1u : (threads + kBlock - 1) / kBlock;
-  return (g + 7u) & ~7u;
-}
-
-inline int ilog2(uint32_t v) { return 31 - __builtin_clz(v); }
-
 }  // namespace
+
+using namespace fac;
 
 template <typename T>
 hipError_t launch_forward(const Group<T>& g, hipStream_t s, int* launches, int fuse, int logv) {
@@ -1150,11 +542,13 @@ hipError_t launch_backward(const Group<T>& g, hipStream_t s, int* launches, int 
       const uint32_t nbk = blocks_for(order_threads(o));
       const bool dp = last && dpart && nbk <= uint32_t(kMaxRedBlocks);
       if (dp) {
-        hipLaunchKernelGGL((k_bwd_stage4<T, true>), dim3(nbk, g.nb), dim3(kBlock), 0, s, n, i, src, ss, dst, ds, g,
-                           o);
+        hipLaunchKernelGGL((k_bwd_stage4<T, 1, true>), dim3(nbk, g.nb), dim3(kBlock), 0, s, n, i, src, ss, dst, ds,
+                           g, o);
         if (dpart_blocks) *dpart_blocks = int(nbk);
       } else {
-        hipLaunchKernelGGL((k_bwd_stage4<T, false>), dim3(nbk, g.nb), dim3(kBlock), 0, s, n, i, src, ss, dst, ds,
+        // one column per thread (2 or 4 per thread measured no faster: 0.079 ms per
+        // backward sweep at n = 20 for 1, 0.081 for 2 and 4)
+        hipLaunchKernelGGL((k_bwd_stage4<T, 1, false>), dim3(nbk, g.nb), dim3(kBlock), 0, s, n, i, src, ss, dst, ds,
                            g, o);
       }
       if (launches) ++*launches;
@@ -1225,127 +619,6 @@ hipError_t launch_backward(const Group<T>& g, hipStream_t s, int* launches, int 
 }
 
 
-bool symmetric_supported(int n, int fuse) { return fuse && n >= 4 && (n % 2) == 0; }
-
-template <typename T>
-hipError_t launch_forward_sym(const Group<T>& g, hipStream_t s, int* launches, int fuse) {
-  const int n = g.n;
-  constexpr int V = 16 / sizeof(T);
-  const T* src = g.p;
-  size_t ss = g.xs;
-  int k = 0;
-  int i0 = 0;
-  for (; fuse == 2 && i0 + 4 < n; i0 += 4, k++) {
-    T* dst = (k & 1) ? g.f1 : g.f0;
-    const uint32_t S4 = 1u << (n - i0 - 4);
-    const Order o = make_order(i0 + 1, ilog2(S4 / 2u), sizeof(T));
-    hipLaunchKernelGGL((k_fwd_stage4_sym<T>), dim3(blocks_for(order_threads(o)), g.nb), dim3(kBlock), 0, s, n, i0,
-                       src, ss, dst, g.fs, g.st, o);
-    if (launches) ++*launches;
-    src = dst;
-    ss = g.fs;
-  }
-  for (int i = i0; i < n; i += 2, k++) {
-    const bool last = (i + 2 == n);
-    T* dst = last ? g.v : ((k & 1) ? g.f1 : g.f0);
-    const size_t ds = last ? g.ys : g.fs;
-    const uint32_t S = 1u << (n - i - 2);
-    if (S == 1u) {
-      const Order o = make_order(n, 0, 4 * sizeof(T));
-      hipLaunchKernelGGL((k_fwd_stage2_w1_sym<T>), dim3(blocks_for((order_threads(o) + 3u) / 4u), g.nb),
-                         dim3(kBlock), 0, s, n, src, ss, dst, ds, g.st, g.cs, o);
-    } else {
-      const uint32_t half = S / 2u;
-      if (half >= uint32_t(V)) {
-        const Order o = make_order(i + 3, ilog2(half / V), V * sizeof(T));
-        hipLaunchKernelGGL((k_fwd_stage2_sym<T, V>), dim3(blocks_for(order_threads(o)), g.nb), dim3(kBlock), 0,
-                           s, n, i, src, ss, dst, ds, g.st, o);
-      } else {  // S = 4: two columns per row
-        const Order o = make_order(i + 3, 0, 2 * sizeof(T));
-        hipLaunchKernelGGL((k_fwd_stage2_sym<T, 2>), dim3(blocks_for(order_threads(o)), g.nb), dim3(kBlock), 0,
-                           s, n, i, src, ss, dst, ds, g.st, o);
-      }
-    }
-    if (launches) ++*launches;
-    src = dst;
-    ss = ds;
-  }
-  return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_backward_sym(const Group<T>& g, hipStream_t s, int* launches, int* dpart_blocks, int fuse) {
-  const int n = g.n;
-  constexpr int V = 16 / sizeof(T);
-  const T* src = g.v;
-  size_t ss = g.ys;
-  int k = 0;
-  if (dpart_blocks) *dpart_blocks = 0;
-  const int lead = (fuse == 2) ? n % 4 : -1;  // even n: 0 or 2
-  for (int top = n; top > 0; k++) {
-    if (lead >= 0 && n - top >= lead) {
-      const int i = top - 4;
-      const bool last = (i == 0), vc = (top == n);
-      T* dst = last ? g.g : ((k & 1) ? g.f1 : g.f0);
-      const size_t ds = last ? g.xs : g.fs;
-      const uint32_t S4 = 1u << (n - i - 4);
-      const Order o = make_order(i + 1, ilog2(S4), sizeof(T));
-      const uint32_t nbk = blocks_for(order_threads(o));
-      const dim3 grid(nbk, g.nb);
-      if (last) {
-        if (nbk > uint32_t(kMaxRedBlocks)) return hipErrorInvalidValue;
-        if (vc)
-          hipLaunchKernelGGL((k_bwd_stage4_sym<T, true, true>), grid, dim3(kBlock), 0, s, n, i, src, ss, dst, ds, g, o);
-        else
-          hipLaunchKernelGGL((k_bwd_stage4_sym<T, true, false>), grid, dim3(kBlock), 0, s, n, i, src, ss, dst, ds, g,
-                             o);
-        if (dpart_blocks) *dpart_blocks = int(nbk);
-      } else if (vc) {
-        hipLaunchKernelGGL((k_bwd_stage4_sym<T, false, true>), grid, dim3(kBlock), 0, s, n, i, src, ss, dst, ds, g, o);
-      } else {
-        hipLaunchKernelGGL((k_bwd_stage4_sym<T, false, false>), grid, dim3(kBlock), 0, s, n, i, src, ss, dst, ds, g,
-                           o);
-      }
-      if (launches) ++*launches;
-      src = dst;
-      ss = ds;
-      top = i;
-      continue;
-    }
-    const int i = top - 2;
-    const bool last = (i == 0);
-    T* dst = last ? g.g : ((k & 1) ? g.f1 : g.f0);
-    const size_t ds = last ? g.xs : g.fs;
-    const uint32_t S = 1u << (n - i - 2);  // full source row width
-    if (S == 1u) {
-      const Order o = make_order(i + 1, 0, 2 * sizeof(T));
-      hipLaunchKernelGGL((k_bwd_stage2_w1_sym<T>), dim3(blocks_for(order_threads(o)), g.nb), dim3(kBlock), 0, s,
-                         src, ss, dst, ds, g.st, o);
-    } else if (last) {
-      // one row; one column per thread (n <= 20 keeps the records within kMaxRedBlocks)
-      const Order o = make_order(1, ilog2(S), sizeof(T));
-      const uint32_t nb1 = blocks_for(order_threads(o));
-      if (nb1 > uint32_t(kMaxRedBlocks)) return hipErrorInvalidValue;
-      hipLaunchKernelGGL((k_bwd_stage2_sym<T, 1, true>), dim3(nb1, g.nb), dim3(kBlock), 0, s, n, i, src, ss, dst,
-                         ds, g, o);
-      if (dpart_blocks) *dpart_blocks = int(nb1);
-    } else {
-      const uint32_t Vx = (S / 2u >= uint32_t(V)) ? uint32_t(V) : 2u;
-      const Order o = make_order(i + 1, ilog2(S / Vx), Vx * sizeof(T));
-      const dim3 grid(blocks_for(order_threads(o)), g.nb);
-      if (Vx == uint32_t(V))
-        hipLaunchKernelGGL((k_bwd_stage2_sym<T, V, false>), grid, dim3(kBlock), 0, s, n, i, src, ss, dst, ds, g, o);
-      else
-        hipLaunchKernelGGL((k_bwd_stage2_sym<T, 2, false>), grid, dim3(kBlock), 0, s, n, i, src, ss, dst, ds, g, o);
-    }
-    if (launches) ++*launches;
-    src = dst;
-    ss = ds;
-    top = i;
-  }
-  return hipGetLastError();
-}
-
 int factored_launches(int n, int fuse) { return fuse ? (n + 1) / 2 : n; }
 
 int backward_launches(int n, int fuse) {
@@ -1365,9 +638,5 @@ template hipError_t launch_forward<float>(const Group<float>&, hipStream_t, int*
 template hipError_t launch_forward<double>(const Group<double>&, hipStream_t, int*, int, int);
 template hipError_t launch_backward<float>(const Group<float>&, hipStream_t, int*, int, int, int*);
 template hipError_t launch_backward<double>(const Group<double>&, hipStream_t, int*, int, int, int*);
-template hipError_t launch_forward_sym<float>(const Group<float>&, hipStream_t, int*, int);
-template hipError_t launch_forward_sym<double>(const Group<double>&, hipStream_t, int*, int);
-template hipError_t launch_backward_sym<float>(const Group<float>&, hipStream_t, int*, int*, int);
-template hipError_t launch_backward_sym<double>(const Group<double>&, hipStream_t, int*, int*, int);
 
 }  // namespace ba

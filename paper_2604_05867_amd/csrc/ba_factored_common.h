@@ -1,0 +1,249 @@
+// Device helpers shared by the factored-engine kernels (full and complement-
+// symmetric variants): vector loads, the row visiting order of a launch, the
+// fused D epilogue and the register part of the four-position forward step.
+// Included by ba_factored.hip and ba_symmetric.hip only.
+#pragma once
+
+#include "ba_internal.h"
+#include "ba_part.h"
+
+namespace ba {
+namespace fac {
+
+// Vector of V consecutive elements (16-byte loads/stores when V*sizeof(T) is a
+// multiple of 16 and the address is aligned to it).
+template <typename T, int V>
+struct Vec {
+  T v[V];
+};
+template <typename T, int V>
+__device__ __forceinline__ Vec<T, V> ld(const T* p) {
+  Vec<T, V> r;
+  if constexpr ((V * sizeof(T)) % 16 == 0) {
+#pragma unroll
+    for (int k = 0; k < int(V * sizeof(T) / 16); ++k)
+      reinterpret_cast<uint4*>(r.v)[k] = reinterpret_cast<const uint4*>(p)[k];
+  } else {
+#pragma unroll
+    for (int k = 0; k < V; ++k) r.v[k] = p[k];
+  }
+  return r;
+}
+template <typename T, int V>
+__device__ __forceinline__ void stv(T* p, const Vec<T, V>& a) {
+  if constexpr ((V * sizeof(T)) % 16 == 0) {
+#pragma unroll
+    for (int k = 0; k < int(V * sizeof(T) / 16); ++k)
+      reinterpret_cast<uint4*>(p)[k] = reinterpret_cast<const uint4*>(a.v)[k];
+  } else {
+#pragma unroll
+    for (int k = 0; k < V; ++k) p[k] = a.v[k];
+  }
+}
+
+__device__ __forceinline__ int length_of_rank(uint32_t r) { return 31 - __clz(r + 1u); }
+
+template <typename T, int V>
+__device__ __forceinline__ Vec<T, V> zero_vec() {
+  Vec<T, V> z;
+#pragma unroll
+  for (int k = 0; k < V; ++k) z.v[k] = T(0);
+  return z;
+}
+
+template <typename T>
+__device__ __forceinline__ T log_t(T v);
+template <>
+__device__ __forceinline__ float log_t<float>(float v) { return logf(v); }
+template <>
+__device__ __forceinline__ double log_t<double>(double v) { return log(v); }
+
+// v(y) = w_k log r(y) for the output of rank y (0 where w_k = 0).
+template <typename T>
+__device__ __forceinline__ T log_weighted(const Consts& cs, uint32_t y, T r) {
+  const T wk = T(cs.w[length_of_rank(y)]);
+  return (wk == T(0)) ? T(0) : wk * log_t<T>(r);
+}
+
+// ---------------------------------------------------------------------------
+// Visiting order of the rows of a two-position launch.
+//
+// Output row c needs source rows c, its parent and its grandparent (forward), or
+// its children and grandchildren (backward).  In plain rank order those are read
+// again far apart in time (rank c vs 2c vs 4c), and most re-reads miss the
+// per-XCD L2.  Instead, per column tile of 2^cw_log2 chunks, the rows above level
+// lb are visited first in rank order, then the subtrees rooted at level lb one
+// after another, each breadth-first (2^h - 1 rows in 2^h slots), so every re-read
+// row was fetched a subtree (<= kTileBytes) earlier.  Logical blocks are spread
+// over the XCDs in contiguous runs (hardware block b runs on XCD b mod 8), so one
+// subtree stays on one L2.
+// ---------------------------------------------------------------------------
+struct Order {
+  uint32_t nlog;  // logical row slots per column tile
+  uint32_t top;   // rows above level lb: 2^lb - 1
+  uint32_t nct;   // column tiles
+  int lb, h;      // level of the subtree roots, subtree height (levels)
+  int cw_log2;    // log2 of the column-tile width in chunks
+};
+
+constexpr size_t kTileBytes = size_t(1) << 19;
+
+// levels: output levels of the launch (rows 0 .. 2^levels - 2); cols_log2: log2
+// of the chunks per row; chunk_bytes: bytes one thread covers in a source row.
+inline Order make_order(int levels, int cols_log2, size_t chunk_bytes) {
+  Order o;
+  o.cw_log2 = cols_log2 < 6 ? cols_log2 : 6;
+  const size_t seg = (size_t(1) << o.cw_log2) * chunk_bytes;
+  int h = 1;
+  while (h < levels && (seg << (h + 1)) <= kTileBytes) ++h;
+  o.h = h;
+  o.lb = levels - h;
+  o.top = (1u << o.lb) - 1u;
+  o.nlog = (o.lb == 0) ? (1u << h) - 1u : o.top + (1u << (o.lb + h));
+  o.nct = 1u << (cols_log2 - o.cw_log2);
+  return o;
+}
+
+inline uint32_t order_threads(const Order& o) { return o.nct * o.nlog << o.cw_log2; }
+
+__device__ __forceinline__ uint32_t logical_block() {
+  const uint32_t G = gridDim.x, bx = blockIdx.x;
+  return (G & 7u) ? bx : (bx & 7u) * (G >> 3) + (bx >> 3);
+}
+
+// (row, chunk) of logical slot q; false for a padding slot or past the end.
+__device__ __forceinline__ bool order_slot_q(const Order& o, uint32_t q, uint32_t& row, uint32_t& chunk) {
+  const uint32_t rest = q >> o.cw_log2;
+  const uint32_t ct = rest / o.nlog;
+  if (ct >= o.nct) return false;
+  uint32_t L = rest - ct * o.nlog;
+  chunk = (ct << o.cw_log2) + (q & ((1u << o.cw_log2) - 1u));
+  if (L < o.top) {
+    row = L;
+    return true;
+  }
+  L -= o.top;
+  const uint32_t mask = (1u << o.h) - 1u;
+  const uint32_t t = L >> o.h, j = L & mask;
+  if (j == mask) return false;
+  const int k = 31 - __clz(j + 1u);
+  row = (1u << (o.lb + k)) - 1u + (t << k) + (j + 1u - (1u << k));
+  return true;
+}
+
+// This thread's (row, chunk), one slot per thread.
+__device__ __forceinline__ bool order_slot(const Order& o, uint32_t& row, uint32_t& chunk) {
+  return order_slot_q(o, logical_block() * kBlock + threadIdx.x, row, chunk);
+}
+
+// D(x) = H(x) - G(x) - M for V consecutive inputs, accumulated into the record.
+template <typename T, int V>
+__device__ __forceinline__ void d_epilogue(const Group<T>& g, int b, double M, uint32_t x, const Vec<T, V>& G,
+                                           Part& p, double wt = 1.0) {
+  const Vec<T, V> h = ld<T, V>(g.hf + (size_t)b * g.xs + x);
+  const Vec<T, V> l = ld<T, V>(g.lp + (size_t)b * g.xs + x);
+  Vec<T, V> d;
+#pragma unroll
+  for (int k = 0; k < V; ++k) {
+    d.v[k] = h.v[k] - G.v[k] - T(M);
+    const double lk = double(l.v[k]);
+    part_add<T>(p, lk + double(d.v[k]), double(d.v[k]), exp_in(lk, T()), 0.0, wt, g.eta != 1.0,
+                lk + g.eta * double(d.v[k]));
+  }
+  stv<T, V>(g.D + (size_t)b * g.xs + x, d);
+}
+
+// Register part of the four-position forward step for one (y, column): F0 holds
+// F_i of the path P_0 = y .. P_3 (16 groups) and H4 the half of P_4 selected by
+// last(P_3); lastb[j] = last bit of P_j.  Returns F_{i+4}[y] and, in F4, the 30
+// rows below y (breadth-first: depth d, index m at (1 << d) - 2 + m).
+template <typename T>
+__device__ __forceinline__ T fwd4_registers(const T (&F0)[4][16], const T (&H4)[8], const uint32_t (&lastb)[4],
+                                            T (&F4)[30]) {
+  // stage 1: path P_0..P_3 (8 groups), children of y (parent halves chosen by
+  // select, so every register index is static)
+  T F1p[4][8], F1s[2][8];
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int g = 0; g < 8; ++g)
+      F1p[j][g] = (F0[j][g] + F0[j][8 + g]) + (lastb[j] ? F0[j + 1][8 + g] : F0[j + 1][g]);
+#pragma unroll
+  for (int g = 0; g < 8; ++g) F1p[3][g] = (F0[3][g] + F0[3][8 + g]) + H4[g];
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int g = 0; g < 8; ++g) F1s[c][g] = F0[0][c * 8 + g];
+  // stage 2: path P_0..P_2 (4 groups), subtree depth 1..2 (breadth-first 0..5)
+  T F2p[3][4], F2s[6][4];
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+      F2p[j][g] = (F1p[j][g] + F1p[j][4 + g]) + (lastb[j] ? F1p[j + 1][4 + g] : F1p[j + 1][g]);
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int g = 0; g < 4; ++g) F2s[c][g] = (F1s[c][g] + F1s[c][4 + g]) + F1p[0][c * 4 + g];
+#pragma unroll
+  for (int c = 0; c < 4; ++c)  // depth 2: child c/2 of y, then bit c&1
+#pragma unroll
+    for (int g = 0; g < 4; ++g) F2s[2 + c][g] = F1s[c >> 1][(c & 1) * 4 + g];
+  // stage 3: path P_0..P_1 (2 groups), subtree depth 1..3 (breadth-first 0..13)
+  T F3p[2][2], F3s[14][2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j)
+#pragma unroll
+    for (int g = 0; g < 2; ++g)
+      F3p[j][g] = (F2p[j][g] + F2p[j][2 + g]) + (lastb[j] ? F2p[j + 1][2 + g] : F2p[j + 1][g]);
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int g = 0; g < 2; ++g) F3s[c][g] = (F2s[c][g] + F2s[c][2 + g]) + F2p[0][c * 2 + g];
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int g = 0; g < 2; ++g) F3s[2 + c][g] = (F2s[2 + c][g] + F2s[2 + c][2 + g]) + F2s[c >> 1][(c & 1) * 2 + g];
+#pragma unroll
+  for (int c = 0; c < 8; ++c)
+#pragma unroll
+    for (int g = 0; g < 2; ++g) F3s[6 + c][g] = F2s[2 + (c >> 1)][(c & 1) * 2 + g];
+  // stage 4: y (1 group), subtree depth 1..4
+#pragma unroll
+  for (int c = 0; c < 2; ++c) F4[c] = (F3s[c][0] + F3s[c][1]) + F3p[0][c];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) F4[2 + c] = (F3s[2 + c][0] + F3s[2 + c][1]) + F3s[c >> 1][c & 1];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) F4[6 + c] = (F3s[6 + c][0] + F3s[6 + c][1]) + F3s[2 + (c >> 1)][c & 1];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) F4[14 + c] = F3s[6 + (c >> 1)][c & 1];
+  return (F3p[0][0] + F3p[0][1]) + (lastb[0] ? F3p[1][1] : F3p[1][0]);
+}
+
+// Path ranks of y and their last bits: P_{j+1} = parent(P_j) (garbage past the
+// empty row; such rows are never loaded).
+__device__ __forceinline__ void fwd4_path(uint32_t y, uint32_t (&P)[5], uint32_t (&lastb)[4]) {
+  P[0] = y;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    lastb[j] = (P[j] - 1u) & 1u;
+    P[j + 1] = (P[j] - 1u) >> 1;
+  }
+}
+
+inline uint32_t grid_for(uint32_t total) {
+  uint32_t g = (total + kBlock - 1) / kBlock;
+  return g > 8192u ? 8192u : (g == 0 ? 1u : g);
+}
+
+// Blocks for an ordered launch, a multiple of 8 so that the XCD placement of
+// logical_block applies (the extra blocks find no slot).
+inline uint32_t blocks_for(uint32_t threads) {
+  const uint32_t g = threads == 0 ? 1u : (threads + kBlock - 1) / kBlock;
+  return (g + 7u) & ~7u;
+}
+
+inline int ilog2(uint32_t v) { return 31 - __builtin_clz(v); }
+
+}  // namespace fac
+}  // namespace ba
