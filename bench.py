@@ -36,22 +36,30 @@ FUSE = 2  # the library default: four positions per launch of the factored engin
 # averaged over the launches of one sweep; valid only for the kernel source it was
 # measured on (summary: profiles/k_fwd_stage2_n20_fp32_x3.md).
 MEASURED_TRAFFIC = {
-    "source": "paper_2604_05867_amd/csrc/ba_factored.hip",
-    "sha256": None,   # no PMC figures taken on the current kernels yet
-    "sweep1": None,
-    "sweep2": None,
+    "sources": ["paper_2604_05867_amd/csrc/ba_factored.hip", "paper_2604_05867_amd/csrc/ba_factored_common.h"],
+    # of the sources concatenated; the figures: profiles/factored_sweeps_n20_fp32_x3.md
+    "sha256": "e44211823bbf326e81990cb2540c8312959adba13b048a0a66c8f52d5b6c977e",
+    # average over the launches of one sweep (forward: 4 four-position + 2 two-position
+    # launches; backward: 5 four-position launches, D fused into the last)
+    "sweep1": 53817613,
+    "sweep2": 63273876,
 }
 
 
-def measured_traffic(sweep):
-    """The PMC traffic figure of a sweep if the kernel source is unchanged since it
-    was taken, else None."""
+def kernel_source_sha():
     import hashlib
-    if MEASURED_TRAFFIC["sha256"] is None:
+    h = hashlib.sha256()
+    for src in MEASURED_TRAFFIC["sources"]:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(sweep):
+    """The PMC traffic figure of a sweep if the kernel sources are unchanged since it
+    was taken, else None."""
+    if MEASURED_TRAFFIC["sha256"] is None or kernel_source_sha() != MEASURED_TRAFFIC["sha256"]:
         return None
-    with open(os.path.join(ROOT, MEASURED_TRAFFIC["source"]), "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != MEASURED_TRAFFIC["sha256"]:
-            return None
     return MEASURED_TRAFFIC[sweep]
 
 
