@@ -114,7 +114,8 @@ __device__ __forceinline__ uint32_t logical_block() {
 // (row, chunk) of logical slot q; false for a padding slot or past the end.
 __device__ __forceinline__ bool order_slot_q(const Order& o, uint32_t q, uint32_t& row, uint32_t& chunk) {
   const uint32_t rest = q >> o.cw_log2;
-  const uint32_t ct = rest / o.nlog;
+  // one column tile (narrow rows): no division
+  const uint32_t ct = (o.nct == 1u) ? (rest >= o.nlog ? 1u : 0u) : rest / o.nlog;
   if (ct >= o.nct) return false;
   uint32_t L = rest - ct * o.nlog;
   chunk = (ct << o.cw_log2) + (q & ((1u << o.cw_log2) - 1u));
