@@ -38,11 +38,11 @@ FUSE = 2  # the library default: four positions per launch of the factored engin
 MEASURED_TRAFFIC = {
     "sources": ["paper_2604_05867_amd/csrc/ba_factored.hip", "paper_2604_05867_amd/csrc/ba_factored_common.h"],
     # of the sources concatenated; the figures: profiles/factored_sweeps_n20_fp32_x3.md
-    "sha256": "e44211823bbf326e81990cb2540c8312959adba13b048a0a66c8f52d5b6c977e",
+    "sha256": "11589f0402b610577ad3aaeaf1c644b95a20148ef6e22b96fb58eb1f396fa19d",
     # average over the launches of one sweep (forward: 4 four-position + 2 two-position
     # launches; backward: 5 four-position launches, D fused into the last)
-    "sweep1": 53817613,
-    "sweep2": 63273876,
+    "sweep1": 53821139,
+    "sweep2": 63265925,
 }
 
 
