@@ -16,7 +16,7 @@ from oracle import bdc
 
 pytestmark = pytest.mark.gpu
 LN2 = math.log(2.0)
-ENGINES = ("factored", "stream")
+ENGINES = ("factored", "stream", "pull")
 
 
 @pytest.fixture(scope="module")
@@ -29,7 +29,7 @@ def ba():
 
 
 def engine_id(ba, name):
-    return ba.ENGINE_FACTORED if name == "factored" else ba.ENGINE_STREAM
+    return {"factored": ba.ENGINE_FACTORED, "stream": ba.ENGINE_STREAM, "pull": ba.ENGINE_PULL}[name]
 
 
 def say(*a):
