@@ -96,27 +96,40 @@ __global__ __launch_bounds__(kBlock) void k_fwd_stage4(int n, int i, const T* __
   const int ly = length_of_rank(y);
   uint32_t P[5], lastb[4];
   fwd4_path(y, P, lastb);
-  T F0[4][16], H4[8];
+  // first stage row by row from the deepest ancestor up, so that only one loaded
+  // row and the half of the row below it are live at a time
+  T F1p[4][8], F1s[2][8], Hc[8];
 #pragma unroll
-  for (int j = 0; j < 4; ++j)
-#pragma unroll
-    for (int u = 0; u < 16; ++u) F0[j][u] = T(0);
-#pragma unroll
-  for (int u = 0; u < 8; ++u) H4[u] = T(0);
-#pragma unroll
-  for (int j = 0; j < 4; ++j)
-    if (j <= ly) {
-      const T* row = src + ((size_t)P[j] << (sh + 4)) + s;
-#pragma unroll
-      for (int u = 0; u < 16; ++u) F0[j][u] = row[uint32_t(u) << sh];
-    }
+  for (int u = 0; u < 8; ++u) Hc[u] = T(0);
   if (4 <= ly) {
     const T* row = src + ((size_t)P[4] << (sh + 4)) + (lastb[3] << (sh + 3)) + s;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) H4[u] = row[uint32_t(u) << sh];
+    for (int u = 0; u < 8; ++u) Hc[u] = row[uint32_t(u) << sh];
+  }
+#pragma unroll
+  for (int j = 3; j >= 0; --j) {
+    T R[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) R[u] = T(0);
+    if (j <= ly) {
+      const T* row = src + ((size_t)P[j] << (sh + 4)) + s;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) R[u] = row[uint32_t(u) << sh];
+    }
+#pragma unroll
+    for (int g = 0; g < 8; ++g) F1p[j][g] = (R[g] + R[8 + g]) + Hc[g];
+    if (j > 0) {
+#pragma unroll
+      for (int g = 0; g < 8; ++g) Hc[g] = lastb[j - 1] ? R[8 + g] : R[g];
+    } else {
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int g = 0; g < 8; ++g) F1s[c][g] = R[c * 8 + g];
+    }
   }
   T F4[30];
-  T vy = fwd4_registers<T>(F0, H4, lastb, F4);
+  T vy = fwd4_after_stage1<T>(F1p, F1s, lastb, F4);
   if constexpr (LOGV) vy = log_weighted<T>(cs[b], y, vy);
   dst[((size_t)y << sh) + s] = vy;
   if (ly != i) return;
@@ -157,11 +170,14 @@ __global__ __launch_bounds__(kBlock) void k_bwd_stage(int n, int i, const T* __r
     Vec<T, V> o;
 #pragma unroll
     for (int k = 0; k < V; ++k) o.v[k] = a.v[k] + c.v[k];
-    if constexpr (DP) d_epilogue<T, V>(g, b, M, idx, o, p);
+    if constexpr (DP) {
+      const uint32_t xs[1] = {idx};
+      const Vec<T, V> gs[1] = {o};
+      d_records<T, V, 1>(g, b, M, xs, gs, p);
+    }
     else stv<T, V>(dst + idx, o);
   }
   if constexpr (DP) {
-    p = block_reduce(p);
     store_block_part(g.part + (size_t)b * g.ps, blockIdx.x, p);
   }
 }
@@ -270,6 +286,120 @@ __global__ __launch_bounds__(kBlock) void k_fwd_stage2_w1(int n, const T* __rest
     if (ok[m]) fwd_w1_finish<T, LOGV>(c[m], w[m], dst, cs[b]);
 }
 
+// The last two positions for n >= kLast2MinN, in the same formula as
+// k_fwd_stage2_w1 (source rows of width 4, output rows of width 1):
+//   r(c) = sum_u F[c][u] + 2 F[p][3 last(c)] + F[p][1] + F[p][2] + F[g][2 last(p) + last(c)]
+// (p the parent, g the grandparent of c; terms of rows longer than n-2 are zero).
+// Deep blocks (blockIdx.x < 2^(n-4) / kBlock): thread t takes the row a of level
+// L = n-4 of rank A0 + t and every output row of a's subtree down to level n (31
+// rows): it loads F of a, its 2 children and 4 grandchildren (its whole source
+// subtree), of a's parent and one value of its grandparent.  Each level of a
+// block's outputs is a contiguous run of ranks (kLast2Threads * 2^j values at
+// level L+j), so the values are staged in LDS (row stride 2^j + 1 against bank
+// conflicts) and written back coalesced.  The other blocks take one output row of
+// level < L per thread.  Each output is the same sum, in the same order, as in
+// k_fwd_stage2_w1.  One wavefront per block: its load, sum and store phases then
+// drift apart from those of the other blocks on the CU (256-thread blocks, whose
+// phases coincide, took 21.4 us at n = 20 and three instances; 64-thread blocks
+// 13.6 us; the per-row kernel 17.4 us).
+constexpr int kLast2Threads = 64;   // threads per block
+constexpr int kLast2MinN = 12;      // 2^(n-4) >= kLast2Threads
+constexpr int kLast2Lds = 1 + 3 + 5 + 9 + 17;  // LDS values per thread (padded)
+
+template <typename T>
+__device__ __forceinline__ T last2_sum(const Vec<T, 4>& own, const Vec<T, 4>& par, uint32_t b, T gv) {
+  const T e = b ? par.v[3] : par.v[0];
+  return (((own.v[0] + own.v[1]) + (own.v[2] + own.v[3])) + ((e + e) + (par.v[1] + par.v[2]))) + gv;
+}
+// No own row (level n-1): the same sum with the own terms zero.
+template <typename T>
+__device__ __forceinline__ T last2_sum_noown(const Vec<T, 4>& par, uint32_t b, T gv) {
+  const T e = b ? par.v[3] : par.v[0];
+  return ((e + e) + (par.v[1] + par.v[2])) + gv;
+}
+
+template <typename T, bool LOGV>
+__global__ __launch_bounds__(kLast2Threads) void k_fwd_last2(int n, const T* __restrict__ src, size_t sstride,
+                                                      T* __restrict__ dst, size_t dstride, const State* st,
+                                                      const Consts* cs) {
+  const int b = blockIdx.y;
+  if (st[b].converged) return;
+  src += (size_t)b * sstride;
+  dst += (size_t)b * dstride;
+  const int L = n - 4;
+  const uint32_t ndeep = (1u << L) / kLast2Threads;
+  const uint32_t t = threadIdx.x;
+  // v = w_k log r at the five levels L .. L+4 (LOGV), else r
+  const T w0 = T(cs[b].w[L]), w1 = T(cs[b].w[L + 1]), w2 = T(cs[b].w[L + 2]), w3 = T(cs[b].w[L + 3]),
+          w4 = T(cs[b].w[L + 4]);
+  auto outv = [](T w, T r) -> T {
+    if constexpr (LOGV) return (w == T(0)) ? T(0) : w * log_t<T>(r);
+    else return r;
+  };
+  if (blockIdx.x >= ndeep) {
+    // shallow rows: levels 0 .. L-1, ranks 0 .. 2^L - 2
+    const uint32_t c = (blockIdx.x - ndeep) * kLast2Threads + t;
+    if (c + 1u >= (1u << L)) return;
+    const Vec<T, 4> own = ld<T, 4>(src + 4u * c);
+    Vec<T, 4> par = zero_vec<T, 4>();
+    T gv = T(0);
+    const uint32_t pr = (c - 1u) >> 1, bb = (c - 1u) & 1u;
+    if (c >= 1u) par = ld<T, 4>(src + 4u * pr);
+    if (c >= 3u) gv = src[4u * ((pr - 1u) >> 1) + 2u * ((pr - 1u) & 1u) + bb];
+    T r = last2_sum<T>(own, par, bb, gv);
+    if constexpr (LOGV) r = log_weighted<T>(cs[b], c, r);
+    dst[c] = r;
+    return;
+  }
+  __shared__ T stage[kLast2Lds * kLast2Threads];
+  const uint32_t A0 = (1u << L) - 1u + blockIdx.x * kLast2Threads;
+  const uint32_t a = A0 + t;
+  const uint32_t pa = (a - 1u) >> 1, ba = (a - 1u) & 1u;  // L >= 8: parent and grandparent exist
+  const uint32_t ga = (pa - 1u) >> 1, bp = (pa - 1u) & 1u;
+  const Vec<T, 4> A = ld<T, 4>(src + 4u * a);
+  const Vec<T, 4> P = ld<T, 4>(src + 4u * pa);
+  const T gA = src[4u * ga + 2u * bp + ba];
+  Vec<T, 4> C[2], GC[4];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) C[q] = ld<T, 4>(src + 4u * (2u * a + 1u + q));
+#pragma unroll
+  for (int q = 0; q < 4; ++q) GC[q] = ld<T, 4>(src + 4u * (4u * a + 3u + q));
+  // the grandparent terms of a's children: P[2 last(a) + q], selected by value
+  const T P0 = P.v[0], P1 = P.v[1], P2 = P.v[2], P3 = P.v[3];
+  const T Pq[2] = {ba ? P2 : P0, ba ? P3 : P1};
+  // level L (stride 1), L+1 (3), L+2 (5), L+3 (9), L+4 (17) regions of the stage
+  T* s0 = stage;
+  T* s1 = s0 + kLast2Threads;
+  T* s2 = s1 + 3 * kLast2Threads;
+  T* s3 = s2 + 5 * kLast2Threads;
+  T* s4 = s3 + 9 * kLast2Threads;
+  s0[t] = outv(w0, last2_sum<T>(A, P, ba, gA));
+#pragma unroll
+  for (int q = 0; q < 2; ++q) s1[3u * t + q] = outv(w1, last2_sum<T>(C[q], A, uint32_t(q), Pq[q]));
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    s2[5u * t + q] = outv(w2, last2_sum<T>(GC[q], C[q >> 1], uint32_t(q & 1), A.v[q]));
+#pragma unroll
+  for (int q = 0; q < 8; ++q)
+    s3[9u * t + q] = outv(w3, last2_sum_noown<T>(GC[q >> 1], uint32_t(q & 1), C[q >> 2].v[q & 3]));
+#pragma unroll
+  for (int q = 0; q < 16; ++q) s4[17u * t + q] = outv(w4, GC[q >> 2].v[q & 3]);
+  __syncthreads();
+  // level L+j: kLast2Threads * 2^j consecutive ranks from 2^j (A0 + 1) - 1
+  dst[A0 + t] = s0[t];
+#pragma unroll
+  for (int j = 1; j <= 4; ++j) {
+    const uint32_t w2 = 1u << j, stride = w2 + 1u;
+    const T* sj = j == 1 ? s1 : j == 2 ? s2 : j == 3 ? s3 : s4;
+    T* out = dst + (w2 * (A0 + 1u) - 1u);
+#pragma unroll
+    for (uint32_t k = 0; k < w2; ++k) {
+      const uint32_t e = k * kLast2Threads + t;
+      out[e] = sj[(e >> j) * stride + (e & (w2 - 1u))];
+    }
+  }
+}
+
 // Two backward stages at once (positions i and i+1): for a row r of B_i and
 // columns (b, c, s''),
 //   B_i[r][b c s''] = B_{i+2}[r] + B_{i+2}[r c] + B_{i+2}[r b] + B_{i+2}[r b c]
@@ -309,10 +439,9 @@ __global__ __launch_bounds__(kBlock) void k_bwd_stage2(int n, int i, const T* __
     }
     if constexpr (DP) {
       const double M = g.st[b].M;
-      d_epilogue<T, V>(g, b, M, s, o00, p);
-      d_epilogue<T, V>(g, b, M, S + s, o01, p);
-      d_epilogue<T, V>(g, b, M, 2 * S + s, o10, p);
-      d_epilogue<T, V>(g, b, M, 3 * S + s, o11, p);
+      const uint32_t xs[4] = {s, S + s, 2 * S + s, 3 * S + s};
+      const Vec<T, V> gs[4] = {o00, o01, o10, o11};
+      d_records<T, V, 4>(g, b, M, xs, gs, p);
     } else {
       T* op = dst + (r << (sh + 2)) + s;
       stv<T, V>(op, o00);
@@ -322,7 +451,6 @@ __global__ __launch_bounds__(kBlock) void k_bwd_stage2(int n, int i, const T* __
     }
   }
   if constexpr (DP) {
-    p = block_reduce(p);
     store_block_part(g.part + (size_t)b * g.ps, blockIdx.x, p);
   }
 }
@@ -336,6 +464,75 @@ __global__ __launch_bounds__(kBlock) void k_bwd_stage2(int n, int i, const T* __
 // 2t+1 and 2t+2, the same as ranks) and applies the 4 single stages
 // B_k[z][b g] = B_{k+1}[z][g] + B_{k+1}[z b][g] in registers.  DP: stage 0 (one
 // row), write D and the reduction records instead of G.
+// Loads of one (y, column s) of the four-position backward step: the 31 rows of
+// y's depth-4 subtree, breadth-first (index t, children 2t+1 and 2t+2, as ranks).
+template <typename T, int V>
+__device__ __forceinline__ void bwd4_load(const T* __restrict__ src, int sh, uint32_t y, uint32_t s,
+                                          Vec<T, V> (&S)[31]) {
+#pragma unroll
+  for (int d = 0; d <= 4; ++d)
+#pragma unroll
+    for (int m = 0; m < (1 << d); ++m)
+      S[(1 << d) - 1 + m] = ld<T, V>(src + ((((y + 1u) << d) - 1u + uint32_t(m)) << sh) + s);
+}
+
+// The 4 single stages B_k[z][b g] = B_{k+1}[z][g] + B_{k+1}[z b][g] in registers:
+// Dv[u] = B_i[y][u s].
+template <typename T, int V>
+__device__ __forceinline__ void bwd4_tree(const Vec<T, V> (&S)[31], Vec<T, V> (&Dv)[16]) {
+  Vec<T, V> A[15][2];
+#pragma unroll
+  for (int t = 0; t < 15; ++t)
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+      A[t][0].v[k] = S[t].v[k] + S[2 * t + 1].v[k];
+      A[t][1].v[k] = S[t].v[k] + S[2 * t + 2].v[k];
+    }
+  Vec<T, V> B[7][4];
+#pragma unroll
+  for (int t = 0; t < 7; ++t)
+#pragma unroll
+    for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int k = 0; k < V; ++k) B[t][bb * 2 + q].v[k] = A[t][q].v[k] + A[2 * t + 1 + bb][q].v[k];
+  Vec<T, V> C[3][8];
+#pragma unroll
+  for (int t = 0; t < 3; ++t)
+#pragma unroll
+    for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int k = 0; k < V; ++k) C[t][bb * 4 + q].v[k] = B[t][q].v[k] + B[2 * t + 1 + bb][q].v[k];
+#pragma unroll
+  for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+#pragma unroll
+      for (int k = 0; k < V; ++k) Dv[bb * 8 + q].v[k] = C[0][q].v[k] + C[1 + bb][q].v[k];
+}
+
+// Row y of B_i at columns u S4 + s (u = 0..15); 16 consecutive values when S4 = 1.
+template <typename T, int V>
+__device__ __forceinline__ void bwd4_store(T* __restrict__ dst, int sh, uint32_t y, uint32_t s,
+                                           const Vec<T, V> (&Dv)[16]) {
+  T* op = dst + (y << (sh + 4)) + s;
+  if (V == 1 && sh == 0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      Vec<T, 4> w;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) w.v[k] = Dv[4 * q + k].v[0];
+      stv<T, 4>(op + 4 * q, w);
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) stv<T, V>(op + (uint32_t(u) << sh), Dv[u]);
+  }
+}
+
 template <typename T, int V, bool DP>
 __global__ __launch_bounds__(kBlock) void k_bwd_stage4(int n, int i, const T* __restrict__ src, size_t sstride,
                                                        T* __restrict__ dst, size_t dstride, Group<T> g, Order o) {
@@ -350,68 +547,20 @@ __global__ __launch_bounds__(kBlock) void k_bwd_stage4(int n, int i, const T* __
   const uint32_t s = chunk * V;
   Part p = part_empty();
   if (valid) {
-    Vec<T, V> S[31];
-#pragma unroll
-    for (int d = 0; d <= 4; ++d)
-#pragma unroll
-      for (int m = 0; m < (1 << d); ++m)
-        S[(1 << d) - 1 + m] = ld<T, V>(src + ((((y + 1u) << d) - 1u + uint32_t(m)) << sh) + s);
-    Vec<T, V> A[15][2];
-#pragma unroll
-    for (int t = 0; t < 15; ++t)
-#pragma unroll
-      for (int k = 0; k < V; ++k) {
-        A[t][0].v[k] = S[t].v[k] + S[2 * t + 1].v[k];
-        A[t][1].v[k] = S[t].v[k] + S[2 * t + 2].v[k];
-      }
-    Vec<T, V> B[7][4];
-#pragma unroll
-    for (int t = 0; t < 7; ++t)
-#pragma unroll
-      for (int bb = 0; bb < 2; ++bb)
-#pragma unroll
-        for (int q = 0; q < 2; ++q)
-#pragma unroll
-          for (int k = 0; k < V; ++k) B[t][bb * 2 + q].v[k] = A[t][q].v[k] + A[2 * t + 1 + bb][q].v[k];
-    Vec<T, V> C[3][8];
-#pragma unroll
-    for (int t = 0; t < 3; ++t)
-#pragma unroll
-      for (int bb = 0; bb < 2; ++bb)
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-          for (int k = 0; k < V; ++k) C[t][bb * 4 + q].v[k] = B[t][q].v[k] + B[2 * t + 1 + bb][q].v[k];
-    Vec<T, V> Dv[16];
-#pragma unroll
-    for (int bb = 0; bb < 2; ++bb)
-#pragma unroll
-      for (int q = 0; q < 8; ++q)
-#pragma unroll
-        for (int k = 0; k < V; ++k) Dv[bb * 8 + q].v[k] = C[0][q].v[k] + C[1 + bb][q].v[k];
-    const uint32_t S4 = 1u << sh;
+    Vec<T, V> S[31], Dv[16];
+    bwd4_load<T, V>(src, sh, y, s, S);
+    bwd4_tree<T, V>(S, Dv);
     if constexpr (DP) {
       const double M = g.st[b].M;
+      uint32_t xs[16];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) d_epilogue<T, V>(g, b, M, uint32_t(u) * S4 + s, Dv[u], p);
+      for (int u = 0; u < 16; ++u) xs[u] = (uint32_t(u) << sh) + s;
+      d_records<T, V, 16>(g, b, M, xs, Dv, p);
     } else {
-      T* op = dst + (y << (sh + 4)) + s;
-      if (V == 1 && sh == 0) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          Vec<T, 4> w;
-#pragma unroll
-          for (int k = 0; k < 4; ++k) w.v[k] = Dv[4 * q + k].v[0];
-          stv<T, 4>(op + 4 * q, w);
-        }
-      } else {
-#pragma unroll
-        for (int u = 0; u < 16; ++u) stv<T, V>(op + uint32_t(u) * S4, Dv[u]);
-      }
+      bwd4_store<T, V>(dst, sh, y, s, Dv);
     }
   }
   if constexpr (DP) {
-    p = block_reduce(p);
     store_block_part(g.part + (size_t)b * g.ps, blockIdx.x, p);
   }
 }
@@ -481,7 +630,15 @@ hipError_t launch_forward(const Group<T>& g, hipStream_t s, int* launches, int f
     else { dst = (k & 1) ? g.f1 : g.f0; ds = g.fs; }
     if (step == 2) {
       const uint32_t S = 1u << (n - i - 2);  // output row width
-      if (S == 1u) {
+      if (S == 1u && n >= kLast2MinN) {
+        const dim3 grid(2u * ((1u << (n - 4)) / kLast2Threads), g.nb);
+        if (lv)
+          hipLaunchKernelGGL((k_fwd_last2<T, true>), grid, dim3(kLast2Threads), 0, s, n, src, ss, dst, ds, g.st,
+                             g.cs);
+        else
+          hipLaunchKernelGGL((k_fwd_last2<T, false>), grid, dim3(kLast2Threads), 0, s, n, src, ss, dst, ds, g.st,
+                             g.cs);
+      } else if (S == 1u) {
         const Order o = make_order(n + 1, 0, 4 * sizeof(T));
         const dim3 grid(blocks_for((order_threads(o) + 3u) / 4u), g.nb);
         if (lv)
@@ -548,6 +705,8 @@ hipError_t launch_backward(const Group<T>& g, hipStream_t s, int* launches, int 
       } else {
         // one column per thread (2 or 4 per thread measured no faster: 0.079 ms per
         // backward sweep at n = 20 for 1, 0.081 for 2 and 4)
+        // (two items per thread with all loads issued first: 0.0774 ms per sweep;
+        // four: 0.0865)
         hipLaunchKernelGGL((k_bwd_stage4<T, 1, false>), dim3(nbk, g.nb), dim3(kBlock), 0, s, n, i, src, ss, dst, ds,
                            g, o);
       }

@@ -51,13 +51,6 @@ __device__ __forceinline__ Vec<T, V> zero_vec() {
   return z;
 }
 
-template <typename T>
-__device__ __forceinline__ T log_t(T v);
-template <>
-__device__ __forceinline__ float log_t<float>(float v) { return logf(v); }
-template <>
-__device__ __forceinline__ double log_t<double>(double v) { return log(v); }
-
 // v(y) = w_k log r(y) for the output of rank y (0 where w_k = 0).
 template <typename T>
 __device__ __forceinline__ T log_weighted(const Consts& cs, uint32_t y, T r) {
@@ -137,44 +130,67 @@ __device__ __forceinline__ bool order_slot(const Order& o, uint32_t& row, uint32
   return order_slot_q(o, logical_block() * kBlock + threadIdx.x, row, chunk);
 }
 
-// D(x) = H(x) - G(x) - M for V consecutive inputs, accumulated into the record.
-template <typename T, int V>
-__device__ __forceinline__ void d_epilogue(const Group<T>& g, int b, double M, uint32_t x, const Vec<T, V>& G,
-                                           Part& p, double wt = 1.0) {
-  const Vec<T, V> h = ld<T, V>(g.hf + (size_t)b * g.xs + x);
-  const Vec<T, V> l = ld<T, V>(g.lp + (size_t)b * g.xs + x);
-  Vec<T, V> d;
+// D(x) = H(x) - G(x) - M for N groups of V consecutive inputs (group u starts at
+// input x[u]): D is stored and the inputs' terms are added to the record p.  The
+// maxima of log p + D (and of log p + eta D) and of D over the groups, then the sums
+// of exponentials relative to those maxima and of p D, are formed in the iterate's
+// precision T with no branch per input, and folded into p once.  wt: the number of
+// inputs each value stands for (2 when only one of each complement pair is
+// evaluated).
+template <typename T, int V, int N>
+__device__ __forceinline__ void d_records(const Group<T>& g, int b, double M, const uint32_t (&x)[N],
+                                          const Vec<T, V> (&G)[N], Part& p, double wt = 1.0) {
+  const T* hf = g.hf + (size_t)b * g.xs;
+  const T* lp = g.lp + (size_t)b * g.xs;
+  T* D = g.D + (size_t)b * g.xs;
+  Vec<T, V> l[N], d[N];
+  T am = T(-INFINITY), dm = T(-INFINITY);
 #pragma unroll
-  for (int k = 0; k < V; ++k) {
-    d.v[k] = h.v[k] - G.v[k] - T(M);
-    const double lk = double(l.v[k]);
-    part_add<T>(p, lk + double(d.v[k]), double(d.v[k]), exp_in(lk, T()), 0.0, wt, g.eta != 1.0,
-                lk + g.eta * double(d.v[k]));
+  for (int u = 0; u < N; ++u) {
+    const Vec<T, V> h = ld<T, V>(hf + x[u]);
+    l[u] = ld<T, V>(lp + x[u]);
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+      d[u].v[k] = h.v[k] - G[u].v[k] - T(M);
+      am = fmax(am, l[u].v[k] + d[u].v[k]);
+      dm = fmax(dm, d[u].v[k]);
+    }
+    stv<T, V>(D + x[u], d[u]);
   }
-  stv<T, V>(g.D + (size_t)b * g.xs + x, d);
+  T s = T(0), i = T(0);
+#pragma unroll
+  for (int u = 0; u < N; ++u)
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+      s += exp_t<T>((l[u].v[k] + d[u].v[k]) - am);
+      i += exp_t<T>(l[u].v[k]) * d[u].v[k];
+    }
+  Part q{double(am), wt * double(s), double(dm), wt * double(i), 0.0, -INFINITY, 0.0};
+  if (g.eta != 1.0) {
+    const T eta = T(g.eta);
+    T m2 = T(-INFINITY), s2 = T(0);
+#pragma unroll
+    for (int u = 0; u < N; ++u)
+#pragma unroll
+      for (int k = 0; k < V; ++k) m2 = fmax(m2, l[u].v[k] + eta * d[u].v[k]);
+#pragma unroll
+    for (int u = 0; u < N; ++u)
+#pragma unroll
+      for (int k = 0; k < V; ++k) s2 += exp_t<T>((l[u].v[k] + eta * d[u].v[k]) - m2);
+    q.m2 = double(m2);
+    q.s2 = wt * double(s2);
+  }
+  p = part_is_empty(p) ? q : combine(p, q);
 }
 
-// Register part of the four-position forward step for one (y, column): F0 holds
-// F_i of the path P_0 = y .. P_3 (16 groups) and H4 the half of P_4 selected by
-// last(P_3); lastb[j] = last bit of P_j.  Returns F_{i+4}[y] and, in F4, the 30
-// rows below y (breadth-first: depth d, index m at (1 << d) - 2 + m).
+// Register part of the four-position forward step for one (y, column), from the
+// first stage on: F1p holds F_{i+1} of the path P_0 = y .. P_3 (8 groups), F1s
+// that of the two children of y; lastb[j] = last bit of P_j.  Returns F_{i+4}[y]
+// and, in F4, the 30 rows below y (breadth-first: depth d, index m at
+// (1 << d) - 2 + m).
 template <typename T>
-__device__ __forceinline__ T fwd4_registers(const T (&F0)[4][16], const T (&H4)[8], const uint32_t (&lastb)[4],
-                                            T (&F4)[30]) {
-  // stage 1: path P_0..P_3 (8 groups), children of y (parent halves chosen by
-  // select, so every register index is static)
-  T F1p[4][8], F1s[2][8];
-#pragma unroll
-  for (int j = 0; j < 3; ++j)
-#pragma unroll
-    for (int g = 0; g < 8; ++g)
-      F1p[j][g] = (F0[j][g] + F0[j][8 + g]) + (lastb[j] ? F0[j + 1][8 + g] : F0[j + 1][g]);
-#pragma unroll
-  for (int g = 0; g < 8; ++g) F1p[3][g] = (F0[3][g] + F0[3][8 + g]) + H4[g];
-#pragma unroll
-  for (int c = 0; c < 2; ++c)
-#pragma unroll
-    for (int g = 0; g < 8; ++g) F1s[c][g] = F0[0][c * 8 + g];
+__device__ __forceinline__ T fwd4_after_stage1(const T (&F1p)[4][8], const T (&F1s)[2][8],
+                                               const uint32_t (&lastb)[4], T (&F4)[30]) {
   // stage 2: path P_0..P_2 (4 groups), subtree depth 1..2 (breadth-first 0..5)
   T F2p[3][4], F2s[6][4];
 #pragma unroll
@@ -219,6 +235,28 @@ __device__ __forceinline__ T fwd4_registers(const T (&F0)[4][16], const T (&H4)[
 #pragma unroll
   for (int c = 0; c < 16; ++c) F4[14 + c] = F3s[6 + (c >> 1)][c & 1];
   return (F3p[0][0] + F3p[0][1]) + (lastb[0] ? F3p[1][1] : F3p[1][0]);
+}
+
+// Stage 1 from the loaded rows F0 (path P_0..P_3, 16 column groups) and H4 (the
+// half of P_4 selected by the last bit of P_3), then stages 2-4.
+template <typename T>
+__device__ __forceinline__ T fwd4_registers(const T (&F0)[4][16], const T (&H4)[8], const uint32_t (&lastb)[4],
+                                            T (&F4)[30]) {
+  // stage 1: path P_0..P_3 (8 groups), children of y (parent halves chosen by
+  // select, so every register index is static)
+  T F1p[4][8], F1s[2][8];
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int g = 0; g < 8; ++g)
+      F1p[j][g] = (F0[j][g] + F0[j][8 + g]) + (lastb[j] ? F0[j + 1][8 + g] : F0[j + 1][g]);
+#pragma unroll
+  for (int g = 0; g < 8; ++g) F1p[3][g] = (F0[3][g] + F0[3][8 + g]) + H4[g];
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int g = 0; g < 8; ++g) F1s[c][g] = F0[0][c * 8 + g];
+  return fwd4_after_stage1<T>(F1p, F1s, lastb, F4);
 }
 
 // Path ranks of y and their last bits: P_{j+1} = parent(P_j) (garbage past the

@@ -13,6 +13,20 @@
 
 namespace ba {
 
+// log and exp in the iterate's precision
+template <typename T>
+__device__ __forceinline__ T log_t(T v);
+template <>
+__device__ __forceinline__ float log_t<float>(float v) { return logf(v); }
+template <>
+__device__ __forceinline__ double log_t<double>(double v) { return log(v); }
+template <typename T>
+__device__ __forceinline__ T exp_t(T v);
+template <>
+__device__ __forceinline__ float exp_t<float>(float v) { return expf(v); }
+template <>
+__device__ __forceinline__ double exp_t<double>(double v) { return exp(v); }
+
 struct Part {
   double m;     // max of a = log p + D
   double s;     // sum exp(a - m)
@@ -45,6 +59,9 @@ __device__ __forceinline__ Part combine(const Part& a, const Part& b) {
   c.s2 = (c.m2 == -INFINITY) ? 0.0 : lse_merge_s(a.m2, a.s2, b.m2, b.s2, c.m2);
   return c;
 }
+
+// True for a record that no input has been added to.
+__device__ __forceinline__ bool part_is_empty(const Part& p) { return p.s == 0.0 && p.dmax == -INFINITY; }
 
 __device__ __forceinline__ double exp_in(double v, double) { return exp(v); }
 __device__ __forceinline__ double exp_in(double v, float) { return double(expf(float(v))); }
@@ -141,10 +158,20 @@ __device__ __forceinline__ Part gather_parts(const double* src, int nblk) {
   return block_reduce(p);
 }
 
-// Store this block's record (index rec) of an instance whose records start at
-// `part` (thread 0 writes).
-__device__ __forceinline__ void store_block_part(double* part, int rec, const Part& blk) {
-  if (threadIdx.x == 0) store_part(part + (size_t)rec * kPartStride, blk);
+// Reduce the block's records and store the result as record rec of an instance
+// whose records start at `part`.  Only thread 0 combines the per-wave records and
+// writes (blockDim.x == kBlock).
+__device__ __forceinline__ void store_block_part(double* part, int rec, Part p) {
+  __shared__ Part sp[kBlock / kWave];
+  p = wave_reduce(p);
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  if (lane == 0) sp[wave] = p;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    Part r = sp[0];
+    for (int w = 1; w < kBlock / kWave; ++w) r = combine(r, sp[w]);
+    store_part(part + (size_t)rec * kPartStride, r);
+  }
 }
 
 }  // namespace ba

@@ -18,19 +18,6 @@ namespace {
 
 __device__ __forceinline__ int length_of_rank(uint32_t r) { return 31 - __clz(r + 1u); }
 
-template <typename T>
-__device__ __forceinline__ T log_t(T v);
-template <>
-__device__ __forceinline__ float log_t<float>(float v) { return logf(v); }
-template <>
-__device__ __forceinline__ double log_t<double>(double v) { return log(v); }
-template <typename T>
-__device__ __forceinline__ T exp_t(T v);
-template <>
-__device__ __forceinline__ float exp_t<float>(float v) { return expf(v); }
-template <>
-__device__ __forceinline__ double exp_t<double>(double v) { return exp(v); }
-
 // v(y) = w_k log r(y)  (or s_k w_k log r(y)); a zero weight gives 0.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_logr(Group<T> g, int use_sw) {
@@ -89,7 +76,6 @@ __global__ __launch_bounds__(kBlock) void k_dpart(Group<T> g, int nblk, int use_
     const double pdd = use_hd ? px * (g.hd[(size_t)b * g.xs + x] - double(gd[(size_t)b * g.xs + x])) : 0.0;
     part_add<T>(p, l + double(dv), double(dv), px, pdd, 1.0, g.eta != 1.0, l + g.eta * double(dv));
   }
-  p = block_reduce(p);
   store_block_part(g.part + (size_t)b * g.ps, blockIdx.x, p);
 }
 

@@ -222,8 +222,9 @@ __global__ __launch_bounds__(kBlock) void k_bwd_stage2_sym(int n, int i, const T
     }
     if constexpr (DP) {
       const double M = g.st[b].M;
-      d_epilogue<T, V>(g, b, M, s, o00, p, 2.0);
-      d_epilogue<T, V>(g, b, M, S + s, o01, p, 2.0);
+      const uint32_t xs[2] = {s, S + s};
+      const Vec<T, V> gs[2] = {o00, o01};
+      d_records<T, V, 2>(g, b, M, xs, gs, p, 2.0);
     } else {
       T* op = dst + (r << (sh + 1)) + s;
       stv<T, V>(op, o00);
@@ -231,7 +232,6 @@ __global__ __launch_bounds__(kBlock) void k_bwd_stage2_sym(int n, int i, const T
     }
   }
   if constexpr (DP) {
-    p = block_reduce(p);
     store_block_part(g.part + (size_t)b * g.ps, blockIdx.x, p);
   }
 }
@@ -381,16 +381,17 @@ __global__ __launch_bounds__(kBlock) void k_bwd_stage4_sym(int n, int i, const T
       if constexpr (DP) {
         // i = 0: w is the empty row; columns s and S4 - 1 - s (the same column when S4 = 1)
         const double M = g.st[b].M;
+        uint32_t xs[8], xm[8];
+        Vec<T, 1> gs[8], gm[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-          Vec<T, 1> gv;
-          gv.v[0] = Dv[u];
-          d_epilogue<T, 1>(g, b, M, uint32_t(u) * S4 + s, gv, p, 2.0);
-          if (S4 > 1u) {
-            gv.v[0] = Dm[u];
-            d_epilogue<T, 1>(g, b, M, uint32_t(u) * S4 + (S4 - 1u - s), gv, p, 2.0);
-          }
+          xs[u] = uint32_t(u) * S4 + s;
+          xm[u] = uint32_t(u) * S4 + (S4 - 1u - s);
+          gs[u].v[0] = Dv[u];
+          gm[u].v[0] = Dm[u];
         }
+        d_records<T, 1, 8>(g, b, M, xs, gs, p, 2.0);
+        if (S4 > 1u) d_records<T, 1, 8>(g, b, M, xm, gm, p, 2.0);
       } else {
         T* op = dst + ((size_t)wr << (sh + 3));
         T* om = dst + ((size_t)wm << (sh + 3));
@@ -403,7 +404,6 @@ __global__ __launch_bounds__(kBlock) void k_bwd_stage4_sym(int n, int i, const T
     }
   }
   if constexpr (DP) {
-    p = block_reduce(p);
     store_block_part(g.part + (size_t)b * g.ps, blockIdx.x, p);
   }
 }
