@@ -28,7 +28,7 @@ sys.path.insert(0, ROOT)
 
 N = 20
 DS = [0.64, 0.80, 0.95]
-FUSE = 2  # the library default: four positions per launch of the factored engine
+FUSE = 3  # the library default: eight (backward) / four positions per launch of the factored engine
 
 
 # HBM bytes per forward-sweep launch of this workload, from rocprofv3 FETCH_SIZE and
@@ -74,19 +74,22 @@ def sweep_launch_bytes(n, esz, nb, fuse, backward):
     and writes its destination stage once; the last backward launch also reads
     H and log p (D is formed there).  Launch sequence as in the library: fuse 2 =
     four positions per launch (forward: the last 1-4 positions two at a time;
-    backward: the first n mod 4 positions two or one at a time), fuse 1 = two."""
+    backward: the first n mod 4 positions two or one at a time), fuse 3 = as 2 with
+    eight positions per backward launch while four remain after it, fuse 1 = two."""
     s = stage_sizes(n)
     steps = []
     if not backward:
         i = 0
         while i < n:
-            t = 4 if (fuse == 2 and i + 4 < n) else (2 if (fuse and i + 2 <= n) else 1)
+            t = 4 if (fuse >= 2 and i + 4 < n) else (2 if (fuse and i + 2 <= n) else 1)
             steps.append((i, i + t))
             i += t
     else:
-        top, lead = n, (n % 4 if (fuse == 2 and n >= 4) else -1)
+        top, lead = n, (n % 4 if (fuse >= 2 and n >= 4) else -1)
         while top > 0:
-            if lead >= 0 and n - top >= lead:
+            if fuse == 3 and lead >= 0 and n - top >= lead and top - 8 >= 4:
+                t = 8
+            elif lead >= 0 and n - top >= lead:
                 t = 4
             else:
                 t = 2 if (fuse and top >= 2 and not (lead >= 0 and n - top + 2 > lead)) else 1
@@ -333,8 +336,8 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
                 "frac": round(achieved / 8000.0, 4),
                 "traffic": measured_traffic(dom),
-                "kernel": ("forward sweep (k_fwd_stage4 x4, k_fwd_stage2, k_fwd_stage2_w1)" if dom == "sweep1"
-                           else "backward sweep (k_bwd_stage4 x5, D fused into the last)"),
+                "kernel": ("forward sweep (k_fwd_stage4 x4, k_fwd_stage2, k_fwd_last2)" if dom == "sweep1"
+                           else "backward sweep (k_bwd_stage8 x2, k_bwd_stage4 with D fused)"),
                 "bytes_per_launch": int(bytes_launch), "avg_launch_us": round(per_launch_ms * 1e3, 2)}
 
     lo, hi = ctx.bounds()

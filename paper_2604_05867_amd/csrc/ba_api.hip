@@ -68,7 +68,7 @@ struct ba_ctx {
   std::string err;
   // tuning
   int scatter_lds_kb = 64;
-  int fuse = 2;  // factored engine: four positions per launch (1: two, 0: one)
+  int fuse = 3;  // factored engine: eight/four positions per launch (2: four, 1: two, 0: one)
   int stop_rule = BA_STOP_ITERATE;
   int sym = 0;   // complement-symmetric iteration requested
   double eta = 1.0;  // update step (1 = BA)
@@ -278,6 +278,9 @@ struct Timer {
 
 // One sweep pair + reductions on group G (iteration or certification group).
 // The complement-symmetric kernels run for this group's iterations.
+// The symmetric kernels go up to four positions per launch.
+int sym_fuse(const ba_ctx* c) { return c->fuse < 2 ? c->fuse : 2; }
+
 bool sym_active(const ba_ctx* c, int n) {
   return c->sym && c->engine == BA_ENGINE_FACTORED && symmetric_supported(n, c->fuse);
 }
@@ -333,14 +336,14 @@ int sweeps(ba_ctx* c, const GroupHost& gh, const Group<T>& G, int use_sw_g, T* g
     }
   } else if (tail && !use_sw_g && sym_active(c, n)) {
     {
-      Timer t(c, BA_K_SWEEP1, forward_launches(n, c->fuse));
-      HIPCHK(c, launch_forward_sym<T>(G, s, nullptr, c->fuse));
+      Timer t(c, BA_K_SWEEP1, forward_launches(n, sym_fuse(c)));
+      HIPCHK(c, launch_forward_sym<T>(G, s, nullptr, sym_fuse(c)));
     }
     {
-      Timer t(c, BA_K_SWEEP2, backward_launches(n, c->fuse));
+      Timer t(c, BA_K_SWEEP2, backward_launches(n, sym_fuse(c)));
       Group<T> G2 = G;
       G2.g = g_out;
-      HIPCHK(c, launch_backward_sym<T>(G2, s, nullptr, tail_done, c->fuse));
+      HIPCHK(c, launch_backward_sym<T>(G2, s, nullptr, tail_done, sym_fuse(c)));
     }
   } else {
     const int fuse_tail = (tail && !use_sw_g) ? 1 : 0;
@@ -503,7 +506,7 @@ int ba_set_tuning(ba_ctx* c, int key, int value) {
     return BA_OK;
   }
   if (key == BA_TUNE_FACTORED_FUSE) {
-    if (value < 0 || value > 2) return fail(c, BA_EINVAL, "fuse must be 0, 1 or 2");
+    if (value < 0 || value > 3) return fail(c, BA_EINVAL, "fuse must be 0, 1, 2 or 3");
     c->fuse = value;
     drop_graph(c);
     return BA_OK;

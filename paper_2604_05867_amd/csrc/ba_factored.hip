@@ -565,6 +565,144 @@ __global__ __launch_bounds__(kBlock) void k_bwd_stage4(int n, int i, const T* __
   }
 }
 
+// Eight backward positions per launch (i .. i+7) as two four-position steps with
+// the intermediate B_{i+4} kept in LDS.  A block takes NR roots y of one level
+// (consecutive ranks) and C columns s of the source width S8 = 2^(n-i-8), with
+// NR * C = P: it copies the depth-8 subtrees of its roots at its columns into LDS
+// (depth k is one run of NR 2^k consecutive ranks), forms B_{i+4}[z][u2 S8 + s]
+// for the 31 rows z of each root's depth-4 subtree (step 1: one thread per
+// (root, z, column), as a four-position thread with y = z), then
+// B_i[y][(16 u1 + u2) S8 + s] (step 2: one thread per (root, u2, column)), staged
+// in LDS and written back.  Every value is the same sum, in the same order, as
+// with two four-position launches.
+template <typename T>
+constexpr int stage8_tile() { return sizeof(T) == 4 ? 16 : 8; }
+
+template <typename T>
+__global__ __launch_bounds__(32 * stage8_tile<T>()) void k_bwd_stage8(int n, int i, const T* __restrict__ src,
+                                                                    size_t sstride, T* __restrict__ dst,
+                                                                    size_t dstride, const State* st) {
+  constexpr int P = stage8_tile<T>();
+  constexpr int LP = P == 16 ? 4 : P == 8 ? 3 : 2;
+  const int b = blockIdx.z;
+  if (st[b].converged) return;
+  src += (size_t)b * sstride;
+  dst += (size_t)b * dstride;
+  const int sh = n - i - 8;                  // log2 of S8
+  const uint32_t S8 = 1u << sh;
+  const int lc = sh < LP ? sh : LP;          // log2 of the columns per block
+  const int lr = LP - lc;                    // log2 of the roots per block
+  const uint32_t C = 1u << lc;
+  // levels below lr hold one (partial) group of roots each
+  const uint32_t bx = blockIdx.x;
+  uint32_t lev, g0;
+  if (bx < uint32_t(lr)) {
+    lev = bx;
+    g0 = 0;
+  } else {
+    const uint32_t q = bx - uint32_t(lr) + 1u;
+    const int k = 31 - __clz(q);
+    lev = uint32_t(lr + k);
+    g0 = (q - (1u << k)) << lr;
+  }
+  const int lnr = int(lev) < lr ? int(lev) : lr;  // log2 of the roots of this block
+  const uint32_t nr = 1u << lnr;
+  const uint32_t r0 = (1u << lev) - 1u + g0;     // rank of the first root
+  const uint32_t s0 = blockIdx.y * C;
+  const uint32_t t = threadIdx.x;
+  // subtree node q of root rho at (rho * kInPitch + q + q / 16) C + c: the padding
+  // keeps the reads of step 1 (nodes 2^d apart across lanes) off shared banks;
+  // 31 16 C + 31 <= kInPitch C, so B_{i+4} fits in the same space
+  constexpr uint32_t kInPitch = 543u;
+  // one LDS buffer, used three times: the input subtrees, then B_{i+4} as
+  // [root][z][u2][column] (pitch 16 C + 1 per (root, z)), then the outputs
+  __shared__ T buf[uint32_t(P) * kInPitch];
+  const uint32_t pitch = 16u * C + 1u;
+  // copy-in: the 9 runs (depth k: NR 2^k rows of C columns) as one index space f,
+  // every load of a thread issued before its LDS stores
+  {
+    constexpr int kPer = (P * 511 + 32 * P - 1) / (32 * P);
+    const int lrc = lnr + lc;
+    const uint32_t total = (nr * 511u) << lc;
+    T v[kPer];
+    uint32_t li[kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      const uint32_t f = t + uint32_t(j) * (32u * P);
+      li[j] = ~0u;
+      if (f < total) {
+        const int k = 31 - __clz((f >> lrc) + 1u);
+        const uint32_t w = f - (((1u << k) - 1u) << lrc);
+        const uint32_t m = w >> lc, c = w & (C - 1u);
+        const uint32_t rho = m >> k, q = (1u << k) - 1u + (m & ((1u << k) - 1u));
+        v[j] = src[((size_t)(((r0 + 1u) << k) - 1u + m) << sh) + s0 + c];
+        li[j] = ((rho * kInPitch + q + (q >> 4)) << lc) + c;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kPer; ++j)
+      if (li[j] != ~0u) buf[li[j]] = v[j];
+  }
+  __syncthreads();
+  Vec<T, 1> Dv[16];
+  const bool s1 = t < ((31u * nr) << lc);
+  uint32_t c1 = 0, rho1 = 0, e1 = 0;
+  if (s1) {
+    c1 = t & (C - 1u);
+    const uint32_t rest = t >> lc;
+    rho1 = rest / 31u;
+    e1 = rest - rho1 * 31u;
+    const int de = 31 - __clz(e1 + 1u);
+    const uint32_t me = e1 + 1u - (1u << de);
+    Vec<T, 1> S[31];
+#pragma unroll
+    for (int d = 0; d <= 4; ++d)
+#pragma unroll
+      for (int m = 0; m < (1 << d); ++m) {
+        const uint32_t q = (1u << (de + d)) - 1u + (me << d) + uint32_t(m);
+        S[(1 << d) - 1 + m].v[0] = buf[((rho1 * kInPitch + q + (q >> 4)) << lc) + c1];
+      }
+    bwd4_tree<T, 1>(S, Dv);
+  }
+  __syncthreads();
+  if (s1) {
+    T* mp = buf + (rho1 * 31u + e1) * pitch + c1;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) mp[uint32_t(u) << lc] = Dv[u].v[0];
+  }
+  __syncthreads();
+  const bool s2 = t < ((16u * nr) << lc);
+  uint32_t c2 = 0, u2 = 0, rho2 = 0;
+  if (s2) {
+    c2 = t & (C - 1u);
+    const uint32_t rest = t >> lc;
+    u2 = rest & 15u;
+    rho2 = rest >> 4;
+    Vec<T, 1> S[31];
+    const T* mp = buf + rho2 * 31u * pitch + (u2 << lc) + c2;
+#pragma unroll
+    for (int e = 0; e < 31; ++e) S[e].v[0] = mp[uint32_t(e) * pitch];
+    bwd4_tree<T, 1>(S, Dv);
+  }
+  __syncthreads();
+  if (s2) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) buf[((rho2 * 256u + uint32_t(u) * 16u + u2) << lc) + c2] = Dv[u].v[0];
+  }
+  __syncthreads();
+  const uint32_t cnt = (nr * 256u) << lc;
+  for (uint32_t e = t; e < cnt; e += blockDim.x) {
+    const uint32_t c = e & (C - 1u), rest = e >> lc;
+    const uint32_t u = rest & 255u, rho = rest >> 8;
+    dst[((size_t)(r0 + rho) << (sh + 8)) + (u << sh) + s0 + c] = buf[e];
+  }
+}
+
+// Blocks (x) of k_bwd_stage8 at position i: one per root group.
+inline uint32_t stage8_groups(int i, int lr) {
+  return (i + 1 <= lr) ? uint32_t(i + 1) : uint32_t(lr) + (1u << (i + 1 - lr)) - 1u;
+}
+
 // The same for source rows of width 1 (the first backward launch, from v): one
 // thread per output row r, which is 4 consecutive values.
 template <typename T>
@@ -602,19 +740,20 @@ hipError_t launch_forward(const Group<T>& g, hipStream_t s, int* launches, int f
   for (int i = 0; i < n; k++) {
     // four positions per launch except the last four or fewer, whose outputs (one
     // value per row) are written by the width-1 two-position kernel
-    if (fuse == 2 && i + 4 < n) {
+    if (fuse >= 2 && i + 4 < n) {
       const bool last = (i + 4 == n);
       const bool lv = last && logv;
       T* dst = last ? (lv ? g.v : g.r) : ((k & 1) ? g.f1 : g.f0);
       const size_t ds = last ? g.ys : g.fs;
       const uint32_t S4 = 1u << (n - i - 4);
       const Order o = make_order(i + 1, ilog2(S4), sizeof(T));
-      const dim3 grid(blocks_for(order_threads(o)), g.nb);
+      const dim3 grid(blocks_for(order_threads(o), kStage4Block), g.nb);
       if (lv)
-        hipLaunchKernelGGL((k_fwd_stage4<T, true>), grid, dim3(kBlock), 0, s, n, i, src, ss, dst, ds, g.st, g.cs, o);
+        hipLaunchKernelGGL((k_fwd_stage4<T, true>), grid, dim3(kStage4Block), 0, s, n, i, src, ss, dst, ds, g.st,
+                           g.cs, o);
       else
-        hipLaunchKernelGGL((k_fwd_stage4<T, false>), grid, dim3(kBlock), 0, s, n, i, src, ss, dst, ds, g.st, g.cs,
-                           o);
+        hipLaunchKernelGGL((k_fwd_stage4<T, false>), grid, dim3(kStage4Block), 0, s, n, i, src, ss, dst, ds, g.st,
+                           g.cs, o);
       if (launches) ++*launches;
       src = dst;
       ss = ds;
@@ -686,9 +825,25 @@ hipError_t launch_backward(const Group<T>& g, hipStream_t s, int* launches, int 
   size_t ss = g.ys;
   int k = 0;
   if (dpart_blocks) *dpart_blocks = 0;
-  // fuse = 2: four positions per launch, the n mod 4 leftover positions first
-  const int lead = (fuse == 2 && n >= 4) ? n % 4 : -1;
+  // fuse = 2: four positions per launch, the n mod 4 leftover positions first;
+  // fuse = 3: the same with eight positions per launch while four remain after
+  const int lead = (fuse >= 2 && n >= 4) ? n % 4 : -1;
   for (int top = n; top > 0; k++) {           // B_top -> B_{top-step}
+    if (fuse == 3 && lead >= 0 && n - top >= lead && top - 8 >= 4) {
+      const int i = top - 8;
+      T* dst = (k & 1) ? g.f1 : g.f0;
+      constexpr int LP = stage8_tile<T>() == 16 ? 4 : stage8_tile<T>() == 8 ? 3 : 2;
+      const int sh = n - i - 8;
+      const int lc = sh < LP ? sh : LP;
+      const dim3 grid(stage8_groups(i, LP - lc), 1u << (sh - lc), g.nb);
+      hipLaunchKernelGGL((k_bwd_stage8<T>), grid, dim3(32 * stage8_tile<T>()), 0, s, n, i, src, ss, dst, g.fs,
+                         g.st);
+      if (launches) ++*launches;
+      src = dst;
+      ss = g.fs;
+      top = i;
+      continue;
+    }
     if (lead >= 0 && n - top >= lead) {
       const int i = top - 4;
       const bool last = (i == 0);
@@ -707,8 +862,8 @@ hipError_t launch_backward(const Group<T>& g, hipStream_t s, int* launches, int 
         // backward sweep at n = 20 for 1, 0.081 for 2 and 4)
         // (two items per thread with all loads issued first: 0.0774 ms per sweep;
         // four: 0.0865)
-        hipLaunchKernelGGL((k_bwd_stage4<T, 1, false>), dim3(nbk, g.nb), dim3(kBlock), 0, s, n, i, src, ss, dst, ds,
-                           g, o);
+        hipLaunchKernelGGL((k_bwd_stage4<T, 1, false>), dim3(blocks_for(order_threads(o), kStage4Block), g.nb),
+                           dim3(kStage4Block), 0, s, n, i, src, ss, dst, ds, g, o);
       }
       if (launches) ++*launches;
       src = dst;
@@ -781,12 +936,16 @@ hipError_t launch_backward(const Group<T>& g, hipStream_t s, int* launches, int 
 int factored_launches(int n, int fuse) { return fuse ? (n + 1) / 2 : n; }
 
 int backward_launches(int n, int fuse) {
+  if (fuse == 3 && n >= 4) {
+    const int four = n / 4, eight = (four - 1) / 2;  // the last launch keeps four positions
+    return four - eight + (n % 4 + 1) / 2;
+  }
   if (fuse == 2 && n >= 4) return n / 4 + (n % 4 + 1) / 2;
   return factored_launches(n, fuse);
 }
 
 int forward_launches(int n, int fuse) {
-  if (fuse == 2 && n > 4) {
+  if (fuse >= 2 && n > 4) {
     const int four = (n - 1) / 4;  // launches of four positions; the rest two at a time
     return four + (n - 4 * four + 1) / 2;
   }

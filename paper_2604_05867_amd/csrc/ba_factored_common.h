@@ -127,7 +127,7 @@ __device__ __forceinline__ bool order_slot_q(const Order& o, uint32_t q, uint32_
 
 // This thread's (row, chunk), one slot per thread.
 __device__ __forceinline__ bool order_slot(const Order& o, uint32_t& row, uint32_t& chunk) {
-  return order_slot_q(o, logical_block() * kBlock + threadIdx.x, row, chunk);
+  return order_slot_q(o, logical_block() * blockDim.x + threadIdx.x, row, chunk);
 }
 
 // D(x) = H(x) - G(x) - M for N groups of V consecutive inputs (group u starts at
@@ -277,10 +277,13 @@ inline uint32_t grid_for(uint32_t total) {
 
 // Blocks for an ordered launch, a multiple of 8 so that the XCD placement of
 // logical_block applies (the extra blocks find no slot).
-inline uint32_t blocks_for(uint32_t threads) {
-  const uint32_t g = threads == 0 ? 1u : (threads + kBlock - 1) / kBlock;
+inline uint32_t blocks_for(uint32_t threads, uint32_t block = kBlock) {
+  const uint32_t g = threads == 0 ? 1u : (threads + block - 1) / block;
   return (g + 7u) & ~7u;
 }
+
+// Threads per block of the four-position launches without records.
+constexpr uint32_t kStage4Block = 256;
 
 inline int ilog2(uint32_t v) { return 31 - __builtin_clz(v); }
 

@@ -368,14 +368,14 @@ def test_graph_needs_a_stream(ba):
     c.close()
 
 
-@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6, 7, 8, 13, 16])
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6, 7, 8, 12, 13, 16, 17])
 def test_factored_fusion_settings_agree(ba, n):
-    """One, two and four input positions per launch give the same evaluation (all
-    against the oracle for n <= 8)."""
+    """One, two, four and eight input positions per launch give the same evaluation
+    (all against the oracle for n <= 8)."""
     d = 0.6
     lp = inp.random_logp(n, seed=40 + n, spread=2.0)
     out = []
-    for fuse in (0, 1, 2):
+    for fuse in (0, 1, 2, 3):
         c = ba.Context(n, d)
         c.set_tuning(ba.TUNE_FACTORED_FUSE, fuse)
         got = c.eval(torch.from_numpy(lp))
@@ -385,6 +385,17 @@ def test_factored_fusion_settings_agree(ba, n):
         assert abs(out[0][0] - o[0]) < 1e-12 and abs(out[0][1] - o[1]) < 1e-12
         assert np.allclose(out[0][2], o[2], rtol=1e-13, atol=0)
         assert np.allclose(out[0][3], o[3], atol=1e-12)
+    # eight positions per launch are two four-position steps with the same sums in
+    # the same order: bitwise equal within one context (H is formed once per context
+    # with atomics, so it may differ in the last bits between contexts)
+    c = ba.Context(n, d)
+    same = []
+    for fuse in (2, 3):
+        c.set_tuning(ba.TUNE_FACTORED_FUSE, fuse)
+        got = c.eval(torch.from_numpy(lp))
+        same.append((got["L"], got["U"], got["r"].cpu().numpy(), got["D"].cpu().numpy()))
+    c.close()
+    assert np.array_equal(same[0][3], same[1][3]) and same[0][0] == same[1][0] and same[0][1] == same[1][1]
     if n <= 8:
         ev = bdc.evaluate(bdc.channel_dense(n, d), lp)
         assert abs(out[1][0] - ev.L / LN2) < 1e-11
@@ -403,6 +414,29 @@ def test_four_position_backward_iterates(ba, n):
         c.close()
     assert np.max(np.abs(out[0][0] - out[1][0])) < 1e-12
     assert abs(out[0][1][0][0] - out[1][1][0][0]) < 1e-12 and abs(out[0][1][1][0] - out[1][1][1][0]) < 1e-12
+
+
+@pytest.mark.parametrize("n,prec", [(12, "fp64"), (13, "fp64"), (17, "fp64"), (20, "fp32"), (19, "fp32")])
+def test_eight_position_backward_is_bitwise_four(ba, n, prec):
+    """Eight positions per backward launch (two four-position steps through LDS)
+    give bitwise the iterates and bounds of four positions per launch."""
+    p = ba.PREC_FP64 if prec == "fp64" else ba.PREC_FP32_LOG
+    ns = [n] * 3 if prec == "fp32" else [n]
+    ds = [0.64, 0.8, 0.95] if prec == "fp32" else [0.7]
+    # one context (the same H), reset to the uniform law between the two runs
+    c = ba.Context(ns, ds, prec=p)
+    X = sum(1 << m for m in ns)
+    start = torch.tensor(np.concatenate([np.full(1 << m, -m * LN2) for m in ns]))
+    out = []
+    for fuse in (2, 3):
+        c.set_logp(start)
+        c.set_tuning(ba.TUNE_FACTORED_FUSE, fuse)
+        c.step(4)
+        out.append((c.get_logp().cpu().numpy(), c.bounds()))
+    c.close()
+    assert out[0][0].shape == (X,)
+    assert np.array_equal(out[0][0], out[1][0])
+    assert out[0][1] == out[1][1]
 
 
 def test_four_position_backward_n20_fp32(ba):
