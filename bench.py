@@ -28,7 +28,7 @@ sys.path.insert(0, ROOT)
 
 N = 20
 DS = [0.64, 0.80, 0.95]
-FUSE = 3  # the library default: eight (backward) / four positions per launch of the factored engine
+FUSE = 4  # the library default (positions per launch of the factored engine)
 
 
 # HBM bytes per forward-sweep launch of this workload, from rocprofv3 FETCH_SIZE and
@@ -75,13 +75,20 @@ def sweep_launch_bytes(n, esz, nb, fuse, backward):
     H and log p (D is formed there).  Launch sequence as in the library: fuse 2 =
     four positions per launch (forward: the last 1-4 positions two at a time;
     backward: the first n mod 4 positions two or one at a time), fuse 3 = as 2 with
-    eight positions per backward launch while four remain after it, fuse 1 = two."""
+    eight positions per backward launch while four remain after it, fuse 4 = as 3
+    with the forward's last four positions in one launch (n >= 12), fuse 1 = two."""
     s = stage_sizes(n)
     steps = []
     if not backward:
         i = 0
+        last4 = fuse >= 4 and n >= 12
         while i < n:
-            t = 4 if (fuse >= 2 and i + 4 < n) else (2 if (fuse and i + 2 <= n) else 1)
+            if last4 and n - i == 4:
+                t = 4
+            elif fuse >= 2 and i + 4 < n and not (last4 and n - i < 8):
+                t = 4
+            else:
+                t = 2 if (fuse and i + 2 <= n and not (last4 and n - i - 2 < 4)) else 1
             steps.append((i, i + t))
             i += t
     else:
@@ -336,7 +343,7 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
                 "frac": round(achieved / 8000.0, 4),
                 "traffic": measured_traffic(dom),
-                "kernel": ("forward sweep (k_fwd_stage4 x4, k_fwd_stage2, k_fwd_last2)" if dom == "sweep1"
+                "kernel": ("forward sweep (k_fwd_stage4 x4, k_fwd_last4)" if dom == "sweep1"
                            else "backward sweep (k_bwd_stage8 x2, k_bwd_stage4 with D fused)"),
                 "bytes_per_launch": int(bytes_launch), "avg_launch_us": round(per_launch_ms * 1e3, 2)}
 

@@ -68,7 +68,7 @@ struct ba_ctx {
   std::string err;
   // tuning
   int scatter_lds_kb = 64;
-  int fuse = 3;  // factored engine: eight/four positions per launch (2: four, 1: two, 0: one)
+  int fuse = 4;  // factored engine: positions per launch (see BA_TUNE_FACTORED_FUSE)
   int stop_rule = BA_STOP_ITERATE;
   int sym = 0;   // complement-symmetric iteration requested
   double eta = 1.0;  // update step (1 = BA)
@@ -506,7 +506,7 @@ int ba_set_tuning(ba_ctx* c, int key, int value) {
     return BA_OK;
   }
   if (key == BA_TUNE_FACTORED_FUSE) {
-    if (value < 0 || value > 3) return fail(c, BA_EINVAL, "fuse must be 0, 1, 2 or 3");
+    if (value < 0 || value > 4) return fail(c, BA_EINVAL, "fuse must be 0 .. 4");
     c->fuse = value;
     drop_graph(c);
     return BA_OK;

@@ -73,31 +73,16 @@ __global__ __launch_bounds__(kBlock) void k_fwd_stage(int n, int i, const T* __r
 }
 
 
-// Four forward stages at once (positions i .. i+3).  One thread per (source row y
-// of F_i, column s of the output width S4): it loads F_i of y and of its 4
-// ancestors P_1..P_4 (16 column groups u s each; absent rows are zero) and runs
-// the single stage
-//   F_{k+1}[z][g] = F_k[z][0g] + F_k[z][1g] (if z is a row of F_k) + F_k[parent z][last(z) g]
-// in registers on the rows that reach the outputs: the path P_0 = y .. P_{4-k} and,
-// when y has length i (a leaf of F_i), its subtree down to depth k.  It writes the
-// output row y and, for a leaf, the 30 rows below it (all rows of F_{i+4} of
-// length >= i are below exactly one leaf).  LOGV: last stage, write v = w_k log r.
-template <typename T, bool LOGV>
-__global__ __launch_bounds__(kBlock) void k_fwd_stage4(int n, int i, const T* __restrict__ src, size_t sstride,
-                                                       T* __restrict__ dst, size_t dstride, const State* st,
-                                                       const Consts* cs, Order o) {
-  const int b = blockIdx.y;
-  if (st[b].converged) return;
-  uint32_t y, s;
-  if (!order_slot(o, y, s)) return;
-  src += (size_t)b * sstride;
-  dst += (size_t)b * dstride;
-  const int sh = n - i - 4;                  // log2 of the output width S4
-  const int ly = length_of_rank(y);
+// The four-position forward step of one (row y of length ly, column s of the output
+// width 2^sh): loads F_i of y's path and returns F_{i+4}[y] (and, in F4, the 30 rows
+// below y; meaningful when y is a leaf).  The first stage is formed row by row from
+// the deepest ancestor up, so that only one loaded row and the half of the row below
+// it are live at a time.
+template <typename T>
+__device__ __forceinline__ T fwd4_thread(const T* __restrict__ src, int sh, uint32_t y, int ly, uint32_t s,
+                                         T (&F4)[30]) {
   uint32_t P[5], lastb[4];
   fwd4_path(y, P, lastb);
-  // first stage row by row from the deepest ancestor up, so that only one loaded
-  // row and the half of the row below it are live at a time
   T F1p[4][8], F1s[2][8], Hc[8];
 #pragma unroll
   for (int u = 0; u < 8; ++u) Hc[u] = T(0);
@@ -128,8 +113,32 @@ __global__ __launch_bounds__(kBlock) void k_fwd_stage4(int n, int i, const T* __
         for (int g = 0; g < 8; ++g) F1s[c][g] = R[c * 8 + g];
     }
   }
+  return fwd4_after_stage1<T>(F1p, F1s, lastb, F4);
+}
+
+// Four forward stages at once (positions i .. i+3).  One thread per (source row y
+// of F_i, column s of the output width S4): it loads F_i of y and of its 4
+// ancestors P_1..P_4 (16 column groups u s each; absent rows are zero) and runs
+// the single stage
+//   F_{k+1}[z][g] = F_k[z][0g] + F_k[z][1g] (if z is a row of F_k) + F_k[parent z][last(z) g]
+// in registers on the rows that reach the outputs: the path P_0 = y .. P_{4-k} and,
+// when y has length i (a leaf of F_i), its subtree down to depth k.  It writes the
+// output row y and, for a leaf, the 30 rows below it (all rows of F_{i+4} of
+// length >= i are below exactly one leaf).  LOGV: last stage, write v = w_k log r.
+template <typename T, bool LOGV>
+__global__ __launch_bounds__(kBlock) void k_fwd_stage4(int n, int i, const T* __restrict__ src, size_t sstride,
+                                                       T* __restrict__ dst, size_t dstride, const State* st,
+                                                       const Consts* cs, Order o) {
+  const int b = blockIdx.y;
+  if (st[b].converged) return;
+  uint32_t y, s;
+  if (!order_slot(o, y, s)) return;
+  src += (size_t)b * sstride;
+  dst += (size_t)b * dstride;
+  const int sh = n - i - 4;                  // log2 of the output width S4
+  const int ly = length_of_rank(y);
   T F4[30];
-  T vy = fwd4_after_stage1<T>(F1p, F1s, lastb, F4);
+  T vy = fwd4_thread<T>(src, sh, y, ly, s, F4);
   if constexpr (LOGV) vy = log_weighted<T>(cs[b], y, vy);
   dst[((size_t)y << sh) + s] = vy;
   if (ly != i) return;
@@ -396,6 +405,73 @@ __global__ __launch_bounds__(kLast2Threads) void k_fwd_last2(int n, const T* __r
     for (uint32_t k = 0; k < w2; ++k) {
       const uint32_t e = k * kLast2Threads + t;
       out[e] = sj[(e >> j) * stride + (e & (w2 - 1u))];
+    }
+  }
+}
+
+// The last four positions (n-4 .. n-1) for n >= kLast4MinN: the four-position step
+// of k_fwd_stage4 at i = n-4 (output rows of width 1), with the outputs staged in
+// LDS.  Deep blocks (blockIdx.x < 2^(n-4) / kLast2Threads): thread t takes the leaf
+// a of rank A0 + t (level L = n-4) and its 30 rows below; level L+j of a block's
+// outputs is one run of kLast2Threads 2^j consecutive ranks, written back coalesced
+// (row stride 2^j + 1 in LDS against bank conflicts).  The other blocks take one row
+// of level < L per thread (its output only).
+constexpr int kLast4MinN = 12;
+
+template <typename T, bool LOGV>
+__global__ __launch_bounds__(kLast2Threads) void k_fwd_last4(int n, const T* __restrict__ src, size_t sstride,
+                                                             T* __restrict__ dst, size_t dstride,
+                                                             const State* st, const Consts* cs) {
+  const int b = blockIdx.y;
+  if (st[b].converged) return;
+  src += (size_t)b * sstride;
+  dst += (size_t)b * dstride;
+  const int L = n - 4;
+  const uint32_t ndeep = (1u << L) / kLast2Threads;
+  const uint32_t t = threadIdx.x;
+  T F4[30];
+  if (blockIdx.x >= ndeep) {
+    const uint32_t c = (blockIdx.x - ndeep) * kLast2Threads + t;
+    if (c + 1u >= (1u << L)) return;
+    T r = fwd4_thread<T>(src, 0, c, length_of_rank(c), 0u, F4);
+    if constexpr (LOGV) r = log_weighted<T>(cs[b], c, r);
+    dst[c] = r;
+    return;
+  }
+  __shared__ T stage[kLast2Lds * kLast2Threads];
+  const uint32_t A0 = (1u << L) - 1u + blockIdx.x * kLast2Threads;
+  const uint32_t a = A0 + t;
+  T va = fwd4_thread<T>(src, 0, a, L, 0u, F4);
+  const T w0 = T(cs[b].w[L]), w1 = T(cs[b].w[L + 1]), w2 = T(cs[b].w[L + 2]), w3 = T(cs[b].w[L + 3]),
+          w4 = T(cs[b].w[L + 4]);
+  auto outv = [](T w, T r) -> T {
+    if constexpr (LOGV) return (w == T(0)) ? T(0) : w * log_t<T>(r);
+    else return r;
+  };
+  T* s1 = stage;
+  T* s2 = s1 + 3 * kLast2Threads;
+  T* s3 = s2 + 5 * kLast2Threads;
+  T* s4 = s3 + 9 * kLast2Threads;
+  dst[a] = outv(w0, va);
+  // F4: depth d, index m at (1 << d) - 2 + m
+#pragma unroll
+  for (int q = 0; q < 2; ++q) s1[3u * t + q] = outv(w1, F4[q]);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) s2[5u * t + q] = outv(w2, F4[2 + q]);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) s3[9u * t + q] = outv(w3, F4[6 + q]);
+#pragma unroll
+  for (int q = 0; q < 16; ++q) s4[17u * t + q] = outv(w4, F4[14 + q]);
+  __syncthreads();
+#pragma unroll
+  for (int j = 1; j <= 4; ++j) {
+    const uint32_t wj = 1u << j, stride = wj + 1u;
+    const T* sj = j == 1 ? s1 : j == 2 ? s2 : j == 3 ? s3 : s4;
+    T* out = dst + (wj * (A0 + 1u) - 1u);
+#pragma unroll
+    for (uint32_t k = 0; k < wj; ++k) {
+      const uint32_t e = k * kLast2Threads + t;
+      out[e] = sj[(e >> j) * stride + (e & (wj - 1u))];
     }
   }
 }
@@ -737,10 +813,25 @@ hipError_t launch_forward(const Group<T>& g, hipStream_t s, int* launches, int f
   const T* src = g.p;
   size_t ss = g.xs;
   int k = 0;
+  // fuse >= 4: the last four positions in one launch with LDS-staged outputs
+  const bool last4 = fuse >= 4 && n >= kLast4MinN;
   for (int i = 0; i < n; k++) {
+    if (last4 && n - i == 4) {
+      T* dst = logv ? g.v : g.r;
+      const dim3 grid(2u * ((1u << (n - 4)) / kLast2Threads), g.nb);
+      if (logv)
+        hipLaunchKernelGGL((k_fwd_last4<T, true>), grid, dim3(kLast2Threads), 0, s, n, src, ss, dst, g.ys, g.st,
+                           g.cs);
+      else
+        hipLaunchKernelGGL((k_fwd_last4<T, false>), grid, dim3(kLast2Threads), 0, s, n, src, ss, dst, g.ys, g.st,
+                           g.cs);
+      if (launches) ++*launches;
+      break;
+    }
     // four positions per launch except the last four or fewer, whose outputs (one
-    // value per row) are written by the width-1 two-position kernel
-    if (fuse >= 2 && i + 4 < n) {
+    // value per row) are written by the width-1 two-position kernel (or, with
+    // last4, down to exactly four positions left)
+    if (fuse >= 2 && i + 4 < n && !(last4 && n - i < 8)) {
       const bool last = (i + 4 == n);
       const bool lv = last && logv;
       T* dst = last ? (lv ? g.v : g.r) : ((k & 1) ? g.f1 : g.f0);
@@ -760,7 +851,7 @@ hipError_t launch_forward(const Group<T>& g, hipStream_t s, int* launches, int f
       i += 4;
       continue;
     }
-    const int step = (fuse && i + 2 <= n) ? 2 : 1;
+    const int step = (fuse && i + 2 <= n && !(last4 && n - i - 2 < 4)) ? 2 : 1;
     const bool last = (i + step == n);
     const bool lv = last && logv;
     T* dst;
@@ -829,7 +920,7 @@ hipError_t launch_backward(const Group<T>& g, hipStream_t s, int* launches, int 
   // fuse = 3: the same with eight positions per launch while four remain after
   const int lead = (fuse >= 2 && n >= 4) ? n % 4 : -1;
   for (int top = n; top > 0; k++) {           // B_top -> B_{top-step}
-    if (fuse == 3 && lead >= 0 && n - top >= lead && top - 8 >= 4) {
+    if (fuse >= 3 && lead >= 0 && n - top >= lead && top - 8 >= 4) {
       const int i = top - 8;
       T* dst = (k & 1) ? g.f1 : g.f0;
       constexpr int LP = stage8_tile<T>() == 16 ? 4 : stage8_tile<T>() == 8 ? 3 : 2;
@@ -936,7 +1027,7 @@ hipError_t launch_backward(const Group<T>& g, hipStream_t s, int* launches, int 
 int factored_launches(int n, int fuse) { return fuse ? (n + 1) / 2 : n; }
 
 int backward_launches(int n, int fuse) {
-  if (fuse == 3 && n >= 4) {
+  if (fuse >= 3 && n >= 4) {
     const int four = n / 4, eight = (four - 1) / 2;  // the last launch keeps four positions
     return four - eight + (n % 4 + 1) / 2;
   }
@@ -945,6 +1036,10 @@ int backward_launches(int n, int fuse) {
 }
 
 int forward_launches(int n, int fuse) {
+  if (fuse >= 4 && n >= kLast4MinN) {
+    const int four = (n - 4) / 4, rest = (n - 4) % 4;  // then 0-3 positions two or one at a time
+    return four + (rest + 1) / 2 + 1;
+  }
   if (fuse >= 2 && n > 4) {
     const int four = (n - 1) / 4;  // launches of four positions; the rest two at a time
     return four + (n - 4 * four + 1) / 2;

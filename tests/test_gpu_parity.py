@@ -370,12 +370,13 @@ def test_graph_needs_a_stream(ba):
 
 @pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6, 7, 8, 12, 13, 16, 17])
 def test_factored_fusion_settings_agree(ba, n):
-    """One, two, four and eight input positions per launch give the same evaluation
-    (all against the oracle for n <= 8)."""
+    """One, two, four and eight input positions per launch, and the last four
+    forward positions in one launch, give the same evaluation (all against the
+    oracle for n <= 8)."""
     d = 0.6
     lp = inp.random_logp(n, seed=40 + n, spread=2.0)
     out = []
-    for fuse in (0, 1, 2, 3):
+    for fuse in (0, 1, 2, 3, 4):
         c = ba.Context(n, d)
         c.set_tuning(ba.TUNE_FACTORED_FUSE, fuse)
         got = c.eval(torch.from_numpy(lp))
