@@ -291,7 +291,7 @@ bool sym_active(const ba_ctx* c, int n) {
 // launches k_dpart).
 template <typename T>
 int sweeps(ba_ctx* c, const GroupHost& gh, const Group<T>& G, int use_sw_g, T* g_out, int tail = 0,
-           int* tail_done = nullptr) {
+           int* tail_done = nullptr, const FusedUpdate* upd = nullptr) {
   if (tail_done) *tail_done = 0;
   hipStream_t s = c->stream;
   const int n = gh.n, n1 = (n + 1) / 2, n2 = n / 2;
@@ -349,7 +349,7 @@ int sweeps(ba_ctx* c, const GroupHost& gh, const Group<T>& G, int use_sw_g, T* g
     const int fuse_tail = (tail && !use_sw_g) ? 1 : 0;
     {
       Timer t(c, BA_K_SWEEP1, forward_launches(n, c->fuse));
-      HIPCHK(c, launch_forward<T>(G, s, nullptr, c->fuse, fuse_tail));
+      HIPCHK(c, launch_forward<T>(G, s, nullptr, c->fuse, fuse_tail, upd));
     }
     if (!fuse_tail) {
       Timer t(c, BA_K_LOGR, 1);
@@ -365,12 +365,24 @@ int sweeps(ba_ctx* c, const GroupHost& gh, const Group<T>& G, int use_sw_g, T* g
   return BA_OK;
 }
 
+// The update of an iteration can be left pending and fused into the next
+// iteration's first forward launch (factored engine, full kernels).
+bool update_fusable(const ba_ctx* c, const GroupHost& gh) {
+  return c->engine == BA_ENGINE_FACTORED && !sym_active(c, gh.n) && forward_update_fusable(gh.n, c->fuse);
+}
+
+// One iteration.  fused_in: the previous iteration's update is pending and done by
+// this iteration's first forward launch; leave_pending: this iteration's update is
+// left to the next iteration's first forward launch.
 template <typename T>
-int iterate_group(ba_ctx* c, const GroupHost& gh, const Group<T>& G0) {
+int iterate_group(ba_ctx* c, const GroupHost& gh, const Group<T>& G0, bool fused_in, bool leave_pending) {
   Group<T> G = G0;
   G.eta = c->eta;
+  const double floor = (sizeof(T) == 4) ? kFloor32 : kFloor64;
+  const int check_tol = c->prec == BA_PREC_FP64 ? 1 : 0;
+  const FusedUpdate fu{floor, check_tol};
   int nblk = 0;  // block records written by the fused D launch, if any
-  int rc = sweeps<T>(c, gh, G, 0, G.g, 1, &nblk);
+  int rc = sweeps<T>(c, gh, G, 0, G.g, 1, &nblk, fused_in ? &fu : nullptr);
   if (rc) return rc;
   {
     Timer t(c, BA_K_REDUCE, nblk ? 1 : 2);
@@ -380,11 +392,10 @@ int iterate_group(ba_ctx* c, const GroupHost& gh, const Group<T>& G0) {
     }
     HIPCHK(c, launch_final_parts<T>(G, nblk, c->stream));
   }
-  {
+  if (!leave_pending) {
     Timer t(c, BA_K_UPDATE, 1);
-    const double floor = (sizeof(T) == 4) ? kFloor32 : kFloor64;
-    HIPCHK(c, launch_update<T>(G, reduce_blocks(gh.n), floor, c->prec == BA_PREC_FP64 ? 1 : 0,
-                               sym_active(c, gh.n) ? 1 : 0, c->stream));
+    HIPCHK(c, launch_update<T>(G, reduce_blocks(gh.n), floor, check_tol, sym_active(c, gh.n) ? 1 : 0,
+                               c->stream));
   }
   return BA_OK;
 }
@@ -588,9 +599,15 @@ int ba_step(ba_ctx* c, int iters) {
   int rc = check_ctx(c);
   if (rc) return rc;
   if (iters < 0) return fail(c, BA_EINVAL, "iters < 0");
+  // within one call, the update of every iteration but the last is fused into the
+  // next iteration's first launch where possible; the call ends with log p and p
+  // of the last iterate in place
   for (int it = 0; it < iters; ++it)
     for (auto& gh : c->groups) {
-      rc = (c->prec == BA_PREC_FP32_LOG) ? iterate_group<float>(c, gh, gh.gf) : iterate_group<double>(c, gh, gh.gd);
+      const bool fu = update_fusable(c, gh);
+      const bool in = fu && it > 0, out = fu && it + 1 < iters;
+      rc = (c->prec == BA_PREC_FP32_LOG) ? iterate_group<float>(c, gh, gh.gf, in, out)
+                                         : iterate_group<double>(c, gh, gh.gd, in, out);
       if (rc) return rc;
     }
   return BA_OK;

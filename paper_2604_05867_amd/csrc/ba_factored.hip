@@ -153,6 +153,62 @@ __global__ __launch_bounds__(kBlock) void k_fwd_stage4(int n, int i, const T* __
     }
 }
 
+// The first four positions (i = 0) fused with the update that the previous
+// iteration left pending: every thread forms the update from the final record
+// (as k_update does), writes the new log p of its 16 inputs x = u 2^(n-4) + s and
+// uses p = e^{log p - M'} in registers as F_0 (p itself is not stored), then runs
+// the step of k_fwd_stage4 for the one row of F_0.  The values equal those of
+// k_update followed by k_fwd_stage4.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fwd_first4_upd(int n, T* __restrict__ dst, size_t dstride, Group<T> g,
+                                                           Order o, double floor, int check_tol) {
+  const int b = blockIdx.y;
+  if (g.st[b].converged) return;
+  const UpdateParams up = update_params<T>(g, b, check_tol, blockIdx.x == 0 && threadIdx.x == 0);
+  if (up.stop) return;
+  uint32_t y, s;
+  if (!order_slot(o, y, s)) return;  // y = 0, the one row of F_0
+  dst += (size_t)b * dstride;
+  T* lp = g.lp + (size_t)b * g.xs;
+  const T* D = g.D + (size_t)b * g.xs;
+  const int sh = n - 4;
+  const T lo = T(up.Mn - floor), eta = T(g.eta);
+  T nl[16], dv[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    nl[u] = lp[(uint32_t(u) << sh) + s];
+    dv[u] = D[(uint32_t(u) << sh) + s];
+  }
+  T R[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    nl[u] = update_value<T>(up, eta, lo, nl[u], dv[u]);
+    lp[(uint32_t(u) << sh) + s] = nl[u];
+    R[u] = exp_t<T>(nl[u] - T(up.Mn));
+  }
+  // the first stage of fwd4_thread for a row without ancestors
+  uint32_t P[5], lastb[4];
+  fwd4_path(0u, P, lastb);
+  T F1p[4][8], F1s[2][8];
+#pragma unroll
+  for (int j = 1; j < 4; ++j)
+#pragma unroll
+    for (int q = 0; q < 8; ++q) F1p[j][q] = (T(0) + T(0)) + T(0);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) F1p[0][q] = (R[q] + R[8 + q]) + T(0);
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int q = 0; q < 8; ++q) F1s[c][q] = R[c * 8 + q];
+  T F4[30];
+  dst[s] = fwd4_after_stage1<T>(F1p, F1s, lastb, F4);
+#pragma unroll
+  for (int d = 1; d <= 4; ++d)
+#pragma unroll
+    for (int m = 0; m < (1 << d); ++m)
+      dst[((size_t)((1u << d) - 1u + uint32_t(m)) << sh) + s] = F4[(1 << d) - 2 + m];
+}
+
 // One backward stage; each thread produces V consecutive columns of one row
 // (V divides the source row width S = 2^(n-i-1)).  DP: stage 0, write D and the
 // reduction records instead of G.
@@ -807,12 +863,14 @@ __global__ __launch_bounds__(kBlock) void k_bwd_stage2_w1(const T* __restrict__ 
 using namespace fac;
 
 template <typename T>
-hipError_t launch_forward(const Group<T>& g, hipStream_t s, int* launches, int fuse, int logv) {
+hipError_t launch_forward(const Group<T>& g, hipStream_t s, int* launches, int fuse, int logv,
+                          const FusedUpdate* upd) {
   const int n = g.n;
   constexpr int V = 16 / sizeof(T);
   const T* src = g.p;
   size_t ss = g.xs;
   int k = 0;
+  if (upd && !forward_update_fusable(n, fuse)) return hipErrorInvalidValue;
   // fuse >= 4: the last four positions in one launch with LDS-staged outputs
   const bool last4 = fuse >= 4 && n >= kLast4MinN;
   for (int i = 0; i < n; k++) {
@@ -839,7 +897,10 @@ hipError_t launch_forward(const Group<T>& g, hipStream_t s, int* launches, int f
       const uint32_t S4 = 1u << (n - i - 4);
       const Order o = make_order(i + 1, ilog2(S4), sizeof(T));
       const dim3 grid(blocks_for(order_threads(o), kStage4Block), g.nb);
-      if (lv)
+      if (i == 0 && upd)
+        hipLaunchKernelGGL((k_fwd_first4_upd<T>), grid, dim3(kStage4Block), 0, s, n, dst, ds, g, o, upd->floor,
+                           upd->check_tol);
+      else if (lv)
         hipLaunchKernelGGL((k_fwd_stage4<T, true>), grid, dim3(kStage4Block), 0, s, n, i, src, ss, dst, ds, g.st,
                            g.cs, o);
       else
@@ -1047,8 +1108,11 @@ int forward_launches(int n, int fuse) {
   return factored_launches(n, fuse);
 }
 
-template hipError_t launch_forward<float>(const Group<float>&, hipStream_t, int*, int, int);
-template hipError_t launch_forward<double>(const Group<double>&, hipStream_t, int*, int, int);
+bool forward_update_fusable(int n, int fuse) { return fuse >= 2 && n > 4; }
+
+template hipError_t launch_forward<float>(const Group<float>&, hipStream_t, int*, int, int, const FusedUpdate*);
+template hipError_t launch_forward<double>(const Group<double>&, hipStream_t, int*, int, int,
+                                           const FusedUpdate*);
 template hipError_t launch_backward<float>(const Group<float>&, hipStream_t, int*, int, int, int*);
 template hipError_t launch_backward<double>(const Group<double>&, hipStream_t, int*, int, int, int*);
 

@@ -165,20 +165,32 @@ hipError_t launch_pull(const Group<T>& g, T* partial, hipStream_t s);
 // fuse = 1: two positions per launch (k_fwd_stage2 / k_bwd_stage2); fuse = 2: four
 // positions per launch (k_fwd_stage4 / k_bwd_stage4) with the leftover positions
 // two (or one) at a time: the last 1-4 in the forward, the first n mod 4 in the
-// backward.
+// backward; fuse = 3: as 2 with eight positions per backward launch
+// (k_bwd_stage8) while four remain for the last; fuse = 4: as 3 with the last four
+// forward positions in one launch (k_fwd_last4, n >= 12).
 // logv = 1: the last forward launch writes v = w_k log r instead of r.
 // dpart = 1: the last backward launch also forms D = H - G - M and the block
 // records of k_dpart, writing D instead of G; *dpart_blocks returns the number of
 // records it wrote, or 0 if it could not fuse (smallest n), in which case the
 // caller launches k_dpart itself.
+//
+// upd: the update of the previous iteration, fused into the forward sweep's first
+// launch (which then reads log p and D instead of p, and writes log p but not p).
+struct FusedUpdate {
+  double floor;
+  int check_tol;
+};
+// True when launch_forward's first launch is the four-position one at i = 0.
+bool forward_update_fusable(int n, int fuse);
 template <typename T>
-hipError_t launch_forward(const Group<T>& g, hipStream_t s, int* launches, int fuse, int logv);  // p -> r
+hipError_t launch_forward(const Group<T>& g, hipStream_t s, int* launches, int fuse, int logv,
+                          const FusedUpdate* upd = nullptr);  // p -> r
 template <typename T>
 hipError_t launch_backward(const Group<T>& g, hipStream_t s, int* launches, int fuse, int dpart,
                            int* dpart_blocks);                                                   // v -> G
 int factored_launches(int n, int fuse);   // forward launches (two positions each when fuse != 0)
-int backward_launches(int n, int fuse);   // fuse = 2: four positions per backward launch
-int forward_launches(int n, int fuse);    // fuse = 2: four positions per forward launch
+int backward_launches(int n, int fuse);   // launches of launch_backward
+int forward_launches(int n, int fuse);    // launches of launch_forward
 // Complement-symmetric iteration (iterate invariant under complement): the two
 // products on the canonical half, v and D fused as above; v is stored at compact
 // indices (2^n entries) and D, G for x < 2^(n-1).  Supported for even n >= 4 with

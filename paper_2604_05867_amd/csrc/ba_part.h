@@ -142,6 +142,57 @@ __device__ __forceinline__ Part block_reduce(Part p) {
   return r;
 }
 
+// The update of one iteration from the final record of its D kernel (at kFinalRec):
+// L = log sum p e^D, U = max D; with a step eta != 1 the normaliser Le of
+// log p + eta D.  Every caller derives the same values; `writer` stores them in
+// the instance state (a stop freezes the instance instead of updating it).
+struct UpdateParams {
+  double L, Le, Mn;  // Mn: the max of the new log p
+  bool step, stop;
+};
+
+template <typename T>
+__device__ __forceinline__ UpdateParams update_params(const Group<T>& g, int b, int check_tol, bool writer) {
+  State* st = g.st + b;
+  const double* q = g.part + (size_t)b * g.ps + kFinalRec;
+  const double m = q[0], s = q[1], dmax = q[2], pi = q[3], m2 = q[5], s2 = q[6];
+  const double L = m + log(s);
+  const double U = dmax;
+  // normaliser of the step: L itself for eta = 1 (BA)
+  const bool step = g.eta != 1.0;
+  const double Le = step ? m2 + log(s2) : L;
+  const double Mn = (step ? m2 : m) - Le;
+  const bool finite = isfinite(L) && isfinite(U) && isfinite(pi) && isfinite(Le);
+  // FP64 iterates (check_tol): these are the exact bounds of the current iterate,
+  // so they also update the best bounds; FP32 iterates leave that to certification.
+  const double bL = (check_tol && finite) ? fmax(st->bestL, L) : st->bestL;
+  const double bU = (check_tol && finite) ? fmin(st->bestU, U) : st->bestU;
+  const double gap = st->stop_best ? (bU - bL) : (U - L);
+  const bool stop = !finite || (check_tol && st->tol >= 0.0 && gap < st->tol);
+  if (writer) {
+    st->L = L;
+    st->U = U;
+    st->I = pi;
+    st->bestL = bL;
+    st->bestU = bU;
+    if (!finite) st->bad = 1;
+    if (stop) {
+      st->converged = 1;
+    } else {
+      st->M = Mn;
+      st->iters += 1;
+    }
+  }
+  return UpdateParams{L, Le, Mn, step, stop};
+}
+
+// New log p of one input: max(log p + D - L, lo), or log p + eta D - Le with a step.
+template <typename T>
+__device__ __forceinline__ T update_value(const UpdateParams& u, T eta, T lo, T lpx, T dx) {
+  const T nl = u.step ? lpx + eta * dx - T(u.Le) : lpx + dx - T(u.L);
+  return nl > lo ? nl : lo;
+}
+
 __device__ __forceinline__ void store_part(double* dst, const Part& p) {
   dst[0] = p.m; dst[1] = p.s; dst[2] = p.dmax; dst[3] = p.i; dst[4] = p.id; dst[5] = p.m2; dst[6] = p.s2;
 }

@@ -95,48 +95,19 @@ __global__ __launch_bounds__(kBlock) void k_final_parts(Group<T> g, int nblk) {
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_update(Group<T> g, int nblk, double floor, int check_tol, int sym) {
   const int b = blockIdx.y;
-  State* st = g.st + b;
-  if (st->converged) return;
-  const Part P = load_part(g.part + (size_t)b * g.ps + kFinalRec);
-  const double L = P.m + log(P.s);
-  const double U = P.dmax;
-  // normaliser of the step: L itself for eta = 1 (BA)
-  const bool step = g.eta != 1.0;
-  const double Le = step ? P.m2 + log(P.s2) : L;
-  const double Mn = (step ? P.m2 : P.m) - Le;
-  const bool finite = isfinite(L) && isfinite(U) && isfinite(P.i) && isfinite(Le);
-  // FP64 iterates (check_tol): these are the exact bounds of the current iterate,
-  // so they also update the best bounds; FP32 iterates leave that to certification.
-  const double bL = (check_tol && finite) ? fmax(st->bestL, L) : st->bestL;
-  const double bU = (check_tol && finite) ? fmin(st->bestU, U) : st->bestU;
-  const double gap = st->stop_best ? (bU - bL) : (U - L);
-  const bool stop = !finite || (check_tol && st->tol >= 0.0 && gap < st->tol);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    st->L = L;
-    st->U = U;
-    st->I = P.i;
-    st->bestL = bL;
-    st->bestU = bU;
-    if (!finite) st->bad = 1;
-    if (stop) {
-      st->converged = 1;
-    } else {
-      st->M = Mn;
-      st->iters += 1;
-    }
-  }
-  if (stop) return;
+  if (g.st[b].converged) return;
+  const UpdateParams u = update_params<T>(g, b, check_tol, blockIdx.x == 0 && threadIdx.x == 0);
+  if (u.stop) return;
   const uint32_t X = 1u << g.n;
   T* lp = g.lp + (size_t)b * g.xs;
   T* p = g.p + (size_t)b * g.xs;
   const T* D = g.D + (size_t)b * g.xs;
-  const T lo = T(Mn - floor);
+  const T lo = T(u.Mn - floor), eta = T(g.eta);
   // sym: D holds the inputs x < 2^(n-1) only; their complements get the same values
   const uint32_t count = sym ? X / 2u : X;
   for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < count; x += gridDim.x * blockDim.x) {
-    T nl = step ? lp[x] + T(g.eta) * D[x] - T(Le) : lp[x] + D[x] - T(L);
-    nl = nl > lo ? nl : lo;
-    const T px = exp_t<T>(nl - T(Mn));
+    const T nl = update_value<T>(u, eta, lo, lp[x], D[x]);
+    const T px = exp_t<T>(nl - T(u.Mn));
     lp[x] = nl;
     p[x] = px;
     if (sym) {

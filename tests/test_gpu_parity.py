@@ -454,3 +454,61 @@ def test_four_position_backward_n20_fp32(ba):
     assert np.max(np.abs(out[0][0] - out[1][0])) < 1e-4
     assert np.max(np.abs(np.array(out[0][1][0]) - np.array(out[1][1][0]))) < 5e-6
     assert np.max(np.abs(np.array(out[0][1][1]) - np.array(out[1][1][1]))) < 5e-6
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_fused_update_is_bitwise_separate(ba, prec):
+    """Within one step call the update of each iteration but the last runs inside
+    the next iteration's first forward launch; the iterates and bounds equal those
+    of one-iteration calls (separate update launches) bit for bit, with and without
+    a step eta."""
+    p = ba.PREC_FP64 if prec == "fp64" else ba.PREC_FP32_LOG
+    ns, ds = ([12, 14], [0.6, 0.9]) if prec == "fp64" else ([16, 20], [0.7, 0.95])
+    # one context (H is formed once per context, with atomics), reset between runs
+    c = ba.Context(ns, ds, prec=p)
+    start = torch.tensor(np.concatenate([np.full(1 << m, -m * LN2) for m in ns]))
+    for eta in (1.0, 1.8):
+        out = []
+        for per_call in (1, 7):
+            c.set_logp(start)
+            c.set_step(eta)
+            for _ in range(7 // per_call):
+                c.step(per_call)
+            out.append((c.get_logp().cpu().numpy(), c.bounds()))
+        assert np.array_equal(out[0][0], out[1][0])
+        assert out[0][1] == out[1][1]
+    c.close()
+
+
+def test_fused_update_stops_at_tolerance(ba):
+    """FP64 iterates stop at the first iterate whose gap is below the tolerance,
+    also when that test is made inside a fused first forward launch (ba_run, eager
+    and graph-replayed)."""
+    n, d, tol = 10, 0.5, 1e-2
+    # reference: one iteration per call (separate update launches, no stop test)
+    ref = ba.Context(n, d)
+    k = 0
+    while k < 3000:
+        ref.step(1)
+        k += 1
+        lo, hi = ref.bounds()  # certified bounds of iterate k
+        if hi[0] - lo[0] < tol:
+            break
+    assert hi[0] - lo[0] < tol and k > 40  # several chunks of the FP64 run loop
+    lp_ref = ref.get_logp().cpu().numpy()
+    ref.close()
+    for graphs in (False, True):
+        s = torch.cuda.Stream()
+        c = ba.Context(n, d, stream=s)
+        c.set_graphs(graphs)
+        with torch.cuda.stream(s):
+            c.run(tol, 3000)
+            lo, hi = c.bounds()
+            its = c.best_bounds()[2]
+            lp = c.get_logp().cpu().numpy()
+        s.synchronize()
+        c.close()
+        # stopped at iterate k (its bounds tested, no update made)
+        assert its[0] == k
+        assert hi[0] - lo[0] < tol
+        assert np.max(np.abs(lp - lp_ref)) < 1e-10
