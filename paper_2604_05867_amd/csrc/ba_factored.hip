@@ -710,52 +710,96 @@ __global__ __launch_bounds__(kBlock) void k_bwd_stage4(int n, int i, const T* __
 template <typename T>
 constexpr int stage8_tile() { return sizeof(T) == 4 ? 16 : 8; }
 
-template <typename T>
+// Root groups of an eight-position launch at position i with 2^lr roots per group:
+// the levels below lr hold one (partial) group each; the full groups form a binary
+// tree (the group of roots g 2^lr .. of level lr + l is node g of level l, its
+// children's roots are its roots' children's) that is visited as the top levels in
+// rank order, then subtrees of up to kStage8TileH levels breadth-first (2^h slots
+// each, one unused), so that groups whose subtrees overlap run close together.
+constexpr int kStage8TileH = 5;
+
+__host__ __device__ inline void stage8_tiling(int i, int lr, uint32_t& npart, int& levels, int& h, int& lb) {
+  npart = uint32_t(lr < i + 1 ? lr : i + 1);
+  levels = i + 1 - lr;  // levels of the group tree
+  h = levels < kStage8TileH ? levels : kStage8TileH;
+  lb = levels - h;
+}
+
+inline uint32_t stage8_slots(int i, int lr) {
+  uint32_t npart;
+  int levels, h, lb;
+  stage8_tiling(i, lr, npart, levels, h, lb);
+  return levels > 0 ? npart + ((1u << lb) - 1u) + ((1u << lb) << h) : npart;
+}
+
+__device__ __forceinline__ bool stage8_group(uint32_t q, int i, int lr, uint32_t& lev, uint32_t& g0) {
+  uint32_t npart;
+  int levels, h, lb;
+  stage8_tiling(i, lr, npart, levels, h, lb);
+  if (q < npart) {
+    lev = q;
+    g0 = 0;
+    return true;
+  }
+  if (levels <= 0) return false;
+  q -= npart;
+  const uint32_t top = (1u << lb) - 1u;
+  uint32_t l, g;
+  if (q < top) {
+    l = uint32_t(31 - __clz(q + 1u));
+    g = q + 1u - (1u << l);
+  } else {
+    q -= top;
+    const uint32_t t = q >> h, j = q & ((1u << h) - 1u);
+    if (j == (1u << h) - 1u || t >= (1u << lb)) return false;
+    const int k = 31 - __clz(j + 1u);
+    l = uint32_t(lb + k);
+    g = (t << k) + (j + 1u - (1u << k));
+  }
+  lev = l + uint32_t(lr);
+  g0 = g << lr;
+  return true;
+}
+
+template <typename T, int LC>
 __global__ __launch_bounds__(32 * stage8_tile<T>()) void k_bwd_stage8(int n, int i, const T* __restrict__ src,
                                                                     size_t sstride, T* __restrict__ dst,
                                                                     size_t dstride, const State* st) {
   constexpr int P = stage8_tile<T>();
   constexpr int LP = P == 16 ? 4 : P == 8 ? 3 : 2;
+  static_assert(LC >= 0 && LC <= LP, "columns per block");
+  constexpr uint32_t C = 1u << LC;           // columns per block
+  constexpr int LR = LP - LC;                // log2 of the roots per (full) block
+  constexpr uint32_t kPitch = 16u * C + 1u;  // B_{i+4} values per (root, z), padded
   const int b = blockIdx.z;
   if (st[b].converged) return;
   src += (size_t)b * sstride;
   dst += (size_t)b * dstride;
   const int sh = n - i - 8;                  // log2 of S8
-  const uint32_t S8 = 1u << sh;
-  const int lc = sh < LP ? sh : LP;          // log2 of the columns per block
-  const int lr = LP - lc;                    // log2 of the roots per block
-  const uint32_t C = 1u << lc;
-  // levels below lr hold one (partial) group of roots each
-  const uint32_t bx = blockIdx.x;
+  // logical block: (root group, column block), column blocks innermost, so that
+  // neighbouring columns and subtree-related groups share an XCD's L2
+  const int lcb = sh - LC;
+  const uint32_t lin = logical_block();
   uint32_t lev, g0;
-  if (bx < uint32_t(lr)) {
-    lev = bx;
-    g0 = 0;
-  } else {
-    const uint32_t q = bx - uint32_t(lr) + 1u;
-    const int k = 31 - __clz(q);
-    lev = uint32_t(lr + k);
-    g0 = (q - (1u << k)) << lr;
-  }
-  const int lnr = int(lev) < lr ? int(lev) : lr;  // log2 of the roots of this block
+  if (!stage8_group(lin >> lcb, i, LR, lev, g0)) return;
+  const int lnr = int(lev) < LR ? int(lev) : LR;  // log2 of the roots of this block
   const uint32_t nr = 1u << lnr;
   const uint32_t r0 = (1u << lev) - 1u + g0;     // rank of the first root
-  const uint32_t s0 = blockIdx.y * C;
+  const uint32_t s0 = (lin & ((1u << lcb) - 1u)) * C;
   const uint32_t t = threadIdx.x;
-  // subtree node q of root rho at (rho * kInPitch + q + q / 16) C + c: the padding
-  // keeps the reads of step 1 (nodes 2^d apart across lanes) off shared banks;
-  // 31 16 C + 31 <= kInPitch C, so B_{i+4} fits in the same space
-  constexpr uint32_t kInPitch = 543u;
-  // one LDS buffer, used three times: the input subtrees, then B_{i+4} as
-  // [root][z][u2][column] (pitch 16 C + 1 per (root, z)), then the outputs
-  __shared__ T buf[uint32_t(P) * kInPitch];
-  const uint32_t pitch = 16u * C + 1u;
-  // copy-in: the 9 runs (depth k: NR 2^k rows of C columns) as one index space f,
-  // every load of a thread issued before its LDS stores
+  // one LDS buffer, used three times: the input subtrees [root][node q][column]
+  // (511 C per root), then B_{i+4} as [root][z][u2][column] (kPitch per (root, z)),
+  // then the outputs [root][u][column].  Lanes take consecutive columns, then
+  // consecutive roots (odd strides 511 C and 31 kPitch), so reads of the same node
+  // across lanes fall on distinct banks.
+  constexpr uint32_t kIn = uint32_t(P) * 511u, kMid = 31u * (uint32_t(P) >> LC) * kPitch;
+  __shared__ T buf[kIn > kMid ? kIn : kMid];
+  // copy-in: depth k of the roots' subtrees is one run of nr 2^k consecutive ranks;
+  // every load of a thread is issued before its LDS stores
   {
     constexpr int kPer = (P * 511 + 32 * P - 1) / (32 * P);
-    const int lrc = lnr + lc;
-    const uint32_t total = (nr * 511u) << lc;
+    const int lrc = lnr + LC;
+    const uint32_t total = (nr * 511u) << LC;
     T v[kPer];
     uint32_t li[kPer];
 #pragma unroll
@@ -765,10 +809,10 @@ __global__ __launch_bounds__(32 * stage8_tile<T>()) void k_bwd_stage8(int n, int
       if (f < total) {
         const int k = 31 - __clz((f >> lrc) + 1u);
         const uint32_t w = f - (((1u << k) - 1u) << lrc);
-        const uint32_t m = w >> lc, c = w & (C - 1u);
+        const uint32_t m = w >> LC, c = w & (C - 1u);
         const uint32_t rho = m >> k, q = (1u << k) - 1u + (m & ((1u << k) - 1u));
         v[j] = src[((size_t)(((r0 + 1u) << k) - 1u + m) << sh) + s0 + c];
-        li[j] = ((rho * kInPitch + q + (q >> 4)) << lc) + c;
+        li[j] = ((rho * 511u + q) << LC) + c;
       }
     }
 #pragma unroll
@@ -776,63 +820,53 @@ __global__ __launch_bounds__(32 * stage8_tile<T>()) void k_bwd_stage8(int n, int
       if (li[j] != ~0u) buf[li[j]] = v[j];
   }
   __syncthreads();
+  // step 1: thread (z = node e1 of root rho1's depth-4 subtree, column c1)
   Vec<T, 1> Dv[16];
-  const bool s1 = t < ((31u * nr) << lc);
-  uint32_t c1 = 0, rho1 = 0, e1 = 0;
+  const bool s1 = t < ((31u * nr) << LC);
+  const uint32_t c1 = t & (C - 1u), rest1 = t >> LC;
+  const uint32_t rho1 = rest1 & (nr - 1u), e1 = rest1 >> lnr;
   if (s1) {
-    c1 = t & (C - 1u);
-    const uint32_t rest = t >> lc;
-    rho1 = rest / 31u;
-    e1 = rest - rho1 * 31u;
-    const int de = 31 - __clz(e1 + 1u);
-    const uint32_t me = e1 + 1u - (1u << de);
+    // node e1's descendant (depth d, index m) is node ((e1 + 1) << d) + m - 1
     Vec<T, 1> S[31];
 #pragma unroll
-    for (int d = 0; d <= 4; ++d)
+    for (int d = 0; d <= 4; ++d) {
+      const T* row = buf + ((rho1 * 511u + ((e1 + 1u) << d) - 1u) << LC) + c1;
 #pragma unroll
-      for (int m = 0; m < (1 << d); ++m) {
-        const uint32_t q = (1u << (de + d)) - 1u + (me << d) + uint32_t(m);
-        S[(1 << d) - 1 + m].v[0] = buf[((rho1 * kInPitch + q + (q >> 4)) << lc) + c1];
-      }
+      for (int m = 0; m < (1 << d); ++m) S[(1 << d) - 1 + m].v[0] = row[uint32_t(m) << LC];
+    }
     bwd4_tree<T, 1>(S, Dv);
   }
   __syncthreads();
   if (s1) {
-    T* mp = buf + (rho1 * 31u + e1) * pitch + c1;
+    T* mp = buf + (rho1 * 31u + e1) * kPitch + c1;
 #pragma unroll
-    for (int u = 0; u < 16; ++u) mp[uint32_t(u) << lc] = Dv[u].v[0];
+    for (int u = 0; u < 16; ++u) mp[uint32_t(u) << LC] = Dv[u].v[0];
   }
   __syncthreads();
-  const bool s2 = t < ((16u * nr) << lc);
-  uint32_t c2 = 0, u2 = 0, rho2 = 0;
+  // step 2: thread (root rho2, u2, column c2)
+  const bool s2 = t < ((16u * nr) << LC);
+  const uint32_t c2 = t & (C - 1u), rest2 = t >> LC;
+  const uint32_t u2 = rest2 & 15u, rho2 = rest2 >> 4;
   if (s2) {
-    c2 = t & (C - 1u);
-    const uint32_t rest = t >> lc;
-    u2 = rest & 15u;
-    rho2 = rest >> 4;
     Vec<T, 1> S[31];
-    const T* mp = buf + rho2 * 31u * pitch + (u2 << lc) + c2;
+    const T* mp = buf + rho2 * 31u * kPitch + (u2 << LC) + c2;
 #pragma unroll
-    for (int e = 0; e < 31; ++e) S[e].v[0] = mp[uint32_t(e) * pitch];
+    for (int e = 0; e < 31; ++e) S[e].v[0] = mp[uint32_t(e) * kPitch];
     bwd4_tree<T, 1>(S, Dv);
   }
   __syncthreads();
   if (s2) {
+    T* op = buf + ((rho2 * 256u + u2) << LC) + c2;
 #pragma unroll
-    for (int u = 0; u < 16; ++u) buf[((rho2 * 256u + uint32_t(u) * 16u + u2) << lc) + c2] = Dv[u].v[0];
+    for (int u = 0; u < 16; ++u) op[(uint32_t(u) * 16u) << LC] = Dv[u].v[0];
   }
   __syncthreads();
-  const uint32_t cnt = (nr * 256u) << lc;
-  for (uint32_t e = t; e < cnt; e += blockDim.x) {
-    const uint32_t c = e & (C - 1u), rest = e >> lc;
+  const uint32_t cnt = (nr * 256u) << LC;
+  for (uint32_t e = t; e < cnt; e += 32u * P) {
+    const uint32_t c = e & (C - 1u), rest = e >> LC;
     const uint32_t u = rest & 255u, rho = rest >> 8;
     dst[((size_t)(r0 + rho) << (sh + 8)) + (u << sh) + s0 + c] = buf[e];
   }
-}
-
-// Blocks (x) of k_bwd_stage8 at position i: one per root group.
-inline uint32_t stage8_groups(int i, int lr) {
-  return (i + 1 <= lr) ? uint32_t(i + 1) : uint32_t(lr) + (1u << (i + 1 - lr)) - 1u;
 }
 
 // The same for source rows of width 1 (the first backward launch, from v): one
@@ -987,9 +1021,18 @@ hipError_t launch_backward(const Group<T>& g, hipStream_t s, int* launches, int 
       constexpr int LP = stage8_tile<T>() == 16 ? 4 : stage8_tile<T>() == 8 ? 3 : 2;
       const int sh = n - i - 8;
       const int lc = sh < LP ? sh : LP;
-      const dim3 grid(stage8_groups(i, LP - lc), 1u << (sh - lc), g.nb);
-      hipLaunchKernelGGL((k_bwd_stage8<T>), grid, dim3(32 * stage8_tile<T>()), 0, s, n, i, src, ss, dst, g.fs,
-                         g.st);
+      const dim3 grid(((stage8_slots(i, LP - lc) << (sh - lc)) + 7u) & ~7u, 1, g.nb);
+      const dim3 block(32 * stage8_tile<T>());
+      switch (lc) {
+        case 0: hipLaunchKernelGGL((k_bwd_stage8<T, 0>), grid, block, 0, s, n, i, src, ss, dst, g.fs, g.st); break;
+        case 1: hipLaunchKernelGGL((k_bwd_stage8<T, 1>), grid, block, 0, s, n, i, src, ss, dst, g.fs, g.st); break;
+        case 2: hipLaunchKernelGGL((k_bwd_stage8<T, 2>), grid, block, 0, s, n, i, src, ss, dst, g.fs, g.st); break;
+        case 3: hipLaunchKernelGGL((k_bwd_stage8<T, 3>), grid, block, 0, s, n, i, src, ss, dst, g.fs, g.st); break;
+        default:
+          if constexpr (LP == 4)
+            hipLaunchKernelGGL((k_bwd_stage8<T, 4>), grid, block, 0, s, n, i, src, ss, dst, g.fs, g.st);
+          break;
+      }
       if (launches) ++*launches;
       src = dst;
       ss = g.fs;
