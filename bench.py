@@ -31,18 +31,19 @@ DS = [0.64, 0.80, 0.95]
 FUSE = 4  # the library default (positions per launch of the factored engine)
 
 
-# HBM bytes per forward-sweep launch of this workload, from rocprofv3 FETCH_SIZE and
+# HBM bytes per launch of this workload's sweeps, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (scaled by a device copy's reading of the same counters: x2.0 and x1.0),
-# averaged over the launches of one sweep; valid only for the kernel source it was
-# measured on (summary: profiles/k_fwd_stage2_n20_fp32_x3.md).
+# averaged over the launches of one sweep of a fused iteration (the first forward
+# launch also making the previous iteration's update); valid only for the kernel
+# sources they were measured on (summary: profiles/factored_sweeps_n20_fp32_x3.md).
 MEASURED_TRAFFIC = {
     "sources": ["paper_2604_05867_amd/csrc/ba_factored.hip", "paper_2604_05867_amd/csrc/ba_factored_common.h"],
-    # of the sources concatenated; the figures: profiles/factored_sweeps_n20_fp32_x3.md
-    "sha256": "11589f0402b610577ad3aaeaf1c644b95a20148ef6e22b96fb58eb1f396fa19d",
-    # average over the launches of one sweep (forward: 4 four-position + 2 two-position
-    # launches; backward: 5 four-position launches, D fused into the last)
-    "sweep1": 53821139,
-    "sweep2": 63265925,
+    # of the sources concatenated
+    "sha256": "d035b0e8a773dd091c41176d63ce5b39ab19ce90235666c29697b47074662efc",
+    # forward: k_fwd_first4_upd, k_fwd_stage4 x3, k_fwd_last4; backward: k_bwd_stage8 x2,
+    # k_bwd_stage4 with D fused
+    "sweep1": 70792000,
+    "sweep2": 62240000,
 }
 
 
@@ -68,11 +69,13 @@ def stage_sizes(n):
     return [((2 << i) - 1) << (n - i) for i in range(n + 1)]
 
 
-def sweep_launch_bytes(n, esz, nb, fuse, backward):
+def sweep_launch_bytes(n, esz, nb, fuse, backward, fused_update=0.0):
     """Algorithmic HBM bytes of each launch of one sweep of the factored engine, in
     launch order: a launch covering positions i..i+t-1 reads its source stage once
     and writes its destination stage once; the last backward launch also reads
-    H and log p (D is formed there).  Launch sequence as in the library: fuse 2 =
+    H and log p (D is formed there); the first forward launch, when it makes the
+    previous iteration's update (a fraction fused_update of the iterations), reads
+    log p and D instead of p and writes log p.  Launch sequence as in the library: fuse 2 =
     four positions per launch (forward: the last 1-4 positions two at a time;
     backward: the first n mod 4 positions two or one at a time), fuse 3 = as 2 with
     eight positions per backward launch while four remain after it, fuse 4 = as 3
@@ -94,7 +97,7 @@ def sweep_launch_bytes(n, esz, nb, fuse, backward):
     else:
         top, lead = n, (n % 4 if (fuse >= 2 and n >= 4) else -1)
         while top > 0:
-            if fuse == 3 and lead >= 0 and n - top >= lead and top - 8 >= 4:
+            if fuse >= 3 and lead >= 0 and n - top >= lead and top - 8 >= 4:
                 t = 8
             elif lead >= 0 and n - top >= lead:
                 t = 4
@@ -105,6 +108,8 @@ def sweep_launch_bytes(n, esz, nb, fuse, backward):
     out = [(s[a] + s[b]) * esz * nb for a, b in steps]
     if backward:
         out[-1] += 2 * (1 << n) * esz * nb
+    else:
+        out[0] += fused_update * 2 * (1 << n) * esz * nb
     return out
 
 
@@ -336,14 +341,16 @@ def main():
     dom = max(("sweep1", "sweep2"), key=lambda k: kt[k][0])
     dom_ms, dom_launches = kt[dom]
     per_launch_ms = dom_ms / max(dom_launches, 1)
-    per_launch = sweep_launch_bytes(N, 4, nb, FUSE, backward=(dom == "sweep2"))
+    # within one step call every iteration but the first makes the previous update
+    per_launch = sweep_launch_bytes(N, 4, nb, FUSE, backward=(dom == "sweep2"),
+                                    fused_update=(args.steps - 1) / args.steps)
     assert len(per_launch) == dom_launches // args.steps, (len(per_launch), dom_launches)
     bytes_launch = sum(per_launch) / len(per_launch)
     achieved = bytes_launch / (per_launch_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
                 "frac": round(achieved / 8000.0, 4),
                 "traffic": measured_traffic(dom),
-                "kernel": ("forward sweep (k_fwd_stage4 x4, k_fwd_last4)" if dom == "sweep1"
+                "kernel": ("forward sweep (k_fwd_first4_upd, k_fwd_stage4 x3, k_fwd_last4)" if dom == "sweep1"
                            else "backward sweep (k_bwd_stage8 x2, k_bwd_stage4 with D fused)"),
                 "bytes_per_launch": int(bytes_launch), "avg_launch_us": round(per_launch_ms * 1e3, 2)}
 
