@@ -796,7 +796,31 @@ __global__ __launch_bounds__(32 * stage8_tile<T>()) void k_bwd_stage8(int n, int
   __shared__ T buf[kIn > kMid ? kIn : kMid];
   // copy-in: depth k of the roots' subtrees is one run of nr 2^k consecutive ranks;
   // every load of a thread is issued before its LDS stores
-  {
+  if constexpr (LR == 0) {
+    // one root: subtree node q (of 511) is C columns (64 bytes) that one thread
+    // copies; 32 P threads take 511 / (32 P) rounded up nodes each
+    constexpr int VW = 16 / int(sizeof(T));
+    constexpr int kRows = (511 + 32 * P - 1) / (32 * P);
+    Vec<T, VW> v[kRows][C / VW];
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) {
+      const uint32_t q = t + uint32_t(r) * (32u * P);
+      if (q < 511u) {
+        const int k = 31 - __clz(q + 1u);
+        const T* g = src + ((size_t)(((r0 + 1u) << k) - 1u + (q + 1u - (1u << k))) << sh) + s0;
+#pragma unroll
+        for (uint32_t j = 0; j < C / VW; ++j) v[r][j] = ld<T, VW>(g + j * VW);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) {
+      const uint32_t q = t + uint32_t(r) * (32u * P);
+      if (q < 511u) {
+#pragma unroll
+        for (uint32_t j = 0; j < C / VW; ++j) stv<T, VW>(buf + (q << LC) + j * VW, v[r][j]);
+      }
+    }
+  } else {
     constexpr int kPer = (P * 511 + 32 * P - 1) / (32 * P);
     const int lrc = lnr + LC;
     const uint32_t total = (nr * 511u) << LC;
