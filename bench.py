@@ -165,7 +165,7 @@ def run_segments(ctx, gap_bits, cap, seg, tag):
     return done
 
 
-def config3(cap, gap_bits, plain_limit_s, plain_graphs=False):
+def config3(cap, gap_bits, plain_limit_s, plain_graphs=False, symmetric=False):
     """Batched FP32 (one graph, 128 instances) against plain FP64 one instance at a
     time, both to a certified gap < gap_bits or the iteration cap.  Prints one JSON
     line with both wall times and the speedup at equal certified gap."""
@@ -184,7 +184,8 @@ def config3(cap, gap_bits, plain_limit_s, plain_graphs=False):
     ctx = ba.Context(ns, ds, prec=ba.PREC_FP32_LOG, engine=ba.ENGINE_FACTORED, cert_every=50, stream=s)
     ctx.set_graphs(True)
     ctx.set_stop_rule(ba.STOP_BEST)
-    ctx.set_symmetry(True)  # p0 uniform: every iterate is complement-invariant (both sides use it)
+    if symmetric:  # p0 uniform: every iterate is complement-invariant (both sides then use it)
+        ctx.set_symmetry(True)
     with torch.cuda.stream(s):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -208,7 +209,8 @@ def config3(cap, gap_bits, plain_limit_s, plain_graphs=False):
         ps = torch.cuda.Stream() if plain_graphs else torch.cuda.current_stream()
         c = ba.Context(n, d, prec=ba.PREC_FP64, engine=ba.ENGINE_FACTORED, stream=ps)
         c.set_stop_rule(ba.STOP_BEST)
-        c.set_symmetry(True)
+        if symmetric:
+            c.set_symmetry(True)
         c.set_graphs(plain_graphs)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -229,7 +231,8 @@ def config3(cap, gap_bits, plain_limit_s, plain_graphs=False):
     out = {
         "metric": "batched FP32 vs plain FP64 speedup at equal certified gap",
         "stop_rule": "best certified bounds so far", "plain_graphs": plain_graphs,
-        "kernels": "factored, four positions per launch, complement-symmetric (both sides)",
+        "kernels": ("factored, default launch plan, complement-symmetric (both sides)" if symmetric
+                    else "factored, default launch plan (both sides)"),
         "gap_bits": gap_bits, "cap": cap, "instances": len(ns), "plain_instances_timed": m,
         "t_batched_s": t_batch, "t_plain_s_timed": t_plain,
         "speedup": (t_plain / share) / t_batch if m else None,
@@ -285,6 +288,8 @@ def main():
     ap.add_argument("--no-stream", action="store_true")
     ap.add_argument("--config3", action="store_true",
                     help="batched FP32 vs plain FP64 at equal certified gap (several minutes)")
+    ap.add_argument("--config3-symmetric", action="store_true",
+                    help="config 3 with the complement-symmetric kernels on both sides")
     ap.add_argument("--cap", type=int, default=200000)
     ap.add_argument("--gap", type=float, default=1e-6)
     ap.add_argument("--plain-limit-s", type=float, default=600.0)
@@ -305,7 +310,7 @@ def main():
         print(json.dumps({"copy_bytes": a.numel() * 4}))
         return
     if args.config3:
-        config3(args.cap, args.gap, args.plain_limit_s, args.plain_graphs)
+        config3(args.cap, args.gap, args.plain_limit_s, args.plain_graphs, args.config3_symmetric)
         return
     if args.step_compare:
         step_compare(args.cap, args.gap, (1.0, 1.5, 2.0))

@@ -146,8 +146,8 @@ int ba_set_step(ba_ctx *c, double eta);
 /* Run ba_run's iteration chunks as one captured HIP graph (replayed until the
  * stopping rule holds) instead of individual launches.  Needs a non-null bound
  * stream (capture is not allowed on the legacy null stream): BA_ESTATE otherwise,
- * reported by ba_run.  The graph is rebuilt after ba_bind, ba_set_engine or a
- * change of chunk length. */
+ * reported by ba_run.  The graph is rebuilt after ba_bind, ba_set_engine,
+ * ba_set_tuning, ba_set_step, ba_set_symmetry or a change of chunk length. */
 int ba_set_graphs(ba_ctx *c, int enable);
 
 /* Tuning knobs (they never change results beyond rounding order).
