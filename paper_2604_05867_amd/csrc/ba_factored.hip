@@ -793,7 +793,7 @@ __global__ __launch_bounds__(32 * stage8_tile<T>()) void k_bwd_stage8(int n, int
   // consecutive roots (odd strides 511 C and 31 kPitch), so reads of the same node
   // across lanes fall on distinct banks.
   constexpr uint32_t kIn = uint32_t(P) * 511u, kMid = 31u * (uint32_t(P) >> LC) * kPitch;
-  __shared__ T buf[kIn > kMid ? kIn : kMid];
+  __shared__ __attribute__((aligned(16))) T buf[kIn > kMid ? kIn : kMid];
   // copy-in: depth k of the roots' subtrees is one run of nr 2^k consecutive ranks;
   // every load of a thread is issued before its LDS stores
   if constexpr (LR == 0) {
@@ -820,6 +820,37 @@ __global__ __launch_bounds__(32 * stage8_tile<T>()) void k_bwd_stage8(int n, int
         for (uint32_t j = 0; j < C / VW; ++j) stv<T, VW>(buf + (q << LC) + j * VW, v[r][j]);
       }
     }
+  } else if (LC == 0 && nr == uint32_t(P)) {
+    // P roots, one column: depth k is a run of P 2^k consecutive ranks; the runs of
+    // depth 5..8 hold 32 P 2^(k-5) values, i.e. 2^(k-5) per thread, and depths 0..4
+    // together 31 P values, one per thread for the first 31 P threads
+    constexpr uint32_t NT = 32u * P;
+    T v[16];
+    uint32_t li[16];
+    {
+      const uint32_t f = t;  // depths 0..4: f = P (2^k - 1) + m
+      const int k = 31 - __clz((f >> LP) + 1u);
+      const uint32_t m = f - ((1u << k) - 1u) * uint32_t(P);
+      li[0] = ~0u;
+      if (f < 31u * P) {
+        v[0] = src[((r0 + 1u) << k) - 1u + m];
+        li[0] = (m >> k) * 511u + (1u << k) - 1u + (m & ((1u << k) - 1u));
+      }
+    }
+#pragma unroll
+    for (int k = 5; k <= 8; ++k) {
+      const uint32_t base = ((r0 + 1u) << k) - 1u;
+#pragma unroll
+      for (int j = 0; j < (1 << (k - 5)); ++j) {
+        const uint32_t m = t + uint32_t(j) * NT;
+        const int sl = (1 << (k - 5)) + j;  // 1, 2-3, 4-7, 8-15
+        v[sl] = src[base + m];
+        li[sl] = (m >> k) * 511u + (1u << k) - 1u + (m & ((1u << k) - 1u));
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+      if (li[j] != ~0u) buf[li[j]] = v[j];
   } else {
     constexpr int kPer = (P * 511 + 32 * P - 1) / (32 * P);
     const int lrc = lnr + LC;
@@ -885,6 +916,17 @@ __global__ __launch_bounds__(32 * stage8_tile<T>()) void k_bwd_stage8(int n, int
     for (int u = 0; u < 16; ++u) op[(uint32_t(u) * 16u) << LC] = Dv[u].v[0];
   }
   __syncthreads();
+  if (LC == 0 && nr == uint32_t(P)) {
+    // the P output rows of 256 values are consecutive: one contiguous block
+    constexpr int VW = 16 / int(sizeof(T));
+    T* o = dst + ((size_t)r0 << 8);
+#pragma unroll
+    for (uint32_t j = 0; j < (P * 256u) / (VW * 32u * P); ++j) {
+      const uint32_t e = (t + j * 32u * P) * VW;
+      stv<T, VW>(o + e, ld<T, VW>(buf + e));
+    }
+    return;
+  }
   const uint32_t cnt = (nr * 256u) << LC;
   for (uint32_t e = t; e < cnt; e += 32u * P) {
     const uint32_t c = e & (C - 1u), rest = e >> LC;
