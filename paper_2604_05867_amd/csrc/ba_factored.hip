@@ -467,57 +467,72 @@ __global__ __launch_bounds__(kLast2Threads) void k_fwd_last2(int n, const T* __r
 
 // The last four positions (n-4 .. n-1) for n >= kLast4MinN: the four-position step
 // of k_fwd_stage4 at i = n-4 (output rows of width 1), with the outputs staged in
-// LDS.  Deep blocks (blockIdx.x < 2^(n-4) / kLast2Threads): thread t takes the leaf
-// a of rank A0 + t (level L = n-4) and its 30 rows below; level L+j of a block's
-// outputs is one run of kLast2Threads 2^j consecutive ranks, written back coalesced
-// (row stride 2^j + 1 in LDS against bank conflicts).  The other blocks take one row
-// of level < L per thread (its output only).
+// LDS.  Deep block: the node a of level L - 6 (L = n-4) of rank 2^(L-6) - 1 +
+// blockIdx.x and its subtree down to level n.  Its first wavefront takes the 64
+// leaves of level L below a and their 30 rows below (level L+j of the block's outputs
+// is one run of 64 2^j consecutive ranks, staged in LDS with row stride 2^j + 1
+// against bank conflicts and written back coalesced); its second wavefront takes the
+// 63 rows of a's subtree above level L (their outputs only), whose source rows are the
+// leaves' ancestors, read again from the same CU's caches.  The other blocks take one
+// row of level < L - 6 per thread.
 constexpr int kLast4MinN = 12;
+constexpr int kLast4Threads = 128;
 
 template <typename T, bool LOGV>
-__global__ __launch_bounds__(kLast2Threads) void k_fwd_last4(int n, const T* __restrict__ src, size_t sstride,
+__global__ __launch_bounds__(kLast4Threads) void k_fwd_last4(int n, const T* __restrict__ src, size_t sstride,
                                                              T* __restrict__ dst, size_t dstride,
                                                              const State* st, const Consts* cs) {
   const int b = blockIdx.y;
   if (st[b].converged) return;
   src += (size_t)b * sstride;
   dst += (size_t)b * dstride;
-  const int L = n - 4;
-  const uint32_t ndeep = (1u << L) / kLast2Threads;
+  const int L = n - 4, La = L - 6;
+  const uint32_t ndeep = 1u << La;
   const uint32_t t = threadIdx.x;
   T F4[30];
   if (blockIdx.x >= ndeep) {
-    const uint32_t c = (blockIdx.x - ndeep) * kLast2Threads + t;
-    if (c + 1u >= (1u << L)) return;
+    const uint32_t c = (blockIdx.x - ndeep) * kLast4Threads + t;
+    if (c + 1u >= (1u << La)) return;
     T r = fwd4_thread<T>(src, 0, c, length_of_rank(c), 0u, F4);
     if constexpr (LOGV) r = log_weighted<T>(cs[b], c, r);
     dst[c] = r;
     return;
   }
-  __shared__ T stage[kLast2Lds * kLast2Threads];
-  const uint32_t A0 = (1u << L) - 1u + blockIdx.x * kLast2Threads;
-  const uint32_t a = A0 + t;
-  T va = fwd4_thread<T>(src, 0, a, L, 0u, F4);
-  const T w0 = T(cs[b].w[L]), w1 = T(cs[b].w[L + 1]), w2 = T(cs[b].w[L + 2]), w3 = T(cs[b].w[L + 3]),
-          w4 = T(cs[b].w[L + 4]);
-  auto outv = [](T w, T r) -> T {
-    if constexpr (LOGV) return (w == T(0)) ? T(0) : w * log_t<T>(r);
-    else return r;
-  };
+  __shared__ T stage[(kLast2Lds - 1) * 64];
+  const uint32_t a = ndeep - 1u + blockIdx.x;       // level La
+  const uint32_t A0 = ((a + 1u) << 6) - 1u;         // its first leaf (level L)
   T* s1 = stage;
-  T* s2 = s1 + 3 * kLast2Threads;
-  T* s3 = s2 + 5 * kLast2Threads;
-  T* s4 = s3 + 9 * kLast2Threads;
-  dst[a] = outv(w0, va);
-  // F4: depth d, index m at (1 << d) - 2 + m
+  T* s2 = s1 + 3 * 64;
+  T* s3 = s2 + 5 * 64;
+  T* s4 = s3 + 9 * 64;
+  if (t < 64u) {
+    const uint32_t y = A0 + t;
+    const T va = fwd4_thread<T>(src, 0, y, L, 0u, F4);
+    const T w0 = T(cs[b].w[L]), w1 = T(cs[b].w[L + 1]), w2 = T(cs[b].w[L + 2]), w3 = T(cs[b].w[L + 3]),
+            w4 = T(cs[b].w[L + 4]);
+    auto outv = [](T w, T r) -> T {
+      if constexpr (LOGV) return (w == T(0)) ? T(0) : w * log_t<T>(r);
+      else return r;
+    };
+    dst[y] = outv(w0, va);
+    // F4: depth d, index m at (1 << d) - 2 + m
 #pragma unroll
-  for (int q = 0; q < 2; ++q) s1[3u * t + q] = outv(w1, F4[q]);
+    for (int q = 0; q < 2; ++q) s1[3u * t + q] = outv(w1, F4[q]);
 #pragma unroll
-  for (int q = 0; q < 4; ++q) s2[5u * t + q] = outv(w2, F4[2 + q]);
+    for (int q = 0; q < 4; ++q) s2[5u * t + q] = outv(w2, F4[2 + q]);
 #pragma unroll
-  for (int q = 0; q < 8; ++q) s3[9u * t + q] = outv(w3, F4[6 + q]);
+    for (int q = 0; q < 8; ++q) s3[9u * t + q] = outv(w3, F4[6 + q]);
 #pragma unroll
-  for (int q = 0; q < 16; ++q) s4[17u * t + q] = outv(w4, F4[14 + q]);
+    for (int q = 0; q < 16; ++q) s4[17u * t + q] = outv(w4, F4[14 + q]);
+  } else if (t < 127u) {
+    // node q of a's subtree above level L: depth d = log2(q + 1)
+    const uint32_t q = t - 64u;
+    const int d = length_of_rank(q);
+    const uint32_t y = ((a + 1u) << d) - 1u + (q + 1u - (1u << d));
+    T r = fwd4_thread<T>(src, 0, y, La + d, 0u, F4);
+    if constexpr (LOGV) r = log_weighted<T>(cs[b], y, r);
+    dst[y] = r;
+  }
   __syncthreads();
 #pragma unroll
   for (int j = 1; j <= 4; ++j) {
@@ -525,8 +540,8 @@ __global__ __launch_bounds__(kLast2Threads) void k_fwd_last4(int n, const T* __r
     const T* sj = j == 1 ? s1 : j == 2 ? s2 : j == 3 ? s3 : s4;
     T* out = dst + (wj * (A0 + 1u) - 1u);
 #pragma unroll
-    for (uint32_t k = 0; k < wj; ++k) {
-      const uint32_t e = k * kLast2Threads + t;
+    for (uint32_t k = 0; k < wj / 2u; ++k) {
+      const uint32_t e = k * kLast4Threads + t;
       out[e] = sj[(e >> j) * stride + (e & (wj - 1u))];
     }
   }
@@ -976,12 +991,13 @@ hipError_t launch_forward(const Group<T>& g, hipStream_t s, int* launches, int f
   for (int i = 0; i < n; k++) {
     if (last4 && n - i == 4) {
       T* dst = logv ? g.v : g.r;
-      const dim3 grid(2u * ((1u << (n - 4)) / kLast2Threads), g.nb);
+      const uint32_t top = (1u << (n - 10)) - 1u;  // rows above the deep blocks' subtrees
+      const dim3 grid((1u << (n - 10)) + (top + kLast4Threads - 1u) / kLast4Threads, g.nb);
       if (logv)
-        hipLaunchKernelGGL((k_fwd_last4<T, true>), grid, dim3(kLast2Threads), 0, s, n, src, ss, dst, g.ys, g.st,
+        hipLaunchKernelGGL((k_fwd_last4<T, true>), grid, dim3(kLast4Threads), 0, s, n, src, ss, dst, g.ys, g.st,
                            g.cs);
       else
-        hipLaunchKernelGGL((k_fwd_last4<T, false>), grid, dim3(kLast2Threads), 0, s, n, src, ss, dst, g.ys, g.st,
+        hipLaunchKernelGGL((k_fwd_last4<T, false>), grid, dim3(kLast4Threads), 0, s, n, src, ss, dst, g.ys, g.st,
                            g.cs);
       if (launches) ++*launches;
       break;
