@@ -39,11 +39,11 @@ FUSE = 4  # the library default (positions per launch of the factored engine)
 MEASURED_TRAFFIC = {
     "sources": ["paper_2604_05867_amd/csrc/ba_factored.hip", "paper_2604_05867_amd/csrc/ba_factored_common.h"],
     # of the sources concatenated
-    "sha256": "b7bb710cc88b294f66d8679156f7742c32bfc680643a748f2e770f4d147011fe",
+    "sha256": "0831092aa54225ed2d0ae394cf15fb1cc398fd06101b945d437ac6908332f46f",
     # forward: k_fwd_first4_upd, k_fwd_stage4 x3, k_fwd_last4; backward: k_bwd_stage8 x2,
     # k_bwd_stage4 with D fused
-    "sweep1": 60066000,
-    "sweep2": 62223000,
+    "sweep1": 52714000,
+    "sweep2": 55180000,
 }
 
 

@@ -474,7 +474,9 @@ __global__ __launch_bounds__(kLast2Threads) void k_fwd_last2(int n, const T* __r
 // against bank conflicts and written back coalesced); its second wavefront takes the
 // 63 rows of a's subtree above level L (their outputs only), whose source rows are the
 // leaves' ancestors, read again from the same CU's caches.  The other blocks take one
-// row of level < L - 6 per thread.
+// row of level < L - 6 per thread.  Neighbouring nodes a share the cache lines at
+// the ends of their rank runs (and their ancestors above level L - 6), so the deep
+// blocks are spread over the XCDs in contiguous runs of a.
 constexpr int kLast4MinN = 12;
 constexpr int kLast4Threads = 128;
 
@@ -499,7 +501,9 @@ __global__ __launch_bounds__(kLast4Threads) void k_fwd_last4(int n, const T* __r
     return;
   }
   __shared__ T stage[(kLast2Lds - 1) * 64];
-  const uint32_t a = ndeep - 1u + blockIdx.x;       // level La
+  // hardware block 8 k + x runs on XCD x: node k of XCD x's run of ndeep / 8
+  const uint32_t da = (ndeep & 7u) ? blockIdx.x : (blockIdx.x & 7u) * (ndeep >> 3) + (blockIdx.x >> 3);
+  const uint32_t a = ndeep - 1u + da;               // level La
   const uint32_t A0 = ((a + 1u) << 6) - 1u;         // its first leaf (level L)
   T* s1 = stage;
   T* s2 = s1 + 3 * 64;
@@ -792,9 +796,19 @@ __global__ __launch_bounds__(32 * stage8_tile<T>()) void k_bwd_stage8(int n, int
   dst += (size_t)b * dstride;
   const int sh = n - i - 8;                  // log2 of S8
   // logical block: (root group, column block), column blocks innermost, so that
-  // neighbouring columns and subtree-related groups share an XCD's L2
+  // neighbouring columns and subtree-related groups share an XCD's L2; with 8 or
+  // more column blocks, XCD x (hardware block 8 k + x) takes its eighth of the
+  // column blocks of every group, so that the overlapping subtrees of a root and
+  // its descendants are all read through one L2
   const int lcb = sh - LC;
-  const uint32_t lin = logical_block();
+  uint32_t lin;
+  if (lcb >= 3) {
+    const uint32_t x = blockIdx.x & 7u, k = blockIdx.x >> 3;
+    const int cl = lcb - 3;
+    lin = ((k >> cl) << lcb) + (x << cl) + (k & ((1u << cl) - 1u));
+  } else {
+    lin = logical_block();
+  }
   uint32_t lev, g0;
   if (!stage8_group(lin >> lcb, i, LR, lev, g0)) return;
   const int lnr = int(lev) < LR ? int(lev) : LR;  // log2 of the roots of this block
@@ -1011,8 +1025,9 @@ hipError_t launch_forward(const Group<T>& g, hipStream_t s, int* launches, int f
       T* dst = last ? (lv ? g.v : g.r) : ((k & 1) ? g.f1 : g.f0);
       const size_t ds = last ? g.ys : g.fs;
       const uint32_t S4 = 1u << (n - i - 4);
-      const Order o = make_order(i + 1, ilog2(S4), sizeof(T));
-      const dim3 grid(blocks_for(order_threads(o), kStage4Block), g.nb);
+      Order o = make_order(i + 1, ilog2(S4), sizeof(T));
+      make_order_xcd(i + 1, ilog2(S4), kStage4Block, o);  // o unchanged where infeasible
+      const dim3 grid(order_blocks(o, kStage4Block), g.nb);
       if (i == 0 && upd)
         hipLaunchKernelGGL((k_fwd_first4_upd<T>), grid, dim3(kStage4Block), 0, s, n, dst, ds, g, o, upd->floor,
                            upd->check_tol);

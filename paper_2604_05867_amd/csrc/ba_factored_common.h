@@ -72,11 +72,12 @@ __device__ __forceinline__ T log_weighted(const Consts& cs, uint32_t y, T r) {
 // subtree stays on one L2.
 // ---------------------------------------------------------------------------
 struct Order {
-  uint32_t nlog;  // logical row slots per column tile
+  uint32_t nlog;  // logical row slots per column tile (per unit when kb > 0)
   uint32_t top;   // rows above level lb: 2^lb - 1
   uint32_t nct;   // column tiles
   int lb, h;      // level of the subtree roots, subtree height (levels)
   int cw_log2;    // log2 of the column-tile width in chunks
+  uint32_t kb;    // 0, or blocks per XCD of the unit partition (make_order_xcd)
 };
 
 constexpr size_t kTileBytes = size_t(1) << 19;
@@ -94,10 +95,52 @@ inline Order make_order(int levels, int cols_log2, size_t chunk_bytes) {
   o.top = (1u << o.lb) - 1u;
   o.nlog = (o.lb == 0) ? (1u << h) - 1u : o.top + (1u << (o.lb + h));
   o.nct = 1u << (cols_log2 - o.cw_log2);
+  o.kb = 0;
   return o;
 }
 
 inline uint32_t order_threads(const Order& o) { return o.nct * o.nlog << o.cw_log2; }
+
+// A partition of the launch into 8 m units that are each read from one XCD's L2
+// only: a unit is one column tile of the whole tree (rows of >= 256 chunks, tiles
+// of 32 or 64 chunks), or, for narrower rows, one of the 8 subtrees rooted at
+// level 3 over all columns.  A row's ancestors then lie in its own unit (or among
+// the 7 rows above level 3, visited by the trailing blocks), so a row read again
+// by its descendants is an L2 hit instead of a fetch by a second XCD.  Each unit
+// holds 2^h slots (the subtree's rows breadth-first and one padding slot) per
+// chunk; XCD x runs units x m .. x m + m - 1 (hardware block 8 k + x, k < kb).
+// False when a unit is not a whole number of blocks.
+inline bool make_order_xcd(int levels, int cols_log2, uint32_t block, Order& o) {
+  int cw, lb;
+  if (cols_log2 >= 8) {
+    cw = cols_log2 - 3 < 6 ? cols_log2 - 3 : 6;
+    lb = 0;
+  } else {
+    cw = cols_log2;
+    lb = 3;
+  }
+  const int h = levels - lb;
+  if (h < 1 || h + cw > 30 || ((uint32_t(1) << (h + cw)) % block) != 0u) return false;
+  o.cw_log2 = cw;
+  o.lb = lb;
+  o.h = h;
+  o.top = (1u << lb) - 1u;
+  o.nct = 1u << (cols_log2 - cw);
+  o.nlog = 1u << h;
+  o.kb = ((o.nct << lb) >> 3) * ((uint32_t(1) << (h + cw)) / block);
+  return true;
+}
+
+// Blocks of an ordered launch with `block` threads per block.
+inline uint32_t order_blocks(const Order& o, uint32_t block) {
+  if (o.kb == 0u) {
+    const uint32_t t = order_threads(o);
+    const uint32_t g = t == 0 ? 1u : (t + block - 1) / block;
+    return (g + 7u) & ~7u;
+  }
+  const uint32_t tb = ((o.top << o.cw_log2) + block - 1u) / block;  // the rows above level lb
+  return 8u * (o.kb + (tb + 7u) / 8u);
+}
 
 __device__ __forceinline__ uint32_t logical_block() {
   const uint32_t G = gridDim.x, bx = blockIdx.x;
@@ -125,8 +168,31 @@ __device__ __forceinline__ bool order_slot_q(const Order& o, uint32_t q, uint32_
   return true;
 }
 
+// (row, chunk) of this thread in the unit partition of make_order_xcd.
+__device__ __forceinline__ bool order_slot_xcd(const Order& o, uint32_t& row, uint32_t& chunk) {
+  const uint32_t x = blockIdx.x & 7u, k = blockIdx.x >> 3;
+  const uint32_t cmask = (1u << o.cw_log2) - 1u;
+  if (k >= o.kb) {  // the rows above level lb (one column tile)
+    const uint32_t q = (((k - o.kb) << 3) + x) * blockDim.x + threadIdx.x;
+    row = q >> o.cw_log2;
+    chunk = q & cmask;
+    return row < o.top;
+  }
+  const uint32_t q = (x * o.kb + k) * blockDim.x + threadIdx.x;
+  const int ul = o.h + o.cw_log2;
+  const uint32_t unit = q >> ul, r = q & ((1u << ul) - 1u);
+  const uint32_t j = r >> o.cw_log2;
+  if (j == o.nlog - 1u) return false;
+  const uint32_t ct = unit >> o.lb, t = unit & o.top;
+  const int lv = 31 - __clz(j + 1u);
+  row = (1u << (o.lb + lv)) - 1u + (t << lv) + (j + 1u - (1u << lv));
+  chunk = (ct << o.cw_log2) + (r & cmask);
+  return true;
+}
+
 // This thread's (row, chunk), one slot per thread.
 __device__ __forceinline__ bool order_slot(const Order& o, uint32_t& row, uint32_t& chunk) {
+  if (o.kb != 0u) return order_slot_xcd(o, row, chunk);
   return order_slot_q(o, logical_block() * blockDim.x + threadIdx.x, row, chunk);
 }
 
