@@ -725,7 +725,9 @@ __global__ __launch_bounds__(kBlock) void k_bwd_stage4(int n, int i, const T* __
 // (root, z, column), as a four-position thread with y = z), then
 // B_i[y][(16 u1 + u2) S8 + s] (step 2: one thread per (root, u2, column)), staged
 // in LDS and written back.  Every value is the same sum, in the same order, as
-// with two four-position launches.
+// with two four-position launches.  k_bwd_stage8 takes the mixed shapes
+// (1 < NR < P); the two extremes, one root or one column, which the widest and the
+// narrowest rows use, are k_bwd_stage8_p with bank-conflict-free layouts.
 template <typename T>
 constexpr int stage8_tile() { return sizeof(T) == 4 ? 16 : 8; }
 
@@ -786,7 +788,7 @@ __global__ __launch_bounds__(32 * stage8_tile<T>()) void k_bwd_stage8(int n, int
                                                                     size_t dstride, const State* st) {
   constexpr int P = stage8_tile<T>();
   constexpr int LP = P == 16 ? 4 : P == 8 ? 3 : 2;
-  static_assert(LC >= 0 && LC <= LP, "columns per block");
+  static_assert(LC >= 1 && LC < LP, "columns per block (one root or one column: k_bwd_stage8_p)");
   constexpr uint32_t C = 1u << LC;           // columns per block
   constexpr int LR = LP - LC;                // log2 of the roots per (full) block
   constexpr uint32_t kPitch = 16u * C + 1u;  // B_{i+4} values per (root, z), padded
@@ -825,31 +827,7 @@ __global__ __launch_bounds__(32 * stage8_tile<T>()) void k_bwd_stage8(int n, int
   __shared__ __attribute__((aligned(16))) T buf[kIn > kMid ? kIn : kMid];
   // copy-in: depth k of the roots' subtrees is one run of nr 2^k consecutive ranks;
   // every load of a thread is issued before its LDS stores
-  if constexpr (LR == 0) {
-    // one root: subtree node q (of 511) is C columns (64 bytes) that one thread
-    // copies; 32 P threads take 511 / (32 P) rounded up nodes each
-    constexpr int VW = 16 / int(sizeof(T));
-    constexpr int kRows = (511 + 32 * P - 1) / (32 * P);
-    Vec<T, VW> v[kRows][C / VW];
-#pragma unroll
-    for (int r = 0; r < kRows; ++r) {
-      const uint32_t q = t + uint32_t(r) * (32u * P);
-      if (q < 511u) {
-        const int k = 31 - __clz(q + 1u);
-        const T* g = src + ((size_t)(((r0 + 1u) << k) - 1u + (q + 1u - (1u << k))) << sh) + s0;
-#pragma unroll
-        for (uint32_t j = 0; j < C / VW; ++j) v[r][j] = ld<T, VW>(g + j * VW);
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < kRows; ++r) {
-      const uint32_t q = t + uint32_t(r) * (32u * P);
-      if (q < 511u) {
-#pragma unroll
-        for (uint32_t j = 0; j < C / VW; ++j) stv<T, VW>(buf + (q << LC) + j * VW, v[r][j]);
-      }
-    }
-  } else if (LC == 0 && nr == uint32_t(P)) {
+  if (LC == 0 && nr == uint32_t(P)) {
     // P roots, one column: depth k is a run of P 2^k consecutive ranks; the runs of
     // depth 5..8 hold 32 P 2^(k-5) values, i.e. 2^(k-5) per thread, and depths 0..4
     // together 31 P values, one per thread for the first 31 P threads
@@ -961,6 +939,200 @@ __global__ __launch_bounds__(32 * stage8_tile<T>()) void k_bwd_stage8(int n, int
     const uint32_t c = e & (C - 1u), rest = e >> LC;
     const uint32_t u = rest & 255u, rho = rest >> 8;
     dst[((size_t)(r0 + rho) << (sh + 8)) + (u << sh) + s0 + c] = buf[e];
+  }
+}
+
+// Eight backward positions with P independent lanes of values per subtree node:
+// one root and P columns (ROOTS = false, rows at least 16 P wide), or P roots of
+// one level (consecutive ranks) and one column (ROOTS = true, rows of width 1; fewer
+// roots on the levels above log2 P, the other lanes idle).  The steps are those of
+// k_bwd_stage8, with LDS layouts free of bank conflicts: every node keeps its P
+// values as one 64-byte row.  Per step-1 load a wavefront reads one subtree node of
+// 4 (FP32; 8 in two halves for FP64) consecutive nodes z, i.e. nodes a 2^d + m for
+// an aligned quad of 1-based heap indices a; with node rows at slot q every such
+// load would hit one group of 16 banks for d >= 2.  Node q (1-based heap index in
+// the depth-8 subtree) is therefore kept at slot sigma(q), whose low two bits are the
+// parities of q's bits and of its odd-position bits: for every d these differ across
+// an aligned quad of a (and the first parity across an aligned pair), so the four
+// rows fall on distinct bank groups.  B_{i+4} is kept as [z][u][lane] with the 16 u
+// rows of node z (1-based) permuted by u ^ (z mod 4), so that both its writers (4
+// consecutive z) and its readers (4 consecutive u) cover 4 bank groups.  With
+// roots, the copy-in writes 64 consecutive nodes of one root per wavefront, so root
+// rho of node q sits at lane position rho ^ (q / 4 mod P) of the row.  The outputs
+// are [u][column] (columns), or [root][u] with a row pitch of 260 (roots: lanes of
+// one u-quad and 16 roots on 64 distinct banks), and leave through 16-byte vectors.
+__host__ __device__ constexpr uint32_t stage8_sigma_bits(uint32_t q) {
+  return ((uint32_t(__builtin_popcount(q & 0xAAAAAAAAu)) & 1u) << 1) | (uint32_t(__builtin_popcount(q)) & 1u);
+}
+
+template <typename T, bool ROOTS>
+__global__ __launch_bounds__(32 * stage8_tile<T>()) void k_bwd_stage8_p(int n, int i, const T* __restrict__ src,
+                                                                      size_t sstride, T* __restrict__ dst,
+                                                                      size_t dstride, const State* st) {
+  constexpr uint32_t P = uint32_t(stage8_tile<T>());  // value lanes per node
+  constexpr int LP = P == 16 ? 4 : 3;
+  constexpr uint32_t NT = 32u * P;                     // threads
+  constexpr int VW = 16 / int(sizeof(T));              // P / VW = 4 vectors per node row
+  constexpr uint32_t kOutPitch = 260u;                 // ROOTS: output row pitch
+  const int b = blockIdx.z;
+  if (st[b].converged) return;
+  src += (size_t)b * sstride;
+  dst += (size_t)b * dstride;
+  const int sh = n - i - 8;                  // log2 of S8 (0 for ROOTS)
+  // logical block (root group, column block), column blocks innermost; with 8 or
+  // more column blocks XCD x takes its eighth of the column blocks of every root
+  const int lcb = ROOTS ? 0 : sh - LP;
+  uint32_t lin;
+  if (lcb >= 3) {
+    const uint32_t x = blockIdx.x & 7u, k = blockIdx.x >> 3;
+    const int cl = lcb - 3;
+    lin = ((k >> cl) << lcb) + (x << cl) + (k & ((1u << cl) - 1u));
+  } else {
+    lin = logical_block();
+  }
+  uint32_t lev, g0;
+  if (!stage8_group(lin >> lcb, i, ROOTS ? LP : 0, lev, g0)) return;
+  const int lnr = ROOTS ? (int(lev) < LP ? int(lev) : LP) : 0;  // log2 of the roots
+  const uint32_t nr = 1u << lnr;
+  const uint32_t r0 = (1u << lev) - 1u + g0;  // rank of the first root
+  const uint32_t s0 = (lin & ((1u << lcb) - 1u)) * P;
+  const uint32_t t = threadIdx.x;
+  __shared__ __attribute__((aligned(16))) T buf[512u * P];
+  if constexpr (ROOTS) {
+    // copy-in: depth k of the roots' subtrees is one run of nr 2^k consecutive ranks;
+    // value m of the run is root m >> k, node 2^k + (m mod 2^k).  Full groups: the
+    // runs of depth 5..8 hold NT 2^(k-5) values (2^(k-5) per thread), depths 0..4
+    // together 31 P (one per thread of the first 31 P)
+    auto lds_index = [](int k, uint32_t m) -> uint32_t {
+      const uint32_t q = (1u << k) + (m & ((1u << k) - 1u)), rho = m >> k;
+      return (((q & ~3u) | stage8_sigma_bits(q)) << LP) + (rho ^ ((q >> 2) & (P - 1u)));
+    };
+    if (nr == P) {
+      T v[16];
+      uint32_t li[16];
+      {
+        const int k = 31 - __clz((t >> LP) + 1u);
+        const uint32_t m = t - ((1u << k) - 1u) * P;
+        li[0] = ~0u;
+        if (t < 31u * P) {
+          v[0] = src[((r0 + 1u) << k) - 1u + m];
+          li[0] = lds_index(k, m);
+        }
+      }
+#pragma unroll
+      for (int k = 5; k <= 8; ++k) {
+        const uint32_t base = ((r0 + 1u) << k) - 1u;
+#pragma unroll
+        for (int j = 0; j < (1 << (k - 5)); ++j) {
+          const uint32_t m = t + uint32_t(j) * NT;
+          const int sl = (1 << (k - 5)) + j;  // 1, 2-3, 4-7, 8-15
+          v[sl] = src[base + m];
+          li[sl] = lds_index(k, m);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 16; ++j)
+        if (li[j] != ~0u) buf[li[j]] = v[j];
+    } else {
+      for (uint32_t f = t; f < nr * 511u; f += NT) {
+        const int k = 31 - __clz((f >> lnr) + 1u);
+        const uint32_t m = f - (((1u << k) - 1u) << lnr);
+        buf[lds_index(k, m)] = src[((r0 + 1u) << k) - 1u + m];
+      }
+    }
+  } else {
+    // copy-in: vector j of node q = f / 4 + 1 for f = t + k NT
+    constexpr int kPer = int((511u * 4u + NT - 1u) / NT);
+    Vec<T, VW> v[kPer];
+    uint32_t li[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const uint32_t f = t + uint32_t(k) * NT;
+      const uint32_t q = (f >> 2) + 1u, j = f & 3u;
+      li[k] = ~0u;
+      if (q < 512u) {
+        const int dq = 31 - __clz(q);
+        const uint32_t rank = ((r0 + 1u) << dq) - 1u + (q - (1u << dq));
+        v[k] = ld<T, VW>(src + ((size_t)rank << sh) + s0 + j * uint32_t(VW));
+        li[k] = (((q & ~3u) | stage8_sigma_bits(q)) << LP) + j * uint32_t(VW);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kPer; ++k)
+      if (li[k] != ~0u) stv<T, VW>(buf + li[k], v[k]);
+  }
+  __syncthreads();
+  // step 1: thread (z = 1-based node a of the depth-4 subtree, lane c1); a = 0 idles
+  Vec<T, 1> Dv[16];
+  const uint32_t c1 = t & (P - 1u), a = t >> LP;
+  if (a != 0u) {
+    // node a 2^d + m (disjoint bits) sits at slot (a 2^d & ~3) + (m & ~3) +
+    // (sigma bits of a 2^d xor those of m): four base addresses per depth, the rest
+    // immediate offsets
+    // (roots: lane position c1 ^ (q / 4 mod P), q / 4 = a 2^d / 4 xor m / 4)
+    Vec<T, 1> S[31];
+#pragma unroll
+    for (int d = 0; d <= 4; ++d) {
+      const uint32_t ad = a << d, fa = stage8_sigma_bits(ad);
+      uint32_t base[4];
+#pragma unroll
+      for (uint32_t k = 0; k < 4u; ++k) base[k] = ((ad & ~3u) + (fa ^ k)) << LP;
+      const uint32_t cx = ROOTS ? c1 ^ ((ad >> 2) & (P - 1u)) : c1;
+#pragma unroll
+      for (int m = 0; m < (1 << d); ++m) {
+        const uint32_t lane = ROOTS ? cx ^ ((uint32_t(m) >> 2) & (P - 1u)) : cx;
+        S[(1 << d) - 1 + m].v[0] = buf[base[stage8_sigma_bits(uint32_t(m))] + ((uint32_t(m) & ~3u) << LP) + lane];
+      }
+    }
+    bwd4_tree<T, 1>(S, Dv);
+  }
+  __syncthreads();
+  if (a != 0u) {
+    uint32_t base[4];
+#pragma unroll
+    for (uint32_t k = 0; k < 4u; ++k) base[k] = (a << (4 + LP)) + ((k ^ (a & 3u)) << LP) + c1;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) buf[base[u & 3] + ((uint32_t(u) & ~3u) << LP)] = Dv[u].v[0];
+  }
+  __syncthreads();
+  // step 2: thread (u2, lane c2), u2 < 16
+  const uint32_t c2 = t & (P - 1u), u2 = t >> LP;
+  if (u2 < 16u) {
+    uint32_t base[4];
+#pragma unroll
+    for (uint32_t k = 0; k < 4u; ++k) base[k] = ((u2 ^ k) << LP) + c2;
+    Vec<T, 1> S[31];
+#pragma unroll
+    for (int e = 1; e <= 31; ++e) S[e - 1].v[0] = buf[base[e & 3] + (uint32_t(e) << (4 + LP))];
+    bwd4_tree<T, 1>(S, Dv);
+  }
+  __syncthreads();
+  if (u2 < 16u) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      if constexpr (ROOTS) buf[c2 * kOutPitch + uint32_t(u) * 16u + u2] = Dv[u].v[0];
+      else buf[((uint32_t(u) * 16u + u2) << LP) + c2] = Dv[u].v[0];
+    }
+  }
+  __syncthreads();
+  if constexpr (ROOTS) {
+    // copy-out: the nr output rows of 256 values are consecutive
+    T* o = dst + ((size_t)r0 << 8);
+#pragma unroll
+    for (uint32_t k = 0; k < (P * 64u) / NT; ++k) {
+      const uint32_t f = t + k * NT;
+      const uint32_t rho = f >> 6, j = f & 63u;
+      if (rho < nr) stv<T, 4>(o + (rho << 8) + 4u * j, ld<T, 4>(buf + rho * kOutPitch + 4u * j));
+    }
+  } else {
+    // copy-out: output column group w = f / 4 of 256, vector j = f mod 4
+    T* o = dst + ((size_t)r0 << (sh + 8)) + s0;
+#pragma unroll
+    for (uint32_t k = 0; k < (256u * 4u) / NT; ++k) {
+      const uint32_t f = t + k * NT;
+      const uint32_t w = f >> 2, j = f & 3u;
+      stv<T, VW>(o + ((size_t)w << sh) + j * uint32_t(VW), ld<T, VW>(buf + (w << LP) + j * uint32_t(VW)));
+    }
   }
 }
 
@@ -1120,14 +1292,16 @@ hipError_t launch_backward(const Group<T>& g, hipStream_t s, int* launches, int 
       const int lc = sh < LP ? sh : LP;
       const dim3 grid(((stage8_slots(i, LP - lc) << (sh - lc)) + 7u) & ~7u, 1, g.nb);
       const dim3 block(32 * stage8_tile<T>());
-      switch (lc) {
-        case 0: hipLaunchKernelGGL((k_bwd_stage8<T, 0>), grid, block, 0, s, n, i, src, ss, dst, g.fs, g.st); break;
+      if (lc == LP) {
+        hipLaunchKernelGGL((k_bwd_stage8_p<T, false>), grid, block, 0, s, n, i, src, ss, dst, g.fs, g.st);
+      } else if (lc == 0) {
+        hipLaunchKernelGGL((k_bwd_stage8_p<T, true>), grid, block, 0, s, n, i, src, ss, dst, g.fs, g.st);
+      } else switch (lc) {
         case 1: hipLaunchKernelGGL((k_bwd_stage8<T, 1>), grid, block, 0, s, n, i, src, ss, dst, g.fs, g.st); break;
         case 2: hipLaunchKernelGGL((k_bwd_stage8<T, 2>), grid, block, 0, s, n, i, src, ss, dst, g.fs, g.st); break;
-        case 3: hipLaunchKernelGGL((k_bwd_stage8<T, 3>), grid, block, 0, s, n, i, src, ss, dst, g.fs, g.st); break;
         default:
           if constexpr (LP == 4)
-            hipLaunchKernelGGL((k_bwd_stage8<T, 4>), grid, block, 0, s, n, i, src, ss, dst, g.fs, g.st);
+            hipLaunchKernelGGL((k_bwd_stage8<T, 3>), grid, block, 0, s, n, i, src, ss, dst, g.fs, g.st);
           break;
       }
       if (launches) ++*launches;

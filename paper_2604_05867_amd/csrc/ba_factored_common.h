@@ -78,6 +78,7 @@ struct Order {
   int lb, h;      // level of the subtree roots, subtree height (levels)
   int cw_log2;    // log2 of the column-tile width in chunks
   uint32_t kb;    // 0, or blocks per XCD of the unit partition (make_order_xcd)
+  uint32_t mir;   // unit partition: subtree t shares its XCD with 2^lb - 1 - t
 };
 
 constexpr size_t kTileBytes = size_t(1) << 19;
@@ -96,6 +97,7 @@ inline Order make_order(int levels, int cols_log2, size_t chunk_bytes) {
   o.nlog = (o.lb == 0) ? (1u << h) - 1u : o.top + (1u << (o.lb + h));
   o.nct = 1u << (cols_log2 - o.cw_log2);
   o.kb = 0;
+  o.mir = 0;
   return o;
 }
 
@@ -109,15 +111,17 @@ inline uint32_t order_threads(const Order& o) { return o.nct * o.nlog << o.cw_lo
 // by its descendants is an L2 hit instead of a fetch by a second XCD.  Each unit
 // holds 2^h slots (the subtree's rows breadth-first and one padding slot) per
 // chunk; XCD x runs units x m .. x m + m - 1 (hardware block 8 k + x, k < kb).
-// False when a unit is not a whole number of blocks.
-inline bool make_order_xcd(int levels, int cols_log2, uint32_t block, Order& o) {
+// mirror: a thread also reads the complement of its row (the complement-symmetric
+// kernels), so the subtrees are rooted at level 4 and XCD x takes the complementary
+// pair x, 15 - x.  False when a unit is not a whole number of blocks.
+inline bool make_order_xcd(int levels, int cols_log2, uint32_t block, Order& o, bool mirror = false) {
   int cw, lb;
   if (cols_log2 >= 8) {
     cw = cols_log2 - 3 < 6 ? cols_log2 - 3 : 6;
     lb = 0;
   } else {
     cw = cols_log2;
-    lb = 3;
+    lb = mirror ? 4 : 3;
   }
   const int h = levels - lb;
   if (h < 1 || h + cw > 30 || ((uint32_t(1) << (h + cw)) % block) != 0u) return false;
@@ -128,6 +132,7 @@ inline bool make_order_xcd(int levels, int cols_log2, uint32_t block, Order& o) 
   o.nct = 1u << (cols_log2 - cw);
   o.nlog = 1u << h;
   o.kb = ((o.nct << lb) >> 3) * ((uint32_t(1) << (h + cw)) / block);
+  o.mir = lb == 4 ? 1u : 0u;
   return true;
 }
 
@@ -183,7 +188,9 @@ __device__ __forceinline__ bool order_slot_xcd(const Order& o, uint32_t& row, ui
   const uint32_t unit = q >> ul, r = q & ((1u << ul) - 1u);
   const uint32_t j = r >> o.cw_log2;
   if (j == o.nlog - 1u) return false;
-  const uint32_t ct = unit >> o.lb, t = unit & o.top;
+  const uint32_t ct = unit >> o.lb;
+  uint32_t t = unit & o.top;
+  if (o.mir) t = (t & 1u) ? o.top - (t >> 1) : (t >> 1);  // units 2x, 2x + 1: subtrees x, 15 - x
   const int lv = 31 - __clz(j + 1u);
   row = (1u << (o.lb + lv)) - 1u + (t << lv) + (j + 1u - (1u << lv));
   chunk = (ct << o.cw_log2) + (r & cmask);

@@ -425,8 +425,9 @@ hipError_t launch_forward_sym(const Group<T>& g, hipStream_t s, int* launches, i
   for (; fuse == 2 && i0 + 4 < n; i0 += 4, k++) {
     T* dst = (k & 1) ? g.f1 : g.f0;
     const uint32_t S4 = 1u << (n - i0 - 4);
-    const Order o = make_order(i0 + 1, ilog2(S4 / 2u), sizeof(T));
-    hipLaunchKernelGGL((k_fwd_stage4_sym<T>), dim3(blocks_for(order_threads(o)), g.nb), dim3(kBlock), 0, s, n, i0,
+    Order o = make_order(i0 + 1, ilog2(S4 / 2u), sizeof(T));
+    make_order_xcd(i0 + 1, ilog2(S4 / 2u), kBlock, o, true);  // o unchanged where infeasible
+    hipLaunchKernelGGL((k_fwd_stage4_sym<T>), dim3(order_blocks(o, kBlock), g.nb), dim3(kBlock), 0, s, n, i0,
                        src, ss, dst, g.fs, g.st, o);
     if (launches) ++*launches;
     src = dst;
@@ -477,9 +478,10 @@ hipError_t launch_backward_sym(const Group<T>& g, hipStream_t s, int* launches, 
       const size_t ds = last ? g.xs : g.fs;
       const uint32_t S4 = 1u << (n - i - 4);
       // rows w x columns s < S4/2, or (from v) the rows of the subtree of "0"
-      const Order o = vc ? (i > 0 ? make_order(i, 0, sizeof(T)) : make_order(1, 0, sizeof(T)))
-                         : make_order(i + 1, ilog2(S4 / 2u), sizeof(T));
-      const uint32_t nbk = blocks_for(order_threads(o));
+      Order o = vc ? (i > 0 ? make_order(i, 0, sizeof(T)) : make_order(1, 0, sizeof(T)))
+                   : make_order(i + 1, ilog2(S4 / 2u), sizeof(T));
+      if (!vc && !last) make_order_xcd(i + 1, ilog2(S4 / 2u), kBlock, o);  // o unchanged where infeasible
+      const uint32_t nbk = order_blocks(o, kBlock);
       const dim3 grid(nbk, g.nb);
       if (last) {
         if (nbk > uint32_t(kMaxRedBlocks)) return hipErrorInvalidValue;
