@@ -216,20 +216,25 @@ __device__ __forceinline__ void d_records(const Group<T>& g, int b, double M, co
   const T* hf = g.hf + (size_t)b * g.xs;
   const T* lp = g.lp + (size_t)b * g.xs;
   T* D = g.D + (size_t)b * g.xs;
+  // every load before the first store: D could alias H or log p as far as the
+  // compiler knows, so a store between them would serialise each load behind it
   Vec<T, V> l[N], d[N];
-  T am = T(-INFINITY), dm = T(-INFINITY);
 #pragma unroll
   for (int u = 0; u < N; ++u) {
-    const Vec<T, V> h = ld<T, V>(hf + x[u]);
+    d[u] = ld<T, V>(hf + x[u]);
     l[u] = ld<T, V>(lp + x[u]);
+  }
+  T am = T(-INFINITY), dm = T(-INFINITY);
+#pragma unroll
+  for (int u = 0; u < N; ++u)
 #pragma unroll
     for (int k = 0; k < V; ++k) {
-      d[u].v[k] = h.v[k] - G[u].v[k] - T(M);
+      d[u].v[k] = d[u].v[k] - G[u].v[k] - T(M);
       am = fmax(am, l[u].v[k] + d[u].v[k]);
       dm = fmax(dm, d[u].v[k]);
     }
-    stv<T, V>(D + x[u], d[u]);
-  }
+#pragma unroll
+  for (int u = 0; u < N; ++u) stv<T, V>(D + x[u], d[u]);
   T s = T(0), i = T(0);
 #pragma unroll
   for (int u = 0; u < N; ++u)
