@@ -337,7 +337,7 @@ int sweeps(ba_ctx* c, const GroupHost& gh, const Group<T>& G, int use_sw_g, T* g
   } else if (tail && !use_sw_g && sym_active(c, n)) {
     {
       Timer t(c, BA_K_SWEEP1, forward_launches(n, sym_fuse(c)));
-      HIPCHK(c, launch_forward_sym<T>(G, s, nullptr, sym_fuse(c)));
+      HIPCHK(c, launch_forward_sym<T>(G, s, nullptr, sym_fuse(c), upd));
     }
     {
       Timer t(c, BA_K_SWEEP2, backward_launches(n, sym_fuse(c)));
@@ -366,9 +366,12 @@ int sweeps(ba_ctx* c, const GroupHost& gh, const Group<T>& G, int use_sw_g, T* g
 }
 
 // The update of an iteration can be left pending and fused into the next
-// iteration's first forward launch (factored engine, full kernels).
+// iteration's first forward launch (factored engine, full or complement-symmetric
+// kernels with four positions per launch).
 bool update_fusable(const ba_ctx* c, const GroupHost& gh) {
-  return c->engine == BA_ENGINE_FACTORED && !sym_active(c, gh.n) && forward_update_fusable(gh.n, c->fuse);
+  if (c->engine != BA_ENGINE_FACTORED) return false;
+  if (sym_active(c, gh.n)) return sym_fuse(c) == 2 && forward_update_fusable(gh.n, 2);
+  return forward_update_fusable(gh.n, c->fuse);
 }
 
 // One iteration.  fused_in: the previous iteration's update is pending and done by

@@ -197,7 +197,8 @@ int forward_launches(int n, int fuse);    // launches of launch_forward
 // two positions per launch.
 bool symmetric_supported(int n, int fuse);
 template <typename T>
-hipError_t launch_forward_sym(const Group<T>& g, hipStream_t s, int* launches, int fuse);
+hipError_t launch_forward_sym(const Group<T>& g, hipStream_t s, int* launches, int fuse,
+                              const FusedUpdate* upd = nullptr);
 template <typename T>
 hipError_t launch_backward_sym(const Group<T>& g, hipStream_t s, int* launches, int* dpart_blocks, int fuse);
 

@@ -408,6 +408,68 @@ __global__ __launch_bounds__(kBlock) void k_bwd_stage4_sym(int n, int i, const T
   }
 }
 
+// The first four positions (i = 0) of the canonical half fused with the pending
+// update, as k_fwd_first4_upd for the full kernels: the thread of column s < S4/2
+// covers the 16 stored inputs x = u S4 + s and u S4 + (S4 - 1 - s) (u < 8, first
+// bit 0, where D is kept), forms their new log p from the final record as k_update
+// does, writes it at x and at cpl x, and uses p = e^{log p - M'} in registers as the
+// row of F_0 that k_fwd_stage4_sym reads (group u >= 8 at s being p(cpl x) of the
+// input u' = 15 - u at column S4 - 1 - s).  The values equal those of k_update
+// followed by k_fwd_stage4_sym.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fwd_first4_upd_sym(int n, T* __restrict__ dst, size_t dstride,
+                                                               Group<T> g, Order o, double floor, int check_tol) {
+  const int b = blockIdx.y;
+  if (g.st[b].converged) return;
+  const UpdateParams up = update_params<T>(g, b, check_tol, blockIdx.x == 0 && threadIdx.x == 0);
+  if (up.stop) return;
+  uint32_t y, s;
+  if (!order_slot(o, y, s)) return;  // y = 0, the one row of F_0
+  dst += (size_t)b * dstride;
+  T* lp = g.lp + (size_t)b * g.xs;
+  const T* D = g.D + (size_t)b * g.xs;
+  const int sh = n - 4;
+  const uint32_t S4 = 1u << sh, sm = S4 - 1u - s, X = 1u << n;
+  const T lo = T(up.Mn - floor), eta = T(g.eta);
+  uint32_t xs[16];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    xs[u] = (uint32_t(u) << sh) + s;
+    xs[8 + u] = (uint32_t(7 - u) << sh) + sm;
+  }
+  T nl[16], dv[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    nl[u] = lp[xs[u]];
+    dv[u] = D[xs[u]];
+  }
+  T F0[4][16], H4[8];
+#pragma unroll
+  for (int j = 1; j < 4; ++j)
+#pragma unroll
+    for (int u = 0; u < 16; ++u) F0[j][u] = T(0);
+#pragma unroll
+  for (int u = 0; u < 8; ++u) H4[u] = T(0);
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    nl[u] = update_value<T>(up, eta, lo, nl[u], dv[u]);
+    lp[xs[u]] = nl[u];
+    lp[X - 1u - xs[u]] = nl[u];
+    F0[0][u] = exp_t<T>(nl[u] - T(up.Mn));
+  }
+  uint32_t P[5], lastb[4];
+  fwd4_path(0u, P, lastb);
+  T F4[30];
+  const T vy = fwd4_registers<T>(F0, H4, lastb, F4);
+  const int ho = sh - 1;                     // log2 of the stored output width
+  dst[s] = vy;
+#pragma unroll
+  for (int d = 1; d <= 4; ++d)
+#pragma unroll
+    for (int m = 0; m < (1 << d); ++m)
+      dst[((size_t)((1u << d) - 1u + uint32_t(m)) << ho) + s] = F4[(1 << d) - 2 + m];
+}
+
 }  // namespace
 
 using namespace fac;
@@ -415,20 +477,25 @@ using namespace fac;
 bool symmetric_supported(int n, int fuse) { return fuse && n >= 4 && (n % 2) == 0; }
 
 template <typename T>
-hipError_t launch_forward_sym(const Group<T>& g, hipStream_t s, int* launches, int fuse) {
+hipError_t launch_forward_sym(const Group<T>& g, hipStream_t s, int* launches, int fuse, const FusedUpdate* upd) {
   const int n = g.n;
   constexpr int V = 16 / sizeof(T);
   const T* src = g.p;
   size_t ss = g.xs;
   int k = 0;
   int i0 = 0;
+  if (upd && !(fuse == 2 && forward_update_fusable(n, fuse))) return hipErrorInvalidValue;
   for (; fuse == 2 && i0 + 4 < n; i0 += 4, k++) {
     T* dst = (k & 1) ? g.f1 : g.f0;
     const uint32_t S4 = 1u << (n - i0 - 4);
     Order o = make_order(i0 + 1, ilog2(S4 / 2u), sizeof(T));
     make_order_xcd(i0 + 1, ilog2(S4 / 2u), kBlock, o, true);  // o unchanged where infeasible
-    hipLaunchKernelGGL((k_fwd_stage4_sym<T>), dim3(order_blocks(o, kBlock), g.nb), dim3(kBlock), 0, s, n, i0,
-                       src, ss, dst, g.fs, g.st, o);
+    if (i0 == 0 && upd)
+      hipLaunchKernelGGL((k_fwd_first4_upd_sym<T>), dim3(order_blocks(o, kBlock), g.nb), dim3(kBlock), 0, s, n,
+                         dst, g.fs, g, o, upd->floor, upd->check_tol);
+    else
+      hipLaunchKernelGGL((k_fwd_stage4_sym<T>), dim3(order_blocks(o, kBlock), g.nb), dim3(kBlock), 0, s, n, i0,
+                         src, ss, dst, g.fs, g.st, o);
     if (launches) ++*launches;
     src = dst;
     ss = g.fs;
@@ -537,8 +604,8 @@ hipError_t launch_backward_sym(const Group<T>& g, hipStream_t s, int* launches, 
   return hipGetLastError();
 }
 
-template hipError_t launch_forward_sym<float>(const Group<float>&, hipStream_t, int*, int);
-template hipError_t launch_forward_sym<double>(const Group<double>&, hipStream_t, int*, int);
+template hipError_t launch_forward_sym<float>(const Group<float>&, hipStream_t, int*, int, const FusedUpdate*);
+template hipError_t launch_forward_sym<double>(const Group<double>&, hipStream_t, int*, int, const FusedUpdate*);
 template hipError_t launch_backward_sym<float>(const Group<float>&, hipStream_t, int*, int*, int);
 template hipError_t launch_backward_sym<double>(const Group<double>&, hipStream_t, int*, int*, int);
 

@@ -163,3 +163,34 @@ def test_symmetric_graph_replay(ba):
     assert out[0][0] == out[1][0] and out[0][3] == out[1][3]
     assert out[0][1] == out[1][1] and out[0][2] == out[1][2]
     assert np.array_equal(out[0][4], out[1][4])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_symmetric_fused_update_is_bitwise_separate(ba, prec):
+    """Within one step call the symmetric kernels make the update of each iteration
+    but the last inside the next iteration's first forward launch; the iterates and
+    bounds equal those of one-iteration calls (separate update launches) bit for
+    bit, with and without a step eta."""
+    p = ba.PREC_FP64 if prec == "fp64" else ba.PREC_FP32_LOG
+    ns, ds = ([12, 14], [0.6, 0.9]) if prec == "fp64" else ([16, 20], [0.7, 0.95])
+    say("symmetric fused update", prec)
+    # one context (H is formed once per context, with atomics), reset between runs
+    c = ba.Context(ns, ds, prec=p)
+    c.set_symmetry(True)
+    start = torch.tensor(np.concatenate([np.full(1 << m, -m * LN2) for m in ns]))
+    for eta in (1.0, 1.8):
+        out = []
+        for per_call in (1, 7):
+            c.set_logp(start)
+            c.set_step(eta)
+            for _ in range(7 // per_call):
+                c.step(per_call)
+            out.append((c.get_logp().cpu().numpy(), c.bounds()))
+        assert np.array_equal(out[0][0], out[1][0])
+        assert out[0][1] == out[1][1]
+        lp = out[1][0]
+        off = 0
+        for m in ns:  # still exactly complement-invariant
+            assert np.array_equal(lp[off:off + (1 << m)], lp[off:off + (1 << m)][::-1])
+            off += 1 << m
+    c.close()
