@@ -39,11 +39,11 @@ FUSE = 4  # the library default (positions per launch of the factored engine)
 MEASURED_TRAFFIC = {
     "sources": ["paper_2604_05867_amd/csrc/ba_factored.hip", "paper_2604_05867_amd/csrc/ba_factored_common.h"],
     # of the sources concatenated
-    "sha256": "0831092aa54225ed2d0ae394cf15fb1cc398fd06101b945d437ac6908332f46f",
-    # forward: k_fwd_first4_upd, k_fwd_stage4 x3, k_fwd_last4; backward: k_bwd_stage8 x2,
+    "sha256": "7b91bc077d86369ffe6c876d132621c4967af0573bf6dd9a4f3f155c5af3a986",
+    # forward: k_fwd_first4_upd, k_fwd_stage4 x3, k_fwd_last4; backward: k_bwd_stage8_p x2,
     # k_bwd_stage4 with D fused
-    "sweep1": 52714000,
-    "sweep2": 55180000,
+    "sweep1": 52718000,
+    "sweep2": 55183000,
 }
 
 
@@ -356,7 +356,7 @@ def main():
                 "frac": round(achieved / 8000.0, 4),
                 "traffic": measured_traffic(dom),
                 "kernel": ("forward sweep (k_fwd_first4_upd, k_fwd_stage4 x3, k_fwd_last4)" if dom == "sweep1"
-                           else "backward sweep (k_bwd_stage8 x2, k_bwd_stage4 with D fused)"),
+                           else "backward sweep (k_bwd_stage8_p x2, k_bwd_stage4 with D fused)"),
                 "bytes_per_launch": int(bytes_launch), "avg_launch_us": round(per_launch_ms * 1e3, 2)}
 
     lo, hi = ctx.bounds()
