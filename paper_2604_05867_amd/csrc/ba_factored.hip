@@ -87,9 +87,9 @@ __device__ __forceinline__ T fwd4_thread(const T* __restrict__ src, int sh, uint
 #pragma unroll
   for (int u = 0; u < 8; ++u) Hc[u] = T(0);
   if (4 <= ly) {
-    const T* row = src + ((size_t)P[4] << (sh + 4)) + (lastb[3] << (sh + 3)) + s;
+    const uint32_t row = (P[4] << (sh + 4)) + (lastb[3] << (sh + 3)) + s;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) Hc[u] = row[uint32_t(u) << sh];
+    for (int u = 0; u < 8; ++u) Hc[u] = at(src, row + (uint32_t(u) << sh));
   }
 #pragma unroll
   for (int j = 3; j >= 0; --j) {
@@ -97,9 +97,9 @@ __device__ __forceinline__ T fwd4_thread(const T* __restrict__ src, int sh, uint
 #pragma unroll
     for (int u = 0; u < 16; ++u) R[u] = T(0);
     if (j <= ly) {
-      const T* row = src + ((size_t)P[j] << (sh + 4)) + s;
+      const uint32_t row = (P[j] << (sh + 4)) + s;
 #pragma unroll
-      for (int u = 0; u < 16; ++u) R[u] = row[uint32_t(u) << sh];
+      for (int u = 0; u < 16; ++u) R[u] = at(src, row + (uint32_t(u) << sh));
     }
 #pragma unroll
     for (int g = 0; g < 8; ++g) F1p[j][g] = (R[g] + R[8 + g]) + Hc[g];
@@ -140,7 +140,7 @@ __global__ __launch_bounds__(kBlock) void k_fwd_stage4(int n, int i, const T* __
   T F4[30];
   T vy = fwd4_thread<T>(src, sh, y, ly, s, F4);
   if constexpr (LOGV) vy = log_weighted<T>(cs[b], y, vy);
-  dst[((size_t)y << sh) + s] = vy;
+  at(dst, (y << sh) + s) = vy;
   if (ly != i) return;
 #pragma unroll
   for (int d = 1; d <= 4; ++d)
@@ -149,7 +149,7 @@ __global__ __launch_bounds__(kBlock) void k_fwd_stage4(int n, int i, const T* __
       const uint32_t rk = ((y + 1u) << d) - 1u + uint32_t(m);
       T v = F4[(1 << d) - 2 + m];
       if constexpr (LOGV) v = log_weighted<T>(cs[b], rk, v);
-      dst[((size_t)rk << sh) + s] = v;
+      at(dst, (rk << sh) + s) = v;
     }
 }
 

@@ -43,6 +43,18 @@ __device__ __forceinline__ void stv(T* p, const Vec<T, V>& a) {
 
 __device__ __forceinline__ int length_of_rank(uint32_t r) { return 31 - __clz(r + 1u); }
 
+// Element idx of an array whose byte size is below 4 GiB, addressed as a 32-bit
+// byte offset from the (wavefront-uniform) base, so that the access can take the
+// base from scalar registers and one vector register for the offset.
+template <typename T>
+__device__ __forceinline__ T& at(T* base, uint32_t idx) {
+  return *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + idx * uint32_t(sizeof(T)));
+}
+template <typename T>
+__device__ __forceinline__ const T& at(const T* base, uint32_t idx) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + idx * uint32_t(sizeof(T)));
+}
+
 template <typename T, int V>
 __device__ __forceinline__ Vec<T, V> zero_vec() {
   Vec<T, V> z;
