@@ -278,8 +278,11 @@ struct Timer {
 
 // One sweep pair + reductions on group G (iteration or certification group).
 // The complement-symmetric kernels run for this group's iterations.
-// The symmetric kernels go up to four positions per launch.
-int sym_fuse(const ba_ctx* c) { return c->fuse < 2 ? c->fuse : 2; }
+// The symmetric kernels go up to four positions per launch: the forward sweep
+// with the last four positions in one launch from fuse level 4 on, the backward
+// sweep at most at level 2.
+int sym_fuse_fwd(const ba_ctx* c) { return c->fuse < 4 ? c->fuse : 4; }
+int sym_fuse_bwd(const ba_ctx* c) { return c->fuse < 2 ? c->fuse : 2; }
 
 bool sym_active(const ba_ctx* c, int n) {
   return c->sym && c->engine == BA_ENGINE_FACTORED && symmetric_supported(n, c->fuse);
@@ -336,14 +339,14 @@ int sweeps(ba_ctx* c, const GroupHost& gh, const Group<T>& G, int use_sw_g, T* g
     }
   } else if (tail && !use_sw_g && sym_active(c, n)) {
     {
-      Timer t(c, BA_K_SWEEP1, forward_launches(n, sym_fuse(c)));
-      HIPCHK(c, launch_forward_sym<T>(G, s, nullptr, sym_fuse(c), upd));
+      Timer t(c, BA_K_SWEEP1, forward_launches(n, sym_fuse_fwd(c)));
+      HIPCHK(c, launch_forward_sym<T>(G, s, nullptr, sym_fuse_fwd(c), upd));
     }
     {
-      Timer t(c, BA_K_SWEEP2, backward_launches(n, sym_fuse(c)));
+      Timer t(c, BA_K_SWEEP2, backward_launches(n, sym_fuse_bwd(c)));
       Group<T> G2 = G;
       G2.g = g_out;
-      HIPCHK(c, launch_backward_sym<T>(G2, s, nullptr, tail_done, sym_fuse(c)));
+      HIPCHK(c, launch_backward_sym<T>(G2, s, nullptr, tail_done, sym_fuse_bwd(c)));
     }
   } else {
     const int fuse_tail = (tail && !use_sw_g) ? 1 : 0;
@@ -370,7 +373,7 @@ int sweeps(ba_ctx* c, const GroupHost& gh, const Group<T>& G, int use_sw_g, T* g
 // kernels with four positions per launch).
 bool update_fusable(const ba_ctx* c, const GroupHost& gh) {
   if (c->engine != BA_ENGINE_FACTORED) return false;
-  if (sym_active(c, gh.n)) return sym_fuse(c) == 2 && forward_update_fusable(gh.n, 2);
+  if (sym_active(c, gh.n)) return forward_update_fusable(gh.n, sym_fuse_fwd(c));
   return forward_update_fusable(gh.n, c->fuse);
 }
 

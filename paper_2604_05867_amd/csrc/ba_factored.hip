@@ -477,8 +477,6 @@ __global__ __launch_bounds__(kLast2Threads) void k_fwd_last2(int n, const T* __r
 // row of level < L - 6 per thread.  Neighbouring nodes a share the cache lines at
 // the ends of their rank runs (and their ancestors above level L - 6), so the deep
 // blocks are spread over the XCDs in contiguous runs of a.
-constexpr int kLast4MinN = 12;
-constexpr int kLast4Threads = 128;
 
 template <typename T, bool LOGV>
 __global__ __launch_bounds__(kLast4Threads) void k_fwd_last4(int n, const T* __restrict__ src, size_t sstride,
@@ -500,7 +498,7 @@ __global__ __launch_bounds__(kLast4Threads) void k_fwd_last4(int n, const T* __r
     dst[c] = r;
     return;
   }
-  __shared__ T stage[(kLast2Lds - 1) * 64];
+  __shared__ T stage[kLast4Stage];
   // hardware block 8 k + x runs on XCD x: node k of XCD x's run of ndeep / 8
   const uint32_t da = (ndeep & 7u) ? blockIdx.x : (blockIdx.x & 7u) * (ndeep >> 3) + (blockIdx.x >> 3);
   const uint32_t a = ndeep - 1u + da;               // level La

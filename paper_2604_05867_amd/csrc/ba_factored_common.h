@@ -375,6 +375,13 @@ inline uint32_t blocks_for(uint32_t threads, uint32_t block = kBlock) {
 // Threads per block of the four-position launches without records.
 constexpr uint32_t kStage4Block = 256;
 
+// The last four forward positions in one launch (k_fwd_last4, k_fwd_last4_sym): from
+// this n on, with blocks of kLast4Threads and kLast4Stage values of LDS staging (the
+// 2 + 4 + 8 + 16 rows below each of 64 leaves, padded to odd row strides).
+constexpr int kLast4MinN = 12;
+constexpr int kLast4Threads = 128;
+constexpr int kLast4Stage = (3 + 5 + 9 + 17) * 64;
+
 inline int ilog2(uint32_t v) { return 31 - __builtin_clz(v); }
 
 }  // namespace fac

@@ -408,6 +408,121 @@ __global__ __launch_bounds__(kBlock) void k_bwd_stage4_sym(int n, int i, const T
   }
 }
 
+// The four-position forward step of k_fwd_stage4_sym for output rows of width 1
+// (sh = 0: every stored source row is its 8 groups of first bit 0).
+template <typename T>
+__device__ __forceinline__ T fwd4_sym_w1(const T* __restrict__ src, uint32_t y, int ly, T (&F4)[30]) {
+  uint32_t P[5], lastb[4];
+  fwd4_path(y, P, lastb);
+  T F0[4][16], H4[8];
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int u = 0; u < 16; ++u) F0[j][u] = T(0);
+#pragma unroll
+  for (int u = 0; u < 8; ++u) H4[u] = T(0);
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    if (j <= ly) {
+      const T* row = src + ((size_t)P[j] << 3);
+      const T* rowm = src + ((size_t)mirror_rank(P[j]) << 3);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        F0[j][u] = row[u];
+        F0[j][8 + u] = rowm[7 - u];
+      }
+    }
+  if (4 <= ly) {
+    if (lastb[3]) {
+      const T* rowm = src + ((size_t)mirror_rank(P[4]) << 3);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) H4[u] = rowm[7 - u];
+    } else {
+      const T* row = src + ((size_t)P[4] << 3);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) H4[u] = row[u];
+    }
+  }
+  return fwd4_registers<T>(F0, H4, lastb, F4);
+}
+
+// The last four positions, canonical half (n >= kLast4MinN, four positions left
+// after the four-position launches): k_fwd_last4 for the outputs that are empty or
+// start with 0, written to the compact v (row R of length k >= 1 starting with 0 at
+// R - 2^(k-1) + 1, the empty row at 0).  Deep block: a node a of level L - 6 (L =
+// n - 4) starting with 0, its 64 leaves of level L and the 30 rows below each (first
+// wavefront, staged in LDS and written as one compact run per level), and the 63
+// rows of a's subtree above level L (second wavefront); the other blocks take the
+// empty row and the rows of level < L - 6 starting with 0, by compact index.
+template <typename T, bool LOGV>
+__global__ __launch_bounds__(kLast4Threads) void k_fwd_last4_sym(int n, const T* __restrict__ src, size_t sstride,
+                                                                 T* __restrict__ dst, size_t dstride,
+                                                                 const State* st, const Consts* cs) {
+  const int b = blockIdx.y;
+  if (st[b].converged) return;
+  src += (size_t)b * sstride;
+  dst += (size_t)b * dstride;
+  const int L = n - 4, La = L - 6;
+  const uint32_t ndeep = 1u << (La - 1);          // nodes of level La starting with 0
+  const uint32_t t = threadIdx.x;
+  T F4[30];
+  auto outv = [&](uint32_t rank, T r) -> T {
+    if constexpr (LOGV) return log_weighted<T>(cs[b], rank, r);
+    else return r;
+  };
+  if (blockIdx.x >= ndeep) {
+    // compact index q < 2^(La-1): the empty row (q = 0) or rank q + 2^floor(log2 q) - 1
+    const uint32_t q = (blockIdx.x - ndeep) * kLast4Threads + t;
+    if (q >= ndeep) return;
+    const uint32_t y = q == 0u ? 0u : q + (1u << (31 - __clz(q))) - 1u;
+    dst[q] = outv(y, fwd4_sym_w1<T>(src, y, length_of_rank(y), F4));
+    return;
+  }
+  __shared__ T stage[kLast4Stage];
+  // hardware block 8 k + x runs on XCD x: node k of XCD x's run of ndeep / 8
+  const uint32_t da = (ndeep & 7u) ? blockIdx.x : (blockIdx.x & 7u) * (ndeep >> 3) + (blockIdx.x >> 3);
+  const uint32_t a = (1u << La) - 1u + da;        // level La, first bit 0
+  const uint32_t A0 = ((a + 1u) << 6) - 1u;       // its first leaf (level L)
+  T* s1 = stage;
+  T* s2 = s1 + 3 * 64;
+  T* s3 = s2 + 5 * 64;
+  T* s4 = s3 + 9 * 64;
+  if (t < 64u) {
+    const uint32_t y = A0 + t;
+    const T va = fwd4_sym_w1<T>(src, y, L, F4);
+    dst[y - (1u << (L - 1)) + 1u] = outv(y, va);
+    // F4: depth d, index m at (1 << d) - 2 + m; every row of depth d has length L + d
+    const uint32_t r1 = ((y + 1u) << 1) - 1u, r2 = ((y + 1u) << 2) - 1u, r3 = ((y + 1u) << 3) - 1u,
+                   r4 = ((y + 1u) << 4) - 1u;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) s1[3u * t + q] = outv(r1 + q, F4[q]);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) s2[5u * t + q] = outv(r2 + q, F4[2 + q]);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) s3[9u * t + q] = outv(r3 + q, F4[6 + q]);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) s4[17u * t + q] = outv(r4 + q, F4[14 + q]);
+  } else if (t < 127u) {
+    // node q of a's subtree above level L: depth d = log2(q + 1), length La + d
+    const uint32_t q = t - 64u;
+    const int d = length_of_rank(q);
+    const uint32_t y = ((a + 1u) << d) - 1u + (q + 1u - (1u << d));
+    dst[y - (1u << (La + d - 1)) + 1u] = outv(y, fwd4_sym_w1<T>(src, y, La + d, F4));
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 1; j <= 4; ++j) {
+    const uint32_t wj = 1u << j, stride = wj + 1u;
+    const T* sj = j == 1 ? s1 : j == 2 ? s2 : j == 3 ? s3 : s4;
+    T* out = dst + (wj * (A0 + 1u) - 1u) - (1u << (L + j - 1)) + 1u;
+#pragma unroll
+    for (uint32_t k = 0; k < wj / 2u; ++k) {
+      const uint32_t e = k * kLast4Threads + t;
+      out[e] = sj[(e >> j) * stride + (e & (wj - 1u))];
+    }
+  }
+}
+
 // The first four positions (i = 0) of the canonical half fused with the pending
 // update, as k_fwd_first4_upd for the full kernels: the thread of column s < S4/2
 // covers the 16 stored inputs x = u S4 + s and u S4 + (S4 - 1 - s) (u < 8, first
@@ -484,8 +599,8 @@ hipError_t launch_forward_sym(const Group<T>& g, hipStream_t s, int* launches, i
   size_t ss = g.xs;
   int k = 0;
   int i0 = 0;
-  if (upd && !(fuse == 2 && forward_update_fusable(n, fuse))) return hipErrorInvalidValue;
-  for (; fuse == 2 && i0 + 4 < n; i0 += 4, k++) {
+  if (upd && !forward_update_fusable(n, fuse)) return hipErrorInvalidValue;
+  for (; fuse >= 2 && i0 + 4 < n; i0 += 4, k++) {
     T* dst = (k & 1) ? g.f1 : g.f0;
     const uint32_t S4 = 1u << (n - i0 - 4);
     Order o = make_order(i0 + 1, ilog2(S4 / 2u), sizeof(T));
@@ -499,6 +614,15 @@ hipError_t launch_forward_sym(const Group<T>& g, hipStream_t s, int* launches, i
     if (launches) ++*launches;
     src = dst;
     ss = g.fs;
+  }
+  // fuse >= 4: the last four positions in one launch (writes the compact v)
+  if (fuse >= 4 && n >= kLast4MinN && n - i0 == 4) {
+    const uint32_t ndeep = 1u << (n - 11), top = ndeep;  // deep blocks; compact rows above
+    const dim3 grid(ndeep + (top + kLast4Threads - 1u) / kLast4Threads, g.nb);
+    hipLaunchKernelGGL((k_fwd_last4_sym<T, true>), grid, dim3(kLast4Threads), 0, s, n, src, ss, g.v, g.ys, g.st,
+                       g.cs);
+    if (launches) ++*launches;
+    return hipGetLastError();
   }
   for (int i = i0; i < n; i += 2, k++) {
     const bool last = (i + 2 == n);

@@ -50,7 +50,7 @@ def run_pair(ba, ns, ds, prec, iters, exact_k=None, fuse=None):
     return out
 
 
-@pytest.mark.parametrize("fuse", [1, 2, 3])
+@pytest.mark.parametrize("fuse", [1, 2, 3, 4])
 @pytest.mark.parametrize("n", [4, 6, 8, 10, 12, 14, 16])
 def test_symmetric_fp64_equals_full(ba, n, fuse):
     say("symmetric fp64 n=%d fuse=%d" % (n, fuse))
