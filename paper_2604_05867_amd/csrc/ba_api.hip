@@ -277,12 +277,16 @@ struct Timer {
 };
 
 // One sweep pair + reductions on group G (iteration or certification group).
-// The complement-symmetric kernels run for this group's iterations.
-// The symmetric kernels go up to four positions per launch: the forward sweep
-// with the last four positions in one launch from fuse level 4 on, the backward
-// sweep at most at level 2.
+// The complement-symmetric kernels run for this group's iterations: up to four
+// positions per launch, the forward sweep with the last four positions in one
+// launch from fuse level 4 on, the backward sweep with its first eight positions
+// in one launch from level 3 on (n % 4 == 0, n >= 12).
 int sym_fuse_fwd(const ba_ctx* c) { return c->fuse < 4 ? c->fuse : 4; }
-int sym_fuse_bwd(const ba_ctx* c) { return c->fuse < 2 ? c->fuse : 2; }
+int sym_fuse_bwd(const ba_ctx* c) { return c->fuse < 3 ? c->fuse : 3; }
+int sym_backward_launches(int n, int fuse) {
+  if (fuse >= 3 && n % 4 == 0 && n >= 12) return backward_launches(n, 2) - 1;
+  return backward_launches(n, fuse < 2 ? fuse : 2);
+}
 
 bool sym_active(const ba_ctx* c, int n) {
   return c->sym && c->engine == BA_ENGINE_FACTORED && symmetric_supported(n, c->fuse);
@@ -343,7 +347,7 @@ int sweeps(ba_ctx* c, const GroupHost& gh, const Group<T>& G, int use_sw_g, T* g
       HIPCHK(c, launch_forward_sym<T>(G, s, nullptr, sym_fuse_fwd(c), upd));
     }
     {
-      Timer t(c, BA_K_SWEEP2, backward_launches(n, sym_fuse_bwd(c)));
+      Timer t(c, BA_K_SWEEP2, sym_backward_launches(n, sym_fuse_bwd(c)));
       Group<T> G2 = G;
       G2.g = g_out;
       HIPCHK(c, launch_backward_sym<T>(G2, s, nullptr, tail_done, sym_fuse_bwd(c)));

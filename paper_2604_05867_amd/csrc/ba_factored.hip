@@ -744,7 +744,7 @@ __host__ __device__ inline void stage8_tiling(int i, int lr, uint32_t& npart, in
   lb = levels - h;
 }
 
-inline uint32_t stage8_slots(int i, int lr) {
+__host__ __device__ inline uint32_t stage8_slots(int i, int lr) {
   uint32_t npart;
   int levels, h, lb;
   stage8_tiling(i, lr, npart, levels, h, lb);
@@ -959,14 +959,22 @@ __global__ __launch_bounds__(32 * stage8_tile<T>()) void k_bwd_stage8(int n, int
 // rho of node q sits at lane position rho ^ (q / 4 mod P) of the row.  The outputs
 // are [u][column] (columns), or [root][u] with a row pitch of 260 (roots: lanes of
 // one u-quad and 16 roots on 64 distinct banks), and leave through 16-byte vectors.
+// kS8SymRoots: the first backward launch of the complement-symmetric iteration
+// (i = n - 8), from the compact v: the roots are the rows starting with 0 (the
+// subtree of "0", grouped as for kS8Roots over its levels) and, in one extra block,
+// the empty row; root w writes its columns u < 128 to row w and its columns
+// u >= 128, reversed, to row cpl w of the canonical-half B_i (row width 128).
+enum Stage8Mode { kS8Columns = 0, kS8Roots = 1, kS8SymRoots = 2 };
+
 __host__ __device__ constexpr uint32_t stage8_sigma_bits(uint32_t q) {
   return ((uint32_t(__builtin_popcount(q & 0xAAAAAAAAu)) & 1u) << 1) | (uint32_t(__builtin_popcount(q)) & 1u);
 }
 
-template <typename T, bool ROOTS>
+template <typename T, int MODE>
 __global__ __launch_bounds__(32 * stage8_tile<T>()) void k_bwd_stage8_p(int n, int i, const T* __restrict__ src,
                                                                       size_t sstride, T* __restrict__ dst,
                                                                       size_t dstride, const State* st) {
+  constexpr bool ROOTS = MODE != kS8Columns, SYM = MODE == kS8SymRoots;
   constexpr uint32_t P = uint32_t(stage8_tile<T>());  // value lanes per node
   constexpr int LP = P == 16 ? 4 : 3;
   constexpr uint32_t NT = 32u * P;                     // threads
@@ -989,8 +997,23 @@ __global__ __launch_bounds__(32 * stage8_tile<T>()) void k_bwd_stage8_p(int n, i
     lin = logical_block();
   }
   uint32_t lev, g0;
-  if (!stage8_group(lin >> lcb, i, ROOTS ? LP : 0, lev, g0)) return;
-  const int lnr = ROOTS ? (int(lev) < LP ? int(lev) : LP) : 0;  // log2 of the roots
+  int lnr;                                   // log2 of the roots
+  if constexpr (SYM) {
+    // groups of the subtree of "0" (its level l is level l + 1), then the empty row
+    const uint32_t nslot = stage8_slots(i - 1, LP);
+    if (lin == nslot) {
+      lev = 0;
+      g0 = 0;
+      lnr = 0;
+    } else {
+      if (lin > nslot || !stage8_group(lin, i - 1, LP, lev, g0)) return;
+      lnr = int(lev) < LP ? int(lev) : LP;
+      ++lev;
+    }
+  } else {
+    if (!stage8_group(lin >> lcb, i, ROOTS ? LP : 0, lev, g0)) return;
+    lnr = ROOTS ? (int(lev) < LP ? int(lev) : LP) : 0;
+  }
   const uint32_t nr = 1u << lnr;
   const uint32_t r0 = (1u << lev) - 1u + g0;  // rank of the first root
   const uint32_t s0 = (lin & ((1u << lcb) - 1u)) * P;
@@ -1013,13 +1036,15 @@ __global__ __launch_bounds__(32 * stage8_tile<T>()) void k_bwd_stage8_p(int n, i
         const uint32_t m = t - ((1u << k) - 1u) * P;
         li[0] = ~0u;
         if (t < 31u * P) {
-          v[0] = src[((r0 + 1u) << k) - 1u + m];
+          const uint32_t rank = ((r0 + 1u) << k) - 1u + m;
+          v[0] = src[SYM ? compact_rank(rank) : rank];
           li[0] = lds_index(k, m);
         }
       }
 #pragma unroll
       for (int k = 5; k <= 8; ++k) {
-        const uint32_t base = ((r0 + 1u) << k) - 1u;
+        // SYM: rows of length lev + k starting with 0 sit at rank - 2^(lev + k - 1) + 1
+        const uint32_t base = SYM ? ((r0 + 1u) << k) - (1u << (int(lev) + k - 1)) : ((r0 + 1u) << k) - 1u;
 #pragma unroll
         for (int j = 0; j < (1 << (k - 5)); ++j) {
           const uint32_t m = t + uint32_t(j) * NT;
@@ -1035,7 +1060,8 @@ __global__ __launch_bounds__(32 * stage8_tile<T>()) void k_bwd_stage8_p(int n, i
       for (uint32_t f = t; f < nr * 511u; f += NT) {
         const int k = 31 - __clz((f >> lnr) + 1u);
         const uint32_t m = f - (((1u << k) - 1u) << lnr);
-        buf[lds_index(k, m)] = src[((r0 + 1u) << k) - 1u + m];
+        const uint32_t rank = ((r0 + 1u) << k) - 1u + m;
+        buf[lds_index(k, m)] = src[SYM ? compact_rank(rank) : rank];
       }
     }
   } else {
@@ -1113,7 +1139,26 @@ __global__ __launch_bounds__(32 * stage8_tile<T>()) void k_bwd_stage8_p(int n, i
     }
   }
   __syncthreads();
-  if constexpr (ROOTS) {
+  if constexpr (SYM) {
+    // copy-out: row w = r0 + rho takes columns 0..127; row cpl w (rank m0 - rho,
+    // m0 = mirror of r0) takes 255 - c for its column c, except for the empty row
+    const uint32_t m0 = r0 == 0u ? 0u : mirror_rank(r0);
+#pragma unroll
+    for (uint32_t k = 0; k < (P * 64u) / NT; ++k) {
+      const uint32_t f = t + k * NT;
+      const uint32_t rho = f >> 6, j = f & 31u;
+      if (rho >= nr) continue;
+      if ((f & 32u) == 0u) {
+        stv<T, 4>(dst + ((size_t)(r0 + rho) << 7) + 4u * j, ld<T, 4>(buf + rho * kOutPitch + 4u * j));
+      } else if (r0 != 0u) {
+        const Vec<T, 4> w = ld<T, 4>(buf + rho * kOutPitch + 252u - 4u * j);
+        Vec<T, 4> rv;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) rv.v[e] = w.v[3 - e];
+        stv<T, 4>(dst + ((size_t)(m0 - rho) << 7) + 4u * j, rv);
+      }
+    }
+  } else if constexpr (ROOTS) {
     // copy-out: the nr output rows of 256 values are consecutive
     T* o = dst + ((size_t)r0 << 8);
 #pragma unroll
@@ -1291,9 +1336,9 @@ hipError_t launch_backward(const Group<T>& g, hipStream_t s, int* launches, int 
       const dim3 grid(((stage8_slots(i, LP - lc) << (sh - lc)) + 7u) & ~7u, 1, g.nb);
       const dim3 block(32 * stage8_tile<T>());
       if (lc == LP) {
-        hipLaunchKernelGGL((k_bwd_stage8_p<T, false>), grid, block, 0, s, n, i, src, ss, dst, g.fs, g.st);
+        hipLaunchKernelGGL((k_bwd_stage8_p<T, kS8Columns>), grid, block, 0, s, n, i, src, ss, dst, g.fs, g.st);
       } else if (lc == 0) {
-        hipLaunchKernelGGL((k_bwd_stage8_p<T, true>), grid, block, 0, s, n, i, src, ss, dst, g.fs, g.st);
+        hipLaunchKernelGGL((k_bwd_stage8_p<T, kS8Roots>), grid, block, 0, s, n, i, src, ss, dst, g.fs, g.st);
       } else switch (lc) {
         case 1: hipLaunchKernelGGL((k_bwd_stage8<T, 1>), grid, block, 0, s, n, i, src, ss, dst, g.fs, g.st); break;
         case 2: hipLaunchKernelGGL((k_bwd_stage8<T, 2>), grid, block, 0, s, n, i, src, ss, dst, g.fs, g.st); break;
@@ -1398,6 +1443,20 @@ hipError_t launch_backward(const Group<T>& g, hipStream_t s, int* launches, int 
 
 
 int factored_launches(int n, int fuse) { return fuse ? (n + 1) / 2 : n; }
+
+template <typename T>
+hipError_t launch_backward8_sym_v(const Group<T>& g, hipStream_t s, T* dst) {
+  const int n = g.n, i = n - 8;
+  constexpr int LP = stage8_tile<T>() == 16 ? 4 : 3;
+  if (n % 4 != 0 || i < 4) return hipErrorInvalidValue;
+  const uint32_t slots = stage8_slots(i - 1, LP) + 1u;  // + the empty row
+  const dim3 grid((slots + 7u) & ~7u, 1, g.nb);
+  hipLaunchKernelGGL((k_bwd_stage8_p<T, kS8SymRoots>), grid, dim3(32 * stage8_tile<T>()), 0, s, n, i, g.v, g.ys,
+                     dst, g.fs, g.st);
+  return hipGetLastError();
+}
+template hipError_t launch_backward8_sym_v<float>(const Group<float>&, hipStream_t, float*);
+template hipError_t launch_backward8_sym_v<double>(const Group<double>&, hipStream_t, double*);
 
 int backward_launches(int n, int fuse) {
   if (fuse >= 3 && n >= 4) {

@@ -55,6 +55,20 @@ __device__ __forceinline__ const T& at(const T* base, uint32_t idx) {
   return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + idx * uint32_t(sizeof(T)));
 }
 
+// Rank of the complement of the string of rank R (same length).
+__device__ __forceinline__ uint32_t mirror_rank(uint32_t R) {
+  return 3u * (1u << length_of_rank(R)) - 3u - R;
+}
+
+// Compact index of the canonical member of {y, cpl y} (complement-symmetric
+// iteration): the empty row at 0, a row 0z of length k at 2^(k-1) + bits(z).
+__device__ __forceinline__ uint32_t compact_rank(uint32_t R) {
+  if (R == 0u) return 0u;
+  const int k = length_of_rank(R);
+  const uint32_t a = R + 1u - (1u << k), half = 1u << (k - 1);
+  return half + (a < half ? a : (2u * half - 1u - a));
+}
+
 template <typename T, int V>
 __device__ __forceinline__ Vec<T, V> zero_vec() {
   Vec<T, V> z;

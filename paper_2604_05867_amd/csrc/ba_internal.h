@@ -201,6 +201,10 @@ hipError_t launch_forward_sym(const Group<T>& g, hipStream_t s, int* launches, i
                               const FusedUpdate* upd = nullptr);
 template <typename T>
 hipError_t launch_backward_sym(const Group<T>& g, hipStream_t s, int* launches, int* dpart_blocks, int fuse);
+// The first backward launch of the complement-symmetric iteration for n % 4 == 0,
+// n >= 12: eight positions (n-8 .. n-1) from the compact v into dst.
+template <typename T>
+hipError_t launch_backward8_sym_v(const Group<T>& g, hipStream_t s, T* dst);
 
 // ba_reduce.hip
 template <typename T>

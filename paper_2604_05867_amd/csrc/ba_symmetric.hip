@@ -17,18 +17,6 @@ using namespace fac;
 // cr(0z) = 2^|z| + bits(z), cr(empty) = 0; D for inputs x < 2^(n-1).
 // ---------------------------------------------------------------------------
 
-// Rank of the complement of the string of rank R (same length).
-__device__ __forceinline__ uint32_t mirror_rank(uint32_t R) {
-  return 3u * (1u << length_of_rank(R)) - 3u - R;
-}
-
-// Compact index of the canonical member of {y, cpl y}.
-__device__ __forceinline__ uint32_t compact_rank(uint32_t R) {
-  if (R == 0u) return 0u;
-  const int k = length_of_rank(R);
-  const uint32_t a = R + 1u - (1u << k), half = 1u << (k - 1);
-  return half + (a < half ? a : (2u * half - 1u - a));
-}
 
 template <typename T, int V>
 __device__ __forceinline__ Vec<T, V> rev(const Vec<T, V>& a) {
@@ -660,8 +648,18 @@ hipError_t launch_backward_sym(const Group<T>& g, hipStream_t s, int* launches, 
   size_t ss = g.ys;
   int k = 0;
   if (dpart_blocks) *dpart_blocks = 0;
-  const int lead = (fuse == 2) ? n % 4 : -1;  // even n: 0 or 2
+  const int lead = (fuse >= 2) ? n % 4 : -1;  // even n: 0 or 2
   for (int top = n; top > 0; k++) {
+    // fuse >= 3: the first eight positions (from the compact v) in one launch
+    if (fuse >= 3 && top == n && n % 4 == 0 && n >= 12) {
+      const hipError_t e = launch_backward8_sym_v<T>(g, s, (k & 1) ? g.f1 : g.f0);
+      if (e != hipSuccess) return e;
+      if (launches) ++*launches;
+      src = (k & 1) ? g.f1 : g.f0;
+      ss = g.fs;
+      top = n - 8;
+      continue;
+    }
     if (lead >= 0 && n - top >= lead) {
       const int i = top - 4;
       const bool last = (i == 0), vc = (top == n);
