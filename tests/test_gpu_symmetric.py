@@ -118,6 +118,19 @@ def test_symmetric_n20_fp32(ba):
         assert np.array_equal(seg, seg[::-1])
 
 
+@pytest.mark.parametrize("fuse", [2, 4])
+def test_symmetric_n20_fp64(ba, fuse):
+    """n = 20 in FP64 (8 roots per eight-position block), where the symmetric
+    backward sweep takes its first eight positions in one launch from the compact v
+    and the forward sweep its last four in one launch: iterates and bounds equal
+    those of the full kernels."""
+    say("symmetric fp64 n=20 fuse=%d" % fuse)
+    (lp_f, lo_f, hi_f), (lp_s, lo_s, hi_s) = run_pair(ba, 20, 0.8, ba.PREC_FP64, 3, fuse=fuse)
+    assert np.max(np.abs(lp_f - lp_s)) < 1e-12
+    assert np.max(np.abs(lo_f - lo_s)) < 1e-12 and np.max(np.abs(hi_f - hi_s)) < 1e-12
+    assert np.array_equal(lp_s, lp_s[::-1])
+
+
 def test_symmetric_rejects_asymmetric_law(ba):
     n = 10
     c = ba.Context(n, 0.7)
