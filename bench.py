@@ -28,7 +28,7 @@ sys.path.insert(0, ROOT)
 
 N = 20
 DS = [0.64, 0.80, 0.95]
-FUSE = 4  # the library default (positions per launch of the factored engine)
+FUSE = 5  # the library default (positions per launch of the factored engine)
 
 
 # HBM bytes per launch of this workload's sweeps, from rocprofv3 FETCH_SIZE and
@@ -40,7 +40,7 @@ MEASURED_TRAFFIC = {
     "sources": ["paper_2604_05867_amd/csrc/ba_factored.hip", "paper_2604_05867_amd/csrc/ba_factored_common.h"],
     # of the sources concatenated
     "sha256": "d96d8be77944e84a314668b5b1830e35a6ebcd4864ef4f4885fe3408dfcbb43f",
-    # forward: k_fwd_first4_upd, k_fwd_stage4 x3, k_fwd_last4; backward: k_bwd_stage8_p x2,
+    # forward: k_fwd_first8, k_fwd_stage4 x2, k_fwd_last4; backward: k_bwd_stage8_p x2,
     # k_bwd_stage4 with D fused
     "sweep1": 52720000,
     "sweep2": 55183000,
@@ -79,14 +79,17 @@ def sweep_launch_bytes(n, esz, nb, fuse, backward, fused_update=0.0):
     four positions per launch (forward: the last 1-4 positions two at a time;
     backward: the first n mod 4 positions two or one at a time), fuse 3 = as 2 with
     eight positions per backward launch while four remain after it, fuse 4 = as 3
-    with the forward's last four positions in one launch (n >= 12), fuse 1 = two."""
+    with the forward's last four positions in one launch (n >= 12), fuse 5 = as 4
+    with the forward's first eight positions in one launch (n >= 12), fuse 1 = two."""
     s = stage_sizes(n)
     steps = []
     if not backward:
         i = 0
         last4 = fuse >= 4 and n >= 12
         while i < n:
-            if last4 and n - i == 4:
+            if fuse >= 5 and n >= 12 and i == 0:
+                t = 8
+            elif last4 and n - i == 4:
                 t = 4
             elif fuse >= 2 and i + 4 < n and not (last4 and n - i < 8):
                 t = 4
@@ -355,7 +358,7 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
                 "frac": round(achieved / 8000.0, 4),
                 "traffic": measured_traffic(dom),
-                "kernel": ("forward sweep (k_fwd_first4_upd, k_fwd_stage4 x3, k_fwd_last4)" if dom == "sweep1"
+                "kernel": ("forward sweep (k_fwd_first8, k_fwd_stage4 x2, k_fwd_last4)" if dom == "sweep1"
                            else "backward sweep (k_bwd_stage8_p x2, k_bwd_stage4 with D fused)"),
                 "bytes_per_launch": int(bytes_launch), "avg_launch_us": round(per_launch_ms * 1e3, 2)}
 

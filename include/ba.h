@@ -156,14 +156,16 @@ int ba_set_graphs(ba_ctx *c, int enable);
  *  before going to device memory.  Capped by the device's per-block limit. */
 enum {
   BA_TUNE_SCATTER_LDS_KB = 0,
-  /* BA_TUNE_FACTORED_FUSE: positions per launch of the factored engine: 4 (default)
-   * as 3, with the forward's last four positions in one launch whose outputs are
-   * staged in LDS (n >= 12); 3 as 2, with the backward's four-position launches
-   * paired into eight-position launches (two four-position steps through LDS, the
-   * same sums in the same order) while four positions remain for the last launch;
-   * 2 four (the forward's last 1-4 positions and the backward's first n mod 4 two
-   * or one at a time), 1 two, 0 one.  The complement-symmetric kernels use at most
-   * 2. */
+  /* BA_TUNE_FACTORED_FUSE: positions per launch of the factored engine: 5 (default)
+   * as 4, with the forward's first eight positions in one launch (two four-position
+   * steps through LDS, the same sums in the same order; n >= 12); 4 as 3, with the
+   * forward's last four positions in one launch whose outputs are staged in LDS
+   * (n >= 12); 3 as 2, with the backward's four-position launches paired into
+   * eight-position launches (the same sums in the same order) while four positions
+   * remain for the last launch; 2 four (the forward's last 1-4 positions and the
+   * backward's first n mod 4 two or one at a time), 1 two, 0 one.  The
+   * complement-symmetric kernels take at most level 4 in the forward sweep and 3 in
+   * the backward sweep. */
   BA_TUNE_FACTORED_FUSE = 1
 };
 int ba_set_tuning(ba_ctx *c, int key, int value);

@@ -7,7 +7,7 @@ and caches the choice in a JSON file keyed by device and workload.  The knobs
 only change the work decomposition, never the results beyond rounding order.
 
 Knobs:
-  engine factored: TUNE_FACTORED_FUSE in {0, 1, 2, 3, 4} (positions per launch)
+  engine factored: TUNE_FACTORED_FUSE in {0, 1, 2, 3, 4, 5} (positions per launch)
   engine stream:   TUNE_SCATTER_LDS_KB in {16, 32, 48, 64} (LDS-privatised
                    output range of the scatter)
 """
@@ -22,7 +22,7 @@ from . import (ENGINE_FACTORED, ENGINE_STREAM, TUNE_FACTORED_FUSE, TUNE_SCATTER_
 
 CANDIDATES = {
     ENGINE_FACTORED: [(TUNE_FACTORED_FUSE, 0), (TUNE_FACTORED_FUSE, 1), (TUNE_FACTORED_FUSE, 2),
-                      (TUNE_FACTORED_FUSE, 3), (TUNE_FACTORED_FUSE, 4)],
+                      (TUNE_FACTORED_FUSE, 3), (TUNE_FACTORED_FUSE, 4), (TUNE_FACTORED_FUSE, 5)],
     ENGINE_STREAM: [(TUNE_SCATTER_LDS_KB, 16), (TUNE_SCATTER_LDS_KB, 32), (TUNE_SCATTER_LDS_KB, 48),
                     (TUNE_SCATTER_LDS_KB, 64)],
 }

@@ -209,6 +209,148 @@ __global__ __launch_bounds__(kBlock) void k_fwd_first4_upd(int n, T* __restrict_
       dst[((size_t)((1u << d) - 1u + uint32_t(m)) << sh) + s] = F4[(1 << d) - 2 + m];
 }
 
+// The first eight positions (i = 0..7) in one launch, for n >= kFirst8MinN; UPD:
+// also the update the previous iteration left pending (as k_fwd_first4_upd).  A
+// block takes 16 consecutive columns s of F_8 (width S8 = 2^(n-8)).  Step 1: thread
+// (u2, c) takes the 16 inputs x = u1 2^(n-4) + u2 S8 + s (u1 = 0..15, s = s0 + c),
+// forms p (from log p and D with UPD) and runs the four-position step of the one row
+// of F_0, leaving F_4[z][u2 S8 + s] for the 31 rows z in LDS.  Step 2: thread (z, c)
+// runs the four-position step of row z of F_4 (k_fwd_stage4 at i = 4) on the LDS rows
+// of its path, giving F_8 of row z and, for a leaf, of the 30 rows below it, which are
+// staged in LDS and written as 511 runs of 16 columns.  Every value is the same sum, in
+// the same order, as with k_fwd_first4_upd (or k_fwd_stage4) and k_fwd_stage4.
+constexpr int kFirst8MinN = 12;
+constexpr uint32_t kFirst8Threads = 512;
+constexpr uint32_t kF4Pitch = 16u * 16u + 16u;  // F_4 row in LDS: 16 u2 x 16 columns, padded
+// F_8 row in LDS: 16 columns, padded to a multiple of 16 bytes
+template <typename T>
+constexpr uint32_t first8_pitch() { return sizeof(T) == 4 ? 20u : 18u; }
+
+template <typename T, bool UPD>
+__global__ __launch_bounds__(kFirst8Threads) void k_fwd_first8(int n, const T* __restrict__ src, size_t sstride,
+                                                               T* __restrict__ dst, size_t dstride, Group<T> g,
+                                                               double floor, int check_tol) {
+  const int b = blockIdx.y;
+  if (g.st[b].converged) return;
+  UpdateParams up{};
+  if constexpr (UPD) {
+    up = update_params<T>(g, b, check_tol, blockIdx.x == 0 && threadIdx.x == 0);
+    if (up.stop) return;
+  }
+  src += (size_t)b * sstride;
+  dst += (size_t)b * dstride;
+  constexpr uint32_t kF8Pitch = first8_pitch<T>();
+  const int sh8 = n - 8;                      // log2 of the F_8 width
+  // neighbouring column blocks share 128-byte lines: consecutive logical blocks on one XCD
+  const uint32_t s0 = logical_block() * 16u, t = threadIdx.x;
+  __shared__ __attribute__((aligned(16))) T buf[31u * kF4Pitch > 511u * kF8Pitch ? 31u * kF4Pitch
+                                                                                 : 511u * kF8Pitch];
+  if (t < 256u) {
+    const uint32_t u2 = t >> 4, c = t & 15u;
+    const uint32_t x0 = (u2 << sh8) + s0 + c;  // u1 = 0
+    T R[16];
+    if constexpr (UPD) {
+      T* lp = g.lp + (size_t)b * g.xs;
+      const T* D = g.D + (size_t)b * g.xs;
+      const T lo = T(up.Mn - floor), eta = T(g.eta);
+      T nl[16], dv[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        nl[u] = lp[(uint32_t(u) << (n - 4)) + x0];
+        dv[u] = D[(uint32_t(u) << (n - 4)) + x0];
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        nl[u] = update_value<T>(up, eta, lo, nl[u], dv[u]);
+        lp[(uint32_t(u) << (n - 4)) + x0] = nl[u];
+        R[u] = exp_t<T>(nl[u] - T(up.Mn));
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < 16; ++u) R[u] = src[(uint32_t(u) << (n - 4)) + x0];
+    }
+    // the first stage of fwd4_thread for the row without ancestors
+    uint32_t P[5], lastb[4];
+    fwd4_path(0u, P, lastb);
+    T F1p[4][8], F1s[2][8];
+#pragma unroll
+    for (int j = 1; j < 4; ++j)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) F1p[j][q] = (T(0) + T(0)) + T(0);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) F1p[0][q] = (R[q] + R[8 + q]) + T(0);
+#pragma unroll
+    for (int cc = 0; cc < 2; ++cc)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) F1s[cc][q] = R[cc * 8 + q];
+    T F4[30];
+    const T v0 = fwd4_after_stage1<T>(F1p, F1s, lastb, F4);
+    T* col = buf + u2 * 16u + c;
+    col[0] = v0;
+#pragma unroll
+    for (int z = 1; z < 31; ++z) col[uint32_t(z) * kF4Pitch] = F4[z - 1];
+  }
+  __syncthreads();
+  // step 2: thread (z, c), z < 31: fwd4_thread on the LDS rows of z's path
+  const uint32_t z = t >> 4, c = t & 15u;
+  T F4[30], vz = T(0);
+  const int lz = length_of_rank(z);
+  if (z < 31u) {
+    uint32_t P[5], lastb[4];
+    fwd4_path(z, P, lastb);
+    T F1p[4][8], F1s[2][8], Hc[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) Hc[u] = T(0);
+    if (4 <= lz) {
+      const T* row = buf + P[4] * kF4Pitch + (lastb[3] << 7) + c;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) Hc[u] = row[uint32_t(u) << 4];
+    }
+#pragma unroll
+    for (int j = 3; j >= 0; --j) {
+      T R[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) R[u] = T(0);
+      if (j <= lz) {
+        const T* row = buf + P[j] * kF4Pitch + c;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) R[u] = row[uint32_t(u) << 4];
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) F1p[j][q] = (R[q] + R[8 + q]) + Hc[q];
+      if (j > 0) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) Hc[q] = lastb[j - 1] ? R[8 + q] : R[q];
+      } else {
+#pragma unroll
+        for (int cc = 0; cc < 2; ++cc)
+#pragma unroll
+          for (int q = 0; q < 8; ++q) F1s[cc][q] = R[cc * 8 + q];
+      }
+    }
+    vz = fwd4_after_stage1<T>(F1p, F1s, lastb, F4);
+  }
+  __syncthreads();
+  if (z < 31u) {
+    buf[z * kF8Pitch + c] = vz;
+    if (lz == 4) {
+#pragma unroll
+      for (int d = 1; d <= 4; ++d)
+#pragma unroll
+        for (int m = 0; m < (1 << d); ++m)
+          buf[(((z + 1u) << d) - 1u + uint32_t(m)) * kF8Pitch + c] = F4[(1 << d) - 2 + m];
+    }
+  }
+  __syncthreads();
+  // copy-out: row r of F_8 at columns s0 .. s0 + 15, 16-byte vectors
+  constexpr int VW = 16 / int(sizeof(T));
+  constexpr uint32_t NV = 16u / uint32_t(VW);  // vectors per row
+  for (uint32_t e = t; e < 511u * NV; e += kFirst8Threads) {
+    const uint32_t r = e / NV, j = e % NV;
+    stv<T, VW>(&at(dst, (r << sh8) + s0 + j * uint32_t(VW)), ld<T, VW>(buf + r * kF8Pitch + j * uint32_t(VW)));
+  }
+}
+
 // One backward stage; each thread produces V consecutive columns of one row
 // (V divides the source row width S = 2^(n-i-1)).  DP: stage 0, write D and the
 // reduction records instead of G.
@@ -1215,9 +1357,26 @@ hipError_t launch_forward(const Group<T>& g, hipStream_t s, int* launches, int f
   size_t ss = g.xs;
   int k = 0;
   if (upd && !forward_update_fusable(n, fuse)) return hipErrorInvalidValue;
-  // fuse >= 4: the last four positions in one launch with LDS-staged outputs
+  // fuse >= 4: the last four positions in one launch with LDS-staged outputs;
+  // fuse >= 5: the first eight positions in one launch
   const bool last4 = fuse >= 4 && n >= kLast4MinN;
+  const bool first8 = fuse >= 5 && n >= kFirst8MinN;
   for (int i = 0; i < n; k++) {
+    if (first8 && i == 0) {
+      T* dst = (k & 1) ? g.f1 : g.f0;
+      const dim3 grid(1u << (n - 12), g.nb);  // 16 columns of F_8 per block
+      if (upd)
+        hipLaunchKernelGGL((k_fwd_first8<T, true>), grid, dim3(kFirst8Threads), 0, s, n, src, ss, dst, g.fs, g,
+                           upd->floor, upd->check_tol);
+      else
+        hipLaunchKernelGGL((k_fwd_first8<T, false>), grid, dim3(kFirst8Threads), 0, s, n, src, ss, dst, g.fs, g,
+                           0.0, 0);
+      if (launches) ++*launches;
+      src = dst;
+      ss = g.fs;
+      i = 8;
+      continue;
+    }
     if (last4 && n - i == 4) {
       T* dst = logv ? g.v : g.r;
       const uint32_t top = (1u << (n - 10)) - 1u;  // rows above the deep blocks' subtrees
@@ -1468,6 +1627,7 @@ int backward_launches(int n, int fuse) {
 }
 
 int forward_launches(int n, int fuse) {
+  if (fuse >= 5 && n >= kFirst8MinN) return forward_launches(n, 4) - 1;
   if (fuse >= 4 && n >= kLast4MinN) {
     const int four = (n - 4) / 4, rest = (n - 4) % 4;  // then 0-3 positions two or one at a time
     return four + (rest + 1) / 2 + 1;

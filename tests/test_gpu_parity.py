@@ -370,13 +370,13 @@ def test_graph_needs_a_stream(ba):
 
 @pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6, 7, 8, 12, 13, 16, 17])
 def test_factored_fusion_settings_agree(ba, n):
-    """One, two, four and eight input positions per launch, and the last four
-    forward positions in one launch, give the same evaluation (all against the
-    oracle for n <= 8)."""
+    """One, two, four and eight input positions per launch, and the last four and
+    the first eight forward positions in one launch, give the same evaluation (all
+    against the oracle for n <= 8)."""
     d = 0.6
     lp = inp.random_logp(n, seed=40 + n, spread=2.0)
     out = []
-    for fuse in (0, 1, 2, 3, 4):
+    for fuse in (0, 1, 2, 3, 4, 5):
         c = ba.Context(n, d)
         c.set_tuning(ba.TUNE_FACTORED_FUSE, fuse)
         got = c.eval(torch.from_numpy(lp))
@@ -391,12 +391,14 @@ def test_factored_fusion_settings_agree(ba, n):
     # with atomics, so it may differ in the last bits between contexts)
     c = ba.Context(n, d)
     same = []
-    for fuse in (2, 3):
+    for fuse in (2, 3, 4, 5):
         c.set_tuning(ba.TUNE_FACTORED_FUSE, fuse)
         got = c.eval(torch.from_numpy(lp))
         same.append((got["L"], got["U"], got["r"].cpu().numpy(), got["D"].cpu().numpy()))
     c.close()
     assert np.array_equal(same[0][3], same[1][3]) and same[0][0] == same[1][0] and same[0][1] == same[1][1]
+    # the first eight forward positions in one launch are two four-position steps
+    assert np.array_equal(same[2][2], same[3][2]) and np.array_equal(same[2][3], same[3][3])
     if n <= 8:
         ev = bdc.evaluate(bdc.channel_dense(n, d), lp)
         assert abs(out[1][0] - ev.L / LN2) < 1e-11
@@ -436,6 +438,28 @@ def test_eight_position_backward_is_bitwise_four(ba, n, prec):
         out.append((c.get_logp().cpu().numpy(), c.bounds()))
     c.close()
     assert out[0][0].shape == (X,)
+    assert np.array_equal(out[0][0], out[1][0])
+    assert out[0][1] == out[1][1]
+
+
+@pytest.mark.parametrize("n,prec", [(12, "fp64"), (17, "fp64"), (20, "fp32"), (20, "fp64")])
+def test_first_eight_forward_is_bitwise_four(ba, n, prec):
+    """The first eight forward positions in one launch (two four-position steps
+    through LDS, with the pending update fused in) give bitwise the iterates and
+    bounds of two four-position launches."""
+    p = ba.PREC_FP64 if prec == "fp64" else ba.PREC_FP32_LOG
+    ns = [n] * 3 if prec == "fp32" else [n]
+    ds = [0.64, 0.8, 0.95] if prec == "fp32" else [0.7]
+    say("first eight forward n=%d %s" % (n, prec))
+    c = ba.Context(ns, ds, prec=p)
+    start = torch.tensor(np.concatenate([np.full(1 << m, -m * LN2) for m in ns]))
+    out = []
+    for fuse in (4, 5):
+        c.set_logp(start)
+        c.set_tuning(ba.TUNE_FACTORED_FUSE, fuse)
+        c.step(4)
+        out.append((c.get_logp().cpu().numpy(), c.bounds()))
+    c.close()
     assert np.array_equal(out[0][0], out[1][0])
     assert out[0][1] == out[1][1]
 
