@@ -47,21 +47,21 @@ __global__ __launch_bounds__(kBlock) void k_fwd_stage2_sym(int n, int i, const T
   const uint32_t gp = (r - 1u) >> 1, lb = (r - 1u) & 1u;
   const bool has_own = c < rows_in, has_par = c >= 1u && r < rows_in, has_gp = c >= 1u && r >= 1u;
   // row y, u in {0,1} (stored half), column chunk at col
-  auto at = [&](uint32_t y, uint32_t u, uint32_t col) { return src + (y << (sh + 1)) + (u << sh) + col; };
+  auto chunk_at = [&](uint32_t y, uint32_t u, uint32_t col) { return src + (y << (sh + 1)) + (u << sh) + col; };
   // present terms loaded before use, absent ones zero (as in k_fwd_stage2)
   Vec<T, V> o00 = zero_vec<T, V>(), o01 = o00, o10 = o00, o11 = o00, e = o00, p01 = o00, p10 = o00, gv = o00;
   if (has_own) {
     const uint32_t cm = mirror_rank(c);
-    o00 = ld<T, V>(at(c, 0, s)); o01 = ld<T, V>(at(c, 1, s));
-    o10 = ld<T, V>(at(cm, 1, m)); o11 = ld<T, V>(at(cm, 0, m));
+    o00 = ld<T, V>(chunk_at(c, 0, s)); o01 = ld<T, V>(chunk_at(c, 1, s));
+    o10 = ld<T, V>(chunk_at(cm, 1, m)); o11 = ld<T, V>(chunk_at(cm, 0, m));
   }
   if (has_par) {
     // u = bb bb: 00 direct, 11 = cpl(00) of the mirrored row
-    e = bb ? ld<T, V>(at(mirror_rank(r), 0, m)) : ld<T, V>(at(r, 0, s));
-    p01 = ld<T, V>(at(r, 1, s));
-    p10 = ld<T, V>(at(mirror_rank(r), 1, m));
+    e = bb ? ld<T, V>(chunk_at(mirror_rank(r), 0, m)) : ld<T, V>(chunk_at(r, 0, s));
+    p01 = ld<T, V>(chunk_at(r, 1, s));
+    p10 = ld<T, V>(chunk_at(mirror_rank(r), 1, m));
   }
-  if (has_gp) gv = lb ? ld<T, V>(at(mirror_rank(gp), 1u - bb, m)) : ld<T, V>(at(gp, bb, s));
+  if (has_gp) gv = lb ? ld<T, V>(chunk_at(mirror_rank(gp), 1u - bb, m)) : ld<T, V>(chunk_at(gp, bb, s));
   // mirrored chunks are read in reverse column order
   o10 = rev(o10);
   o11 = rev(o11);
