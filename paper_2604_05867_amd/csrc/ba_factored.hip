@@ -216,15 +216,12 @@ __global__ __launch_bounds__(kBlock) void k_fwd_first4_upd(int n, T* __restrict_
 // forms p (from log p and D with UPD) and runs the four-position step of the one row
 // of F_0, leaving F_4[z][u2 S8 + s] for the 31 rows z in LDS.  Step 2: thread (z, c)
 // runs the four-position step of row z of F_4 (k_fwd_stage4 at i = 4) on the LDS rows
-// of its path, giving F_8 of row z and, for a leaf, of the 30 rows below it, which are
-// staged in LDS and written as 511 runs of 16 columns.  Every value is the same sum, in
+// of its path and writes F_8 of row z and, for a leaf, of the 30 rows below it (16
+// lanes per row: 64-byte runs).  Every value is the same sum, in
 // the same order, as with k_fwd_first4_upd (or k_fwd_stage4) and k_fwd_stage4.
 constexpr int kFirst8MinN = 12;
 constexpr uint32_t kFirst8Threads = 512;
 constexpr uint32_t kF4Pitch = 16u * 16u + 16u;  // F_4 row in LDS: 16 u2 x 16 columns, padded
-// F_8 row in LDS: 16 columns, padded to a multiple of 16 bytes
-template <typename T>
-constexpr uint32_t first8_pitch() { return sizeof(T) == 4 ? 20u : 18u; }
 
 template <typename T, bool UPD>
 __global__ __launch_bounds__(kFirst8Threads) void k_fwd_first8(int n, const T* __restrict__ src, size_t sstride,
@@ -239,12 +236,10 @@ __global__ __launch_bounds__(kFirst8Threads) void k_fwd_first8(int n, const T* _
   }
   src += (size_t)b * sstride;
   dst += (size_t)b * dstride;
-  constexpr uint32_t kF8Pitch = first8_pitch<T>();
   const int sh8 = n - 8;                      // log2 of the F_8 width
   // neighbouring column blocks share 128-byte lines: consecutive logical blocks on one XCD
   const uint32_t s0 = logical_block() * 16u, t = threadIdx.x;
-  __shared__ __attribute__((aligned(16))) T buf[31u * kF4Pitch > 511u * kF8Pitch ? 31u * kF4Pitch
-                                                                                 : 511u * kF8Pitch];
+  __shared__ T buf[31u * kF4Pitch];
   if (t < 256u) {
     const uint32_t u2 = t >> 4, c = t & 15u;
     const uint32_t x0 = (u2 << sh8) + s0 + c;  // u1 = 0
@@ -293,9 +288,9 @@ __global__ __launch_bounds__(kFirst8Threads) void k_fwd_first8(int n, const T* _
   __syncthreads();
   // step 2: thread (z, c), z < 31: fwd4_thread on the LDS rows of z's path
   const uint32_t z = t >> 4, c = t & 15u;
-  T F4[30], vz = T(0);
   const int lz = length_of_rank(z);
   if (z < 31u) {
+    T F4[30];
     uint32_t P[5], lastb[4];
     fwd4_path(z, P, lastb);
     T F1p[4][8], F1s[2][8], Hc[8];
@@ -328,26 +323,17 @@ __global__ __launch_bounds__(kFirst8Threads) void k_fwd_first8(int n, const T* _
           for (int q = 0; q < 8; ++q) F1s[cc][q] = R[cc * 8 + q];
       }
     }
-    vz = fwd4_after_stage1<T>(F1p, F1s, lastb, F4);
-  }
-  __syncthreads();
-  if (z < 31u) {
-    buf[z * kF8Pitch + c] = vz;
+    const T vz = fwd4_after_stage1<T>(F1p, F1s, lastb, F4);
+    // F_8 of row z and, for a leaf, of the 30 rows below it: 16 consecutive columns of
+    // each row per 16 lanes
+    at(dst, (z << sh8) + s0 + c) = vz;
     if (lz == 4) {
 #pragma unroll
       for (int d = 1; d <= 4; ++d)
 #pragma unroll
         for (int m = 0; m < (1 << d); ++m)
-          buf[(((z + 1u) << d) - 1u + uint32_t(m)) * kF8Pitch + c] = F4[(1 << d) - 2 + m];
+          at(dst, ((((z + 1u) << d) - 1u + uint32_t(m)) << sh8) + s0 + c) = F4[(1 << d) - 2 + m];
     }
-  }
-  __syncthreads();
-  // copy-out: row r of F_8 at columns s0 .. s0 + 15, 16-byte vectors
-  constexpr int VW = 16 / int(sizeof(T));
-  constexpr uint32_t NV = 16u / uint32_t(VW);  // vectors per row
-  for (uint32_t e = t; e < 511u * NV; e += kFirst8Threads) {
-    const uint32_t r = e / NV, j = e % NV;
-    stv<T, VW>(&at(dst, (r << sh8) + s0 + j * uint32_t(VW)), ld<T, VW>(buf + r * kF8Pitch + j * uint32_t(VW)));
   }
 }
 
