@@ -211,10 +211,11 @@ __global__ __launch_bounds__(kBlock) void k_fwd_first4_upd(int n, T* __restrict_
 
 // The first eight positions (i = 0..7) in one launch, for n >= kFirst8MinN; UPD:
 // also the update the previous iteration left pending (as k_fwd_first4_upd).  A
-// block takes 16 consecutive columns s of F_8 (width S8 = 2^(n-8)).  Step 1: thread
-// (u2, c) takes the 16 inputs x = u1 2^(n-4) + u2 S8 + s (u1 = 0..15, s = s0 + c),
-// forms p (from log p and D with UPD) and runs the four-position step of the one row
-// of F_0, leaving F_4[z][u2 S8 + s] for the 31 rows z in LDS.  Step 2: thread (z, c)
+// block takes 16 consecutive columns s of F_8 (width S8 = 2^(n-8)).  Step 1: the 16
+// inputs x = u1 2^(n-4) + u2 S8 + s (u1 = 0..15, s = s0 + c) of pair (u2, c) are loaded
+// (p, or log p and D with the update made) by two threads, eight each; the first runs
+// the four-position step of the one row of F_0, leaving F_4[z][u2 S8 + s] for the 31
+// rows z in LDS.  Step 2: thread (z, c)
 // runs the four-position step of row z of F_4 (k_fwd_stage4 at i = 4) on the LDS rows
 // of its path and writes F_8 of row z and, for a leaf, of the 30 rows below it (16
 // lanes per row: 64-byte runs).  Every value is the same sum, in
@@ -240,30 +241,45 @@ __global__ __launch_bounds__(kFirst8Threads) void k_fwd_first8(int n, const T* _
   // neighbouring column blocks share 128-byte lines: consecutive logical blocks on one XCD
   const uint32_t s0 = logical_block() * 16u, t = threadIdx.x;
   __shared__ T buf[31u * kF4Pitch];
-  if (t < 256u) {
-    const uint32_t u2 = t >> 4, c = t & 15u;
-    const uint32_t x0 = (u2 << sh8) + s0 + c;  // u1 = 0
-    T R[16];
-    if constexpr (UPD) {
-      T* lp = g.lp + (size_t)b * g.xs;
-      const T* D = g.D + (size_t)b * g.xs;
-      const T lo = T(up.Mn - floor), eta = T(g.eta);
-      T nl[16], dv[16];
+  // step 1a: all threads load (and update) 8 of the 16 inputs of pair pr = (u2, c):
+  // u1 = 8 h .. 8 h + 7; the upper halves pass through LDS (the start of buf)
+  const uint32_t h = t >> 8, pr = t & 255u;
+  const uint32_t u2 = pr >> 4, c1 = pr & 15u;
+  const uint32_t x0 = (u2 << sh8) + s0 + c1;  // u1 = 0
+  T R[16];
+  if constexpr (UPD) {
+    T* lp = g.lp + (size_t)b * g.xs;
+    const T* D = g.D + (size_t)b * g.xs;
+    const T lo = T(up.Mn - floor), eta = T(g.eta);
+    T nl[8], dv[8];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        nl[u] = lp[(uint32_t(u) << (n - 4)) + x0];
-        dv[u] = D[(uint32_t(u) << (n - 4)) + x0];
-      }
-#pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        nl[u] = update_value<T>(up, eta, lo, nl[u], dv[u]);
-        lp[(uint32_t(u) << (n - 4)) + x0] = nl[u];
-        R[u] = exp_t<T>(nl[u] - T(up.Mn));
-      }
-    } else {
-#pragma unroll
-      for (int u = 0; u < 16; ++u) R[u] = src[(uint32_t(u) << (n - 4)) + x0];
+    for (int k = 0; k < 8; ++k) {
+      const uint32_t x = ((8u * h + uint32_t(k)) << (n - 4)) + x0;
+      nl[k] = lp[x];
+      dv[k] = D[x];
     }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      nl[k] = update_value<T>(up, eta, lo, nl[k], dv[k]);
+      lp[((8u * h + uint32_t(k)) << (n - 4)) + x0] = nl[k];
+      R[k] = exp_t<T>(nl[k] - T(up.Mn));
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) R[k] = src[((8u * h + uint32_t(k)) << (n - 4)) + x0];
+  }
+  if (h) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) buf[uint32_t(k) * 256u + pr] = R[k];
+  }
+  __syncthreads();
+  if (!h) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) R[8 + k] = buf[uint32_t(k) * 256u + pr];
+  }
+  __syncthreads();
+  // step 1b: the four-position step of the one row of F_0 for pair pr
+  if (!h) {
     // the first stage of fwd4_thread for the row without ancestors
     uint32_t P[5], lastb[4];
     fwd4_path(0u, P, lastb);
@@ -280,7 +296,7 @@ __global__ __launch_bounds__(kFirst8Threads) void k_fwd_first8(int n, const T* _
       for (int q = 0; q < 8; ++q) F1s[cc][q] = R[cc * 8 + q];
     T F4[30];
     const T v0 = fwd4_after_stage1<T>(F1p, F1s, lastb, F4);
-    T* col = buf + u2 * 16u + c;
+    T* col = buf + u2 * 16u + c1;
     col[0] = v0;
 #pragma unroll
     for (int z = 1; z < 31; ++z) col[uint32_t(z) * kF4Pitch] = F4[z - 1];
@@ -1116,8 +1132,10 @@ __global__ __launch_bounds__(32 * stage8_tile<T>()) void k_bwd_stage8_p(int n, i
   // logical block (root group, column block), column blocks innermost; with 8 or
   // more column blocks XCD x takes its eighth of the column blocks of every root
   const int lcb = ROOTS ? 0 : sh - LP;
-  uint32_t lin;
-  if (lcb >= 3) {
+  uint32_t lin = 0;
+  if constexpr (ROOTS) {
+    lin = logical_block();
+  } else if (lcb >= 3) {
     const uint32_t x = blockIdx.x & 7u, k = blockIdx.x >> 3;
     const int cl = lcb - 3;
     lin = ((k >> cl) << lcb) + (x << cl) + (k & ((1u << cl) - 1u));
