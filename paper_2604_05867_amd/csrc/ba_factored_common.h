@@ -204,12 +204,12 @@ __device__ __forceinline__ bool order_slot_xcd(const Order& o, uint32_t& row, ui
   const uint32_t x = blockIdx.x & 7u, k = blockIdx.x >> 3;
   const uint32_t cmask = (1u << o.cw_log2) - 1u;
   if (k >= o.kb) {  // the rows above level lb (one column tile)
-    const uint32_t q = (((k - o.kb) << 3) + x) * blockDim.x + threadIdx.x;
+    const uint32_t q = (((k - o.kb) << 3) + x) * kBlock + threadIdx.x;
     row = q >> o.cw_log2;
     chunk = q & cmask;
     return row < o.top;
   }
-  const uint32_t q = (x * o.kb + k) * blockDim.x + threadIdx.x;
+  const uint32_t q = (x * o.kb + k) * kBlock + threadIdx.x;
   const int ul = o.h + o.cw_log2;
   const uint32_t unit = q >> ul, r = q & ((1u << ul) - 1u);
   const uint32_t j = r >> o.cw_log2;
@@ -223,10 +223,13 @@ __device__ __forceinline__ bool order_slot_xcd(const Order& o, uint32_t& row, ui
   return true;
 }
 
-// This thread's (row, chunk), one slot per thread.
+// This thread's (row, chunk), one slot per thread.  Every kernel that takes an
+// Order runs kBlock threads per block; the block size is that constant rather than
+// blockDim.x, which is read from the dispatch packet with a vector load that each
+// wavefront would wait for before forming its first address.
 __device__ __forceinline__ bool order_slot(const Order& o, uint32_t& row, uint32_t& chunk) {
   if (o.kb != 0u) return order_slot_xcd(o, row, chunk);
-  return order_slot_q(o, logical_block() * blockDim.x + threadIdx.x, row, chunk);
+  return order_slot_q(o, logical_block() * kBlock + threadIdx.x, row, chunk);
 }
 
 // D(x) = H(x) - G(x) - M for N groups of V consecutive inputs (group u starts at
@@ -387,7 +390,7 @@ inline uint32_t blocks_for(uint32_t threads, uint32_t block = kBlock) {
 }
 
 // Threads per block of the four-position launches without records.
-constexpr uint32_t kStage4Block = 256;
+constexpr uint32_t kStage4Block = kBlock;
 
 // The last four forward positions in one launch (k_fwd_last4, k_fwd_last4_sym): from
 // this n on, with blocks of kLast4Threads and kLast4Stage values of LDS staging (the
