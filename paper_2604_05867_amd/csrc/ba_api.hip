@@ -74,6 +74,8 @@ struct ba_ctx {
   double eta = 1.0;  // update step (1 = BA)
   // graph replay of ba_run chunks
   bool use_graph = false;
+  // set once a gap tolerance has been given (ba_run): instances may then be frozen
+  bool armed = false;
   hipGraphExec_t gexec = nullptr;
   int gchunk = -1;
   int gengine = -1;
@@ -227,6 +229,7 @@ Group<T> make_group(char* ws, const GroupHost& g, bool cert) {
   G.st = reinterpret_cast<State*>(ws + (cert ? L.c_st : L.st));
   G.cs = reinterpret_cast<const Consts*>(ws + L.cs);
   G.eta = 1.0;
+  G.frz = 1;
   return G;
 }
 
@@ -388,6 +391,10 @@ template <typename T>
 int iterate_group(ba_ctx* c, const GroupHost& gh, const Group<T>& G0, bool fused_in, bool leave_pending) {
   Group<T> G = G0;
   G.eta = c->eta;
+  // before any tolerance is set only a non-finite value freezes an instance (and
+  // marks it bad); its iterate and state stay untouched, as the update kernels test
+  // the flag, so the sweeps need not
+  G.frz = c->armed ? 1 : 0;
   const double floor = (sizeof(T) == 4) ? kFloor32 : kFloor64;
   const int check_tol = c->prec == BA_PREC_FP64 ? 1 : 0;
   const FusedUpdate fu{floor, check_tol};
@@ -630,6 +637,7 @@ int ba_run(ba_ctx* c, double gap_bits, int max_iters, int* iters_done) {
   std::vector<State> st;
   if ((rc = read_states(c, st))) return rc;
   std::vector<int> start(c->count);
+  c->armed = true;
   for (int i = 0; i < c->count; ++i) {
     start[i] = st[i].iters;
     st[i].tol = gap_bits * kLn2;

@@ -128,9 +128,9 @@ __device__ __forceinline__ T fwd4_thread(const T* __restrict__ src, int sh, uint
 template <typename T, bool LOGV>
 __global__ __launch_bounds__(kBlock) void k_fwd_stage4(int n, int i, const T* __restrict__ src, size_t sstride,
                                                        T* __restrict__ dst, size_t dstride, const State* st,
-                                                       const Consts* cs, Order o) {
+                                                       const Consts* cs, Order o, int frz) {
   const int b = blockIdx.y;
-  if (st[b].converged) return;
+  if (frz && st[b].converged) return;
   uint32_t y, s;
   if (!order_slot(o, y, s)) return;
   src += (size_t)b * sstride;
@@ -229,7 +229,7 @@ __global__ __launch_bounds__(kFirst8Threads) void k_fwd_first8(int n, const T* _
                                                                T* __restrict__ dst, size_t dstride, Group<T> g,
                                                                double floor, int check_tol) {
   const int b = blockIdx.y;
-  if (g.st[b].converged) return;
+  if ((UPD || g.frz) && g.st[b].converged) return;
   UpdateParams up{};
   if constexpr (UPD) {
     up = update_params<T>(g, b, check_tol, blockIdx.x == 0 && threadIdx.x == 0);
@@ -625,9 +625,9 @@ __global__ __launch_bounds__(kLast2Threads) void k_fwd_last2(int n, const T* __r
 template <typename T, bool LOGV>
 __global__ __launch_bounds__(kLast4Threads) void k_fwd_last4(int n, const T* __restrict__ src, size_t sstride,
                                                              T* __restrict__ dst, size_t dstride,
-                                                             const State* st, const Consts* cs) {
+                                                             const State* st, const Consts* cs, int frz) {
   const int b = blockIdx.y;
-  if (st[b].converged) return;
+  if (frz && st[b].converged) return;
   src += (size_t)b * sstride;
   dst += (size_t)b * dstride;
   const int L = n - 4, La = L - 6;
@@ -830,7 +830,7 @@ template <typename T, int V, bool DP>
 __global__ __launch_bounds__(kBlock) void k_bwd_stage4(int n, int i, const T* __restrict__ src, size_t sstride,
                                                        T* __restrict__ dst, size_t dstride, Group<T> g, Order o) {
   const int b = blockIdx.y;
-  if (g.st[b].converged) return;
+  if (g.frz && g.st[b].converged) return;
   uint32_t y, chunk;
   const bool valid = order_slot(o, y, chunk);
   if (!DP && !valid) return;
@@ -1117,7 +1117,7 @@ __host__ __device__ constexpr uint32_t stage8_sigma_bits(uint32_t q) {
 template <typename T, int MODE>
 __global__ __launch_bounds__(32 * stage8_tile<T>()) void k_bwd_stage8_p(int n, int i, const T* __restrict__ src,
                                                                       size_t sstride, T* __restrict__ dst,
-                                                                      size_t dstride, const State* st) {
+                                                                      size_t dstride, const State* st, int frz) {
   constexpr bool ROOTS = MODE != kS8Columns, SYM = MODE == kS8SymRoots;
   constexpr uint32_t P = uint32_t(stage8_tile<T>());  // value lanes per node
   constexpr int LP = P == 16 ? 4 : 3;
@@ -1125,7 +1125,7 @@ __global__ __launch_bounds__(32 * stage8_tile<T>()) void k_bwd_stage8_p(int n, i
   constexpr int VW = 16 / int(sizeof(T));              // P / VW = 4 vectors per node row
   constexpr uint32_t kOutPitch = 260u;                 // ROOTS: output row pitch
   const int b = blockIdx.z;
-  if (st[b].converged) return;
+  if (frz && st[b].converged) return;
   src += (size_t)b * sstride;
   dst += (size_t)b * dstride;
   const int sh = n - i - 8;                  // log2 of S8 (0 for ROOTS)
@@ -1387,10 +1387,10 @@ hipError_t launch_forward(const Group<T>& g, hipStream_t s, int* launches, int f
       const dim3 grid((1u << (n - 10)) + (top + kLast4Threads - 1u) / kLast4Threads, g.nb);
       if (logv)
         hipLaunchKernelGGL((k_fwd_last4<T, true>), grid, dim3(kLast4Threads), 0, s, n, src, ss, dst, g.ys, g.st,
-                           g.cs);
+                           g.cs, g.frz);
       else
         hipLaunchKernelGGL((k_fwd_last4<T, false>), grid, dim3(kLast4Threads), 0, s, n, src, ss, dst, g.ys, g.st,
-                           g.cs);
+                           g.cs, g.frz);
       if (launches) ++*launches;
       break;
     }
@@ -1411,10 +1411,10 @@ hipError_t launch_forward(const Group<T>& g, hipStream_t s, int* launches, int f
                            upd->check_tol);
       else if (lv)
         hipLaunchKernelGGL((k_fwd_stage4<T, true>), grid, dim3(kStage4Block), 0, s, n, i, src, ss, dst, ds, g.st,
-                           g.cs, o);
+                           g.cs, o, g.frz);
       else
         hipLaunchKernelGGL((k_fwd_stage4<T, false>), grid, dim3(kStage4Block), 0, s, n, i, src, ss, dst, ds, g.st,
-                           g.cs, o);
+                           g.cs, o, g.frz);
       if (launches) ++*launches;
       src = dst;
       ss = ds;
@@ -1499,9 +1499,11 @@ hipError_t launch_backward(const Group<T>& g, hipStream_t s, int* launches, int 
       const dim3 grid(((stage8_slots(i, LP - lc) << (sh - lc)) + 7u) & ~7u, 1, g.nb);
       const dim3 block(32 * stage8_tile<T>());
       if (lc == LP) {
-        hipLaunchKernelGGL((k_bwd_stage8_p<T, kS8Columns>), grid, block, 0, s, n, i, src, ss, dst, g.fs, g.st);
+        hipLaunchKernelGGL((k_bwd_stage8_p<T, kS8Columns>), grid, block, 0, s, n, i, src, ss, dst, g.fs, g.st,
+                           g.frz);
       } else if (lc == 0) {
-        hipLaunchKernelGGL((k_bwd_stage8_p<T, kS8Roots>), grid, block, 0, s, n, i, src, ss, dst, g.fs, g.st);
+        hipLaunchKernelGGL((k_bwd_stage8_p<T, kS8Roots>), grid, block, 0, s, n, i, src, ss, dst, g.fs, g.st,
+                           g.frz);
       } else switch (lc) {
         case 1: hipLaunchKernelGGL((k_bwd_stage8<T, 1>), grid, block, 0, s, n, i, src, ss, dst, g.fs, g.st); break;
         case 2: hipLaunchKernelGGL((k_bwd_stage8<T, 2>), grid, block, 0, s, n, i, src, ss, dst, g.fs, g.st); break;
@@ -1615,7 +1617,7 @@ hipError_t launch_backward8_sym_v(const Group<T>& g, hipStream_t s, T* dst) {
   const uint32_t slots = stage8_slots(i - 1, LP) + 1u;  // + the empty row
   const dim3 grid((slots + 7u) & ~7u, 1, g.nb);
   hipLaunchKernelGGL((k_bwd_stage8_p<T, kS8SymRoots>), grid, dim3(32 * stage8_tile<T>()), 0, s, n, i, g.v, g.ys,
-                     dst, g.fs, g.st);
+                     dst, g.fs, g.st, g.frz);
   return hipGetLastError();
 }
 template hipError_t launch_backward8_sym_v<float>(const Group<float>&, hipStream_t, float*);

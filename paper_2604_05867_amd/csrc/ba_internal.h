@@ -124,6 +124,9 @@ struct Group {
   State* st;          // [nb]
   const Consts* cs;   // [nb]
   double eta;         // update step: log p <- log p + eta D - log sum p e^{eta D} (1 = BA)
+  int frz;            // 0: no instance can be frozen by a gap tolerance (none is set); the
+                      // sweep kernels of the default launch plan then skip reading the
+                      // frozen flag, which the update kernels always test
 };
 
 enum StreamOp { kOpScatter = 0, kOpGather = 1, kOpInit = 2, kOpRow = 3, kOpVerify = 4 };

@@ -83,7 +83,7 @@ __global__ __launch_bounds__(kBlock) void k_dpart(Group<T> g, int nblk, int use_
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_final_parts(Group<T> g, int nblk) {
   const int b = blockIdx.x;
-  if (g.st[b].converged) return;
+  if (g.frz && g.st[b].converged) return;
   double* part = g.part + (size_t)b * g.ps;
   const Part P = gather_parts(part, nblk);
   if (threadIdx.x == 0) store_part(part + kFinalRec, P);

@@ -464,6 +464,32 @@ def test_first_eight_forward_is_bitwise_four(ba, n, prec):
     assert out[0][1] == out[1][1]
 
 
+@pytest.mark.parametrize("n,prec", [(16, "fp32"), (13, "fp64")])
+def test_freeze_flag_skip_is_bitwise(ba, n, prec):
+    """Until a gap tolerance is set (ba_run) no instance can be frozen by one, and the
+    sweep kernels skip reading the frozen flag: the iterates of step() then equal,
+    bit for bit, those of the same iterations run by ba_run (flag read) in the same
+    context.  After ba_run has frozen the instances, step() leaves them untouched."""
+    p = ba.PREC_FP64 if prec == "fp64" else ba.PREC_FP32_LOG
+    ns, ds = [n, n], [0.6, 0.9]
+    say("freeze flag skip n=%d %s" % (n, prec))
+    c = ba.Context(ns, ds, prec=p)
+    start = torch.tensor(np.concatenate([np.full(1 << m, -m * LN2) for m in ns]))
+    c.set_logp(start)
+    c.step(6)
+    skipped = c.get_logp().cpu().numpy()
+    c.set_logp(start)
+    assert c.run(1e-12, 6) == 6
+    read = c.get_logp().cpu().numpy()
+    assert np.array_equal(skipped, read)
+    # a gap every iterate meets: frozen after the first chunk, then step() is a no-op
+    c.run(20.0, 10)
+    frozen = c.get_logp().cpu().numpy()
+    c.step(3)
+    assert np.array_equal(frozen, c.get_logp().cpu().numpy())
+    c.close()
+
+
 def test_four_position_backward_n20_fp32(ba):
     ds = [0.64, 0.8, 0.95]
     out = []
