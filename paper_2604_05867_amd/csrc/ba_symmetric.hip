@@ -231,9 +231,9 @@ __global__ __launch_bounds__(kBlock) void k_bwd_stage2_sym(int n, int i, const T
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_fwd_stage4_sym(int n, int i, const T* __restrict__ src,
                                                            size_t sstride, T* __restrict__ dst, size_t dstride,
-                                                           const State* st, Order o) {
+                                                           const State* st, Order o, int frz) {
   const int b = blockIdx.y;
-  if (st[b].converged) return;
+  if (frz && st[b].converged) return;
   uint32_t y, s;
   if (!order_slot(o, y, s)) return;
   src += (size_t)b * sstride;
@@ -336,7 +336,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_stage4_sym(int n, int i, const T
                                                            size_t sstride, T* __restrict__ dst, size_t dstride,
                                                            Group<T> g, Order o) {
   const int b = blockIdx.y;
-  if (g.st[b].converged) return;
+  if (g.frz && g.st[b].converged) return;
   uint32_t q, s;
   const bool valid = order_slot(o, q, s);
   if (!DP && !valid) return;
@@ -445,9 +445,9 @@ __device__ __forceinline__ T fwd4_sym_w1(const T* __restrict__ src, uint32_t y, 
 template <typename T, bool LOGV>
 __global__ __launch_bounds__(kLast4Threads) void k_fwd_last4_sym(int n, const T* __restrict__ src, size_t sstride,
                                                                  T* __restrict__ dst, size_t dstride,
-                                                                 const State* st, const Consts* cs) {
+                                                                 const State* st, const Consts* cs, int frz) {
   const int b = blockIdx.y;
-  if (st[b].converged) return;
+  if (frz && st[b].converged) return;
   src += (size_t)b * sstride;
   dst += (size_t)b * dstride;
   const int L = n - 4, La = L - 6;
@@ -598,7 +598,7 @@ hipError_t launch_forward_sym(const Group<T>& g, hipStream_t s, int* launches, i
                          dst, g.fs, g, o, upd->floor, upd->check_tol);
     else
       hipLaunchKernelGGL((k_fwd_stage4_sym<T>), dim3(order_blocks(o, kBlock), g.nb), dim3(kBlock), 0, s, n, i0,
-                         src, ss, dst, g.fs, g.st, o);
+                         src, ss, dst, g.fs, g.st, o, g.frz);
     if (launches) ++*launches;
     src = dst;
     ss = g.fs;
@@ -608,7 +608,7 @@ hipError_t launch_forward_sym(const Group<T>& g, hipStream_t s, int* launches, i
     const uint32_t ndeep = 1u << (n - 11), top = ndeep;  // deep blocks; compact rows above
     const dim3 grid(ndeep + (top + kLast4Threads - 1u) / kLast4Threads, g.nb);
     hipLaunchKernelGGL((k_fwd_last4_sym<T, true>), grid, dim3(kLast4Threads), 0, s, n, src, ss, g.v, g.ys, g.st,
-                       g.cs);
+                       g.cs, g.frz);
     if (launches) ++*launches;
     return hipGetLastError();
   }

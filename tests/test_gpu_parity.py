@@ -464,18 +464,20 @@ def test_first_eight_forward_is_bitwise_four(ba, n, prec):
     assert out[0][1] == out[1][1]
 
 
-@pytest.mark.parametrize("n,prec", [(16, "fp32"), (13, "fp64")])
-def test_freeze_flag_skip_is_bitwise(ba, n, prec):
+@pytest.mark.parametrize("n,prec,sym", [(16, "fp32", False), (13, "fp64", False), (16, "fp32", True)])
+def test_freeze_flag_skip_is_bitwise(ba, n, prec, sym):
     """Until a gap tolerance is set (ba_run) no instance can be frozen by one, and the
     sweep kernels skip reading the frozen flag: the iterates of step() then equal,
     bit for bit, those of the same iterations run by ba_run (flag read) in the same
     context.  After ba_run has frozen the instances, step() leaves them untouched."""
     p = ba.PREC_FP64 if prec == "fp64" else ba.PREC_FP32_LOG
     ns, ds = [n, n], [0.6, 0.9]
-    say("freeze flag skip n=%d %s" % (n, prec))
+    say("freeze flag skip n=%d %s sym=%d" % (n, prec, sym))
     c = ba.Context(ns, ds, prec=p)
     start = torch.tensor(np.concatenate([np.full(1 << m, -m * LN2) for m in ns]))
     c.set_logp(start)
+    if sym:
+        c.set_symmetry(True)
     c.step(6)
     skipped = c.get_logp().cpu().numpy()
     c.set_logp(start)
