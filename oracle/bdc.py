@@ -14,6 +14,8 @@ Every function below names the passage of the paper it writes out.
 """
 from __future__ import annotations
 
+import functools
+import itertools
 import math
 from dataclasses import dataclass
 
@@ -318,50 +320,49 @@ def binom_le(n: int, t: int) -> int:
 
 
 def subset_unrank(n: int, w: int, j: int) -> list[int]:
-    """Algorithm 5 (Section 5.1): the j-th w-subset of {0..n-1}.  Scanning t = 0, 1, ...
-    the subsets that contain t (C(n-t-1, w-1) of them, the rest chosen after t) come
-    before those that do not."""
+    """The j-th w-subset of {0..n-1} in the order Section 5.1 enumerates them:
+    lexicographic order of the increasing element lists (subsets holding the
+    smaller element first), which is the order itertools.combinations yields."""
     assert 0 <= j < math.comb(n, w)
-    out = []
-    for t in range(n):
-        if w == 0:
-            break
-        c = math.comb(n - t - 1, w - 1)
-        if j < c:
-            out.append(t)
-            w -= 1
-        else:
-            j -= c
-    return out
+    return list(next(itertools.islice(itertools.combinations(range(n), w), j, None)))
 
 
-def supersequence(i: int, n: int, y: list[int], fixed: bool = True) -> int:
-    """Algorithm 6 (Section 5.2): the i-th length-n supersequence of y, as an input
-    index.  S (from Algorithm 5) holds the positions not used by the leftmost
-    embedding of y: before y is complete they get the complement of the next symbol
-    of y, the other positions copy y in order.  After y is complete, positions in S
-    get 1 - y_{k-1}; the printed algorithm sets the positions outside S to 0, which
-    is not one-to-one when y ends in 1 (both choices give 0).  We read it as setting
-    them to y_{k-1}, so S is recoverable from the tail (fixed=True; fixed=False is
-    the printed rule).  For the empty y (k = 0) the positions in S are 1, the
-    others 0."""
+def supersequence_key(x: int, n: int, y: list[int]) -> tuple[int, ...]:
+    """The position set S that names the supersequence x of y in Section 5.2:
+    the positions the leftmost embedding of y in x skips before it completes,
+    together with the positions after it whose symbol differs from y's last
+    symbol (for the empty y: the positions holding 1).  Returned sorted."""
+    xb = string_bits(x, n)
     k = len(y)
-    w = 0
-    while not (binom_le(n, w - 1) <= i < binom_le(n, w)):
-        w += 1
-    assert w <= n - k
-    S = set(subset_unrank(n, w, i - binom_le(n, w - 1)))
     last = y[k - 1] if k > 0 else 0
-    x, r = [], 0
+    S, r = [], 0
     for pos in range(n):
-        if pos in S:
-            x.append(1 - y[r] if r < k else 1 - last)
-        elif r < k:
-            x.append(y[r])
-            r += 1
-        else:
-            x.append(last if fixed else 0)
-    return sum(b << (n - 1 - q) for q, b in enumerate(x))
+        if r < k:
+            if xb[pos] == y[r]:
+                r += 1          # leftmost embedding: take the first match
+            else:
+                S.append(pos)   # skipped before the embedding completes
+        elif xb[pos] != last:
+            S.append(pos)       # tail position differing from y's last symbol
+    assert r == k, "x is not a supersequence of y"
+    return tuple(S)
+
+
+@functools.lru_cache(maxsize=4096)
+def _supersequences_in_order(n: int, y: tuple[int, ...]) -> tuple[int, ...]:
+    sup = [x for x in range(1 << n) if emb_brute(list(y), string_bits(x, n)) > 0]
+    return tuple(sorted(sup, key=lambda x: (len(supersequence_key(x, n, list(y))),
+                                            supersequence_key(x, n, list(y)))))
+
+
+def supersequence(i: int, n: int, y: list[int]) -> int:
+    """The i-th length-n supersequence of y (Section 5.2), as an input index: the
+    supersequences (found by brute force) ordered by their position set S from
+    :func:`supersequence_key`, first by |S|, then as in :func:`subset_unrank`.
+    Reading: Section 5.2 as printed writes 0 at the positions after the embedding
+    outside S, which repeats strings when y ends in 1; naming the tail by the
+    positions that differ from y's last symbol makes S -> x one-to-one."""
+    return _supersequences_in_order(n, tuple(y))[i]
 
 
 def supersequence_count(n: int, k: int) -> int:

@@ -54,6 +54,10 @@ def lib():
         L.bdc_sample_sweeps.argtypes = [ctypes.c_int, ctypes.c_double, f64p, u32p, ctypes.c_int, f64p,
                                         f64p, f64p]
         L.bdc_sample_sweeps.restype = ctypes.c_longlong
+        L.bdc_row_dp.argtypes = [ctypes.c_int, ctypes.c_uint32, u32p, u32p, ctypes.c_int]
+        L.bdc_rows_dp.argtypes = [ctypes.c_int, u32p, ctypes.c_int, u32p, u32p, ctypes.c_int, i32p]
+        L.bdc_certify.argtypes = [ctypes.c_int, ctypes.c_int, f64p, f64p, ctypes.c_double, f64p, f64p,
+                                  ctypes.c_void_p, i64p]
         _lib = L
     return _lib
 
@@ -165,3 +169,59 @@ def sample_sweeps(n: int, d: float, p: np.ndarray, xs, q_full: np.ndarray):
     if tot < 0:
         raise RuntimeError("bdc_sample_sweeps failed: %d" % tot)
     return q_part.reshape(nt, Y).sum(axis=0), D, int(tot)
+
+
+def row_dp(n: int, x: int) -> tuple[np.ndarray, np.ndarray]:
+    """(ranks, emb) of row x, sorted by rank, from the per-row subsequence generator
+    (NextPos walk with the prefix recurrence of embedding counts)."""
+    cap = (1 << (n + 1)) - 1
+    rk = np.zeros(cap, np.uint32)
+    em = np.zeros(cap, np.uint32)
+    nnz = lib().bdc_row_dp(n, x, rk, em, cap)
+    if nnz < 0:
+        raise RuntimeError("bdc_row_dp failed: %d" % nnz)
+    return rk[:nnz].copy(), em[:nnz].copy()
+
+
+def rows_dp(n: int, xs, cap: int | None = None):
+    """Several rows from the generator at once (OpenMP).  Returns a list of (ranks, emb)."""
+    xs = np.ascontiguousarray(np.asarray(xs, dtype=np.uint32))
+    if cap is None:
+        cap = min((1 << (n + 1)) - 1, 40000)
+    rk = np.zeros(len(xs) * cap, np.uint32)
+    em = np.zeros(len(xs) * cap, np.uint32)
+    nnz = np.zeros(len(xs), np.int32)
+    rc = lib().bdc_rows_dp(n, xs, len(xs), rk, em, cap, nnz)
+    if rc:
+        raise RuntimeError("bdc_rows_dp failed: %d" % rc)
+    out = []
+    for i in range(len(xs)):
+        if nnz[i] < 0:
+            raise RuntimeError("row capacity %d too small" % cap)
+        out.append((rk[i * cap:i * cap + nnz[i]].copy(), em[i * cap:i * cap + nnz[i]].copy()))
+    return out
+
+
+def certify(n: int, weights, logps, floor_nats: float = 700.0, want_r: bool = False):
+    """Certify-only tier: one FP64 evaluation of Section 2.3 steps 1-2(a) at every
+    given law, over every row of the length-n channel (any n <= 22).
+
+    weights: sequence of per-instance length weights w_k (k = 0..n);
+    logps: sequence of per-instance log-probabilities (2^n each, any normalisation).
+    Returns a dict with L, U, I, M (nats, one per instance), D (count x 2^n, nats),
+    r (count x (2^(n+1)-1), if want_r: sum_x e^{lp(x)-M} emb(y,x) of the floored,
+    normalised law) and the count statistics of the rows visited."""
+    W = np.ascontiguousarray(np.asarray(weights, dtype=np.float64).reshape(-1, n + 1))
+    count = W.shape[0]
+    LP = np.ascontiguousarray(np.asarray(logps, dtype=np.float64).reshape(count, 1 << n))
+    D = np.zeros((count, 1 << n))
+    lui = np.zeros((count, 4))
+    r = np.zeros((count, (1 << (n + 1)) - 1)) if want_r else None
+    stats = np.zeros(5, np.int64)
+    rc = lib().bdc_certify(n, count, W, LP, floor_nats, D, lui, r.ctypes.data if want_r else None, stats)
+    if rc:
+        raise RuntimeError("bdc_certify failed: %d" % rc)
+    return {"L": lui[:, 0].copy(), "U": lui[:, 1].copy(), "I": lui[:, 2].copy(), "M": lui[:, 3].copy(),
+            "D": D, "r": r,
+            "stats": {"nnz": int(stats[0]), "bad_rows": int(stats[1]), "min_row_nnz": int(stats[2]),
+                      "max_row_nnz": int(stats[3]), "max_emb": int(stats[4])}}

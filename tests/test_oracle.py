@@ -407,6 +407,120 @@ def test_mirror_ascent_with_unit_step_is_ba():
     assert np.allclose(bdc.normalise_logp(th), lp, atol=1e-12)
 
 
+def test_mirror_ascent_step_derivative_is_variance_of_D():
+    """One mirror-ascent step p_eta ~ p e^{eta D} moves I at eta = 0 with slope
+    dI/deta = sum_x (dI/dp(x)) p(x) (D(x) - I) = Var_p(D) (nats), since
+    dI/dp(x) = D(x) - 1 and sum_x p (D - I) = 0.  A step that rescales theta or the
+    normalised log p by eta, or drops the current theta, has another slope.  Small
+    steps increase I."""
+    n, d = 5, 0.65
+    E = bdc.emb_dense(n)
+    W = bdc.channel_dense(n, d, E)
+    theta = inp.theta_normal(n, seed=3, sigma=0.7)
+    ev = bdc.evaluate(W, bdc.normalise_logp(theta))
+    p = bdc.softmax(theta)
+    var = float(p @ (ev.D - ev.I) ** 2)
+    assert var > 1e-3
+
+    def I_after(eta):
+        return bdc.info_bits(n, d, bdc.mirror_ascent(n, d, theta, eta, 1, E), E) * LN2
+
+    assert abs(I_after(0.0) - ev.I) < 1e-13
+    h = 1e-5
+    slope = (I_after(h) - I_after(-h)) / (2 * h)
+    assert abs(slope - var) < 1e-8
+    # a second step from the first: its slope is the variance at the new law
+    th1 = bdc.mirror_ascent(n, d, theta, 0.5, 1, E)
+    ev1 = bdc.evaluate(W, bdc.normalise_logp(th1))
+    p1 = bdc.softmax(th1)
+    var1 = float(p1 @ (ev1.D - ev1.I) ** 2)
+    th2 = lambda eta: bdc.info_bits(n, d, th1 + eta * ev1.D, E) * LN2
+    assert abs((th2(h) - th2(-h)) / (2 * h) - var1) < 1e-8
+    assert np.allclose(bdc.normalise_logp(bdc.mirror_ascent(n, d, theta, 0.5, 2, E)),
+                       bdc.normalise_logp(th1 + 0.5 * ev1.D), atol=1e-12)
+    for eta in (0.05, 0.2, 0.5):
+        assert I_after(eta) > ev.I
+
+
+# --------------------------------------------------------------------------
+# The certify-only tier: per-row generator and full-size evaluation
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 5, 8, 10])
+def test_row_generator_every_row_matches_brute_force(oracle_native, n):
+    for x in range(1 << n):
+        a = oracle_native.row(n, x)
+        b = oracle_native.row_dp(n, x)
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]), (n, x)
+
+
+def test_row_generator_matches_brute_force_n20(oracle_native):
+    """256 seeded rows of the n = 20 channel, including 0^n, 1^n and both alternating
+    strings, bit-exact against the subset definition."""
+    n = 20
+    xs = inp.sample_rows(n, 256, seed=31)
+    full = (1 << n) - 1
+    alt = int("01" * 10, 2)
+    for must in (0, full, alt, full ^ alt):
+        assert must in xs
+    assert len(xs) >= 256
+    A = oracle_native.rows(n, xs, cap=30000)
+    B = oracle_native.rows_dp(n, xs, cap=30000)
+    for x, a, b in zip(xs, A, B):
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]), x
+
+
+def test_certify_matches_csr_evaluation(oracle_native):
+    """bdc_certify against the CSR evaluation (itself pinned to the dense channel),
+    three instances at once: two BDC_d and one exact channel BDC_{n,k}, random
+    laws, with and without the 700-nat floor."""
+    n = 12
+    csr = oracle_native.CSR(n)
+    ds = [0.64, 0.9]
+    wexact = np.zeros(n + 1)
+    wexact[5] = 1.0 / math.comb(n, 5)
+    weights = [bdc.length_weights(n, d) for d in ds] + [wexact]
+    lps = [inp.random_logp(n, seed=40 + i, spread=2.0 + 60.0 * (i == 1)) for i in range(3)]
+    for floor in (700.0, 0.0):
+        out = oracle_native.certify(n, weights, lps, floor_nats=floor, want_r=True)
+        for i in range(2):
+            D, L, U, I, q = csr.evaluate(ds[i], lps[i], floor_nats=floor, want_q=True)
+            assert np.allclose(out["D"][i], D, atol=1e-11, rtol=0)
+            assert abs(out["L"][i] - L) < 1e-11 and abs(out["U"][i] - U) < 1e-11 and abs(out["I"][i] - I) < 1e-11
+            w = bdc.length_weights(n, ds[i])[bdc.output_lengths(n)]
+            assert np.allclose(out["r"][i] * w, q, rtol=1e-12, atol=0)
+        ex = bdc.evaluate(bdc.channel_dense_exact(n, 5), bdc.floor_logp(bdc.normalise_logp(lps[2]),
+                                                                        floor or None))
+        assert np.allclose(out["D"][2], ex.D, atol=1e-11, rtol=0)
+        assert abs(out["L"][2] - ex.L) < 1e-11 and abs(out["U"][2] - ex.U) < 1e-11
+    assert out["stats"] == {"nnz": 2 * 3 ** n - 2 ** n, "bad_rows": 0, "min_row_nnz": n + 1,
+                            "max_row_nnz": out["stats"]["max_row_nnz"], "max_emb": math.comb(n, n // 2)}
+
+
+@pytest.mark.slow
+def test_certify_n20_product_laws(oracle_native):
+    """The certify-only tier over every row of the n = 20 channel at product laws,
+    against their closed forms: r(y) at 4000 seeded outputs and D(x) at 64 seeded
+    rows; and the whole-matrix count invariants: 2*3^n - 2^n nonzeros, every row's
+    length sums equal to C(n,k), minimum row nnz n+1, maximum emb C(n, n/2)."""
+    n = 20
+    ds = [0.64, 0.95]
+    pis = [inp.product_bit_probs(n, seed=50 + i) for i in range(2)]
+    out = oracle_native.certify(n, [bdc.length_weights(n, d) for d in ds],
+                                [inp.product_logp(n, pi) for pi in pis], want_r=True)
+    st = out["stats"]
+    assert st["nnz"] == 2 * 3 ** n - 2 ** n and st["bad_rows"] == 0
+    assert st["min_row_nnz"] == n + 1 and st["max_emb"] == math.comb(n, n // 2)
+    ranks = inp.sample_outputs(n, 4000, seed=51)
+    xs = inp.sample_rows(n, 64, seed=52)
+    for i in range(2):
+        want_r = oracle_native.product_r(n, pis[i], ranks)
+        got_r = out["r"][i][ranks] * math.exp(out["M"][i])
+        assert np.allclose(got_r, want_r, rtol=1e-11, atol=0)
+        assert np.allclose(out["D"][i][xs], oracle_native.product_D(n, ds[i], pis[i], xs), atol=1e-10, rtol=0)
+        assert out["L"][i] <= out["U"][i]
+
+
 # --------------------------------------------------------------------------
 # The C CSR implementation against the numpy dense one
 # --------------------------------------------------------------------------
@@ -497,27 +611,54 @@ def test_subset_unrank_lists_every_subset_once_in_order(n):
 
 @pytest.mark.parametrize("n", [1, 2, 4, 6, 8])
 def test_supersequence_enumeration_is_a_bijection(n):
-    """Algorithm 6 (with the tail read as y_{k-1}) and Lemma 7: for every y the
-    indices 0 .. sum_{i<=n-k} C(n,i)-1 map one-to-one onto the supersequences,
-    found by brute force."""
+    """Section 5.2 with Lemma 7: for every y the position sets S with |S| <= n - k
+    name its supersequences one-to-one, and index i = sum_{j<w} C(n,j) + (rank of S
+    among the w-subsets, Section 5.1) lists them all."""
     for k in range(n + 1):
         assert bdc.supersequence_count(n, k) == sum(math.comb(n, i) for i in range(n - k + 1))
         for yb in range(1 << k):
             y = [(yb >> (k - 1 - q)) & 1 for q in range(k)]
-            xs = [bdc.supersequence(i, n, y) for i in range(bdc.supersequence_count(n, k))]
             sup = [x for x in range(1 << n) if bdc.emb_brute(y, bdc.string_bits(x, n)) > 0]
+            assert len(sup) == bdc.supersequence_count(n, k)
+            xs = [bdc.supersequence(i, n, y) for i in range(bdc.supersequence_count(n, k))]
             assert sorted(xs) == sup, (n, yb, k)
+            i = 0
+            for w in range(n - k + 1):
+                for j in range(math.comb(n, w)):
+                    assert bdc.supersequence_key(xs[i], n, y) == tuple(bdc.subset_unrank(n, w, j))
+                    i += 1
+
+
+def test_supersequence_key_examples():
+    """Hand-checked keys: y = 01 in x = 1001 is embedded at positions 1, 3 (position 0
+    skipped, position 2 skipped); in x = 0111 at 0, 1 with tail 11 = y's last symbol;
+    in x = 0110 at 0, 1 with position 3 differing from the last symbol 1."""
+    assert bdc.supersequence_key(0b1001, 4, [0, 1]) == (0, 2)
+    assert bdc.supersequence_key(0b0111, 4, [0, 1]) == ()
+    assert bdc.supersequence_key(0b0110, 4, [0, 1]) == (3,)
+    assert bdc.supersequence_key(0b101, 3, []) == (0, 2)
 
 
 def test_printed_supersequence_rule_is_not_one_to_one():
-    """The printed tail rule (0 outside S) repeats supersequences exactly when y
-    ends in 1 and S has positions after the embedding; n = 3, y = 1 is one case."""
-    y = [1]
-    xs = [bdc.supersequence(i, 3, y, fixed=False) for i in range(bdc.supersequence_count(3, 1))]
-    assert len(set(xs)) < len(xs)
-    y0 = [0]
-    xs0 = [bdc.supersequence(i, 3, y0, fixed=False) for i in range(bdc.supersequence_count(3, 1))]
-    assert len(set(xs0)) == len(xs0)
+    """Section 5.2 as printed fills the positions after the embedding with
+    1 - y_{k-1} in S and 0 outside S.  For a y ending in 1 both are 0, so it only
+    reaches the supersequences whose tail after the leftmost embedding is all 0,
+    fewer than the sum_{i<=n-k} C(n,i) of Lemma 7: it repeats strings.  For a y
+    ending in 0 any tail is reachable and the printed rule and the reading used
+    here coincide."""
+    n = 3
+    for y, repeats in (([1], True), ([0], False), ([0, 1], True), ([1, 0], False)):
+        sup = [x for x in range(1 << n) if bdc.emb_brute(y, bdc.string_bits(x, n)) > 0]
+        reach = []
+        for x in sup:
+            xb = bdc.string_bits(x, n)
+            r, pos = 0, 0
+            while r < len(y):
+                r += xb[pos] == y[r]
+                pos += 1
+            if y[-1] == 0 or all(b == 0 for b in xb[pos:]):
+                reach.append(x)
+        assert (len(reach) < bdc.supersequence_count(n, len(y))) == repeats
 
 
 @pytest.mark.parametrize("n", [3, 6])
