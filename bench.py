@@ -7,11 +7,20 @@ log-domain iterates (FP64 certification reported after the timed steps).  One
 step = one BA iteration of all three instances: q = W^T p, D(x), the Blahut
 reductions and the update, over all 2*3^20 - 2^20 nonzeros of W per instance.
 
-metric: W-nonzero terms per second = iterations/s x nnz(W) x instances, and BA
-iterations per second.  The default engine evaluates the two products of each
-iteration stage by stage (BA_ENGINE_FACTORED); the per-nonzero engine of the
-paper's method (BA_ENGINE_STREAM) is measured on the same workload and reported
-beside it.  The FP64 plain iteration of one instance is reported too.
+metric: BA iterations per second, and W-nonzero terms per second =
+iterations/s x nnz(W) x instances.  The default engine evaluates the two products
+of each iteration stage by stage (BA_ENGINE_FACTORED) and never visits a nonzero,
+so for it the terms/s figure is nonzero-equivalent (accounted, not visited); the
+per-nonzero engine of the paper's method (BA_ENGINE_STREAM), which visits every
+nonzero, is measured on the same workload and reported beside it.  The FP64 plain
+iteration of one instance is reported too.
+
+After the timed steps (outside the timed region) the same three instances are
+run to the stopping rule of Section 2.3 (certified gap < 1e-6 bits, with an
+iteration cap): certified bounds on C_20(d), the gap reached, the FP32-vs-FP64
+difference of the bounds (FP64 iterates with the same floor, same iteration
+counts) and the orbit check of Theorem 4 on the final laws.  The CPU baseline is
+the oracle's FP64 certification of those final laws.
 """
 from __future__ import annotations
 
@@ -28,6 +37,7 @@ sys.path.insert(0, ROOT)
 
 N = 20
 DS = [0.64, 0.80, 0.95]
+UNIT_EQUIV = "W-nonzero-equivalent terms/s (factored engine: nonzeros accounted, not visited)"
 FUSE = 5  # the library default (positions per launch of the factored engine)
 
 
@@ -116,51 +126,128 @@ def sweep_launch_bytes(n, esz, nb, fuse, backward, fused_update=0.0):
     return out
 
 
-def cpu_baseline(target_s=10.0):
-    """The oracle (plain C, brute-force rows) doing both sweeps of the first BA
-    iteration on a bounded sample of n = 20 input rows, timed on this host."""
+def cpu_baseline(logps, gpu_bounds):
+    """The oracle's certify-only tier on this host: one FP64 evaluation (sweep 1
+    over every row, sweep 2 over every row, then L, U, I) of the three n = 20
+    instances at the given laws, with every row of the channel regenerated by the
+    oracle's own subsequence generator.  This is one BA iteration's worth of work
+    over the whole workload (3 x 6,972,520,226 nonzeros per sweep).  Its L and U
+    are compared with the GPU's FP64 certification of the same laws."""
     import numpy as np
 
-    import bdc_inputs as inp
     import oracle.native as on
     from oracle import bdc
 
     on.lib()
-    p = np.full(1 << N, 2.0 ** -N)
-    w = bdc.length_weights(N, 0.8)[bdc.output_lengths(N)]
-    q_full = w * bdc.r_uniform(N)  # exact output law of the uniform input
-    # size the sample from a probe that itself runs long enough (>= 1 s) to time
-    probe_n = 64
-    while True:
-        probe = inp.sample_rows(N, probe_n, seed=21)
-        t0 = time.perf_counter()
-        on.sample_sweeps(N, 0.8, p, probe, q_full)
-        dt = time.perf_counter() - t0
-        if dt >= 1.0 or probe_n >= (1 << N) // 4:
-            break
-        probe_n *= 4
-    count = int(min(1 << N, max(64, probe_n * target_s / max(dt, 1e-6))))
-    xs = inp.sample_rows(N, count, seed=22)
+    weights = [bdc.length_weights(N, d) for d in DS]
     t0 = time.perf_counter()
-    _, _, visited = on.sample_sweeps(N, 0.8, p, xs, q_full)
+    cert = on.certify(N, weights, np.asarray(logps))
     el = time.perf_counter() - t0
-    return {"value": visited / el, "unit": "W-nonzero terms/s", "cores": on.num_threads(),
-            "kind": "oracle",
-            "sample": "both sweeps of the first BA iteration (uniform p, d=0.8) on %d seeded rows "
-                      "of the n=20 channel (%d nonzeros, brute-force rows), %.1f s" % (len(xs), visited, el),
+    visited = cert["stats"]["nnz"] * len(DS)
+    ln2 = math.log(2.0)
+    diff = max(max(abs(cert["L"][i] / ln2 - gpu_bounds[0][i]), abs(cert["U"][i] / ln2 - gpu_bounds[1][i]))
+               for i in range(len(DS)))
+    return {"value": visited / el, "unit": "W-nonzero terms/s (visited)", "cores": on.num_threads(),
+            "kind": "oracle", "iters_per_s": 1.0 / el,
+            "sample": "one FP64 evaluation (both sweeps, L, U, I) of the whole workload: n=20, d in %s, at the "
+                      "final laws of the stopping-rule run, every row regenerated on the host "
+                      "(%d nonzeros visited per sweep), %.1f s" % (DS, visited, el),
+            "max_abs_bound_diff_vs_gpu_certification_bits": diff,
             "cpu": platform.processor() or platform.machine()}
 
 
-def run_segments(ctx, gap_bits, cap, seg, tag):
+def orbit_deviation(lp, n):
+    """Theorem 4 (Appendix A): the BA iterates from the uniform law are invariant
+    under complement and reversal.  For g = complement and reversal: the largest
+    |log p(g x) - log p(x)| (nats) over the inputs within 5 and within 30 nats of the
+    maximum, and its mean under p."""
+    import numpy as np
+    x = np.arange(1 << n)
+    cp = x ^ ((1 << n) - 1)
+    rv = np.zeros_like(x)
+    for i in range(n):
+        rv |= ((x >> i) & 1) << (n - 1 - i)
+    lp = lp - (lp.max() + np.log(np.exp(lp - lp.max()).sum()))
+    p = np.exp(lp)
+    out = {}
+    for name, g in (("complement", cp), ("reversal", rv)):
+        dev = np.abs(lp[g] - lp)
+        out[name] = {"max_within_5_nats": float(np.max(dev[lp > lp.max() - 5.0])),
+                     "max_within_30_nats": float(np.max(dev[lp > lp.max() - 30.0])),
+                     "mean_under_p": float(p @ dev)}
+    return out
+
+
+def config5(cap, gap_bits, dev):
+    """The workload run to the stopping rule: FP32 iterates, FP64 certification
+    every 50 iterations, graph-replayed chunks, stop per instance when the
+    certified gap of the current iterate is below gap_bits (Section 2.3) or at the
+    cap.  Then: the same instances iterated in FP64 with the same floor for the
+    same number of iterations (difference of the certified bounds), and the orbit
+    check of Theorem 4 on the final laws.  Returns (block, final laws, bounds)."""
+    import numpy as np
+    import torch
+
+    import paper_2604_05867_amd as ba
+
+    s = torch.cuda.Stream(dev)
+    ctx = ba.Context([N] * len(DS), DS, prec=ba.PREC_FP32_LOG, cert_every=50, device=dev, stream=s)
+    ctx.set_graphs(True)
+    with torch.cuda.stream(s):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run_segments(ctx, gap_bits, cap, 25000, "config5", current=True)
+        s.synchronize()
+        el = time.perf_counter() - t0
+        lo, hi = ctx.bounds()
+        blo, bhi, its = ctx.best_bounds()
+        lp = ctx.get_logp().cpu().numpy().reshape(len(DS), 1 << N)
+    ctx.close()
+    out = []
+    t64 = 0.0
+    for i, d in enumerate(DS):
+        c = ba.Context(N, d, prec=ba.PREC_FP64, device=dev)
+        c.set_floor(80.0)  # the FP32 iterates' floor: the comparison isolates the precision
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        c.step(its[i])
+        torch.cuda.synchronize()
+        t64 += time.perf_counter() - t1
+        lo64, hi64 = c.bounds()
+        lp64 = c.get_logp().cpu().numpy()
+        c.close()
+        out.append({"d": d, "iterations": its[i], "converged": hi[i] - lo[i] < gap_bits,
+                    "certified_lower_bits": lo[i], "certified_upper_bits": hi[i], "gap_bits": hi[i] - lo[i],
+                    "best_lower_bits": blo[i], "best_upper_bits": bhi[i],
+                    "fp64_same_iterations": {"certified_lower_bits": lo64[0], "certified_upper_bits": hi64[0],
+                                             "abs_dL_bits": abs(lo64[0] - lo[i]),
+                                             "abs_dU_bits": abs(hi64[0] - hi[i])},
+                    "orbit_abs_dlogp_nats": orbit_deviation(lp[i], N),
+                    "orbit_abs_dlogp_nats_fp64_iterate": orbit_deviation(lp64, N)})
+        print("config5: d=%.2f  %d iterations  [%.9f, %.9f] bits  |FP32-FP64| = %.1e / %.1e" % (
+            d, its[i], lo[i], hi[i], abs(lo64[0] - lo[i]), abs(hi64[0] - hi[i])), file=sys.stderr, flush=True)
+    block = {"gap_bits": gap_bits, "cap": cap, "stop_rule": "certified gap of the current iterate (Section 2.3)",
+             "seconds_fp32_batched": el, "seconds_fp64_same_iterations": t64,
+             "fp64_floor_nats": 80.0,
+             "instances": out}
+    return block, lp, (lo, hi)
+
+
+def run_segments(ctx, gap_bits, cap, seg, tag, current=False):
     """ba_run in segments of `seg` iterations (continuing the same run), printing
-    progress after each; returns when every instance meets gap_bits or after cap."""
+    progress after each; returns when every instance meets gap_bits (by its best
+    bounds, or with current=True by the last certification of its current
+    iterate) or after cap."""
     import numpy as np
     done = 0
     while done < cap:
         k = min(seg, cap - done)
         ctx.run(gap_bits, k)
         done += k
-        lo, hi, it = ctx.best_bounds()
+        if current:
+            lo, hi = ctx.bounds()
+        else:
+            lo, hi, _ = ctx.best_bounds()
         left = int(np.sum(np.array(hi) - np.array(lo) >= gap_bits))
         print("%s: %d iterations, %d instances above the gap" % (tag, done, left), file=sys.stderr, flush=True)
         if left == 0:
@@ -289,6 +376,9 @@ def main():
     ap.add_argument("--stream-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stream", action="store_true")
+    ap.add_argument("--no-config5", action="store_true",
+                    help="skip the stopping-rule run of the workload (and the CPU baseline on its laws)")
+    ap.add_argument("--config5-cap", type=int, default=200000)
     ap.add_argument("--config3", action="store_true",
                     help="batched FP32 vs plain FP64 at equal certified gap (several minutes)")
     ap.add_argument("--config3-symmetric", action="store_true",
@@ -381,7 +471,7 @@ def main():
     esym = time.perf_counter() - t0
     ktsym = csym.time_kernels(args.steps)
     lo_s, hi_s = csym.bounds()
-    extra["symmetric"] = {"value": args.steps / esym * nnz * nb, "unit": "W-nonzero terms/s",
+    extra["symmetric"] = {"value": args.steps / esym * nnz * nb, "unit": UNIT_EQUIV,
                           "iters_per_s": args.steps / esym, "ms_per_step": esym / args.steps * 1e3,
                           "kernel_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in ktsym.items()},
                           "certified_lower_bits": lo_s, "certified_upper_bits": hi_s}
@@ -396,7 +486,8 @@ def main():
         torch.cuda.synchronize()
         es = time.perf_counter() - t0
         kts = cs.time_kernels(1)
-        extra["stream_engine"] = {"value": args.stream_steps / es * nnz * nb, "unit": "W-nonzero terms/s",
+        extra["stream_engine"] = {"value": args.stream_steps / es * nnz * nb, "unit": "W-nonzero terms/s (visited)",
+                                  "iters_per_s": args.stream_steps / es,
                                   "ms_per_step": es / args.stream_steps * 1e3,
                                   "kernel_ms_per_step": {k: round(v[0], 3) for k, v in kts.items()}}
         cs.close()
@@ -411,7 +502,8 @@ def main():
         torch.cuda.synchronize()
         ep = time.perf_counter() - t0
         ktp = cp.time_kernels(1)
-        extra["pull_engine"] = {"value": nnz * nb / ep, "unit": "W-nonzero terms/s", "ms_per_step": ep * 1e3,
+        extra["pull_engine"] = {"value": nnz * nb / ep, "unit": "W-nonzero terms/s (visited; sweep 1 in pull form)",
+                                "ms_per_step": ep * 1e3,
                                 "kernel_ms_per_step": {k: round(v[0], 3) for k, v in ktp.items()}}
         cp.close()
     print("bench: fp64 plain", file=sys.stderr, flush=True)
@@ -423,19 +515,23 @@ def main():
     c64.step(k64)
     torch.cuda.synchronize()
     e64 = time.perf_counter() - t0
-    extra["fp64_single"] = {"iters_per_s": k64 / e64, "value": k64 / e64 * nnz, "unit": "W-nonzero terms/s",
+    extra["fp64_single"] = {"iters_per_s": k64 / e64, "value": k64 / e64 * nnz, "unit": UNIT_EQUIV,
                             "ms_per_step": e64 / k64 * 1e3}
     c64.close()
 
     cpu = None
-    if not args.no_cpu_baseline:
-        print("bench: cpu baseline", file=sys.stderr, flush=True)
-        cpu = cpu_baseline()
+    if not args.no_config5:
+        print("bench: config5 (stopping rule, cap %d)" % args.config5_cap, file=sys.stderr, flush=True)
+        c5, c5_lp, c5_bounds = config5(args.config5_cap, 1e-6, dev)
+        extra["config5"] = c5
+        if not args.no_cpu_baseline:
+            print("bench: cpu baseline (oracle certification of the final laws)", file=sys.stderr, flush=True)
+            cpu = cpu_baseline(c5_lp, c5_bounds)
 
     line = {
         "metric": "W-nonzero terms/s and BA iters/s at n=20",
         "value": value,
-        "unit": "W-nonzero terms/s",
+        "unit": UNIT_EQUIV,
         "iters_per_s": iters_s,
         "n_gpus": 1,
         "steps": args.steps,
@@ -455,6 +551,8 @@ def main():
         "cpu_baseline": cpu,
     }
     line.update(extra)
+    if "stream_engine" in extra:
+        line["visited_terms_per_s_stream_engine"] = extra["stream_engine"]["value"]
     print(json.dumps(line))
 
 

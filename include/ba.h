@@ -143,6 +143,18 @@ int ba_set_symmetry(ba_ctx *c, int enable);
  * eta = 3 oscillated at n = 10, d = 0.67).  0 < eta <= 8, else BA_EINVAL. */
 int ba_set_step(ba_ctx *c, double eta);
 
+/* Floor of the iterates' log-probabilities (Section 2.3 leaves zero-probability
+ * inputs untreated: at the BA optimum of BDC_d many inputs have p = 0, and their
+ * log p falls without bound).  After every update and after ba_set_logp,
+ * log p(x) >= max_x log p(x) - nats.  Defaults: 700 nats for BA_PREC_FP64 iterates,
+ * 80 for BA_PREC_FP32_LOG (e^-80 is a normal float).  Allowed: 50 <= nats <= 700
+ * (FP64) or <= 87 (FP32), else BA_EINVAL (below 50 nats the floored mass, up to
+ * 2^n e^-nats, would no longer be negligible next to the iterate's own bounds).  A
+ * lower floor lets an input whose D(x) rises above L again recover sooner; the
+ * certified bounds hold for any full-support law, so they stay valid.  Certification (ba_bounds, ba_run's
+ * checks, ba_eval, ba_grad) always floors at 700 nats. */
+int ba_set_floor(ba_ctx *c, double nats);
+
 /* Run ba_run's iteration chunks as one captured HIP graph (replayed until the
  * stopping rule holds) instead of individual launches.  Needs a non-null bound
  * stream (capture is not allowed on the legacy null stream): BA_ESTATE otherwise,
@@ -198,7 +210,9 @@ int ba_step(ba_ctx *c, int iters);
 /* Iterate until the FP64-certified gap U - L is below gap_bits for every instance
  * or until max_iters further iterations, certifying every cert_every iterations
  * (FP32 iterates; FP64 iterates are tested every iteration on the device).
- * Synchronises once per chunk of iterations.  Instances that already meet gap_bits
+ * Synchronises once per chunk of iterations; while no instance is frozen the
+ * chunk's sweep kernels skip the per-instance frozen-flag test (the kernels that
+ * write the iterate always make it).  Instances that already meet gap_bits
  * stay frozen, so repeated calls continue a run.
  * *iters_done (host, may be NULL) receives the number of iterations performed by
  * the slowest instance.  The stopping rule is that of Section 2.3 with the

@@ -181,10 +181,13 @@ def evaluate(W: np.ndarray, lp: np.ndarray) -> Eval:
     return Eval(q_scaled=q_scaled, D=D, L=L, U=U, I=I)
 
 
-def ba_update(lp: np.ndarray, ev: Eval) -> np.ndarray:
+def ba_update(lp: np.ndarray, ev: Eval, floor_nats: float | None = None) -> np.ndarray:
     """Step 2(b) of Section 2.3: X^{(t+1)} = W^{(t)} / sum W^{(t)}, i.e.
-    log X^{(t+1)} = log X^{(t)} + D - L."""
-    return normalise_logp(lp) + ev.D - ev.L
+    log X^{(t+1)} = log X^{(t)} + D - L.  With floor_nats, the new log law is then
+    raised to at least its maximum minus floor_nats (reading: the paper leaves
+    inputs whose probability decays to zero untreated; the floor keeps every input
+    representable and the Blahut bounds of the floored law remain valid)."""
+    return floor_logp(normalise_logp(lp) + ev.D - ev.L, floor_nats)
 
 
 def uniform_logp(n: int) -> np.ndarray:
@@ -221,10 +224,11 @@ def ba(W: np.ndarray, n: int, tol_bits: float, max_iters: int,
         t += 1
 
 
-def ba_iterate(W: np.ndarray, lp: np.ndarray, iters: int) -> np.ndarray:
-    """``iters`` BA updates from lp (no stopping test)."""
+def ba_iterate(W: np.ndarray, lp: np.ndarray, iters: int, floor_nats: float | None = None) -> np.ndarray:
+    """``iters`` BA updates from lp (no stopping test), optionally floored as in
+    :func:`ba_update`."""
     for _ in range(iters):
-        lp = ba_update(lp, evaluate(W, lp))
+        lp = ba_update(lp, evaluate(W, lp), floor_nats)
     return normalise_logp(lp)
 
 

@@ -79,6 +79,7 @@ def lib():
     L.ba_set_stop_rule.argtypes = [vp, i32]
     L.ba_set_symmetry.argtypes = [vp, i32]
     L.ba_set_step.argtypes = [vp, ctypes.c_double]
+    L.ba_set_floor.argtypes = [vp, ctypes.c_double]
     _lib = L
     return L
 
@@ -169,6 +170,10 @@ class Context:
     def set_step(self, eta: float):
         """Update step eta of the iterations (1 = BA; see ba_set_step)."""
         self._check(lib().ba_set_step(self._h, float(eta)), "ba_set_step")
+
+    def set_floor(self, nats: float):
+        """Floor of the iterates' log p below their maximum, in nats (see ba_set_floor)."""
+        self._check(lib().ba_set_floor(self._h, float(nats)), "ba_set_floor")
 
     def set_tuning(self, key: int, value: int):
         self._check(lib().ba_set_tuning(self._h, key, value), "ba_set_tuning")

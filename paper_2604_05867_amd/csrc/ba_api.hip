@@ -72,11 +72,16 @@ struct ba_ctx {
   int stop_rule = BA_STOP_ITERATE;
   int sym = 0;   // complement-symmetric iteration requested
   double eta = 1.0;  // update step (1 = BA)
+  double floor = 0.0;  // floor of the iterates' log p below their max (nats); 0 = precision default
   // graph replay of ba_run chunks
   bool use_graph = false;
   // set once a gap tolerance has been given (ba_run): instances may then be frozen
   bool armed = false;
-  hipGraphExec_t gexec = nullptr;
+  // frozen-flag test in the sweep kernels: -1 = decided by `armed` (ba_step), else
+  // the value ba_run chose for the current chunk
+  int frz_override = -1;
+  // one graph per frozen-flag mode (index = frz)
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
   int gchunk = -1;
   int gengine = -1;
   // timing hook
@@ -128,6 +133,13 @@ void make_consts(int n, double d, Consts* c) {
 }
 
 size_t elem(const ba_ctx* c) { return c->prec == BA_PREC_FP32_LOG ? sizeof(float) : sizeof(double); }
+
+// Floor of the iterates' log p below their maximum (ba_set_floor, else the default
+// of the iteration precision).
+double iterate_floor(const ba_ctx* c) {
+  if (c->floor > 0.0) return c->floor;
+  return c->prec == BA_PREC_FP32_LOG ? kFloor32 : kFloor64;
+}
 
 void plan(ba_ctx* c) {
   // group instances by n (order of first appearance)
@@ -391,11 +403,14 @@ template <typename T>
 int iterate_group(ba_ctx* c, const GroupHost& gh, const Group<T>& G0, bool fused_in, bool leave_pending) {
   Group<T> G = G0;
   G.eta = c->eta;
-  // before any tolerance is set only a non-finite value freezes an instance (and
-  // marks it bad); its iterate and state stay untouched, as the update kernels test
-  // the flag, so the sweeps need not
-  G.frz = c->armed ? 1 : 0;
-  const double floor = (sizeof(T) == 4) ? kFloor32 : kFloor64;
+  // The kernels that write log p, p and the state always test the frozen flag, so
+  // a frozen instance's iterate and state stay untouched whether or not the sweeps
+  // test it too; skipping the test there (frz = 0) only sweeps a frozen instance
+  // again into its own scratch arrays.  ba_run chooses per chunk (0 while no
+  // instance is frozen); otherwise the test is made once a tolerance has been set,
+  // before which only a non-finite value can freeze an instance.
+  G.frz = c->frz_override >= 0 ? c->frz_override : (c->armed ? 1 : 0);
+  const double floor = iterate_floor(c);
   const int check_tol = c->prec == BA_PREC_FP64 ? 1 : 0;
   const FusedUpdate fu{floor, check_tol};
   int nblk = 0;  // block records written by the fused D launch, if any
@@ -465,8 +480,10 @@ int write_states(ba_ctx* c, const std::vector<State>& in) {
 }
 
 void drop_graph(ba_ctx* c) {
-  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
-  c->gexec = nullptr;
+  for (auto& g : c->gexec) {
+    if (g) (void)hipGraphExecDestroy(g);
+    g = nullptr;
+  }
   c->gchunk = -1;
   c->gengine = -1;
 }
@@ -656,11 +673,24 @@ int ba_run(ba_ctx* c, double gap_bits, int max_iters, int* iters_done) {
   bool all = false;
   if (c->use_graph && !c->stream)
     return fail(c, BA_ESTATE, "graph capture needs a non-null stream (bind one)");
+  // the sweeps skip the frozen-flag test while no instance is frozen (the host
+  // knows from the states it reads after every chunk)
+  auto any_frozen = [&]() {
+    for (int i = 0; i < c->count; ++i)
+      if (st[i].converged || st[i].bad) return true;
+    return false;
+  };
+  struct FrzScope {
+    ba_ctx* c;
+    ~FrzScope() { c->frz_override = -1; }
+  } frz_scope{c};
   while (done < max_iters) {
     const int k = std::min(chunk, max_iters - done);
+    const int frz = any_frozen() ? 1 : 0;
+    c->frz_override = frz;
     if (c->use_graph && k == chunk) {
-      if (!c->gexec || c->gchunk != chunk || c->gengine != c->engine) {
-        drop_graph(c);
+      if (c->gchunk != chunk || c->gengine != c->engine) drop_graph(c);
+      if (!c->gexec[frz]) {
         hipGraph_t graph = nullptr;
         HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
         int rc2 = ba_step(c, k);
@@ -668,13 +698,13 @@ int ba_run(ba_ctx* c, double gap_bits, int max_iters, int* iters_done) {
         hipError_t ec = hipStreamEndCapture(c->stream, &graph);
         if (rc2) { if (graph) (void)hipGraphDestroy(graph); return rc2; }
         HIPCHK(c, ec);
-        hipError_t ei = hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0);
+        hipError_t ei = hipGraphInstantiate(&c->gexec[frz], graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
         HIPCHK(c, ei);
         c->gchunk = chunk;
         c->gengine = c->engine;
       }
-      HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
+      HIPCHK(c, hipGraphLaunch(c->gexec[frz], c->stream));
     } else {
       if ((rc = ba_step(c, k))) return rc;
       if (c->prec == BA_PREC_FP32_LOG && (rc = certify_all(c, 1))) return rc;
@@ -880,7 +910,7 @@ int ba_set_logp(ba_ctx* c, const double* logp_dev) {
     const auto [gi, slot] = c->where[i];
     GroupHost& gh = c->groups[gi];
     const int nblk = reduce_blocks(gh.n);
-    const double floor = (c->prec == BA_PREC_FP32_LOG) ? kFloor32 : kFloor64;
+    const double floor = iterate_floor(c);
     if (c->prec == BA_PREC_FP32_LOG) HIPCHK(c, launch_set_logp<float>(slot_view(gh.gf, slot), logp_dev + off, nblk, floor, c->stream));
     else HIPCHK(c, launch_set_logp<double>(slot_view(gh.gd, slot), logp_dev + off, nblk, floor, c->stream));
     off += size_t(1) << c->n[i];
@@ -901,6 +931,17 @@ int ba_set_step(ba_ctx* c, double eta) {
   if (!c) return BA_EINVAL;
   if (!(eta > 0.0 && eta <= 8.0)) return fail(c, BA_EINVAL, "step must be in (0, 8]");
   c->eta = eta;
+  drop_graph(c);
+  return BA_OK;
+}
+
+int ba_set_floor(ba_ctx* c, double nats) {
+  if (!c) return BA_EINVAL;
+  const double top = (c->prec == BA_PREC_FP32_LOG) ? kFloor32Max : kFloor64;
+  if (!(nats >= kFloorMin && nats <= top))
+    return fail(c, BA_EINVAL, "floor must be in [" + std::to_string(int(kFloorMin)) + ", " +
+                                  std::to_string(int(top)) + "] nats for this precision");
+  c->floor = nats;
   drop_graph(c);
   return BA_OK;
 }

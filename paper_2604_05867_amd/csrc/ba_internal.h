@@ -27,6 +27,11 @@ constexpr int kTile = 8;        // instances handled together by one stream-engi
 constexpr double kLn2 = 0.69314718055994530942;
 constexpr double kFloor64 = 700.0;  // floor on log p, nats below the max (FP64)
 constexpr double kFloor32 = 80.0;   // floor on log p, nats below the max (FP32 iterates)
+constexpr double kFloor32Max = 87.0;  // largest FP32 floor: e^-87 is still a normal float
+// smallest floor: the floored mass, at most 2^20 e^-50 < 2.0e-16 of the total, stays
+// below FP64 resolution, so the bounds the kernels form from an iterate without
+// renormalising it after the floor are those of its normalised law
+constexpr double kFloorMin = 50.0;
 constexpr int kPartStride = 8;      // doubles per block record of a reduction
 constexpr int kMaxRedBlocks = 1024; // blocks per instance of a reduction
 // per-instance record buffer: block records [0, kMaxRedBlocks), a second set used

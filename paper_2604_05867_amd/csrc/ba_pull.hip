@@ -2,13 +2,17 @@
 // of y of p(x) emb(y, x), without atomics.
 //
 // A length-k output has N_k = sum_{i <= n-k} C(n, i) supersequences (Lemma 7).
-// Index i in [0, N_k) names one: w = the number of positions not used by the
-// leftmost embedding of y (the smallest w with i < sum_{j <= w} C(n, j)), S = the
-// (i - sum_{j < w} C(n, j))-th w-subset of the positions (Algorithm 5), and x is
-// built position by position (Algorithm 6): a position in S gets the complement
-// of the next symbol of y (of y's last symbol once y is complete), any other
-// position the next symbol of y, or y's last symbol once y is complete (the
-// printed algorithm's 0 there is not one-to-one).
+// Each supersequence x of y is named by a position set S with |S| <= n - k: the
+// positions that the leftmost embedding of y skips before it completes, together
+// with the positions after it whose symbol differs from y's last symbol.
+// Index i in [0, N_k) names one: w = |S| is the smallest w with
+// i < sum_{j <= w} C(n, j), and S is the (i - sum_{j < w} C(n, j))-th w-subset
+// in lexicographic order (the order of Section 5.1's unranking).  Given S, the
+// positions outside S carry y in order followed by copies of y's last symbol,
+// and every position in S carries the complement of the symbol at the next
+// position outside S (of y's last symbol if there is none), so the leftmost
+// embedding skips exactly S.  (The construction of Section 5.2 as printed writes 0
+// after the embedding instead of y's last symbol, which is not one-to-one.)
 //
 // Work decomposition: the supersequence indices of every output are cut into
 // chunks of kPullChunk; one thread takes one (output, chunk) item, runs the
@@ -50,32 +54,33 @@ __device__ __forceinline__ uint32_t supersequence_of(const PullPlan& P, uint32_t
   const int n = P.n;
   int w = 0;
   while (i >= P.cum[w + 1]) ++w;
-  uint32_t j = i - P.cum[w];
-  // Algorithm 5: positions in S, as a bit mask over positions 0..n-1
+  // S from its lexicographic rank j: the reflected set {n-1-s : s in S} has
+  // colexicographic rank C(n,w) - 1 - j in the combinatorial number system, read
+  // off greedily by the largest binomial C(c, t) that fits, t = w .. 1
+  uint32_t N = kBinom.c[n][w] - 1u - (i - P.cum[w]);
   uint32_t smask = 0;
-  for (int t = 0; t < n && w > 0; ++t) {
-    const uint32_t c = kBinom.c[n - t - 1][w - 1];
-    if (j < c) {
-      smask |= 1u << t;
-      --w;
-    } else {
-      j -= c;
-    }
+  int c = n - 1;
+  for (int t = w; t >= 1; --t) {
+    while (kBinom.c[c][t] > N) --c;  // stops at c = t - 1 at the latest: C(t-1, t) = 0
+    N -= kBinom.c[c][t];
+    smask |= 1u << (n - 1 - c);
+    --c;
   }
-  // Algorithm 6 with the tail fixed to y's last symbol
+  // right to left: `carry` is the symbol at the nearest position outside S seen so
+  // far (y's last symbol before any); outside S the m-th position (from the left)
+  // holds y_m, or y's last symbol for m >= k
   const uint32_t last = k > 0 ? (y & 1u) : 0u;
-  uint32_t x = 0;
-  int r = 0;
-  for (int pos = 0; pos < n; ++pos) {
-    const uint32_t next = r < k ? (y >> (k - 1 - r)) & 1u : last;
+  uint32_t carry = last, x = 0;
+  for (int pos = n - 1; pos >= 0; --pos) {
     uint32_t bit;
     if ((smask >> pos) & 1u) {
-      bit = 1u - next;
+      bit = 1u - carry;
     } else {
-      bit = next;
-      if (r < k) ++r;
+      const int m = pos - __popc(smask & ((1u << pos) - 1u));
+      bit = m < k ? (y >> (k - 1 - m)) & 1u : last;
+      carry = bit;
     }
-    x = (x << 1) | bit;
+    x |= bit << (n - 1 - pos);
   }
   return x;
 }

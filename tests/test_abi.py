@@ -58,11 +58,21 @@ def test_argument_errors(L):
     assert b"ba_bind" in L.ba_last_error(h)
     assert L.ba_set_engine(h, 5) == -1
     assert L.ba_set_engine(h, 0) == 0
+    # iterate floor: 50..700 nats for FP64 iterates
+    for bad in (0.0, 49.9, 701.0, float("nan"), float("inf")):
+        assert L.ba_set_floor(h, ctypes.c_double(bad)) == -1
+    assert L.ba_set_floor(h, ctypes.c_double(80.0)) == 0
+    assert L.ba_set_floor(h, ctypes.c_double(700.0)) == 0
     sz = ctypes.c_size_t()
     assert L.ba_workspace_bytes(h, ctypes.byref(sz)) == 0 and sz.value > 0
     assert L.ba_bind(h, None, sz.value, None) == -1
     assert L.ba_bind(h, ctypes.c_void_p(256), 16, None) == -2  # too small, checked before any device use
     L.ba_free(h)
+    h32 = ctypes.c_void_p()
+    assert L.ba_init_batch(2, n, d, 1, 50, ctypes.byref(h32)) == 0
+    assert L.ba_set_floor(h32, ctypes.c_double(88.0)) == -1   # e^-88 is below the normal floats
+    assert L.ba_set_floor(h32, ctypes.c_double(87.0)) == 0
+    L.ba_free(h32)
     L.ba_free(None)
     assert L.ba_strerror(-5) == b"non-finite value"
 

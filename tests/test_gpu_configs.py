@@ -174,21 +174,51 @@ def test_config4_mirror_ascent_vs_ba(ba):
 # config 5: n = 20, FP32 iterates, FP64 certification, orbit check
 # ---------------------------------------------------------------------------
 
-def test_config5_n20_properties(ba):
+def test_config5_n20_stopped_iterate_against_oracle_certification(ba, oracle_native):
+    """Config 5 (n = 20, d in {0.64, 0.80, 0.95}, FP32 log-domain iterates, FP64
+    certification every 50 iterations) run by ba_run toward a 1e-6-bit gap with a
+    cap of 2000 iterations.  At the iterate where it stopped:
+      - ba_bounds (the GPU's FP64 certification of the FP32 iterate) equals the
+        oracle's certify-only evaluation of the same law (every row of the channel
+        regenerated on the host) within 1e-9 bits, for L and U (Section 2.3: the
+        Blahut bounds hold for any full-support law);
+      - D(x) at every input (GPU FP64 evaluation of that law) equals the oracle's
+        within 1e-9 nats;
+      - the orbit check of Theorem 4 (Appendix A): the iterate from the uniform law
+        is invariant under complement and reversal;
+      - L <= U, C_n(d) <= n (1 - d), monotone in d, C_20 <= 2 C_10."""
+    import time
     n = 20
     ds = [0.64, 0.80, 0.95]
     ctx = ba.Context([n] * 3, ds, prec=ba.PREC_FP32_LOG, cert_every=50)
-    done = ctx.run(1e-6, 1500)
-    lo, hi, its = ctx.best_bounds()
-    say("config5: iters=%s L=%s U=%s" % (its, lo, hi))
+    done = ctx.run(1e-6, 2000)
+    lo, hi = ctx.bounds()
+    blo, bhi, its = ctx.best_bounds()
+    lp = ctx.get_logp().cpu().numpy().reshape(3, 1 << n)
+    say("config5: %d iterations, certified L=%s U=%s (best L=%s U=%s)" % (done, lo, hi, blo, bhi))
+    assert done == 2000 and its == [2000] * 3
+    t0 = time.time()
+    cert = oracle_native.certify(n, [bdc.length_weights(n, d) for d in ds], lp)
+    say("config5: oracle certification of the same iterates in %.1f s on %d threads: L=%s U=%s"
+        % (time.time() - t0, oracle_native.num_threads(), list(cert["L"] / LN2), list(cert["U"] / LN2)))
+    st = cert["stats"]
+    assert st["nnz"] == 2 * 3 ** n - 2 ** n and st["bad_rows"] == 0
     for i, d in enumerate(ds):
-        assert lo[i] <= hi[i]
-        assert hi[i] - lo[i] < 0.05
+        assert abs(lo[i] - cert["L"][i] / LN2) < 1e-9
+        assert abs(hi[i] - cert["U"][i] / LN2) < 1e-9
+        c1 = ba.Context(n, d)
+        ev = c1.eval(torch.from_numpy(lp[i]), want_r=False)
+        D = ev["D"].cpu().numpy()
+        err = float(np.max(np.abs(D - cert["D"][i])))
+        say("config5: d=%.2f  max |D_gpu - D_oracle| over all %d inputs = %.2e nats" % (d, 1 << n, err))
+        assert err < 1e-9
+        assert abs(ev["L"] - lo[i]) < 1e-9 and abs(ev["U"] - hi[i]) < 1e-9
+        c1.close()
+        assert lo[i] <= hi[i] and blo[i] <= bhi[i]
         assert lo[i] <= n * (1 - d) + 1e-12          # C_n(d) <= n C_1(d)
     for i in range(2):                                  # non-increasing in d
-        assert lo[i + 1] <= hi[i] + 1e-12
+        assert blo[i + 1] <= bhi[i] + 1e-12
     # orbit check (Theorem 4): the final FP32 iterate is cpl/rev invariant
-    lp = ctx.get_logp().cpu().numpy().reshape(3, 1 << n)
     cp, rv = cpl_rev_maps(n)
     for i in range(3):
         top = lp[i] > lp[i].max() - 30.0               # inputs that carry probability
@@ -199,7 +229,7 @@ def test_config5_n20_properties(ba):
     c10.run(1e-8, 50000)
     lo10, hi10, _ = c10.best_bounds()
     for i in range(3):
-        assert lo[i] <= 2 * hi10[i] + 1e-9
+        assert blo[i] <= 2 * hi10[i] + 1e-9
     c10.close()
     ctx.close()
 

@@ -366,6 +366,39 @@ def test_monotone_in_deletion_probability():
         prev = c
 
 
+def test_floored_iterates_keep_valid_bounds():
+    """The floored update (ba_update with floor_nats) keeps every log p within
+    floor_nats of the maximum, equals the plain update wherever the floor does not
+    bind, and the Blahut bounds of its iterates stay valid: every lower bound seen,
+    floored or not, is below every upper bound seen (each brackets the same
+    capacity)."""
+    n, d = 8, 0.8
+    W = bdc.channel_dense(n, d)
+    lp = bdc.uniform_logp(n)
+    plain = bdc.uniform_logp(n)
+    Ls, Us = [], []
+    floored_seen = 0
+    for t in range(1500):
+        ev = bdc.evaluate(W, lp)
+        Ls.append(ev.L)
+        Us.append(ev.U)
+        nxt = bdc.ba_update(lp, ev, floor_nats=50.0)
+        free = bdc.normalise_logp(lp) + ev.D - ev.L
+        assert np.all(nxt >= nxt.max() - 50.0 - 1e-12)
+        at_floor = free < free.max() - 50.0
+        assert np.array_equal(nxt[~at_floor], free[~at_floor])
+        floored_seen = max(floored_seen, int(at_floor.sum()))
+        lp = nxt
+        if t < 300:
+            evp = bdc.evaluate(W, plain)
+            Ls.append(evp.L)
+            Us.append(evp.U)
+            plain = bdc.ba_update(plain, evp)
+    assert floored_seen > 10
+    assert max(Ls) <= min(Us) + 1e-12
+    assert min(Us) - max(Ls) < 1e-3
+
+
 def test_certify_floor_keeps_bounds_finite():
     n = 5
     W = bdc.channel_dense(n, 0.6)
