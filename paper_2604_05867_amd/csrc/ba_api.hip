@@ -615,6 +615,10 @@ int ba_bind(ba_ctx* c, void* ws, size_t bytes, void* stream) {
     StreamExtra ex{};
     ex.h = reinterpret_cast<double*>(c->ws + gh.L.h);
     ex.hd = reinterpret_cast<double*>(c->ws + gh.L.hd);
+    // the init pass's fixed-point words (4 per input and instance) live in the FP64
+    // certification arrays c_lp .. c_v (at least 2 xs + 2 ys doubles per instance),
+    // which hold nothing yet
+    ex.fix = reinterpret_cast<unsigned long long*>(c->ws + gh.L.c_lp);
     HIPCHK(c, launch_stream<double>(kOpInit, gh.tb, gh.cert, 0, ex, s));
     if (c->prec == BA_PREC_FP32_LOG)
       HIPCHK(c, launch_to_float(reinterpret_cast<const double*>(c->ws + gh.L.h),

@@ -140,11 +140,43 @@ enum StreamOp { kOpScatter = 0, kOpGather = 1, kOpInit = 2, kOpRow = 3, kOpVerif
 struct StreamExtra {
   double* h;                  // init: H(x), stride xs
   double* hd;                 // init: Hd(x)
+  unsigned long long* fix;    // init: fixed-point accumulators, 4 words per input, stride 4 xs
   uint32_t target_x;          // row
   uint32_t* row_dense;        // row: dense counts by rank
   uint32_t* bins;             // verify: [2^n][n+2] length sums and nonzero counts
   unsigned long long* stats;  // verify: [6]
 };
+
+// ---- order-independent sums of doubles ---------------------------------------
+// A value v is split exactly into v = a 2^-40 + b 2^-80 + r with integers a, b
+// (0 <= b < 2^40, 0 <= r < 2^-80) and the integer parts are added with 64-bit
+// integer atomics, whose result does not depend on the order of the additions.
+// Used for sums of at most a few thousand terms with |sum| < 2^22 (H and the
+// scaled Hd of the init pass): no overflow, truncation below 2^-68 in total.
+constexpr double kFixScale = 1099511627776.0;  // 2^40
+
+__device__ __forceinline__ void fix_add(unsigned long long* w, double v) {
+  const double s = v * kFixScale;
+  const double a = floor(s);
+  const double b = floor((s - a) * kFixScale);
+  __hip_atomic_fetch_add(w, (unsigned long long)(long long)a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_fetch_add(w + 1, (unsigned long long)(long long)b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ double fix_value(const unsigned long long* w) {
+  return double((long long)w[0]) / kFixScale + double((long long)w[1]) / (kFixScale * kFixScale);
+}
+
+// Hd(x) = sum_y s_k w_k emb log emb is accumulated as Hd 2^-e with 2^e > max_k |s_k|,
+// so that each scaled term is bounded like the terms of H.
+__device__ __forceinline__ int hd_exponent(const Consts& c, int n) {
+  double smax = 0.0;
+  for (int k = 0; k <= n; ++k)
+    if (c.w[k] > 0.0) smax = fmax(smax, fabs(c.sw[k] / c.w[k]));
+  int e = 0;
+  if (smax > 0.0) (void)frexp(smax, &e);
+  return e > 0 ? e : 0;
+}
 
 // ---- launch wrappers (defined in the .hip files) ---------------------------
 

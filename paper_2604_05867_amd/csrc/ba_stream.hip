@@ -18,7 +18,8 @@
 //
 // Ops: scatter  r(y) += p(x) emb(y,x)   (outputs with |y| <= k0 in LDS first)
 //      gather   G(x) += emb(y,x) v(y)    (v in split layout V2[rank(y2)][rank(y1)])
-//      init     H(x) += w_k emb log emb, Hd(x) += s_k w_k emb log emb
+//      init     H(x) += w_k emb log emb, Hd(x) += s_k w_k emb log emb (fixed-point
+//               integer atomics: the same bits in every run)
 //      row      dense row of one x (parity hook)
 //      verify   per-row length sums and nonzero counts
 #include "ba_internal.h"
@@ -122,8 +123,10 @@ __global__ __launch_bounds__(kBlock) void k_stream(Tables tb, Group<T> g, int k0
 
   double wk[kNMax + 1], swk[kNMax + 1];
   if (OP == kOpInit) {
-    // only used for single-instance init launches (nbt == 1 enforced by the host)
-    for (int k = 0; k <= kNMax; ++k) { wk[k] = g.cs[b0].w[k]; swk[k] = g.cs[b0].sw[k]; }
+    // only used for single-instance init launches (nbt == 1 enforced by the host);
+    // s_k w_k is taken pre-scaled by 2^-e (see hd_exponent)
+    const int e = hd_exponent(g.cs[b0], g.n);
+    for (int k = 0; k <= kNMax; ++k) { wk[k] = g.cs[b0].w[k]; swk[k] = ldexp(g.cs[b0].sw[k], -e); }
   }
 
   for (uint32_t ch = cb + wave; ch < ce; ch += kBlock / kWave) {
@@ -269,8 +272,9 @@ __global__ __launch_bounds__(kBlock) void k_stream(Tables tb, Group<T> g, int k0
         if (b < nbt && ((live >> b) & 1u)) lds_add(&gs[b * X1 + x1], acc[b]);
     }
     if (OP == kOpInit && valid) {
-      atomic_add(&ex.h[(size_t)b0 * g.xs + x], ah);
-      atomic_add(&ex.hd[(size_t)b0 * g.xs + x], ahd);
+      // order-independent: H and Hd are the same bits in every run
+      fix_add(ex.fix + 2 * (size_t)x, ah);
+      fix_add(ex.fix + 2 * (g.xs + (size_t)x), ahd);
     }
   }
 
@@ -369,6 +373,19 @@ __global__ __launch_bounds__(1024) void k_row_compact(const uint32_t* dense, uin
   if (threadIdx.x == 0) *nnz_dev = base;
 }
 
+// H(x) and Hd(x) from the fixed-point words of the init pass (one thread per input).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fix_finish(Group<T> g, StreamExtra ex) {
+  const int b = blockIdx.y;
+  const uint32_t X = 1u << g.n;
+  const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= X) return;
+  const unsigned long long* w = ex.fix + (size_t)b * 4 * g.xs;
+  const int e = hd_exponent(g.cs[b], g.n);
+  ex.h[(size_t)b * g.xs + x] = fix_value(w + 2 * (size_t)x);
+  ex.hd[(size_t)b * g.xs + x] = ldexp(fix_value(w + 2 * (g.xs + (size_t)x)), e);
+}
+
 template <typename T, int OP>
 hipError_t launch_op(const Tables& tb, const Group<T>& g, int k0, const StreamExtra& ex, hipStream_t s) {
   const uint32_t X2 = 1u << tb.n2;
@@ -385,19 +402,22 @@ hipError_t launch_op(const Tables& tb, const Group<T>& g, int k0, const StreamEx
   if (OP == kOpScatter) lds = size_t((2u << k0) - 1u) * nbt * sizeof(T);
   if (OP == kOpGather) lds = size_t(1u << tb.n1) * nbt * sizeof(T);
   if (OP == kOpInit) {
-    // one instance per launch grid row: blockIdx.y selects the instance tile of size 1
-    Group<T> g1 = g;
+    // one launch per instance (its own weights); per-lane partial sums go to the
+    // fixed-point words, which k_fix_finish turns into H and Hd
+    hipError_t e = launch_fill_zero(ex.fix, (size_t)g.nb * g.xs * 32, s);
+    if (e != hipSuccess) return e;
     for (int b = 0; b < g.nb; ++b) {
-      Group<T> gb = g1;
+      Group<T> gb = g;
       gb.nb = 1;
       gb.st = g.st + b;
       gb.cs = g.cs + b;
       StreamExtra eb = ex;
-      eb.h = ex.h + (size_t)b * g.xs;
-      eb.hd = ex.hd + (size_t)b * g.xs;
+      eb.fix = ex.fix + (size_t)b * 4 * g.xs;
       hipLaunchKernelGGL((k_stream<T, OP>), dim3(X2 * parts, 1), dim3(kBlock), 0, s, tb, gb, k0,
                          parts, eb);
     }
+    const uint32_t X = 1u << g.n;
+    hipLaunchKernelGGL(k_fix_finish<T>, dim3((X + kBlock - 1) / kBlock, g.nb), dim3(kBlock), 0, s, g, ex);
     return hipGetLastError();
   }
   if (lds > 65536) {

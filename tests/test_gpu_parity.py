@@ -342,8 +342,7 @@ def test_graph_replay_matches_eager(ba, prec):
     c = ba.Context(ns, ds, prec=p, cert_every=20, stream=s)
     start = torch.cat([torch.full((1 << n,), 0.0, dtype=torch.float64) for n in ns])
     for graphs in (False, True):
-        # same context (H(x) is accumulated with atomics once per context) and the
-        # same starting state for both runs
+        # the same starting state for both runs
         c.set_graphs(graphs)
         with torch.cuda.stream(s):
             c.set_logp(start)
@@ -387,8 +386,7 @@ def test_factored_fusion_settings_agree(ba, n):
         assert np.allclose(out[0][2], o[2], rtol=1e-13, atol=0)
         assert np.allclose(out[0][3], o[3], atol=1e-12)
     # eight positions per launch are two four-position steps with the same sums in
-    # the same order: bitwise equal within one context (H is formed once per context
-    # with atomics, so it may differ in the last bits between contexts)
+    # the same order: bitwise equal
     c = ba.Context(n, d)
     same = []
     for fuse in (2, 3, 4, 5):
@@ -516,7 +514,7 @@ def test_fused_update_is_bitwise_separate(ba, prec):
     a step eta."""
     p = ba.PREC_FP64 if prec == "fp64" else ba.PREC_FP32_LOG
     ns, ds = ([12, 14], [0.6, 0.9]) if prec == "fp64" else ([16, 20], [0.7, 0.95])
-    # one context (H is formed once per context, with atomics), reset between runs
+    # one context, reset between runs
     c = ba.Context(ns, ds, prec=p)
     start = torch.tensor(np.concatenate([np.full(1 << m, -m * LN2) for m in ns]))
     for eta in (1.0, 1.8):
@@ -564,3 +562,35 @@ def test_fused_update_stops_at_tolerance(ba):
         assert its[0] == k
         assert hi[0] - lo[0] < tol
         assert np.max(np.abs(lp - lp_ref)) < 1e-10
+
+
+@pytest.mark.parametrize("case", ["fp64_batch", "fp32_n20", "exact"])
+def test_init_is_deterministic_across_contexts(ba, case):
+    """H(x) and Hd(x) (the init pass over every nonzero, Section 3's per-input
+    constant) are summed with order-independent fixed-point integer atomics, so two
+    contexts of the same instances give bitwise-identical H, iterates, certified
+    bounds and gradients (the factored engine has no atomics in its sweeps)."""
+    if case == "fp64_batch":
+        kw = dict(n=[12, 9, 12], d=[0.64, 0.3, 0.9], prec=ba.PREC_FP64)
+    elif case == "fp32_n20":
+        kw = dict(n=[20, 20], d=[0.64, 0.95], prec=ba.PREC_FP32_LOG)
+    else:
+        kw = dict(n=[10, 10], d=None, prec=ba.PREC_FP64, k=[3, 7])
+    res = []
+    for _ in range(2):
+        c = ba.Context(kw["n"], kw["d"], prec=kw["prec"], k=kw.get("k"))
+        c.step(25)
+        lo, hi = c.bounds()
+        lp = c.get_logp().cpu().numpy()
+        grad = None
+        if case == "fp64_batch":
+            theta = torch.from_numpy(inp.theta_normal(12, seed=5, sigma=0.3))
+            I, g, dd = c.grad(theta)
+            grad = (I, dd, g.cpu().numpy())
+        res.append((lo, hi, lp, grad))
+        c.close()
+    assert res[0][0] == res[1][0] and res[0][1] == res[1][1]
+    assert np.array_equal(res[0][2], res[1][2])
+    if res[0][3] is not None:
+        assert res[0][3][0] == res[1][3][0] and res[0][3][1] == res[1][3][1]
+        assert np.array_equal(res[0][3][2], res[1][3][2])

@@ -187,7 +187,7 @@ def test_symmetric_fused_update_is_bitwise_separate(ba, prec):
     p = ba.PREC_FP64 if prec == "fp64" else ba.PREC_FP32_LOG
     ns, ds = ([12, 14], [0.6, 0.9]) if prec == "fp64" else ([16, 20], [0.7, 0.95])
     say("symmetric fused update", prec)
-    # one context (H is formed once per context, with atomics), reset between runs
+    # one context, reset between runs
     c = ba.Context(ns, ds, prec=p)
     c.set_symmetry(True)
     start = torch.tensor(np.concatenate([np.full(1 << m, -m * LN2) for m in ns]))
