@@ -198,6 +198,21 @@ int ba_workspace_bytes(const ba_ctx *c, size_t *bytes);
  * too small, BA_EINVAL if the pointer is NULL or misaligned. */
 int ba_bind(ba_ctx *c, void *workspace_dev, size_t bytes, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): ba_bind without a
+ * workspace.  The context is bound to a device array owned by the library, one
+ * copy per GPU (32 MiB, held until the process ends), on the device current on the
+ * calling thread; hip_stream must belong to that device (may be NULL).  Enough for
+ * one FP64 instance up to n = 16 or a small batch: BA_ENOMEM, with the sizes in
+ * ba_last_error, if ba_workspace_bytes exceeds 32 MiB.  Does what ba_bind does
+ * (count tables, constants, H, uniform start; everything the iterations read is
+ * written first, so the array's previous contents do not matter) and calls no
+ * device allocation routine.  Every context bound this way on one GPU shares that
+ * GPU's array: binding one takes it from the previous one, whose later calls
+ * return BA_ESTATE until it is bound again, and calls that overlap on one GPU race.
+ * ba_bind or ba_free releases the array. */
+int ba_bind_static(ba_ctx *c, void *hip_stream);
+
 /* ---- iteration ---------------------------------------------------------------- */
 
 /* Queue `iters` >= 0 BA iterations (Section 2.3: output law, refined input law,

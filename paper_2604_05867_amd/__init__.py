@@ -55,6 +55,7 @@ def lib():
     L.ba_free.restype = None
     L.ba_workspace_bytes.argtypes = [vp, ctypes.POINTER(sz)]
     L.ba_bind.argtypes = [vp, vp, sz, vp]
+    L.ba_bind_static.argtypes = [vp, vp]
     L.ba_step.argtypes = [vp, i32]
     L.ba_run.argtypes = [vp, f64, i32, pi32]
     L.ba_bounds.argtypes = [vp, pf64, pf64]

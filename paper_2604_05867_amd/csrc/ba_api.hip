@@ -10,6 +10,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -18,6 +19,12 @@
 #include "ba_internal.h"
 
 using namespace ba;
+
+// Device memory owned by the library for ba_bind_static: one copy of this array
+// per GPU, alive until the process ends.  In host code its name is only a
+// stand-in; the device address is obtained with hipGetSymbolAddress per device.
+constexpr size_t kStaticScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
 
 namespace {
 
@@ -65,6 +72,7 @@ struct ba_ctx {
   size_t ws_bytes = 0;
   hipStream_t stream = nullptr;
   bool bound = false;
+  int static_dev = -1;   // device whose static scratch this context is bound to, else -1
   std::string err;
   // tuning
   int scatter_lds_kb = 64;
@@ -488,9 +496,40 @@ void drop_graph(ba_ctx* c) {
   c->gengine = -1;
 }
 
+// Per-device address of `scratch` (set once per device by hipGetSymbolAddress with
+// that device current) and the context currently bound to it.
+constexpr int kMaxDevices = 64;
+struct StaticScratch {
+  std::mutex mu;
+  void* ptr[kMaxDevices] = {};
+  const ba_ctx* owner[kMaxDevices] = {};
+};
+StaticScratch& static_scratch() {
+  static StaticScratch s;
+  return s;
+}
+
+// Give up this context's claim on a device's static scratch (if it holds one).
+void release_static(ba_ctx* c) {
+  if (c->static_dev < 0) return;
+  StaticScratch& S = static_scratch();
+  std::lock_guard<std::mutex> lock(S.mu);
+  if (S.owner[c->static_dev] == c) S.owner[c->static_dev] = nullptr;
+  c->static_dev = -1;
+}
+
 int check_ctx(ba_ctx* c) {
   if (!c) return BA_EINVAL;
   if (!c->bound) return fail(c, BA_ESTATE, "context is not bound to a workspace (call ba_bind)");
+  if (c->static_dev >= 0) {
+    StaticScratch& S = static_scratch();
+    std::lock_guard<std::mutex> lock(S.mu);
+    if (S.owner[c->static_dev] != c) {
+      c->bound = false;
+      return fail(c, BA_ESTATE, "the library's static workspace on device " + std::to_string(c->static_dev) +
+                                    " was bound to another context since (bind this one again)");
+    }
+  }
   return BA_OK;
 }
 
@@ -574,6 +613,7 @@ int ba_set_graphs(ba_ctx* c, int enable) {
 
 void ba_free(ba_ctx* c) {
   if (!c) return;
+  release_static(c);
   drop_graph(c);
   for (auto e : c->ev) (void)hipEventDestroy(e);
   delete c;
@@ -585,9 +625,11 @@ int ba_workspace_bytes(const ba_ctx* c, size_t* bytes) {
   return BA_OK;
 }
 
-int ba_bind(ba_ctx* c, void* ws, size_t bytes, void* stream) {
-  if (!c || !ws || (reinterpret_cast<uintptr_t>(ws) & 255u)) return fail(c, BA_EINVAL, "workspace pointer NULL or not 256-byte aligned");
-  if (bytes < c->need) return fail(c, BA_ENOMEM, "workspace smaller than ba_workspace_bytes");
+namespace {
+
+// Lay the context out in `ws` and build its count tables, constants, H and start
+// states on `stream` (every array the iterations read is written here first).
+int bind_workspace(ba_ctx* c, void* ws, size_t bytes, void* stream) {
   drop_graph(c);
   c->ws = static_cast<char*>(ws);
   c->ws_bytes = bytes;
@@ -631,6 +673,44 @@ int ba_bind(ba_ctx* c, void* ws, size_t bytes, void* stream) {
   HIPCHK(c, hipStreamSynchronize(s));
   c->bound = true;
   return BA_OK;
+}
+
+}  // namespace
+
+int ba_bind(ba_ctx* c, void* ws, size_t bytes, void* stream) {
+  if (!c || !ws || (reinterpret_cast<uintptr_t>(ws) & 255u)) return fail(c, BA_EINVAL, "workspace pointer NULL or not 256-byte aligned");
+  if (bytes < c->need) return fail(c, BA_ENOMEM, "workspace smaller than ba_workspace_bytes");
+  release_static(c);
+  return bind_workspace(c, ws, bytes, stream);
+}
+
+int ba_bind_static(ba_ctx* c, void* stream) {
+  if (!c) return BA_EINVAL;
+  if (c->need > kStaticScratchBytes)
+    return fail(c, BA_ENOMEM, "context needs " + std::to_string(c->need) + " bytes of workspace; the static workspace "
+                              "holds " + std::to_string(kStaticScratchBytes) + " (use ba_bind)");
+  int dev = -1;
+  HIPCHK(c, hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(c, BA_EDEVICE, "device index out of range for the static workspace");
+  void* ptr = nullptr;
+  {
+    StaticScratch& S = static_scratch();
+    std::lock_guard<std::mutex> lock(S.mu);
+    if (!S.ptr[dev]) {
+      void* p = nullptr;
+      HIPCHK(c, hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+      if (!p || (reinterpret_cast<uintptr_t>(p) & 255u))
+        return fail(c, BA_EDEVICE, "static workspace address missing or not 256-byte aligned");
+      S.ptr[dev] = p;
+    }
+    ptr = S.ptr[dev];
+    if (c->static_dev >= 0 && S.owner[c->static_dev] == c) S.owner[c->static_dev] = nullptr;
+    S.owner[dev] = c;  // a context bound here before loses it (its next call: BA_ESTATE)
+    c->static_dev = dev;
+  }
+  const int rc = bind_workspace(c, ptr, kStaticScratchBytes, stream);
+  if (rc) release_static(c);
+  return rc;
 }
 
 int ba_step(ba_ctx* c, int iters) {
