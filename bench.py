@@ -255,10 +255,12 @@ def run_segments(ctx, gap_bits, cap, seg, tag, current=False):
     return done
 
 
-def config3(cap, gap_bits, plain_limit_s, plain_graphs=False, symmetric=False):
+def config3(cap, gap_bits, plain_limit_s, plain_graphs=False, symmetric=False, plain_floor=None):
     """Batched FP32 (one graph, 128 instances) against plain FP64 one instance at a
     time, both to a certified gap < gap_bits or the iteration cap.  Prints one JSON
-    line with both wall times and the speedup at equal certified gap."""
+    line with both wall times and the speedup at equal certified gap.  plain_floor
+    (nats): floor of the plain FP64 iterates' log p (the FP32 iterates' 80 makes the
+    two sides iterate the same floored map; None keeps the FP64 default, 700)."""
     import numpy as np
     import torch
 
@@ -299,6 +301,8 @@ def config3(cap, gap_bits, plain_limit_s, plain_graphs=False, symmetric=False):
         ps = torch.cuda.Stream() if plain_graphs else torch.cuda.current_stream()
         c = ba.Context(n, d, prec=ba.PREC_FP64, engine=ba.ENGINE_FACTORED, stream=ps)
         c.set_stop_rule(ba.STOP_BEST)
+        if plain_floor is not None:
+            c.set_floor(plain_floor)
         if symmetric:
             c.set_symmetry(True)
         c.set_graphs(plain_graphs)
@@ -307,9 +311,11 @@ def config3(cap, gap_bits, plain_limit_s, plain_graphs=False, symmetric=False):
         with torch.cuda.stream(ps):
             c.run(target * (1 + 1e-9), cap)
         torch.cuda.synchronize()
-        t_plain += time.perf_counter() - t0
+        ti = time.perf_counter() - t0
+        t_plain += ti
         lo, hi, it = c.best_bounds()
-        plain.append({"i": i, "n": n, "d": d, "iters": it[0], "L": lo[0], "U": hi[0]})
+        plain.append({"i": i, "n": n, "d": d, "iters": it[0], "L": lo[0], "U": hi[0], "t_s": ti,
+                      "reached_batched_gap": hi[0] - lo[0] <= target * (1 + 1e-9)})
         c.close()
         print("config3: plain %d/%d n=%d d=%.3f iters=%d gap=%.2e" % (count_done + 1, len(ns), n, d, it[0],
                                                                       hi[0] - lo[0]),
@@ -321,16 +327,19 @@ def config3(cap, gap_bits, plain_limit_s, plain_graphs=False, symmetric=False):
     out = {
         "metric": "batched FP32 vs plain FP64 speedup at equal certified gap",
         "stop_rule": "best certified bounds so far", "plain_graphs": plain_graphs,
+        "floor_nats": {"batched_fp32": 80.0, "plain_fp64": plain_floor if plain_floor is not None else 700.0},
         "kernels": ("factored, default launch plan, complement-symmetric (both sides)" if symmetric
                     else "factored, default launch plan (both sides)"),
         "gap_bits": gap_bits, "cap": cap, "instances": len(ns), "plain_instances_timed": m,
         "t_batched_s": t_batch, "t_plain_s_timed": t_plain,
         "speedup": (t_plain / share) / t_batch if m else None,
+        "speedup_is_extrapolated": m < len(ns),
         "batched": [{"n": n, "d": d, "iters": it, "L": l, "U": h} for n, d, it, l, h in zip(ns, ds, it_b, lo_b, hi_b)],
         "plain": plain,
         "max_abs_L_diff_bits": max((abs(p["L"] - lo_b[p["i"]]) for p in plain), default=None),
         "max_abs_U_diff_bits": max((abs(p["U"] - hi_b[p["i"]]) for p in plain), default=None),
         "converged_batched": int(np.sum(np.array(hi_b) - np.array(lo_b) < gap_bits)),
+        "plain_reached_batched_gap": int(sum(1 for p in plain if p["reached_batched_gap"])),
     }
     print(json.dumps(out))
 
@@ -388,6 +397,8 @@ def main():
     ap.add_argument("--plain-limit-s", type=float, default=600.0)
     ap.add_argument("--step-compare", action="store_true",
                     help="iterations to the gap for update steps 1, 1.5, 2 (several minutes)")
+    ap.add_argument("--plain-floor", type=float, default=80.0,
+                    help="config3: floor (nats) of the plain FP64 iterates; <= 0 keeps the FP64 default (700)")
     ap.add_argument("--plain-graphs", action="store_true",
                     help="config3: replay the plain FP64 runs as graphs too")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -403,7 +414,8 @@ def main():
         print(json.dumps({"copy_bytes": a.numel() * 4}))
         return
     if args.config3:
-        config3(args.cap, args.gap, args.plain_limit_s, args.plain_graphs, args.config3_symmetric)
+        config3(args.cap, args.gap, args.plain_limit_s, args.plain_graphs, args.config3_symmetric,
+                None if args.plain_floor <= 0 else args.plain_floor)
         return
     if args.step_compare:
         step_compare(args.cap, args.gap, (1.0, 1.5, 2.0))

@@ -178,7 +178,13 @@ enum {
    * backward's first n mod 4 two or one at a time), 1 two, 0 one.  The
    * complement-symmetric kernels take at most level 4 in the forward sweep and 3 in
    * the backward sweep. */
-  BA_TUNE_FACTORED_FUSE = 1
+  BA_TUNE_FACTORED_FUSE = 1,
+  /* BA_TUNE_CONCURRENT_GROUPS: 1 (default) gives every group of instances (one
+   * length n) its own branch of the graph that ba_run captures (ba_set_graphs), so
+   * the groups' launches run concurrently; 0 captures them one group after another
+   * on the bound stream.  The iterates are the same either way (groups share no
+   * arrays).  Eager launches (ba_step) always use the bound stream. */
+  BA_TUNE_CONCURRENT_GROUPS = 2
 };
 int ba_set_tuning(ba_ctx *c, int key, int value);
 

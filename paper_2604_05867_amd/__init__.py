@@ -26,6 +26,7 @@ ENGINE_STREAM, ENGINE_FACTORED, ENGINE_PULL = 0, 1, 2
 KCLASS = ("sweep1", "logr", "sweep2", "reduce", "update")
 TUNE_SCATTER_LDS_KB = 0
 TUNE_FACTORED_FUSE = 1
+TUNE_CONCURRENT_GROUPS = 2
 STOP_ITERATE, STOP_BEST = 0, 1
 
 _lib = None

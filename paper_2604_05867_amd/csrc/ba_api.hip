@@ -90,6 +90,11 @@ struct ba_ctx {
   int frz_override = -1;
   // one graph per frozen-flag mode (index = frz)
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  // captured chunks: each group of instances (one n) on its own branch of the graph
+  int concurrent = 1;
+  std::vector<hipStream_t> aux;      // one per group, default priority
+  std::vector<hipEvent_t> join_ev;   // one per group
+  hipEvent_t fork_ev = nullptr;
   int gchunk = -1;
   int gengine = -1;
   // timing hook
@@ -589,6 +594,12 @@ int ba_set_tuning(ba_ctx* c, int key, int value) {
     drop_graph(c);
     return BA_OK;
   }
+  if (key == BA_TUNE_CONCURRENT_GROUPS) {
+    if (value != 0 && value != 1) return fail(c, BA_EINVAL, "concurrent groups must be 0 or 1");
+    c->concurrent = value;
+    drop_graph(c);
+    return BA_OK;
+  }
   if (key == BA_TUNE_FACTORED_FUSE) {
     if (value < 0 || value > 5) return fail(c, BA_EINVAL, "fuse must be 0 .. 5");
     c->fuse = value;
@@ -615,6 +626,9 @@ void ba_free(ba_ctx* c) {
   if (!c) return;
   release_static(c);
   drop_graph(c);
+  for (auto e : c->join_ev) (void)hipEventDestroy(e);
+  if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
+  for (auto st : c->aux) (void)hipStreamDestroy(st);
   for (auto e : c->ev) (void)hipEventDestroy(e);
   delete c;
 }
@@ -713,6 +727,72 @@ int ba_bind_static(ba_ctx* c, void* stream) {
   return rc;
 }
 
+namespace {
+
+// `iters` iterations of one group, each update but the last fused into the next
+// iteration's first launch where possible (the group's launches in ba_step's order).
+int step_group(ba_ctx* c, GroupHost& gh, int iters) {
+  const bool fu = update_fusable(c, gh);
+  for (int it = 0; it < iters; ++it) {
+    const bool in = fu && it > 0, out = fu && it + 1 < iters;
+    const int rc = (c->prec == BA_PREC_FP32_LOG) ? iterate_group<float>(c, gh, gh.gf, in, out)
+                                                 : iterate_group<double>(c, gh, gh.gd, in, out);
+    if (rc) return rc;
+  }
+  return BA_OK;
+}
+
+// Streams and events that give each group its own branch of a captured chunk
+// (created once, outside any capture).
+int ensure_branches(ba_ctx* c) {
+  const size_t ng = c->groups.size();
+  if (!c->fork_ev) HIPCHK(c, hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
+  while (c->aux.size() < ng) {
+    hipStream_t st = nullptr;
+    HIPCHK(c, hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    c->aux.push_back(st);
+  }
+  while (c->join_ev.size() < ng) {
+    hipEvent_t e = nullptr;
+    HIPCHK(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    c->join_ev.push_back(e);
+  }
+  return BA_OK;
+}
+
+// One chunk of ba_run inside a capture on c->stream: k iterations and, for FP32
+// iterates, the FP64 certification.  With several groups and concurrency on, every
+// group's work goes on its own stream forked from and joined back into c->stream,
+// so the graph holds one independent branch per group and the short launches of
+// the small groups overlap the long ones of the large groups.
+int capture_chunk(ba_ctx* c, int k) {
+  if (!(c->concurrent && c->groups.size() > 1)) {
+    int rc = ba_step(c, k);
+    if (!rc && c->prec == BA_PREC_FP32_LOG) rc = certify_all(c, 1);
+    return rc;
+  }
+  hipStream_t main = c->stream;
+  HIPCHK(c, hipEventRecord(c->fork_ev, main));
+  int rc = BA_OK;
+  for (size_t gi = 0; gi < c->groups.size() && !rc; ++gi) {
+    GroupHost& gh = c->groups[gi];
+    hipStream_t br = c->aux[gi];
+    HIPCHK(c, hipStreamWaitEvent(br, c->fork_ev, 0));
+    c->stream = br;
+    rc = step_group(c, gh, k);
+    if (!rc && c->prec == BA_PREC_FP32_LOG)
+      rc = certify_group<float>(c, gh, gh.gf, gh.cert, gh.gf.st, 1);
+    c->stream = main;
+    if (rc) break;
+    HIPCHK(c, hipEventRecord(c->join_ev[gi], br));
+    HIPCHK(c, hipStreamWaitEvent(main, c->join_ev[gi], 0));
+  }
+  c->stream = main;
+  return rc;
+}
+
+}  // namespace
+
 int ba_step(ba_ctx* c, int iters) {
   int rc = check_ctx(c);
   if (rc) return rc;
@@ -757,6 +837,7 @@ int ba_run(ba_ctx* c, double gap_bits, int max_iters, int* iters_done) {
   bool all = false;
   if (c->use_graph && !c->stream)
     return fail(c, BA_ESTATE, "graph capture needs a non-null stream (bind one)");
+  if (c->use_graph && c->concurrent && c->groups.size() > 1 && (rc = ensure_branches(c))) return rc;
   // the sweeps skip the frozen-flag test while no instance is frozen (the host
   // knows from the states it reads after every chunk)
   auto any_frozen = [&]() {
@@ -777,8 +858,7 @@ int ba_run(ba_ctx* c, double gap_bits, int max_iters, int* iters_done) {
       if (!c->gexec[frz]) {
         hipGraph_t graph = nullptr;
         HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-        int rc2 = ba_step(c, k);
-        if (!rc2 && c->prec == BA_PREC_FP32_LOG) rc2 = certify_all(c, 1);
+        const int rc2 = capture_chunk(c, k);
         hipError_t ec = hipStreamEndCapture(c->stream, &graph);
         if (rc2) { if (graph) (void)hipGraphDestroy(graph); return rc2; }
         HIPCHK(c, ec);

@@ -594,3 +594,31 @@ def test_init_is_deterministic_across_contexts(ba, case):
     if res[0][3] is not None:
         assert res[0][3][0] == res[1][3][0] and res[0][3][1] == res[1][3][1]
         assert np.array_equal(res[0][3][2], res[1][3][2])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_concurrent_group_branches_are_bitwise(ba, prec):
+    """ba_run's captured chunk with one graph branch per group (n) gives bitwise the
+    iterates, certified and best bounds of the same chunk captured group after group,
+    and of eager launches: the groups share no arrays."""
+    ns = [10, 12, 14, 10, 12, 14]
+    ds = [0.64, 0.7, 0.8, 0.9, 0.95, 0.66]
+    p = ba.PREC_FP64 if prec == "fp64" else ba.PREC_FP32_LOG
+    out = []
+    for mode in ("eager", "sequential", "concurrent"):
+        s = torch.cuda.Stream()
+        c = ba.Context(ns, ds, prec=p, cert_every=25, stream=s)
+        c.set_graphs(mode != "eager")
+        c.set_tuning(ba.TUNE_CONCURRENT_GROUPS, 1 if mode == "concurrent" else 0)
+        with torch.cuda.stream(s):
+            done = c.run(1e-5, 300)
+            lo, hi, its = c.best_bounds()
+            clo, chi = c.bounds()
+            lp = c.get_logp().cpu().numpy()
+        s.synchronize()
+        out.append((done, lo, hi, its, clo, chi, lp))
+        c.close()
+    for o in out[1:]:
+        assert o[0] == out[0][0] and o[3] == out[0][3]
+        assert o[1] == out[0][1] and o[2] == out[0][2] and o[4] == out[0][4] and o[5] == out[0][5]
+        assert np.array_equal(o[6], out[0][6])
