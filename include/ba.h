@@ -184,7 +184,14 @@ enum {
    * the groups' launches run concurrently; 0 captures them one group after another
    * on the bound stream.  The iterates are the same either way (groups share no
    * arrays).  Eager launches (ba_step) always use the bound stream. */
-  BA_TUNE_CONCURRENT_GROUPS = 2
+  BA_TUNE_CONCURRENT_GROUPS = 2,
+  /* BA_TUNE_PERSISTENT: 1 (default) runs all iterations of one ba_step call (or of
+   * one ba_run chunk) of a group with n <= 13 (FP32 iterates) or n <= 12 (FP64) as
+   * one launch: one block per instance iterates it with every intermediate array in
+   * LDS, one input position per stage (factored engine, not with ba_set_symmetry;
+   * timed as BA_K_SWEEP1 by ba_time_kernels).  0 uses the launch chain.  Same
+   * iteration up to the order of additions. */
+  BA_TUNE_PERSISTENT = 3
 };
 int ba_set_tuning(ba_ctx *c, int key, int value);
 

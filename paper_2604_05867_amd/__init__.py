@@ -27,6 +27,7 @@ KCLASS = ("sweep1", "logr", "sweep2", "reduce", "update")
 TUNE_SCATTER_LDS_KB = 0
 TUNE_FACTORED_FUSE = 1
 TUNE_CONCURRENT_GROUPS = 2
+TUNE_PERSISTENT = 3
 STOP_ITERATE, STOP_BEST = 0, 1
 
 _lib = None

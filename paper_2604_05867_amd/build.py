@@ -14,7 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libba.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["ba_tables.hip", "ba_stream.hip", "ba_pull.hip", "ba_factored.hip", "ba_symmetric.hip", "ba_reduce.hip", "ba_api.hip"]
+SOURCES = ["ba_tables.hip", "ba_stream.hip", "ba_pull.hip", "ba_factored.hip", "ba_symmetric.hip", "ba_reduce.hip", "ba_persist.hip",
+           "ba_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

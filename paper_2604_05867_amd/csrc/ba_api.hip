@@ -92,6 +92,8 @@ struct ba_ctx {
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   // captured chunks: each group of instances (one n) on its own branch of the graph
   int concurrent = 1;
+  // groups small enough for LDS iterate in one persistent launch per call/chunk
+  int persistent = 1;
   std::vector<hipStream_t> aux;      // one per group, default priority
   std::vector<hipEvent_t> join_ev;   // one per group
   hipEvent_t fork_ev = nullptr;
@@ -594,6 +596,12 @@ int ba_set_tuning(ba_ctx* c, int key, int value) {
     drop_graph(c);
     return BA_OK;
   }
+  if (key == BA_TUNE_PERSISTENT) {
+    if (value != 0 && value != 1) return fail(c, BA_EINVAL, "persistent must be 0 or 1");
+    c->persistent = value;
+    drop_graph(c);
+    return BA_OK;
+  }
   if (key == BA_TUNE_CONCURRENT_GROUPS) {
     if (value != 0 && value != 1) return fail(c, BA_EINVAL, "concurrent groups must be 0 or 1");
     c->concurrent = value;
@@ -729,9 +737,32 @@ int ba_bind_static(ba_ctx* c, void* stream) {
 
 namespace {
 
-// `iters` iterations of one group, each update but the last fused into the next
-// iteration's first launch where possible (the group's launches in ba_step's order).
+// Whether a group's iterations run as one persistent launch (ba_persist.hip): the
+// factored engine's products, without the complement-symmetric kernels, for groups
+// whose arrays fit in LDS.
+bool use_persist(const ba_ctx* c, const GroupHost& gh) {
+  return c->persistent && c->engine == BA_ENGINE_FACTORED && !sym_active(c, gh.n) &&
+         persist_supported(gh.n, elem(c));
+}
+
+// `iters` iterations of one group: one persistent launch, or the launch chain with
+// each update but the last fused into the next iteration's first launch where
+// possible.
 int step_group(ba_ctx* c, GroupHost& gh, int iters) {
+  if (iters > 0 && use_persist(c, gh)) {
+    Timer t(c, BA_K_SWEEP1, 1);
+    const double floor = iterate_floor(c);
+    if (c->prec == BA_PREC_FP32_LOG) {
+      Group<float> G = gh.gf;
+      G.eta = c->eta;
+      HIPCHK(c, launch_persist<float>(G, iters, floor, 0, c->stream));
+    } else {
+      Group<double> G = gh.gd;
+      G.eta = c->eta;
+      HIPCHK(c, launch_persist<double>(G, iters, floor, 1, c->stream));
+    }
+    return BA_OK;
+  }
   const bool fu = update_fusable(c, gh);
   for (int it = 0; it < iters; ++it) {
     const bool in = fu && it > 0, out = fu && it + 1 < iters;
@@ -797,17 +828,11 @@ int ba_step(ba_ctx* c, int iters) {
   int rc = check_ctx(c);
   if (rc) return rc;
   if (iters < 0) return fail(c, BA_EINVAL, "iters < 0");
-  // within one call, the update of every iteration but the last is fused into the
-  // next iteration's first launch where possible; the call ends with log p and p
-  // of the last iterate in place
-  for (int it = 0; it < iters; ++it)
-    for (auto& gh : c->groups) {
-      const bool fu = update_fusable(c, gh);
-      const bool in = fu && it > 0, out = fu && it + 1 < iters;
-      rc = (c->prec == BA_PREC_FP32_LOG) ? iterate_group<float>(c, gh, gh.gf, in, out)
-                                         : iterate_group<double>(c, gh, gh.gd, in, out);
-      if (rc) return rc;
-    }
+  // group after group (they share no arrays); within one call, the update of every
+  // iteration but the last is fused into the next iteration's first launch where
+  // possible; the call ends with log p and p of the last iterate in place
+  for (auto& gh : c->groups)
+    if ((rc = step_group(c, gh, iters))) return rc;
   return BA_OK;
 }
 

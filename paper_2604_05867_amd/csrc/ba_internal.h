@@ -180,6 +180,12 @@ __device__ __forceinline__ int hd_exponent(const Consts& c, int n) {
 
 // ---- launch wrappers (defined in the .hip files) ---------------------------
 
+// ba_persist.hip: `iters` iterations of every instance of a small group in one launch
+// (one block per instance, all arrays in LDS); n <= 13 (FP32) or 12 (FP64).
+bool persist_supported(int n, size_t esz);
+template <typename T>
+hipError_t launch_persist(const Group<T>& g, int iters, double floor, int check_tol, hipStream_t s);
+
 // ba_tables.hip
 size_t table_bytes(int n);
 hipError_t build_tables(int n, void* mem, hipStream_t s, Tables* out_host);

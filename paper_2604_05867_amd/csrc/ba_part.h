@@ -151,11 +151,12 @@ struct UpdateParams {
   bool step, stop;
 };
 
+// From the instance's final record P (any caller that holds it).
 template <typename T>
-__device__ __forceinline__ UpdateParams update_params(const Group<T>& g, int b, int check_tol, bool writer) {
+__device__ __forceinline__ UpdateParams update_params_rec(const Group<T>& g, int b, const Part& P, int check_tol,
+                                                          bool writer) {
   State* st = g.st + b;
-  const double* q = g.part + (size_t)b * g.ps + kFinalRec;
-  const double m = q[0], s = q[1], dmax = q[2], pi = q[3], m2 = q[5], s2 = q[6];
+  const double m = P.m, s = P.s, dmax = P.dmax, pi = P.i, m2 = P.m2, s2 = P.s2;
   const double L = m + log(s);
   const double U = dmax;
   // normaliser of the step: L itself for eta = 1 (BA)
@@ -184,6 +185,14 @@ __device__ __forceinline__ UpdateParams update_params(const Group<T>& g, int b, 
     }
   }
   return UpdateParams{L, Le, Mn, step, stop};
+}
+
+// From the final record that an earlier kernel stored at kFinalRec.
+template <typename T>
+__device__ __forceinline__ UpdateParams update_params(const Group<T>& g, int b, int check_tol, bool writer) {
+  const double* q = g.part + (size_t)b * g.ps + kFinalRec;
+  const Part P{q[0], q[1], q[2], q[3], q[4], q[5], q[6]};
+  return update_params_rec<T>(g, b, P, check_tol, writer);
 }
 
 // New log p of one input: max(log p + D - L, lo), or log p + eta D - Le with a step.

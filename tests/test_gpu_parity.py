@@ -32,6 +32,18 @@ def engine_id(ba, name):
     return {"factored": ba.ENGINE_FACTORED, "stream": ba.ENGINE_STREAM, "pull": ba.ENGINE_PULL}[name]
 
 
+def chain(ctx):
+    """Use the launch chain even for groups small enough for the persistent kernel
+    (tests of the chain's launch plans)."""
+    ctx.set_tuning(ctx_mod().TUNE_PERSISTENT, 0)
+    return ctx
+
+
+def ctx_mod():
+    import paper_2604_05867_amd as m
+    return m
+
+
 def say(*a):
     print(*a, flush=True)
 
@@ -162,12 +174,14 @@ def test_eval_product_law_sampled_n20(ba, oracle_native, engine):
 # iterations
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("engine", ENGINES)
+@pytest.mark.parametrize("engine", list(ENGINES) + ["persistent"])
 @pytest.mark.parametrize("n,d,iters", [(2, 0.5, 40), (8, 0.5, 25), (11, 0.7, 10)])
 def test_fp64_iterates_match_oracle(ba, engine, n, d, iters):
     say("iterates n=%d %s" % (n, engine))
     W = bdc.channel_dense(n, d)
-    ctx = ba.Context(n, d, engine=engine_id(ba, engine))
+    ctx = ba.Context(n, d, engine=engine_id(ba, "factored" if engine == "persistent" else engine))
+    if engine == "factored":
+        chain(ctx)
     ctx.step(iters)
     lp_g = ctx.get_logp().cpu().numpy()
     lp_o = bdc.ba_iterate(W, bdc.uniform_logp(n), iters)
@@ -178,13 +192,17 @@ def test_fp64_iterates_match_oracle(ba, engine, n, d, iters):
     ctx.close()
 
 
-def test_config1_n8_to_1e9(ba):
+@pytest.mark.parametrize("path", ["chain", "persistent"])
+def test_config1_n8_to_1e9(ba, path):
     """n = 8, d = 0.5, FP64 until the gap is below 1e-9 bits, against the oracle's
-    BA with the same stopping rule (Section 2.3)."""
+    BA with the same stopping rule (Section 2.3), with the launch chain and with
+    the persistent launch (which tests the gap of every iterate in the kernel)."""
     n, d = 8, 0.5
     W = bdc.channel_dense(n, d)
     res = bdc.ba(W, n, tol_bits=1e-9, max_iters=20000)
     ctx = ba.Context(n, d)
+    if path == "chain":
+        chain(ctx)
     done = ctx.run(1e-9, 20000)
     lo, hi, its = ctx.best_bounds()
     say("C1: gpu iters=%d oracle iters=%d" % (its[0], res.iters))
@@ -408,7 +426,7 @@ def test_four_position_backward_iterates(ba, n):
     one) equal those with two, FP64."""
     out = []
     for fuse in (1, 2):
-        c = ba.Context(n, 0.65)
+        c = chain(ba.Context(n, 0.65))
         c.set_tuning(ba.TUNE_FACTORED_FUSE, fuse)
         c.step(20)
         out.append((c.get_logp().cpu().numpy(), c.bounds()))
@@ -425,7 +443,7 @@ def test_eight_position_backward_is_bitwise_four(ba, n, prec):
     ns = [n] * 3 if prec == "fp32" else [n]
     ds = [0.64, 0.8, 0.95] if prec == "fp32" else [0.7]
     # one context (the same H), reset to the uniform law between the two runs
-    c = ba.Context(ns, ds, prec=p)
+    c = chain(ba.Context(ns, ds, prec=p))
     X = sum(1 << m for m in ns)
     start = torch.tensor(np.concatenate([np.full(1 << m, -m * LN2) for m in ns]))
     out = []
@@ -449,7 +467,7 @@ def test_first_eight_forward_is_bitwise_four(ba, n, prec):
     ns = [n] * 3 if prec == "fp32" else [n]
     ds = [0.64, 0.8, 0.95] if prec == "fp32" else [0.7]
     say("first eight forward n=%d %s" % (n, prec))
-    c = ba.Context(ns, ds, prec=p)
+    c = chain(ba.Context(ns, ds, prec=p))
     start = torch.tensor(np.concatenate([np.full(1 << m, -m * LN2) for m in ns]))
     out = []
     for fuse in (4, 5):
@@ -471,7 +489,7 @@ def test_freeze_flag_skip_is_bitwise(ba, n, prec, sym):
     p = ba.PREC_FP64 if prec == "fp64" else ba.PREC_FP32_LOG
     ns, ds = [n, n], [0.6, 0.9]
     say("freeze flag skip n=%d %s sym=%d" % (n, prec, sym))
-    c = ba.Context(ns, ds, prec=p)
+    c = chain(ba.Context(ns, ds, prec=p))
     start = torch.tensor(np.concatenate([np.full(1 << m, -m * LN2) for m in ns]))
     c.set_logp(start)
     if sym:
@@ -515,7 +533,7 @@ def test_fused_update_is_bitwise_separate(ba, prec):
     p = ba.PREC_FP64 if prec == "fp64" else ba.PREC_FP32_LOG
     ns, ds = ([12, 14], [0.6, 0.9]) if prec == "fp64" else ([16, 20], [0.7, 0.95])
     # one context, reset between runs
-    c = ba.Context(ns, ds, prec=p)
+    c = chain(ba.Context(ns, ds, prec=p))
     start = torch.tensor(np.concatenate([np.full(1 << m, -m * LN2) for m in ns]))
     for eta in (1.0, 1.8):
         out = []
@@ -530,13 +548,15 @@ def test_fused_update_is_bitwise_separate(ba, prec):
     c.close()
 
 
-def test_fused_update_stops_at_tolerance(ba):
+@pytest.mark.parametrize("path", ["chain", "persistent"])
+def test_fused_update_stops_at_tolerance(ba, path):
     """FP64 iterates stop at the first iterate whose gap is below the tolerance,
-    also when that test is made inside a fused first forward launch (ba_run, eager
-    and graph-replayed)."""
+    also when that test is made inside a fused first forward launch, or inside the
+    persistent launch's loop (ba_run, eager and graph-replayed)."""
     n, d, tol = 10, 0.5, 1e-2
+    setp = chain if path == "chain" else (lambda c: c)
     # reference: one iteration per call (separate update launches, no stop test)
-    ref = ba.Context(n, d)
+    ref = setp(ba.Context(n, d))
     k = 0
     while k < 3000:
         ref.step(1)
@@ -549,7 +569,7 @@ def test_fused_update_stops_at_tolerance(ba):
     ref.close()
     for graphs in (False, True):
         s = torch.cuda.Stream()
-        c = ba.Context(n, d, stream=s)
+        c = setp(ba.Context(n, d, stream=s))
         c.set_graphs(graphs)
         with torch.cuda.stream(s):
             c.run(tol, 3000)
@@ -622,3 +642,45 @@ def test_concurrent_group_branches_are_bitwise(ba, prec):
         assert o[0] == out[0][0] and o[3] == out[0][3]
         assert o[1] == out[0][1] and o[2] == out[0][2] and o[4] == out[0][4] and o[5] == out[0][5]
         assert np.array_equal(o[6], out[0][6])
+
+
+PERSIST_CASES = {
+    "fp64": dict(n=[3, 7, 12, 9], d=[0.1, 0.64, 0.8, 0.99], prec="fp64"),
+    "fp64_eta": dict(n=[10, 12], d=[0.7, 0.9], prec="fp64", eta=1.7),
+    "fp32": dict(n=[10, 13, 12, 13], d=[0.64, 0.8, 0.96, 0.5], prec="fp32"),
+    "exact": dict(n=[11, 11, 6], k=[4, 9, 6], prec="fp64"),
+    "floor": dict(n=[8], d=[0.8], prec="fp64", floor=50.0, iters=1500),
+    "mixed": dict(n=[12, 14, 13, 16], d=[0.7, 0.7, 0.9, 0.9], prec="fp64"),
+}
+
+
+@pytest.mark.parametrize("case", sorted(PERSIST_CASES))
+def test_persistent_equals_chain(ba, case):
+    """The persistent launch (one block per instance iterating in LDS, one position
+    per stage) against the launch chain (four or eight positions per launch): the
+    same iteration up to the order of additions.  FP64: iterates within 1e-11 nats
+    and certified bounds within 1e-11 bits; FP32: within FP32 rounding (iterates
+    1e-4 nats, certified bounds 1e-5 bits).  Groups too large for LDS (n = 14, 16
+    in "mixed") take the chain on both sides."""
+    kw = PERSIST_CASES[case]
+    p = ba.PREC_FP64 if kw["prec"] == "fp64" else ba.PREC_FP32_LOG
+    iters = kw.get("iters", 40)
+    say("persistent vs chain: %s" % case)
+    out = []
+    for persistent in (0, 1):
+        c = ba.Context(kw["n"], kw.get("d", None), prec=p, k=kw.get("k"))
+        c.set_tuning(ba.TUNE_PERSISTENT, persistent)
+        if "eta" in kw:
+            c.set_step(kw["eta"])
+        if "floor" in kw:
+            c.set_floor(kw["floor"])
+        c.step(iters // 2)
+        c.step(iters - iters // 2)
+        lo, hi = c.bounds()
+        out.append((c.get_logp().cpu().numpy(), lo, hi, c.best_bounds()[2]))
+        c.close()
+    tl, tb = (1e-11, 1e-11) if kw["prec"] == "fp64" else (1e-4, 1e-5)
+    assert np.max(np.abs(out[0][0] - out[1][0])) < tl
+    assert np.max(np.abs(np.array(out[0][1]) - np.array(out[1][1]))) < tb
+    assert np.max(np.abs(np.array(out[0][2]) - np.array(out[1][2]))) < tb
+    assert out[0][3] == out[1][3] == [iters] * len(kw["n"])
