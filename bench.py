@@ -503,6 +503,22 @@ def main():
                                   "ms_per_step": es / args.stream_steps * 1e3,
                                   "kernel_ms_per_step": {k: round(v[0], 3) for k, v in kts.items()}}
         cs.close()
+        # the same engine with sweep 1 over complement/reversal orbits (Algorithm 7;
+        # valid from the uniform start by Theorem 4)
+        print("bench: stream engine, orbit-reduced sweep 1", file=sys.stderr, flush=True)
+        co = ba.Context([N] * nb, DS, prec=ba.PREC_FP32_LOG, engine=ba.ENGINE_STREAM, device=dev)
+        co.set_symmetry(2)
+        co.step(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        co.step(args.stream_steps)
+        torch.cuda.synchronize()
+        eo = time.perf_counter() - t0
+        kto = co.time_kernels(1)
+        extra["stream_engine_orbits"] = {"iters_per_s": args.stream_steps / eo,
+                                         "ms_per_step": eo / args.stream_steps * 1e3,
+                                         "kernel_ms_per_step": {k: round(v[0], 3) for k, v in kto.items()}}
+        co.close()
     if not args.no_stream and args.stream_steps > 0:
         # sweep 1 in pull form (supersequence enumeration), sweep 2 as the stream engine
         print("bench: pull engine", file=sys.stderr, flush=True)

@@ -119,19 +119,26 @@ int ba_set_engine(ba_ctx *c, int engine);
 enum { BA_STOP_ITERATE = 0, BA_STOP_BEST = 1 };
 int ba_set_stop_rule(ba_ctx *c, int rule);
 
-/* Complement-symmetric iteration (Appendix A, Theorem 4: from the uniform law
- * every BA iterate of BDC_d and of BDC_{n,k} satisfies p(cpl x) = p(x), cpl = bitwise
- * complement).  enable = 1: the iterations of the factored engine evaluate only
- * the inputs x < 2^(n-1) and the stage entries whose first column bit is 0, reading
- * the other half from the complement (about half the memory traffic; same results
- * up to rounding).  Applies to groups with even n >= 4 and BA_TUNE_FACTORED_FUSE
- * >= 1 (its kernels take two positions per launch); other groups, the stream engine, certification,
- * ba_eval and ba_grad run the full kernels.  Enabling it on a bound context checks
- * that every iterate is invariant under complement (max |log p(x) - log p(cpl x)|
- * <= 1e-9 nats for FP64, 1e-4 for FP32 iterates) and then makes it exactly so;
- * BA_EINVAL (mode left off) if not.  While enabled, ba_set_logp applies the same
- * check after setting the law and switches the mode off (BA_EINVAL) if it fails.
- * enable = 0 switches back to the full kernels.  Off by default. */
+/* Symmetric iteration (Appendix A, Theorem 4: from the uniform law every BA iterate
+ * of BDC_d and of BDC_{n,k} satisfies p(g x) = p(x) for g = complement and
+ * reversal, and then q(g y) = q(y)).
+ * enable = 1: complement.  The iterations of the factored engine evaluate only the
+ * inputs x < 2^(n-1) and the stage entries whose first column bit is 0, reading the
+ * other half from the complement (about half the memory traffic; same results up
+ * to rounding).  Applies to groups with even n >= 4 and BA_TUNE_FACTORED_FUSE >= 1
+ * (its kernels take two positions per launch).
+ * enable = 2: complement and reversal.  As 1 for the factored engine; in addition
+ * the iterations of the stream engine compute q = W^T p by Algorithm 7: only inputs
+ * that are the smallest member of their orbit {x, cpl x, rev x, cpl rev x} are
+ * visited, each nonzero adding (|O_x| / |O_y|) p(x) emb(y,x) to the output's orbit
+ * representative, whose value the other members of the orbit then take.
+ * Other groups, the pull engine, certification, ba_eval and ba_grad run the full
+ * kernels.  Enabling it on a bound context checks that every iterate is invariant
+ * (max |log p(x) - log p(g x)| <= 1e-9 nats for FP64, 1e-4 for FP32 iterates, over
+ * the group's maps) and then makes it exactly so; BA_EINVAL (mode left off) if
+ * not.  While enabled, ba_set_logp applies the same check after setting the law
+ * and switches the mode off (BA_EINVAL) if it fails.  enable = 0 switches back to
+ * the full kernels.  Off by default. */
 int ba_set_symmetry(ba_ctx *c, int enable);
 
 /* Update step of the iterations (ba_step, ba_run): log p <- log p + eta D - log
@@ -185,12 +192,14 @@ enum {
    * on the bound stream.  The iterates are the same either way (groups share no
    * arrays).  Eager launches (ba_step) always use the bound stream. */
   BA_TUNE_CONCURRENT_GROUPS = 2,
-  /* BA_TUNE_PERSISTENT: 1 (default) runs all iterations of one ba_step call (or of
-   * one ba_run chunk) of a group with n <= 13 (FP32 iterates) or n <= 12 (FP64) as
-   * one launch: one block per instance iterates it with every intermediate array in
-   * LDS, one input position per stage (factored engine, not with ba_set_symmetry;
-   * timed as BA_K_SWEEP1 by ba_time_kernels).  0 uses the launch chain.  Same
-   * iteration up to the order of additions. */
+  /* BA_TUNE_PERSISTENT: all iterations of one ba_step call (or of one ba_run chunk)
+   * of a group with n <= 13 (FP32 iterates) or n <= 12 (FP64) as one launch: one
+   * block per instance iterates it with every intermediate array in LDS, one input
+   * position per stage (factored engine, not with ba_set_symmetry; timed as
+   * BA_K_SWEEP1 by ba_time_kernels).  0: never (the launch chain); 1 (default):
+   * for n <= 11, and for any such group of a context with several groups (its
+   * launch then overlaps the other groups' launches); 2: whenever the group fits.
+   * Same iteration up to the order of additions. */
   BA_TUNE_PERSISTENT = 3
 };
 int ba_set_tuning(ba_ctx *c, int key, int value);

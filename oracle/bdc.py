@@ -387,6 +387,47 @@ def r_pull(n: int, lp: np.ndarray, y_bits: int, k: int) -> float:
 
 
 # ---------------------------------------------------------------------------
+# Orbits under complement and reversal (Appendix A).
+# ---------------------------------------------------------------------------
+
+def orbit(bits: int, k: int) -> set[int]:
+    """{y, cpl(y), rev(y), cpl(rev(y))} for the k-bit string y (Appendix A)."""
+    full = (1 << k) - 1
+    rv = int(format(bits, "0%db" % k)[::-1], 2) if k > 0 else 0
+    return {bits, bits ^ full, rv, rv ^ full}
+
+
+def orbit_rep(bits: int, k: int) -> int:
+    """The orbit's representative: its lexicographically smallest member, i.e. the
+    smallest as an integer (x_0 most significant)."""
+    return min(orbit(bits, k))
+
+
+def r_orbits(n: int, lp: np.ndarray) -> np.ndarray:
+    """Algorithm 7 (Appendix A) in the units of r(y) = sum_x p(x) emb(y,x): for every
+    input x that represents its orbit and every subsequence y of x,
+    r(rep y) += (|O_x| / |O_y|) p(x) emb(y,x); the other outputs of each orbit take
+    their representative's value.  Equals the full sum when p is invariant under
+    complement and reversal (Theorem 4); dense counts, small n only."""
+    E = emb_dense(n)
+    p = np.exp(normalise_logp(np.asarray(lp, dtype=float)))
+    Y = (1 << (n + 1)) - 1
+    r = np.zeros(Y)
+    for x in range(1 << n):
+        if orbit_rep(x, n) != x:
+            continue
+        ox = len(orbit(x, n))
+        for R in np.nonzero(E[x])[0]:
+            yb, k = unrank(int(R))
+            oy = len(orbit(yb, k))
+            r[rank(orbit_rep(yb, k), k)] += ox / oy * p[x] * E[x, R]
+    for R in range(Y):
+        yb, k = unrank(R)
+        r[R] = r[rank(orbit_rep(yb, k), k)]
+    return r
+
+
+# ---------------------------------------------------------------------------
 # Closed forms of the output law for special inputs.
 # ---------------------------------------------------------------------------
 

@@ -165,10 +165,11 @@ class Context:
         """STOP_ITERATE (gap of the current iterate) or STOP_BEST (best bounds so far)."""
         self._check(lib().ba_set_stop_rule(self._h, rule), "ba_set_stop_rule")
 
-    def set_symmetry(self, enable: bool = True):
-        """Complement-symmetric iteration (iterates invariant under bitwise
-        complement, as from the uniform start); see ba_set_symmetry."""
-        self._check(lib().ba_set_symmetry(self._h, 1 if enable else 0), "ba_set_symmetry")
+    def set_symmetry(self, enable=True):
+        """Symmetric iteration (iterates invariant under complement, or with 2 under
+        complement and reversal, as from the uniform start); see ba_set_symmetry.
+        True/False mean 1/0."""
+        self._check(lib().ba_set_symmetry(self._h, int(enable)), "ba_set_symmetry")
 
     def set_step(self, eta: float):
         """Update step eta of the iterations (1 = BA; see ba_set_step)."""

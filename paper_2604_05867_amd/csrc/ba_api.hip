@@ -93,6 +93,7 @@ struct ba_ctx {
   // captured chunks: each group of instances (one n) on its own branch of the graph
   int concurrent = 1;
   // groups small enough for LDS iterate in one persistent launch per call/chunk
+  // (0 never, 1 automatic, 2 whenever they fit)
   int persistent = 1;
   std::vector<hipStream_t> aux;      // one per group, default priority
   std::vector<hipEvent_t> join_ev;   // one per group
@@ -353,12 +354,15 @@ int sweeps(ba_ctx* c, const GroupHost& gh, const Group<T>& G, int use_sw_g, T* g
     const int nbt = G.nb < kTile ? G.nb : kTile;
     const size_t budget = std::min<size_t>(size_t(c->scatter_lds_kb) * 1024, size_t(stream_lds_limit()));
     const int k0 = k0_for(n, nbt, sizeof(T), budget);
+    // iterations under ba_set_symmetry(2): Algorithm 7 over complement/reversal orbits
+    const bool orbit = tail && c->sym == 2;
     {
       Timer t(c, BA_K_SWEEP1, 1);
       HIPCHK(c, launch_fill_zero(G.r, size_t(G.nb) * G.ys * sizeof(T), s));
       HIPCHK(c, launch_fill_zero(G.v2, size_t(G.nb) * G.v2s * sizeof(T), s));
-      HIPCHK(c, launch_stream<T>(kOpScatter, gh.tb, G, k0, ex, s));
+      HIPCHK(c, launch_stream<T>(orbit ? kOpScatterOrbit : kOpScatter, gh.tb, G, k0, ex, s));
       HIPCHK(c, launch_combine_r<T>(G, n1, n2, k0, s));
+      if (orbit) HIPCHK(c, launch_orbit_expand<T>(G, s));
     }
     {
       Timer t(c, BA_K_LOGR, 1);
@@ -597,7 +601,7 @@ int ba_set_tuning(ba_ctx* c, int key, int value) {
     return BA_OK;
   }
   if (key == BA_TUNE_PERSISTENT) {
-    if (value != 0 && value != 1) return fail(c, BA_EINVAL, "persistent must be 0 or 1");
+    if (value < 0 || value > 2) return fail(c, BA_EINVAL, "persistent must be 0, 1 or 2");
     c->persistent = value;
     drop_graph(c);
     return BA_OK;
@@ -739,10 +743,15 @@ namespace {
 
 // Whether a group's iterations run as one persistent launch (ba_persist.hip): the
 // factored engine's products, without the complement-symmetric kernels, for groups
-// whose arrays fit in LDS.
+// whose arrays fit in LDS.  Automatic choice (measured on MI355X, per iteration): a
+// block per instance beats the launch chain up to n = 11 on its own (n = 8: 11
+// against 22 us); from n = 12 one CU per instance is slower than the chain over the
+// whole GPU, unless other groups' launches fill the GPU meanwhile (several groups).
 bool use_persist(const ba_ctx* c, const GroupHost& gh) {
-  return c->persistent && c->engine == BA_ENGINE_FACTORED && !sym_active(c, gh.n) &&
-         persist_supported(gh.n, elem(c));
+  if (!c->persistent || c->engine != BA_ENGINE_FACTORED || sym_active(c, gh.n) ||
+      !persist_supported(gh.n, elem(c)))
+    return false;
+  return c->persistent == 2 || gh.n <= 11 || c->groups.size() > 1;
 }
 
 // `iters` iterations of one group: one persistent launch, or the launch chain with
@@ -1067,8 +1076,9 @@ int sym_check_and_fix(ba_ctx* c) {
   size_t k = 0;
   std::vector<std::pair<size_t, size_t>> span;  // per group: first slot in dev, count
   for (auto& gh : c->groups) {
-    if (c->prec == BA_PREC_FP32_LOG) HIPCHK(c, launch_sym_check<float>(gh.gf, dev + k, s));
-    else HIPCHK(c, launch_sym_check<double>(gh.gd, dev + k, s));
+    const int orbit = c->sym == 2 ? 1 : 0;
+    if (c->prec == BA_PREC_FP32_LOG) HIPCHK(c, launch_sym_check<float>(gh.gf, dev + k, orbit, s));
+    else HIPCHK(c, launch_sym_check<double>(gh.gd, dev + k, orbit, s));
     span.push_back({k, gh.inst.size()});
     k += gh.inst.size();
   }
@@ -1080,12 +1090,15 @@ int sym_check_and_fix(ba_ctx* c) {
       const double dv = host[span[gi].first + j];
       if (!(dv <= tol))
         return fail(c, BA_EINVAL, "iterate of instance " + std::to_string(c->groups[gi].inst[j]) +
-                                      " is not complement-symmetric (max |log p(x) - log p(cpl x)| = " +
+                                      (c->sym == 2 ? " is not invariant under complement and reversal"
+                                                    : " is not complement-symmetric") +
+                                      " (max |log p(x) - log p(g x)| = " +
                                       std::to_string(dv) + ")");
     }
   for (auto& gh : c->groups) {
-    if (c->prec == BA_PREC_FP32_LOG) HIPCHK(c, launch_symmetrize<float>(gh.gf, s));
-    else HIPCHK(c, launch_symmetrize<double>(gh.gd, s));
+    const int orbit = c->sym == 2 ? 1 : 0;
+    if (c->prec == BA_PREC_FP32_LOG) HIPCHK(c, launch_symmetrize<float>(gh.gf, orbit, s));
+    else HIPCHK(c, launch_symmetrize<double>(gh.gd, orbit, s));
   }
   return BA_OK;
 }
@@ -1136,9 +1149,9 @@ int ba_set_floor(ba_ctx* c, double nats) {
 }
 
 int ba_set_symmetry(ba_ctx* c, int enable) {
-  if (!c || (enable != 0 && enable != 1)) return c ? fail(c, BA_EINVAL, "enable must be 0 or 1") : BA_EINVAL;
+  if (!c || enable < 0 || enable > 2) return c ? fail(c, BA_EINVAL, "enable must be 0, 1 or 2") : BA_EINVAL;
   if (enable && c->bound) {
-    c->sym = 1;
+    c->sym = enable;
     const int rc = sym_check_and_fix(c);
     if (rc) {
       c->sym = 0;

@@ -134,7 +134,17 @@ struct Group {
                       // frozen flag, which the update kernels always test
 };
 
-enum StreamOp { kOpScatter = 0, kOpGather = 1, kOpInit = 2, kOpRow = 3, kOpVerify = 4 };
+enum StreamOp { kOpScatter = 0, kOpGather = 1, kOpInit = 2, kOpRow = 3, kOpVerify = 4, kOpScatterOrbit = 5 };
+
+// Orbits of Appendix A: the k-bit string v under complement and reversal (the group
+// {id, cpl, rev, cpl rev}); rep = its smallest member (lexicographic order is
+// numeric order), size = the number of distinct members (1, 2 or 4).
+__device__ __forceinline__ void orbit_of(uint32_t v, int k, uint32_t& rep, uint32_t& size) {
+  const uint32_t m = k ? (0xffffffffu >> (32 - k)) : 0u;
+  const uint32_t a = v, b = v ^ m, c = k ? (__brev(v) >> (32 - k)) : 0u, d = c ^ m;
+  rep = min(min(a, b), min(c, d));
+  size = 1u + (b != a ? 1u : 0u) + ((c != a && c != b) ? 1u : 0u) + ((d != a && d != b && d != c) ? 1u : 0u);
+}
 
 // Extra arguments of the non-iteration stream ops.
 struct StreamExtra {
@@ -194,6 +204,9 @@ hipError_t build_tables(int n, void* mem, hipStream_t s, Tables* out_host);
 template <typename T>
 hipError_t launch_stream(StreamOp op, const Tables& tb, const Group<T>& g, int k0,
                          const StreamExtra& ex, hipStream_t s);
+// r(y) = r(rep(y)) for every output that is not its orbit's representative.
+template <typename T>
+hipError_t launch_orbit_expand(const Group<T>& g, hipStream_t s);
 template <typename T>
 hipError_t launch_combine_r(const Group<T>& g, int n1, int n2, int k0, hipStream_t s);
 int stream_lds_limit();  // largest dynamic LDS a block may request on this device
@@ -266,9 +279,9 @@ template <typename T>
 hipError_t launch_update(const Group<T>& g, int nblk, double floor, int check_tol, int sym, hipStream_t s);
 // out[b] = max_x |log p(x) - log p(cpl x)| (device, one double per instance).
 template <typename T>
-hipError_t launch_sym_check(const Group<T>& g, double* out, hipStream_t s);
+hipError_t launch_sym_check(const Group<T>& g, double* out, int orbit, hipStream_t s);
 template <typename T>
-hipError_t launch_symmetrize(const Group<T>& g, hipStream_t s);
+hipError_t launch_symmetrize(const Group<T>& g, int orbit, hipStream_t s);
 int reduce_blocks(int n);
 
 // Certification: FP64 evaluation of the current iterate of a group (any T).

@@ -72,14 +72,16 @@ __device__ __forceinline__ V4<T> v4_zero() {
   return r;
 }
 
-// Block reduction over kPersistThreads threads; the result is valid in every thread.
+// Block reduction over kPersistThreads threads: each wave reduces its lanes, then
+// the first wave reduces the per-wave records (lanes past kPersistWaves empty); the
+// result is valid in thread 0 only.
 __device__ __forceinline__ Part persist_reduce(Part p, Part* sp) {
   p = wave_reduce(p);
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   if (lane == 0) sp[wave] = p;
   __syncthreads();
-  Part r = sp[0];
-  for (int w = 1; w < kPersistWaves; ++w) r = combine(r, sp[w]);
+  Part r = part_empty();
+  if (wave == 0) r = wave_reduce(lane < kPersistWaves ? sp[lane] : part_empty());
   return r;
 }
 
@@ -189,7 +191,7 @@ __global__ __launch_bounds__(kPersistThreads) void k_persist(Group<T> g, int ite
         part_add<T>(p, l + double(dv[j]), double(dv[j]), exp_in(l, T()), 0.0, 1.0, step, l + g.eta * double(dv[j]));
       }
     }
-    const Part P = persist_reduce(p, sp);
+    const Part P = persist_reduce(p, sp);  // valid in thread 0
     if (t == 0) up_sh = update_params_rec<T>(g, b, P, check_tol, true);
     __syncthreads();
     const UpdateParams u = up_sh;

@@ -117,15 +117,18 @@ __global__ __launch_bounds__(kBlock) void k_update(Group<T> g, int nblk, double 
   }
 }
 
-// Largest |log p(x) - log p(cpl x)| of every instance (one block per instance).
+// Largest |log p(x) - log p(cpl x)| of every instance (one block per instance),
+// with orbit = 1 also |log p(x) - log p(rev x)|.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_sym_check(Group<T> g, double* out) {
+__global__ __launch_bounds__(kBlock) void k_sym_check(Group<T> g, double* out, int orbit) {
   const int b = blockIdx.x;
-  const uint32_t X = 1u << g.n;
+  const int n = g.n;
+  const uint32_t X = 1u << n;
   const T* lp = g.lp + (size_t)b * g.xs;
   double m = 0.0;
-  for (uint32_t x = threadIdx.x; x < X / 2u; x += blockDim.x) {
-    const double dv = fabs(double(lp[x]) - double(lp[X - 1u - x]));
+  for (uint32_t x = threadIdx.x; x < X; x += blockDim.x) {
+    double dv = fabs(double(lp[x]) - double(lp[X - 1u - x]));
+    if (orbit) dv = fmax(dv, fabs(double(lp[x]) - double(lp[__brev(x) >> (32 - n)])));
     m = (dv > m || dv != dv) ? dv : m;  // NaN propagates
   }
   __shared__ double sm[kBlock];
@@ -141,13 +144,27 @@ __global__ __launch_bounds__(kBlock) void k_sym_check(Group<T> g, double* out) {
   if (threadIdx.x == 0) out[b] = sm[0];
 }
 
-// Copy the half x < 2^(n-1) onto the complements (log p and p).
+// Make the iterate exactly invariant: copy the half x < 2^(n-1) onto the
+// complements (log p and p), or with orbit = 1 give every input the values of its
+// orbit's representative under complement and reversal (representatives are only
+// read, the other members only written).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_symmetrize(Group<T> g) {
+__global__ __launch_bounds__(kBlock) void k_symmetrize(Group<T> g, int orbit) {
   const int b = blockIdx.y;
   const uint32_t X = 1u << g.n;
   T* lp = g.lp + (size_t)b * g.xs;
   T* p = g.p + (size_t)b * g.xs;
+  if (orbit) {
+    for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < X; x += gridDim.x * blockDim.x) {
+      uint32_t rep, size;
+      orbit_of(x, g.n, rep, size);
+      if (rep != x) {
+        lp[x] = lp[rep];
+        p[x] = p[rep];
+      }
+    }
+    return;
+  }
   for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < X / 2u; x += gridDim.x * blockDim.x) {
     lp[X - 1u - x] = lp[x];
     p[X - 1u - x] = p[x];
@@ -384,14 +401,14 @@ hipError_t launch_update(const Group<T>& g, int nblk, double floor, int check_to
 }
 
 template <typename T>
-hipError_t launch_sym_check(const Group<T>& g, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_sym_check<T>, dim3(g.nb), dim3(kBlock), 0, s, g, out);
+hipError_t launch_sym_check(const Group<T>& g, double* out, int orbit, hipStream_t s) {
+  hipLaunchKernelGGL(k_sym_check<T>, dim3(g.nb), dim3(kBlock), 0, s, g, out, orbit);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_symmetrize(const Group<T>& g, hipStream_t s) {
-  hipLaunchKernelGGL(k_symmetrize<T>, dim3(grid_for(1u << (g.n - 1)), g.nb), dim3(kBlock), 0, s, g);
+hipError_t launch_symmetrize(const Group<T>& g, int orbit, hipStream_t s) {
+  hipLaunchKernelGGL(k_symmetrize<T>, dim3(grid_for(1u << g.n), g.nb), dim3(kBlock), 0, s, g, orbit);
   return hipGetLastError();
 }
 
@@ -471,8 +488,8 @@ hipError_t launch_copy_f64(double* dst, const double* src, size_t count, hipStre
   template hipError_t launch_logr<T>(const Group<T>&, int, int, int, int, hipStream_t);          \
   template hipError_t launch_dpart<T>(const Group<T>&, int, int, const T*, hipStream_t);         \
   template hipError_t launch_update<T>(const Group<T>&, int, double, int, int, hipStream_t);     \
-  template hipError_t launch_sym_check<T>(const Group<T>&, double*, hipStream_t);               \
-  template hipError_t launch_symmetrize<T>(const Group<T>&, hipStream_t);                       \
+  template hipError_t launch_sym_check<T>(const Group<T>&, double*, int, hipStream_t);          \
+  template hipError_t launch_symmetrize<T>(const Group<T>&, int, hipStream_t);                  \
   template hipError_t launch_final_parts<T>(const Group<T>&, int, hipStream_t);                 \
   template hipError_t launch_cert_prepare<T>(const Group<T>&, const Group<double>&, int, double, \
                                              hipStream_t);                                       \

@@ -17,6 +17,11 @@
 // rule), so y2 lies entirely in x2 to the right of y1's last bit.
 //
 // Ops: scatter  r(y) += p(x) emb(y,x)   (outputs with |y| <= k0 in LDS first)
+//      scatter over orbits (Appendix A, Algorithm 7; iterates invariant under
+//               complement and reversal): only inputs x that represent their orbit
+//               take part, r(rep y) += (|O_x| / |O_y|) p(x) emb(y,x) (the split
+//               layout at rep y's split into the same lengths), and the other
+//               outputs of each orbit are filled in after the combine
 //      gather   G(x) += emb(y,x) v(y)    (v in split layout V2[rank(y2)][rank(y1)])
 //      init     H(x) += w_k emb log emb, Hd(x) += s_k w_k emb log emb (fixed-point
 //               integer atomics: the same bits in every run)
@@ -81,6 +86,8 @@ template <typename T, int OP>
 __global__ __launch_bounds__(kBlock) void k_stream(Tables tb, Group<T> g, int k0, int parts,
                                                    StreamExtra ex) {
   extern __shared__ __align__(16) unsigned char smem[];
+  constexpr bool ORB = OP == kOpScatterOrbit;         // Algorithm 7
+  constexpr bool SCAT = OP == kOpScatter || ORB;
   const int n1 = tb.n1, n2 = tb.n2;
   const uint32_t x2 = blockIdx.x / parts;
   const uint32_t part = blockIdx.x % parts;
@@ -92,7 +99,7 @@ __global__ __launch_bounds__(kBlock) void k_stream(Tables tb, Group<T> g, int k0
   // Instances of this launch's tile and which of them are still iterating.
   int b0 = 0, nbt = 1;
   uint32_t live = 1;
-  if (OP == kOpScatter || OP == kOpGather || OP == kOpInit) {
+  if (SCAT || OP == kOpGather || OP == kOpInit) {
     b0 = blockIdx.y * kTile;
     nbt = min(kTile, g.nb - b0);
     live = 0;
@@ -105,14 +112,14 @@ __global__ __launch_bounds__(kBlock) void k_stream(Tables tb, Group<T> g, int k0
   const uint32_t nshort = (2u << k0) - 1u;
   T* rs = reinterpret_cast<T*>(smem);  // scatter: [nbt][nshort]
   T* gs = reinterpret_cast<T*>(smem);  // gather:  [nbt][X1]
-  if (OP == kOpScatter) {
+  if (SCAT) {
     for (uint32_t i = threadIdx.x; i < nshort * nbt; i += kBlock) rs[i] = T(0);
   } else if (OP == kOpGather) {
     for (uint32_t i = threadIdx.x; i < X1 * nbt; i += kBlock) gs[i] = T(0);
   }
   __syncthreads();
 
-  const uint4* __restrict__ t1 = (OP == kOpGather || OP == kOpScatter) ? tb.t1g : tb.t1s;
+  const uint4* __restrict__ t1 = (OP == kOpGather || SCAT) ? tb.t1g : tb.t1s;
   const uint32_t o2 = tb.off2[x2];
   const uint32_t c2 = tb.off2[x2 + 1] - o2;
   const uint32_t z0 = tb.n0_2[x2];
@@ -174,10 +181,18 @@ __global__ __launch_bounds__(kBlock) void k_stream(Tables tb, Group<T> g, int k0
     // sum in its last lane (sm_d = 1 when lane-d is in the same run and row).
     T sm1 = T(0), sm2 = T(0), sm4 = T(0), sm8 = T(0);
     bool emit = false;
-    if (OP == kOpScatter) {
+    if (SCAT) {
+      // Algorithm 7: an input that is not its orbit's representative adds nothing;
+      // a representative stands for its |O_x| orbit members
+      T ox = T(1);
+      if constexpr (ORB) {
+        uint32_t xr, xs;
+        orbit_of(x, n1 + n2, xr, xs);
+        ox = (xr == x) ? T(xs) : T(0);
+      }
 #pragma unroll
       for (int b = 0; b < kTile; ++b)
-        pl[b] = (b < nbt && valid) ? g.p[(size_t)(b0 + b) * g.xs + x] : T(0);
+        pl[b] = (b < nbt && valid) ? ox * g.p[(size_t)(b0 + b) * g.xs + x] : T(0);
       const int key = valid ? int(((ent.x >> 24) & 3u) << 12 | R1) : -1;
       const int rl = lane & 15;
       // The DPP reads run with every lane active (a disabled source lane reads 0).
@@ -215,17 +230,29 @@ __global__ __launch_bounds__(kBlock) void k_stream(Tables tb, Group<T> g, int k0
         for (int j = 0; j <= kHalfMax; ++j)
           if (j <= jmax) emb = __umul24(l[j], byte_of(t, j)) + emb;
         const int k = k1 + k2;
-        if (OP == kOpScatter) {
+        if (SCAT) {
           // All lanes take part in the run reduction (inactive lanes add 0), then
           // the last lane of each run (per 16-lane row) issues one atomic.
           const T fe = ok ? T(emb) : T(0);
-          const uint32_t rank = (A1 << k2) + y2 - 1u;
-          const size_t i2 = size_t((1u << k2) - 1u + y2) * S1 + R1;
+          uint32_t rank = (A1 << k2) + y2 - 1u;
+          size_t i2 = size_t((1u << k2) - 1u + y2) * S1 + R1;
+          T oy = T(1);
+          if constexpr (ORB) {
+            // the run's output y (shared by its lanes) goes to its representative,
+            // weighted 1 / |O_y|, at the representative's split into the same
+            // lengths k1 + k2 (the combine sums every split of an output)
+            uint32_t yr, ys;
+            orbit_of((y1 << k2) | y2, k, yr, ys);
+            rank = ((1u << k) - 1u) + yr;
+            i2 = size_t((1u << k2) - 1u + (yr & ((1u << k2) - 1u))) * S1 + ((1u << k1) - 1u + (yr >> k2));
+            oy = T(ys);
+          }
 #pragma unroll
           for (int b = 0; b < kTile; ++b) {
             if (b >= nbt || !((live >> b) & 1u)) continue;  // uniform
-            const T cv = seg_row_sum(pl[b] * fe, sm1, sm2, sm4, sm8);
+            T cv = seg_row_sum(pl[b] * fe, sm1, sm2, sm4, sm8);
             if (emit && ok && cv != T(0)) {
+              if constexpr (ORB) cv = cv / oy;
               if (k <= k0) lds_add(&rs[b * nshort + rank], cv);
               else atomic_add(&g.v2[(size_t)(b0 + b) * g.v2s + i2], cv);
             }
@@ -278,7 +305,7 @@ __global__ __launch_bounds__(kBlock) void k_stream(Tables tb, Group<T> g, int k0
     }
   }
 
-  if (OP == kOpScatter) {
+  if (SCAT) {
     __syncthreads();
     for (int b = 0; b < nbt; ++b) {
       if (!((live >> b) & 1u)) continue;
@@ -395,11 +422,11 @@ hipError_t launch_op(const Tables& tb, const Group<T>& g, int k0, const StreamEx
   if (OP != kOpRow) {
     while ((uint64_t)X2 * parts < 2048 && (uint32_t)parts * 8 < nchunk) parts *= 2;
   }
-  const int tiles = (OP == kOpScatter || OP == kOpGather) ? (g.nb + kTile - 1) / kTile
-                    : (OP == kOpInit ? g.nb : 1);
-  const int nbt = (OP == kOpScatter || OP == kOpGather) ? (g.nb < kTile ? g.nb : kTile) : 1;
+  constexpr bool SCAT = OP == kOpScatter || OP == kOpScatterOrbit;
+  const int tiles = (SCAT || OP == kOpGather) ? (g.nb + kTile - 1) / kTile : (OP == kOpInit ? g.nb : 1);
+  const int nbt = (SCAT || OP == kOpGather) ? (g.nb < kTile ? g.nb : kTile) : 1;
   size_t lds = 0;
-  if (OP == kOpScatter) lds = size_t((2u << k0) - 1u) * nbt * sizeof(T);
+  if (SCAT) lds = size_t((2u << k0) - 1u) * nbt * sizeof(T);
   if (OP == kOpGather) lds = size_t(1u << tb.n1) * nbt * sizeof(T);
   if (OP == kOpInit) {
     // one launch per instance (its own weights); per-lane partial sums go to the
@@ -437,6 +464,7 @@ hipError_t launch_stream(StreamOp op, const Tables& tb, const Group<T>& g, int k
                          const StreamExtra& ex, hipStream_t s) {
   switch (op) {
     case kOpScatter: return launch_op<T, kOpScatter>(tb, g, k0, ex, s);
+    case kOpScatterOrbit: return launch_op<T, kOpScatterOrbit>(tb, g, k0, ex, s);
     case kOpGather: return launch_op<T, kOpGather>(tb, g, k0, ex, s);
     case kOpInit: return launch_op<T, kOpInit>(tb, g, k0, ex, s);
     case kOpRow: return launch_op<T, kOpRow>(tb, g, k0, ex, s);
@@ -456,6 +484,35 @@ template hipError_t launch_stream<float>(StreamOp, const Tables&, const Group<fl
                                          const StreamExtra&, hipStream_t);
 template hipError_t launch_stream<double>(StreamOp, const Tables&, const Group<double>&, int,
                                           const StreamExtra&, hipStream_t);
+
+// After the orbit scatter: the outputs that do not represent their orbit take the
+// representative's value (Theorem 4: r(g y) = r(y) for an invariant input law).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_orbit_expand(Group<T> g) {
+  const int b = blockIdx.y;
+  if (g.st[b].converged) return;
+  const uint32_t Y = out_count(g.n);
+  T* r = g.r + (size_t)b * g.ys;
+  for (uint32_t y = blockIdx.x * blockDim.x + threadIdx.x; y < Y; y += gridDim.x * blockDim.x) {
+    const int k = 31 - __clz(y + 1u);
+    const uint32_t bits = y + 1u - (1u << k);
+    uint32_t rep, size;
+    orbit_of(bits, k, rep, size);
+    if (rep != bits) r[y] = r[(1u << k) - 1u + rep];
+  }
+}
+
+template <typename T>
+hipError_t launch_orbit_expand(const Group<T>& g, hipStream_t s) {
+  const uint32_t Y = out_count(g.n);
+  uint32_t grid = (Y + kBlock - 1) / kBlock;
+  if (grid > 8192u) grid = 8192u;
+  hipLaunchKernelGGL(k_orbit_expand<T>, dim3(grid, g.nb), dim3(kBlock), 0, s, g);
+  return hipGetLastError();
+}
+
+template hipError_t launch_orbit_expand<float>(const Group<float>&, hipStream_t);
+template hipError_t launch_orbit_expand<double>(const Group<double>&, hipStream_t);
 
 template <typename T>
 hipError_t launch_combine_r(const Group<T>& g, int n1, int n2, int k0, hipStream_t s) {

@@ -207,3 +207,99 @@ def test_symmetric_fused_update_is_bitwise_separate(ba, prec):
             assert np.array_equal(lp[off:off + (1 << m)], lp[off:off + (1 << m)][::-1])
             off += 1 << m
     c.close()
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 7: the stream engine's output law over complement/reversal orbits
+# ---------------------------------------------------------------------------
+
+def stream_pair(ba, ns, ds, prec, iters):
+    """(logp, bounds) after `iters` stream-engine iterations with the full scatter
+    and with Algorithm 7 (ba_set_symmetry(2))."""
+    out = []
+    for mode in (0, 2):
+        c = ba.Context(ns, ds, prec=prec, engine=ba.ENGINE_STREAM)
+        if mode:
+            c.set_symmetry(mode)
+        c.step(iters)
+        lo, hi = c.bounds()
+        out.append((c.get_logp().cpu().numpy(), np.array(lo), np.array(hi)))
+        c.close()
+    return out
+
+
+@pytest.mark.parametrize("n", [5, 8, 10])
+def test_orbit_scatter_matches_oracle(ba, n):
+    """Algorithm 7 (representative inputs, weights |O_x| / |O_y|, outputs filled from
+    their orbit's representative) inside the stream engine's iterations: FP64
+    iterates and certified bounds within 1e-10 of the oracle's BA from the uniform
+    law; the oracle's own Algorithm 7 reproduces the output law of the iterate."""
+    d = 0.7
+    W = bdc.channel_dense(n, d)
+    c = ba.Context(n, d, prec=ba.PREC_FP64, engine=ba.ENGINE_STREAM)
+    c.set_symmetry(2)
+    c.step(20)
+    lp = c.get_logp().cpu().numpy()
+    want = bdc.ba_iterate(W, bdc.uniform_logp(n), 20)
+    assert np.max(np.abs(lp - want)) < 1e-10
+    lo, hi = c.bounds()
+    L, U = bdc.certify(W, want)
+    assert abs(lo[0] - L) < 1e-10 and abs(hi[0] - U) < 1e-10
+    E = bdc.emb_dense(n)
+    assert np.allclose(bdc.r_orbits(n, lp), np.exp(bdc.normalise_logp(lp)) @ E, rtol=1e-12, atol=0)
+    c.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_orbit_scatter_equals_full_scatter(ba, prec):
+    """Batches with odd and even n (orbits of size 1, 2 and 4 at every length): the
+    Algorithm 7 scatter gives the iterates and bounds of the full scatter (FP64
+    within 1e-12; FP32 within its rounding), and the iterate stays exactly invariant
+    under complement and reversal."""
+    p = ba.PREC_FP64 if prec == "fp64" else ba.PREC_FP32_LOG
+    ns, ds = [9, 12, 11, 12], [0.64, 0.8, 0.9, 0.96]
+    (lp_f, lo_f, hi_f), (lp_o, lo_o, hi_o) = stream_pair(ba, ns, ds, p, 12)
+    tl, tb = (1e-12, 1e-12) if prec == "fp64" else (1e-4, 1e-5)
+    assert np.max(np.abs(lp_f - lp_o)) < tl
+    assert np.max(np.abs(lo_f - lo_o)) < tb and np.max(np.abs(hi_f - hi_o)) < tb
+    off = 0
+    for n in ns:
+        x = np.arange(1 << n)
+        rv = np.zeros_like(x)
+        for i in range(n):
+            rv |= ((x >> i) & 1) << (n - 1 - i)
+        seg = lp_o[off:off + (1 << n)]
+        top = seg > seg.max() - 30.0
+        assert np.max(np.abs(seg[rv] - seg)[top]) < (1e-12 if prec == "fp64" else 1e-4)
+        off += 1 << n
+
+
+def test_orbit_mode_rejects_non_invariant_laws(ba):
+    """ba_set_symmetry(2) refuses a law that is complement-symmetric but not
+    reversal-invariant (mode 1 accepts it), and any non-invariant ba_set_logp."""
+    n = 6
+    x = np.arange(1 << n)
+    cp = x ^ ((1 << n) - 1)
+    lp = inp.random_logp(n, seed=90, spread=1.0)
+    lp = 0.5 * (lp + lp[cp])             # complement-invariant only
+    c = ba.Context(n, 0.7, engine=ba.ENGINE_STREAM)
+    c.set_logp(torch.from_numpy(lp))
+    with pytest.raises(ba.BAError) as e:
+        c.set_symmetry(2)
+    assert e.value.code == ba.BA_EINVAL and "reversal" in str(e.value)
+    c.set_symmetry(1)
+    c.set_symmetry(0)
+    c.set_logp(torch.from_numpy(np.full(1 << n, -n * LN2)))
+    c.set_symmetry(2)
+    with pytest.raises(ba.BAError):
+        c.set_logp(torch.from_numpy(lp))
+    c.close()
+
+
+def test_orbit_scatter_n20_fp32(ba):
+    """The workload size: three n = 20 FP32 instances, one stream-engine iteration
+    with each scatter; the laws agree within FP32 rounding."""
+    ds = [0.64, 0.8, 0.95]
+    (lp_f, lo_f, hi_f), (lp_o, lo_o, hi_o) = stream_pair(ba, [20] * 3, ds, ba.PREC_FP32_LOG, 1)
+    assert np.max(np.abs(lp_f - lp_o)) < 1e-4
+    assert np.max(np.abs(lo_f - lo_o)) < 1e-5 and np.max(np.abs(hi_f - hi_o)) < 1e-5

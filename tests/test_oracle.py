@@ -703,3 +703,39 @@ def test_pull_sum_matches_push(n):
     for R in range((2 << n) - 1):
         yb, k = bdc.unrank(R)
         assert abs(bdc.r_pull(n, lp, yb, k) - r[R]) <= 1e-12 * max(1.0, abs(r[R]))
+
+
+# ---------------------------------------------------------------------------
+# orbit-reduced output law (Appendix A)
+# ---------------------------------------------------------------------------
+
+def test_orbit_examples():
+    """Hand-checked orbits: 0110 is its own complement-reversal image; 0011 maps to
+    1100 (complement) and 1100 (reversal); 0001 has four members."""
+    assert bdc.orbit(0b0110, 4) == {0b0110, 0b1001}
+    assert bdc.orbit(0b0011, 4) == {0b0011, 0b1100}
+    assert bdc.orbit(0b0001, 4) == {0b0001, 0b1110, 0b1000, 0b0111}
+    assert bdc.orbit(0, 0) == {0}
+    assert bdc.orbit_rep(0b1110, 4) == 0b0001
+
+
+@pytest.mark.parametrize("n", [3, 5, 6])
+def test_orbit_output_law_equals_full_sum_for_invariant_laws(n):
+    """Algorithm 7 gives r = E^T p exactly (to rounding) for laws invariant under
+    complement and reversal: the uniform law, a random invariant law and a BA
+    iterate from the uniform law (Theorem 4); it does not for a law that is not
+    invariant (the reduction relies on that invariance)."""
+    E = bdc.emb_dense(n)
+    W = bdc.channel_dense(n, 0.7, E)
+    rng = np.random.default_rng(60 + n)
+    inv = np.zeros(1 << n)
+    for x in range(1 << n):
+        rep = bdc.orbit_rep(x, n)
+        if rep == x:
+            inv[[y for y in bdc.orbit(x, n)]] = rng.normal(0, 1.5)
+    it = bdc.ba_iterate(W, bdc.uniform_logp(n), 7)
+    for lp in (bdc.uniform_logp(n), inv, it):
+        full = np.exp(bdc.normalise_logp(lp)) @ E
+        assert np.allclose(bdc.r_orbits(n, lp), full, rtol=1e-13, atol=0)
+    bad = inp.random_logp(n, seed=61, spread=2.0)
+    assert not np.allclose(bdc.r_orbits(n, bad), np.exp(bdc.normalise_logp(bad)) @ E, rtol=1e-6)
