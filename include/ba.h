@@ -200,7 +200,16 @@ enum {
    * for n <= 11, and for any such group of a context with several groups (its
    * launch then overlaps the other groups' launches); 2: whenever the group fits.
    * Same iteration up to the order of additions. */
-  BA_TUNE_PERSISTENT = 3
+  BA_TUNE_PERSISTENT = 3,
+  /* BA_TUNE_STAGE8_COLUMNS: log2 of the columns each block of the factored engine's
+   * eight-position backward launches covers (with correspondingly more subtree
+   * roots per block): 0 (default) as many as the rows hold up to 16 (FP32) or 8
+   * (FP64), else 1 .. 4 (FP32) / 1 .. 3 (FP64), capped by the row width.  The same
+   * sums in the same order (bitwise-equal iterates). */
+  BA_TUNE_STAGE8_COLUMNS = 4,
+  /* BA_TUNE_PERSIST_THREADS: threads per block of the persistent launch (256, 512
+   * or 1024, the default). */
+  BA_TUNE_PERSIST_THREADS = 5
 };
 int ba_set_tuning(ba_ctx *c, int key, int value);
 

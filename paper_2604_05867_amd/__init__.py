@@ -28,6 +28,8 @@ TUNE_SCATTER_LDS_KB = 0
 TUNE_FACTORED_FUSE = 1
 TUNE_CONCURRENT_GROUPS = 2
 TUNE_PERSISTENT = 3
+TUNE_STAGE8_COLUMNS = 4
+TUNE_PERSIST_THREADS = 5
 STOP_ITERATE, STOP_BEST = 0, 1
 
 _lib = None

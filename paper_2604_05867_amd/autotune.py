@@ -1,15 +1,23 @@
 """Autotuner for the launch parameters of libba.
 
 For a workload (input lengths, iteration precision, engine) it times a few BA
-iterations for every candidate setting of the tuning knobs (``ba_set_tuning``)
-with HIP events on the bound stream (``ba_time_kernels``), keeps the fastest,
-and caches the choice in a JSON file keyed by device and workload.  The knobs
-only change the work decomposition, never the results beyond rounding order.
+iterations per candidate setting of the tuning knobs (``ba_set_tuning``) with HIP
+events on the bound stream (``ba_time_kernels``), and keeps the fastest.  The knobs
+are searched one after another (coordinate descent from the library defaults:
+each knob tries all its values with the others at their best so far), and the
+choice is cached in a JSON file keyed by device and workload.  The knobs only
+change the work decomposition, never the results beyond rounding order.
 
 Knobs:
-  engine factored: TUNE_FACTORED_FUSE in {0, 1, 2, 3, 4, 5} (positions per launch)
-  engine stream:   TUNE_SCATTER_LDS_KB in {16, 32, 48, 64} (LDS-privatised
-                   output range of the scatter)
+  engine factored:
+    TUNE_FACTORED_FUSE     positions per launch (launch plan level 5 .. 0)
+    TUNE_STAGE8_COLUMNS    columns per block of the eight-position backward
+                           launches, log2 (0 = widest, 1 .. 4), i.e. the tile of
+                           (subtree roots x columns) a block stages in LDS
+    TUNE_PERSISTENT        small groups as one persistent launch (auto, off, always)
+    TUNE_PERSIST_THREADS   threads per block of that launch (1024, 512, 256)
+  engine stream:
+    TUNE_SCATTER_LDS_KB    LDS-privatised output range of the scatter (KB)
 """
 from __future__ import annotations
 
@@ -18,13 +26,16 @@ import os
 
 import torch
 
-from . import (ENGINE_FACTORED, ENGINE_STREAM, TUNE_FACTORED_FUSE, TUNE_SCATTER_LDS_KB, Context)
+from . import (ENGINE_FACTORED, ENGINE_STREAM, TUNE_FACTORED_FUSE, TUNE_PERSIST_THREADS, TUNE_PERSISTENT,
+               TUNE_SCATTER_LDS_KB, TUNE_STAGE8_COLUMNS, Context)
 
-CANDIDATES = {
-    ENGINE_FACTORED: [(TUNE_FACTORED_FUSE, 0), (TUNE_FACTORED_FUSE, 1), (TUNE_FACTORED_FUSE, 2),
-                      (TUNE_FACTORED_FUSE, 3), (TUNE_FACTORED_FUSE, 4), (TUNE_FACTORED_FUSE, 5)],
-    ENGINE_STREAM: [(TUNE_SCATTER_LDS_KB, 16), (TUNE_SCATTER_LDS_KB, 32), (TUNE_SCATTER_LDS_KB, 48),
-                    (TUNE_SCATTER_LDS_KB, 64)],
+# knob -> candidate values, the library default first
+KNOBS = {
+    ENGINE_FACTORED: [(TUNE_FACTORED_FUSE, [5, 4, 3, 2, 1, 0]),
+                      (TUNE_STAGE8_COLUMNS, [0, 1, 2, 3, 4]),
+                      (TUNE_PERSISTENT, [1, 0, 2]),
+                      (TUNE_PERSIST_THREADS, [1024, 512, 256])],
+    ENGINE_STREAM: [(TUNE_SCATTER_LDS_KB, [64, 48, 32, 16])],
 }
 
 
@@ -33,36 +44,54 @@ def _key(ns, prec, engine):
     return "%s|n=%s|prec=%d|engine=%d" % (dev, ",".join(str(v) for v in sorted(set(ns))), prec, engine)
 
 
-def tune(ctx: Context, iters: int = 3, cache_path: str | None = None, force: bool = False) -> dict:
-    """Choose and apply the fastest knob setting for ``ctx``'s workload.
+def _apply(ctx: Context, choice: dict):
+    for knob, value in choice.items():
+        ctx.set_tuning(int(knob), int(value))
 
-    Returns {"key", "choice": (knob, value), "ms_per_iter": {value: ms}}.  The
-    timing runs ``iters`` iterations per candidate on the context itself and then
-    restores the starting iterate."""
-    if ctx.engine not in CANDIDATES:
-        return {"key": None, "choice": None, "ms_per_iter": {}}
+
+def _time(ctx: Context, start: torch.Tensor, iters: int) -> float:
+    ctx.set_logp(start)
+    ctx.step(1)  # warm-up (first launch of a new shape)
+    t = ctx.time_kernels(iters)
+    return sum(ms for ms, _ in t.values()) / iters
+
+
+def tune(ctx: Context, iters: int = 3, cache_path: str | None = None, force: bool = False) -> dict:
+    """Choose and apply the fastest knob settings for ``ctx``'s workload.
+
+    Returns {"key", "choice": {knob: value}, "ms_per_iter": {"knob=value": ms}}.
+    The timing runs ``iters`` iterations per candidate on the context itself and
+    then restores the starting iterate."""
+    if ctx.engine not in KNOBS:
+        return {"key": None, "choice": {}, "ms_per_iter": {}}
     key = _key(ctx.n, ctx.prec, ctx.engine)
     cache = {}
     if cache_path and os.path.exists(cache_path):
         with open(cache_path) as f:
             cache = json.load(f)
     if key in cache and not force:
-        knob, value = cache[key]["choice"]
-        ctx.set_tuning(knob, value)
+        _apply(ctx, cache[key]["choice"])
         return cache[key]
     start = ctx.get_logp()
+    choice = {str(knob): values[0] for knob, values in KNOBS[ctx.engine]}
+    _apply(ctx, choice)
     results = {}
-    for knob, value in CANDIDATES[ctx.engine]:
-        ctx.set_tuning(knob, value)
-        ctx.set_logp(start)
-        ctx.step(1)  # warm-up (first launch with new LDS size / shape)
-        t = ctx.time_kernels(iters)
-        results[value] = sum(ms for ms, _ in t.values()) / iters
-    best = min(results, key=results.get)
-    knob = CANDIDATES[ctx.engine][0][0]
-    ctx.set_tuning(knob, best)
+    best_ms = None
+    for knob, values in KNOBS[ctx.engine]:
+        for value in values:
+            trial = dict(choice)
+            trial[str(knob)] = value
+            label = "%d=%d" % (knob, value)
+            if label not in results:
+                _apply(ctx, trial)
+                results[label] = _time(ctx, start, iters)
+            if best_ms is None or results[label] < best_ms:
+                best_ms = results[label]
+                choice = trial
+        _apply(ctx, choice)
+    _apply(ctx, choice)
     ctx.set_logp(start)
-    entry = {"key": key, "choice": [knob, best], "ms_per_iter": {str(k): v for k, v in results.items()}}
+    entry = {"key": key, "choice": choice, "ms_per_iter": results}
     if cache_path:
         cache[key] = entry
         tmp = cache_path + ".tmp"

@@ -93,8 +93,11 @@ struct ba_ctx {
   // captured chunks: each group of instances (one n) on its own branch of the graph
   int concurrent = 1;
   // groups small enough for LDS iterate in one persistent launch per call/chunk
-  // (0 never, 1 automatic, 2 whenever they fit)
+  // (0 never, 1 automatic, 2 whenever they fit), with this many threads per block
   int persistent = 1;
+  int persist_threads = 1024;
+  // eight-position backward launches: log2 of the columns per block (0: widest)
+  int s8lc = 0;
   std::vector<hipStream_t> aux;      // one per group, default priority
   std::vector<hipEvent_t> join_ev;   // one per group
   hipEvent_t fork_ev = nullptr;
@@ -258,6 +261,7 @@ Group<T> make_group(char* ws, const GroupHost& g, bool cert) {
   G.cs = reinterpret_cast<const Consts*>(ws + L.cs);
   G.eta = 1.0;
   G.frz = 1;
+  G.s8lc = 0;
   return G;
 }
 
@@ -400,6 +404,7 @@ int sweeps(ba_ctx* c, const GroupHost& gh, const Group<T>& G, int use_sw_g, T* g
       Timer t(c, BA_K_SWEEP2, backward_launches(n, c->fuse));
       Group<T> G2 = G;
       G2.g = g_out;
+      G2.s8lc = c->s8lc;
       HIPCHK(c, launch_backward<T>(G2, s, nullptr, c->fuse, fuse_tail, tail_done));
     }
   }
@@ -600,6 +605,19 @@ int ba_set_tuning(ba_ctx* c, int key, int value) {
     drop_graph(c);
     return BA_OK;
   }
+  if (key == BA_TUNE_STAGE8_COLUMNS) {
+    if (value < 0 || value > 4) return fail(c, BA_EINVAL, "stage-8 columns must be 0 .. 4 (log2)");
+    c->s8lc = value;
+    drop_graph(c);
+    return BA_OK;
+  }
+  if (key == BA_TUNE_PERSIST_THREADS) {
+    if (value != 256 && value != 512 && value != 1024)
+      return fail(c, BA_EINVAL, "persistent threads must be 256, 512 or 1024");
+    c->persist_threads = value;
+    drop_graph(c);
+    return BA_OK;
+  }
   if (key == BA_TUNE_PERSISTENT) {
     if (value < 0 || value > 2) return fail(c, BA_EINVAL, "persistent must be 0, 1 or 2");
     c->persistent = value;
@@ -764,11 +782,11 @@ int step_group(ba_ctx* c, GroupHost& gh, int iters) {
     if (c->prec == BA_PREC_FP32_LOG) {
       Group<float> G = gh.gf;
       G.eta = c->eta;
-      HIPCHK(c, launch_persist<float>(G, iters, floor, 0, c->stream));
+      HIPCHK(c, launch_persist<float>(G, iters, floor, 0, c->persist_threads, c->stream));
     } else {
       Group<double> G = gh.gd;
       G.eta = c->eta;
-      HIPCHK(c, launch_persist<double>(G, iters, floor, 1, c->stream));
+      HIPCHK(c, launch_persist<double>(G, iters, floor, 1, c->persist_threads, c->stream));
     }
     return BA_OK;
   }
@@ -1015,6 +1033,7 @@ int ba_grad(ba_ctx* c, const double* theta_dev, double* I_bits, double* dI_dthet
       HIPCHK(c, launch_fill_zero(cert.gd, cert.xs * sizeof(double), s));
       HIPCHK(c, launch_stream<double>(kOpGather, gh.tb, Gd, 0, ex, s));
     } else {
+      Gd.s8lc = c->s8lc;
       HIPCHK(c, launch_backward<double>(Gd, s, nullptr, c->fuse, 0, nullptr));
     }
   }

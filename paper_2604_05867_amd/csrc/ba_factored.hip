@@ -1495,7 +1495,8 @@ hipError_t launch_backward(const Group<T>& g, hipStream_t s, int* launches, int 
       T* dst = (k & 1) ? g.f1 : g.f0;
       constexpr int LP = stage8_tile<T>() == 16 ? 4 : stage8_tile<T>() == 8 ? 3 : 2;
       const int sh = n - i - 8;
-      const int lc = sh < LP ? sh : LP;
+      int lc = sh < LP ? sh : LP;
+      if (g.s8lc > 0 && g.s8lc < lc) lc = g.s8lc;  // tuned: fewer columns, more roots per block
       const dim3 grid(((stage8_slots(i, LP - lc) << (sh - lc)) + 7u) & ~7u, 1, g.nb);
       const dim3 block(32 * stage8_tile<T>());
       if (lc == LP) {

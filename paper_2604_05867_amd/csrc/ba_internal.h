@@ -132,6 +132,8 @@ struct Group {
   int frz;            // 0: no instance can be frozen by a gap tolerance (none is set); the
                       // sweep kernels of the default launch plan then skip reading the
                       // frozen flag, which the update kernels always test
+  int s8lc;           // eight-position backward launches: log2 of the columns per block
+                      // (0: as many as the rows hold, up to the value lanes of a node)
 };
 
 enum StreamOp { kOpScatter = 0, kOpGather = 1, kOpInit = 2, kOpRow = 3, kOpVerify = 4, kOpScatterOrbit = 5 };
@@ -194,7 +196,7 @@ __device__ __forceinline__ int hd_exponent(const Consts& c, int n) {
 // (one block per instance, all arrays in LDS); n <= 13 (FP32) or 12 (FP64).
 bool persist_supported(int n, size_t esz);
 template <typename T>
-hipError_t launch_persist(const Group<T>& g, int iters, double floor, int check_tol, hipStream_t s);
+hipError_t launch_persist(const Group<T>& g, int iters, double floor, int check_tol, int threads, hipStream_t s);
 
 // ba_tables.hip
 size_t table_bytes(int n);

@@ -25,9 +25,9 @@
 namespace ba {
 namespace {
 
-constexpr int kPersistThreads = 1024;
-constexpr int kPersistWaves = kPersistThreads / kWave;
-constexpr int kPersistMaxPer = 8;  // inputs per thread: 2^13 / 1024
+// NT threads per block (tuned: 256, 512 or 1024); each thread holds up to 2^13 / NT
+// inputs' D values in registers.
+constexpr int kPersistMaxInputs = 1 << 13;
 
 __device__ __forceinline__ int rank_length(uint32_t r) { return 31 - __clz(r + 1u); }
 
@@ -72,26 +72,29 @@ __device__ __forceinline__ V4<T> v4_zero() {
   return r;
 }
 
-// Block reduction over kPersistThreads threads: each wave reduces its lanes, then
-// the first wave reduces the per-wave records (lanes past kPersistWaves empty); the
-// result is valid in thread 0 only.
+// Block reduction over NT threads: each wave reduces its lanes, then the first wave
+// reduces the per-wave records (lanes past NT / 64 empty); the result is valid in
+// thread 0 only.
+template <int NT>
 __device__ __forceinline__ Part persist_reduce(Part p, Part* sp) {
   p = wave_reduce(p);
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   if (lane == 0) sp[wave] = p;
   __syncthreads();
   Part r = part_empty();
-  if (wave == 0) r = wave_reduce(lane < kPersistWaves ? sp[lane] : part_empty());
+  if (wave == 0) r = wave_reduce(lane < NT / kWave ? sp[lane] : part_empty());
   return r;
 }
 
-template <typename T>
-__global__ __launch_bounds__(kPersistThreads) void k_persist(Group<T> g, int iters, double floor, int check_tol) {
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_persist(Group<T> g, int iters, double floor, int check_tol) {
+  constexpr int kPersistThreads = NT;
+  constexpr int kPersistMaxPer = kPersistMaxInputs / NT;
   const int b = blockIdx.x;
   State* st = g.st + b;
   if (st->converged) return;  // uniform: frozen instances are not iterated
   extern __shared__ __attribute__((aligned(16))) unsigned char persist_smem[];
-  __shared__ Part sp[kPersistWaves];
+  __shared__ Part sp[NT / kWave];
   __shared__ UpdateParams up_sh;
   const int n = g.n;
   const uint32_t X = 1u << n, Y = (2u << n) - 1u, t = threadIdx.x;
@@ -191,7 +194,7 @@ __global__ __launch_bounds__(kPersistThreads) void k_persist(Group<T> g, int ite
         part_add<T>(p, l + double(dv[j]), double(dv[j]), exp_in(l, T()), 0.0, 1.0, step, l + g.eta * double(dv[j]));
       }
     }
-    const Part P = persist_reduce(p, sp);  // valid in thread 0
+    const Part P = persist_reduce<NT>(p, sp);  // valid in thread 0
     if (t == 0) up_sh = update_params_rec<T>(g, b, P, check_tol, true);
     __syncthreads();
     const UpdateParams u = up_sh;
@@ -218,20 +221,29 @@ bool persist_supported(int n, size_t esz) {
   return n >= 1 && n <= top;
 }
 
-template <typename T>
-hipError_t launch_persist(const Group<T>& g, int iters, double floor, int check_tol, hipStream_t s) {
-  const size_t lds = size_t(4u << g.n) * sizeof(T);
-  static_assert(kPersistMaxPer * kPersistThreads >= (1 << 13), "inputs per thread");
+template <typename T, int NT>
+hipError_t launch_persist_nt(const Group<T>& g, int iters, double floor, int check_tol, size_t lds, hipStream_t s) {
   if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_persist<T>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_persist<T, NT>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_persist<T>, dim3(g.nb), dim3(kPersistThreads), lds, s, g, iters, floor, check_tol);
+  hipLaunchKernelGGL((k_persist<T, NT>), dim3(g.nb), dim3(NT), lds, s, g, iters, floor, check_tol);
   return hipGetLastError();
 }
 
-template hipError_t launch_persist<float>(const Group<float>&, int, double, int, hipStream_t);
-template hipError_t launch_persist<double>(const Group<double>&, int, double, int, hipStream_t);
+template <typename T>
+hipError_t launch_persist(const Group<T>& g, int iters, double floor, int check_tol, int threads, hipStream_t s) {
+  const size_t lds = size_t(4u << g.n) * sizeof(T);
+  switch (threads) {
+    case 256: return launch_persist_nt<T, 256>(g, iters, floor, check_tol, lds, s);
+    case 512: return launch_persist_nt<T, 512>(g, iters, floor, check_tol, lds, s);
+    case 1024: return launch_persist_nt<T, 1024>(g, iters, floor, check_tol, lds, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template hipError_t launch_persist<float>(const Group<float>&, int, double, int, int, hipStream_t);
+template hipError_t launch_persist<double>(const Group<double>&, int, double, int, int, hipStream_t);
 
 }  // namespace ba

@@ -240,29 +240,59 @@ def test_config5_n20_stopped_iterate_against_oracle_certification(ba, oracle_nat
 
 @pytest.mark.parametrize("engine", ["factored", "stream"])
 def test_autotuner_choices_do_not_change_results(ba, engine, tmp_path):
+    """Every value of every tuning knob (launch plan, eight-position tile, persistent
+    launch and its block size, scatter LDS budget) gives the same bounds within FP32
+    rounding on a mixed batch with n = 10, 12, 13, 14 (small groups persistent or
+    not, large ones through the launch chain); the tuner's choice is one of the
+    candidates, is cached, and leaves the results unchanged."""
     from paper_2604_05867_amd import autotune
-    ns, ds = [10, 12, 10], [0.64, 0.8, 0.96]
+    ns, ds = [10, 12, 13, 14], [0.64, 0.8, 0.96, 0.7]
     eng = ba.ENGINE_FACTORED if engine == "factored" else ba.ENGINE_STREAM
     ref = None
-    for knob, value in autotune.CANDIDATES[eng]:
-        c = ba.Context(ns, ds, prec=ba.PREC_FP32_LOG, engine=eng)
-        c.set_tuning(knob, value)
-        c.step(10)
-        lo, hi = c.bounds()
-        if ref is None:
-            ref = (lo, hi)
-        assert np.allclose(lo, ref[0], atol=1e-6) and np.allclose(hi, ref[1], atol=1e-6)
-        c.close()
+    for knob, values in autotune.KNOBS[eng]:
+        for value in values:
+            c = ba.Context(ns, ds, prec=ba.PREC_FP32_LOG, engine=eng)
+            c.set_tuning(knob, value)
+            c.step(10)
+            lo, hi = c.bounds()
+            if ref is None:
+                ref = (lo, hi)
+            assert np.allclose(lo, ref[0], atol=1e-6) and np.allclose(hi, ref[1], atol=1e-6), (knob, value)
+            c.close()
     c = ba.Context(ns, ds, prec=ba.PREC_FP32_LOG, engine=eng)
     path = str(tmp_path / "tune.json")
     entry = autotune.tune(c, iters=2, cache_path=path)
-    assert entry["choice"][1] in [v for _, v in autotune.CANDIDATES[eng]]
+    for knob, values in autotune.KNOBS[eng]:
+        assert entry["choice"][str(knob)] in values
     again = autotune.tune(c, cache_path=path)
     assert again["choice"] == entry["choice"]
     c.step(10)
     lo, hi = c.bounds()
     assert np.allclose(lo, ref[0], atol=1e-6) and np.allclose(hi, ref[1], atol=1e-6)
     c.close()
+
+
+@pytest.mark.parametrize("n,prec", [(20, "fp32"), (17, "fp64"), (16, "fp32")])
+def test_stage8_columns_are_bitwise(ba, n, prec):
+    """Every tile of the eight-position backward launches (2^lc columns and
+    correspondingly more subtree roots per block) forms the same sums in the same
+    order: bitwise-equal iterates and bounds."""
+    p = ba.PREC_FP64 if prec == "fp64" else ba.PREC_FP32_LOG
+    ns = [n] * 2
+    ds = [0.64, 0.95]
+    c = ba.Context(ns, ds, prec=p)
+    c.set_tuning(ba.TUNE_PERSISTENT, 0)
+    start = torch.tensor(np.concatenate([np.full(1 << m, -m * LN2) for m in ns]))
+    out = []
+    top = 4 if prec == "fp32" else 3
+    for lc in range(0, top + 1):
+        c.set_logp(start)
+        c.set_tuning(ba.TUNE_STAGE8_COLUMNS, lc)
+        c.step(3)
+        out.append((c.get_logp().cpu().numpy(), c.bounds()))
+    c.close()
+    for o in out[1:]:
+        assert np.array_equal(o[0], out[0][0]) and o[1] == out[0][1]
 
 
 # ---------------------------------------------------------------------------
