@@ -56,12 +56,15 @@ def _time(ctx: Context, start: torch.Tensor, iters: int) -> float:
     return sum(ms for ms, _ in t.values()) / iters
 
 
-def tune(ctx: Context, iters: int = 3, cache_path: str | None = None, force: bool = False) -> dict:
+def tune(ctx: Context, iters: int = 3, cache_path: str | None = None, force: bool = False,
+         margin: float = 0.02) -> dict:
     """Choose and apply the fastest knob settings for ``ctx``'s workload.
 
     Returns {"key", "choice": {knob: value}, "ms_per_iter": {"knob=value": ms}}.
     The timing runs ``iters`` iterations per candidate on the context itself and
-    then restores the starting iterate."""
+    then restores the starting iterate.  A candidate replaces the current choice
+    only if it is faster by more than ``margin`` (relative), so that timing noise
+    does not move a knob away from its default."""
     if ctx.engine not in KNOBS:
         return {"key": None, "choice": {}, "ms_per_iter": {}}
     key = _key(ctx.n, ctx.prec, ctx.engine)
@@ -85,7 +88,9 @@ def tune(ctx: Context, iters: int = 3, cache_path: str | None = None, force: boo
             if label not in results:
                 _apply(ctx, trial)
                 results[label] = _time(ctx, start, iters)
-            if best_ms is None or results[label] < best_ms:
+            if best_ms is None:
+                best_ms = results[label]
+            elif results[label] < best_ms * (1.0 - margin):
                 best_ms = results[label]
                 choice = trial
         _apply(ctx, choice)
