@@ -117,16 +117,6 @@ def lemma2_bound(n: int, d: float, c_nk) -> float:
     return float(sum(math.comb(n, k) * w[k] * c_nk[k] for k in range(n + 1)))
 
 
-def lemma10_bound(n: int, k: int, s: int, c_small, c_rest) -> float:
-    """Lemma 10 (RC23): C_{n,k} <= sum_i [C(s,i) C(n-s,k-i) / C(n,k)] (C_{s,i} + C_{n-s,k-i});
-    c_small[i] = C_{s,i}, c_rest[j] = C_{n-s,j}."""
-    tot = 0.0
-    for i in range(0, s + 1):
-        if 0 <= k - i <= n - s:
-            tot += math.comb(s, i) * math.comb(n - s, k - i) / math.comb(n, k) * (c_small[i] + c_rest[k - i])
-    return tot
-
-
 # ---------------------------------------------------------------------------
 # One Blahut-Arimoto iteration, in the order of Section 2.3 (and Algorithm 1).
 # Probabilities are carried as logs; the paper itself evaluates log W^{(t)} for
