@@ -175,6 +175,7 @@ __global__ __launch_bounds__(kBlock) void k_stream(Tables tb, Group<T> g, int k0
     double ah = 0.0, ahd = 0.0;
     const uint32_t A1 = y1 | (1u << k1);
     const uint32_t R1 = A1 - 1u;  // rank of y1
+    const uint32_t ry1 = (ORB && k1) ? (__brev(y1) >> (32 - k1)) : 0u;  // reversal of y1
     // Scatter: lanes are sorted by (class, y1, x1), so lanes with the same y1 form
     // contiguous runs that, for a given y2, add into the same output.  Per run and
     // 16-lane row a segmented Hillis-Steele scan over DPP row shifts leaves the run's
@@ -236,23 +237,29 @@ __global__ __launch_bounds__(kBlock) void k_stream(Tables tb, Group<T> g, int k0
           const T fe = ok ? T(emb) : T(0);
           uint32_t rank = (A1 << k2) + y2 - 1u;
           size_t i2 = size_t((1u << k2) - 1u + y2) * S1 + R1;
-          T oy = T(1);
+          T oy = T(1);  // orbit mode: 1 / |O_y|
           if constexpr (ORB) {
             // the run's output y (shared by its lanes) goes to its representative,
             // weighted 1 / |O_y|, at the representative's split into the same
-            // lengths k1 + k2 (the combine sums every split of an output)
-            uint32_t yr, ys;
-            orbit_of((y1 << k2) | y2, k, yr, ys);
-            rank = ((1u << k) - 1u) + yr;
+            // lengths k1 + k2 (the combine sums every split of an output).  The
+            // reversal of y1 y2 is rev(y2) rev(y1): rev(y1) is the lane's, rev(y2)
+            // is uniform across the wavefront.
+            const uint32_t yv = (y1 << k2) | y2, mk = (1u << k) - 1u;
+            const uint32_t ry = ((k2 ? (__brev(y2) >> (32 - k2)) : 0u) << k1) | ry1;
+            const uint32_t a = yv, bb = yv ^ mk, cc = ry, dd = ry ^ mk;
+            const uint32_t yr = min(min(a, bb), min(cc, dd));
+            const uint32_t ys = 1u + (bb != a ? 1u : 0u) + ((cc != a && cc != bb) ? 1u : 0u) +
+                                ((dd != a && dd != bb && dd != cc) ? 1u : 0u);
+            rank = mk + yr;
             i2 = size_t((1u << k2) - 1u + (yr & ((1u << k2) - 1u))) * S1 + ((1u << k1) - 1u + (yr >> k2));
-            oy = T(ys);
+            oy = ys == 4u ? T(0.25) : (ys == 2u ? T(0.5) : T(1));  // 1 / |O_y|, exact
           }
 #pragma unroll
           for (int b = 0; b < kTile; ++b) {
             if (b >= nbt || !((live >> b) & 1u)) continue;  // uniform
             T cv = seg_row_sum(pl[b] * fe, sm1, sm2, sm4, sm8);
             if (emit && ok && cv != T(0)) {
-              if constexpr (ORB) cv = cv / oy;
+              if constexpr (ORB) cv = cv * oy;
               if (k <= k0) lds_add(&rs[b * nshort + rank], cv);
               else atomic_add(&g.v2[(size_t)(b0 + b) * g.v2s + i2], cv);
             }
