@@ -182,6 +182,8 @@ def test_fp64_iterates_match_oracle(ba, engine, n, d, iters):
     ctx = ba.Context(n, d, engine=engine_id(ba, "factored" if engine == "persistent" else engine))
     if engine == "factored":
         chain(ctx)
+    elif engine == "persistent":
+        ctx.set_tuning(ba.TUNE_PERSISTENT, 2)
     ctx.step(iters)
     lp_g = ctx.get_logp().cpu().numpy()
     lp_o = bdc.ba_iterate(W, bdc.uniform_logp(n), iters)
@@ -667,7 +669,7 @@ def test_persistent_equals_chain(ba, case):
     iters = kw.get("iters", 40)
     say("persistent vs chain: %s" % case)
     out = []
-    for persistent in (0, 1):
+    for persistent in (0, 2):
         c = ba.Context(kw["n"], kw.get("d", None), prec=p, k=kw.get("k"))
         c.set_tuning(ba.TUNE_PERSISTENT, persistent)
         if "eta" in kw:
