@@ -49,11 +49,11 @@ FUSE = 5  # the library default (positions per launch of the factored engine)
 MEASURED_TRAFFIC = {
     "sources": ["paper_2604_05867_amd/csrc/ba_factored.hip", "paper_2604_05867_amd/csrc/ba_factored_common.h"],
     # of the sources concatenated
-    "sha256": "6e9b3fcc395f4e055e1fc4beb8af028e35772f480005b4cd5f203227e5120674",
+    "sha256": "181e503da10d9152f13247f1f339fd4a89b32d3bc33078ab06d7fd10cb589761",
     # forward: k_fwd_first8, k_fwd_stage4 x2, k_fwd_last4; backward: k_bwd_stage8_p x2,
     # k_bwd_stage4 with D fused
-    "sweep1": 53683000,
-    "sweep2": 55173000,
+    "sweep1": 53678000,
+    "sweep2": 55172000,
 }
 
 
