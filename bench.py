@@ -38,7 +38,7 @@ sys.path.insert(0, ROOT)
 N = 20
 DS = [0.64, 0.80, 0.95]
 UNIT_EQUIV = "W-nonzero-equivalent terms/s (factored engine: nonzeros accounted, not visited)"
-FUSE = 5  # the library default (positions per launch of the factored engine)
+FUSE = 6  # the library default (positions per launch of the factored engine)
 
 
 # HBM bytes per launch of this workload's sweeps, from rocprofv3 FETCH_SIZE and
@@ -50,8 +50,8 @@ MEASURED_TRAFFIC = {
     "sources": ["paper_2604_05867_amd/csrc/ba_factored.hip", "paper_2604_05867_amd/csrc/ba_factored_common.h"],
     # of the sources concatenated
     "sha256": "181e503da10d9152f13247f1f339fd4a89b32d3bc33078ab06d7fd10cb589761",
-    # forward: k_fwd_first8, k_fwd_stage4 x2, k_fwd_last4; backward: k_bwd_stage8_p x2,
-    # k_bwd_stage4 with D fused
+    # forward: k_fwd_first8, k_fwd_stage4 x2, k_fwd_last4; backward: k_bwd_stage12,
+    # k_bwd_stage8_p with D fused
     "sweep1": 53678000,
     "sweep2": 55172000,
 }
@@ -90,7 +90,8 @@ def sweep_launch_bytes(n, esz, nb, fuse, backward, fused_update=0.0):
     backward: the first n mod 4 positions two or one at a time), fuse 3 = as 2 with
     eight positions per backward launch while four remain after it, fuse 4 = as 3
     with the forward's last four positions in one launch (n >= 12), fuse 5 = as 4
-    with the forward's first eight positions in one launch (n >= 12), fuse 1 = two."""
+    with the forward's first eight positions in one launch (n >= 12), fuse 6 = as 5
+    with the backward at n = 20 as twelve positions then eight, fuse 1 = two."""
     s = stage_sizes(n)
     steps = []
     if not backward:
@@ -107,6 +108,8 @@ def sweep_launch_bytes(n, esz, nb, fuse, backward, fused_update=0.0):
                 t = 2 if (fuse and i + 2 <= n and not (last4 and n - i - 2 < 4)) else 1
             steps.append((i, i + t))
             i += t
+    elif fuse >= 6 and n == 20:
+        steps = [(20, 8), (8, 0)]
     else:
         top, lead = n, (n % 4 if (fuse >= 2 and n >= 4) else -1)
         while top > 0:
@@ -461,7 +464,7 @@ def main():
                 "frac": round(achieved / 8000.0, 4),
                 "traffic": measured_traffic(dom),
                 "kernel": ("forward sweep (k_fwd_first8, k_fwd_stage4 x2, k_fwd_last4)" if dom == "sweep1"
-                           else "backward sweep (k_bwd_stage8_p x2, k_bwd_stage4 with D fused)"),
+                           else "backward sweep (k_bwd_stage12, k_bwd_stage8_p with D fused)"),
                 "bytes_per_launch": int(bytes_launch), "avg_launch_us": round(per_launch_ms * 1e3, 2)}
 
     lo, hi = ctx.bounds()

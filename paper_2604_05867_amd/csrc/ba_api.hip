@@ -76,7 +76,7 @@ struct ba_ctx {
   std::string err;
   // tuning
   int scatter_lds_kb = 64;
-  int fuse = 5;  // factored engine: positions per launch (see BA_TUNE_FACTORED_FUSE)
+  int fuse = 6;  // factored engine: positions per launch (see BA_TUNE_FACTORED_FUSE)
   int stop_rule = BA_STOP_ITERATE;
   int sym = 0;   // complement-symmetric iteration requested
   double eta = 1.0;  // update step (1 = BA)
@@ -631,7 +631,7 @@ int ba_set_tuning(ba_ctx* c, int key, int value) {
     return BA_OK;
   }
   if (key == BA_TUNE_FACTORED_FUSE) {
-    if (value < 0 || value > 5) return fail(c, BA_EINVAL, "fuse must be 0 .. 5");
+    if (value < 0 || value > 6) return fail(c, BA_EINVAL, "fuse must be 0 .. 6");
     c->fuse = value;
     drop_graph(c);
     return BA_OK;

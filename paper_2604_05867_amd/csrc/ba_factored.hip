@@ -1108,7 +1108,10 @@ __global__ __launch_bounds__(32 * stage8_tile<T>()) void k_bwd_stage8(int n, int
 // subtree of "0", grouped as for kS8Roots over its levels) and, in one extra block,
 // the empty row; root w writes its columns u < 128 to row w and its columns
 // u >= 128, reversed, to row cpl w of the canonical-half B_i (row width 128).
-enum Stage8Mode { kS8Columns = 0, kS8Roots = 1, kS8SymRoots = 2 };
+// kS8ColumnsD: kS8Columns at i = 0 (the one root is the empty row, B_0 = G) with
+// D(x) = H(x) - G(x) - M and the block's record formed instead of writing G; the
+// record index is the block's column block.
+enum Stage8Mode { kS8Columns = 0, kS8Roots = 1, kS8SymRoots = 2, kS8ColumnsD = 3 };
 
 __host__ __device__ constexpr uint32_t stage8_sigma_bits(uint32_t q) {
   return ((uint32_t(__builtin_popcount(q & 0xAAAAAAAAu)) & 1u) << 1) | (uint32_t(__builtin_popcount(q)) & 1u);
@@ -1117,8 +1120,10 @@ __host__ __device__ constexpr uint32_t stage8_sigma_bits(uint32_t q) {
 template <typename T, int MODE>
 __global__ __launch_bounds__(32 * stage8_tile<T>()) void k_bwd_stage8_p(int n, int i, const T* __restrict__ src,
                                                                       size_t sstride, T* __restrict__ dst,
-                                                                      size_t dstride, const State* st, int frz) {
-  constexpr bool ROOTS = MODE != kS8Columns, SYM = MODE == kS8SymRoots;
+                                                                      size_t dstride, const State* st, int frz,
+                                                                      Group<T> g) {
+  constexpr bool ROOTS = MODE == kS8Roots || MODE == kS8SymRoots, SYM = MODE == kS8SymRoots;
+  constexpr bool DP = MODE == kS8ColumnsD;
   constexpr uint32_t P = uint32_t(stage8_tile<T>());  // value lanes per node
   constexpr int LP = P == 16 ? 4 : 3;
   constexpr uint32_t NT = 32u * P;                     // threads
@@ -1313,6 +1318,23 @@ __global__ __launch_bounds__(32 * stage8_tile<T>()) void k_bwd_stage8_p(int n, i
       const uint32_t rho = f >> 6, j = f & 63u;
       if (rho < nr) stv<T, 4>(o + (rho << 8) + 4u * j, ld<T, 4>(buf + rho * kOutPitch + 4u * j));
     }
+  } else if constexpr (DP) {
+    // D at the inputs x = w S8 + s0 + (vector j) of output column group w = f / 4
+    // of 256, vector j = f mod 4, and the block's record
+    constexpr int K = int((256u * 4u) / NT);
+    const double M = g.st[b].M;
+    uint32_t xs[K];
+    Vec<T, VW> gv[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const uint32_t f = t + uint32_t(k) * NT;
+      const uint32_t w = f >> 2, j = f & 3u;
+      xs[k] = (w << sh) + s0 + j * uint32_t(VW);
+      gv[k] = ld<T, VW>(buf + (w << LP) + j * uint32_t(VW));
+    }
+    Part p = part_empty();
+    d_records<T, VW, K>(g, b, M, xs, gv, p);
+    store_block_part_nt<int(NT)>(g.part + (size_t)b * g.ps, int(lin & ((1u << lcb) - 1u)), p);
   } else {
     // copy-out: output column group w = f / 4 of 256, vector j = f mod 4
     T* o = dst + ((size_t)r0 << (sh + 8)) + s0;
@@ -1322,6 +1344,136 @@ __global__ __launch_bounds__(32 * stage8_tile<T>()) void k_bwd_stage8_p(int n, i
       const uint32_t w = f >> 2, j = f & 3u;
       stv<T, VW>(o + ((size_t)w << sh) + j * uint32_t(VW), ld<T, VW>(buf + (w << LP) + j * uint32_t(VW)));
     }
+  }
+}
+
+// Twelve backward positions from v in one launch (i = n - 12 .. n - 1, for n =
+// kStage12N), one root row y of B_i per block.  The depth-12 subtree of y in v (depth
+// k is one run of 2^k consecutive ranks) is copied to LDS; three four-position steps
+// then form B_{i+8} at the 511 nodes of depth <= 8 (16 columns each), B_{i+4} at the
+// 31 nodes of depth <= 4 (256 columns) and the row B_i[y] (4096 columns), every value
+// as bwd4_tree on 31 values: the same sums in the same order as three four-position
+// launches.  Column u3 2^8 + u2 2^4 + u1 of B_i: u3 holds the input bits of
+// positions i .. i+3, u2 of i+4 .. i+7, u1 of i+8 .. i+11 (the first one highest).
+// Root order: XCD x (blockIdx.x mod 8) takes the roots in the subtree of node x of
+// level 3, deepest level first, then root x of the 7 above level 3 (x < 7).  The
+// subtrees of the roots an XCD takes lie in that node's eighth of v, except for
+// those 7.
+// LDS, 32 banks of 4 bytes: node q (1-based heap index in y's subtree) at
+// stage12_slot(q) = q ^ ((q >> 5) & 15): for 32 consecutive nodes a of one level
+// (32-aligned) and any descendant offset (d <= 4, m < 2^d), the nodes a 2^d + m have
+// distinct slots mod 32.  B_{i+8} as [column][node] under the same permutation
+// (written by consecutive nodes, read by 32 consecutive nodes z < 32 at one column);
+// B_{i+4} as [node z][column ^ z] (written by 32 nodes z at one column, read at
+// consecutive columns of one node).
+constexpr int kStage12N = 20;
+constexpr uint32_t kStage12Threads = 512;
+
+__device__ __forceinline__ uint32_t stage12_slot(uint32_t q) { return q ^ ((q >> 5) & 15u); }
+
+template <typename T>
+__global__ __launch_bounds__(kStage12Threads) void k_bwd_stage12(int n, const T* __restrict__ src, size_t sstride,
+                                                                 T* __restrict__ dst, size_t dstride, const State* st,
+                                                                 int frz) {
+  const int b = blockIdx.y;
+  if (frz && st[b].converged) return;
+  const int i = n - 12;
+  // slot k of XCD x: the 2^(L+1) - 1 roots of level-3 node x's subtree (L = i - 3
+  // levels below it), then top root x
+  const uint32_t x = blockIdx.x & 7u, k = blockIdx.x >> 3;
+  const int L = i - 3;
+  uint32_t root;
+  if (k + 1u == (2u << L)) {
+    if (x >= 7u) return;
+    root = x;
+  } else {
+    const uint32_t r = (2u << L) - 1u - k;  // 1 .. 2^(L+1) - 1
+    const int l = 31 - __clz(r);            // level l below level 3
+    root = ((8u + x) << l) - 1u + ((2u << l) - 1u - r);
+  }
+  src += (size_t)b * sstride;
+  dst += (size_t)b * dstride;
+  __shared__ __attribute__((aligned(16))) T buf[8192];
+  const uint32_t t = threadIdx.x;
+  {
+    // copy-in, every load of a thread before its LDS stores: depths 0..8 one node
+    // q = t + 1 per thread, depth k >= 9 2^(k-9) per thread
+    T v[16];
+    uint32_t li[16];
+    {
+      const uint32_t q = t + 1u;
+      const int kq = 31 - __clz(q);
+      li[0] = ~0u;
+      if (q < 512u) {
+        v[0] = src[((root + 1u) << kq) - 1u + (q - (1u << kq))];
+        li[0] = stage12_slot(q);
+      }
+    }
+#pragma unroll
+    for (int kk = 9; kk <= 12; ++kk) {
+      const uint32_t base = ((root + 1u) << kk) - 1u;
+#pragma unroll
+      for (int j = 0; j < (1 << (kk - 9)); ++j) {
+        const uint32_t m = t + uint32_t(j) * kStage12Threads;
+        const int sl = (1 << (kk - 9)) + j;  // 1, 2-3, 4-7, 8-15
+        v[sl] = src[base + m];
+        li[sl] = stage12_slot((1u << kk) + m);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+      if (li[j] != ~0u) buf[li[j]] = v[j];
+  }
+  __syncthreads();
+  // step 1: thread a = node of depth <= 8 (a = 0 idles): B_{i+8}[a][u1]
+  Vec<T, 1> Dv[16];
+  const uint32_t a = t;
+  if (a != 0u) {
+    Vec<T, 1> S[31];
+#pragma unroll
+    for (int d = 0; d <= 4; ++d)
+#pragma unroll
+      for (int m = 0; m < (1 << d); ++m) S[(1 << d) - 1 + m].v[0] = buf[stage12_slot((a << d) + uint32_t(m))];
+    bwd4_tree<T, 1>(S, Dv);
+  }
+  __syncthreads();
+  if (a != 0u) {
+    const uint32_t sa = stage12_slot(a);
+#pragma unroll
+    for (int u = 0; u < 16; ++u) buf[uint32_t(u) * 512u + sa] = Dv[u].v[0];
+  }
+  __syncthreads();
+  // step 2: thread (column c = u1, node z of depth <= 4; z = 0 idles): B_{i+4}[z][u2 16 + c]
+  const uint32_t c = t >> 5, z = t & 31u;
+  if (z != 0u) {
+    Vec<T, 1> S[31];
+    const T* col = buf + c * 512u;
+#pragma unroll
+    for (int d = 0; d <= 4; ++d)
+#pragma unroll
+      for (int m = 0; m < (1 << d); ++m) S[(1 << d) - 1 + m].v[0] = col[stage12_slot((z << d) + uint32_t(m))];
+    bwd4_tree<T, 1>(S, Dv);
+  }
+  __syncthreads();
+  if (z != 0u) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) buf[z * 256u + ((uint32_t(u) * 16u + c) ^ z)] = Dv[u].v[0];
+  }
+  __syncthreads();
+  // step 3: thread c2 < 256 (column u2 16 + u1): B_i[root][u3 256 + c2], written out
+  if (t < 256u) {
+    Vec<T, 1> S[31];
+#pragma unroll
+    for (int d = 0; d <= 4; ++d)
+#pragma unroll
+      for (int m = 0; m < (1 << d); ++m) {
+        const uint32_t q = (1u << d) + uint32_t(m);
+        S[(1 << d) - 1 + m].v[0] = buf[q * 256u + (t ^ q)];
+      }
+    bwd4_tree<T, 1>(S, Dv);
+    T* o = dst + ((size_t)root << 12) + t;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) o[uint32_t(u) * 256u] = Dv[u].v[0];
   }
 }
 
@@ -1490,6 +1642,35 @@ hipError_t launch_backward(const Group<T>& g, hipStream_t s, int* launches, int 
   // fuse = 3: the same with eight positions per launch while four remain after
   const int lead = (fuse >= 2 && n >= 4) ? n % 4 : -1;
   for (int top = n; top > 0; k++) {           // B_top -> B_{top-step}
+    // fuse >= 6 at n = kStage12N: the last twelve positions in one launch, then the
+    // first eight in one (with D and its records when dpart)
+    if (fuse >= 6 && n == kStage12N && top == n) {
+      const int i = n - 12;
+      T* dst = (k & 1) ? g.f1 : g.f0;
+      hipLaunchKernelGGL((k_bwd_stage12<T>), dim3(8u << (i - 2), g.nb), dim3(kStage12Threads), 0, s, n, src, ss,
+                         dst, g.fs, g.st, g.frz);
+      if (launches) ++*launches;
+      src = dst;
+      ss = g.fs;
+      top = i;
+      continue;
+    }
+    if (fuse >= 6 && n == kStage12N && top == 8) {
+      constexpr int LP = stage8_tile<T>() == 16 ? 4 : 3;
+      const dim3 grid(1u << (n - 8 - LP), 1, g.nb);  // column blocks of P columns
+      const dim3 block(32 * stage8_tile<T>());
+      if (dpart) {
+        hipLaunchKernelGGL((k_bwd_stage8_p<T, kS8ColumnsD>), grid, block, 0, s, n, 0, src, ss, g.g, g.xs, g.st,
+                           g.frz, g);
+        if (dpart_blocks) *dpart_blocks = int(grid.x);
+      } else {
+        hipLaunchKernelGGL((k_bwd_stage8_p<T, kS8Columns>), grid, block, 0, s, n, 0, src, ss, g.g, g.xs, g.st,
+                           g.frz, g);
+      }
+      if (launches) ++*launches;
+      top = 0;
+      continue;
+    }
     if (fuse >= 3 && lead >= 0 && n - top >= lead && top - 8 >= 4) {
       const int i = top - 8;
       T* dst = (k & 1) ? g.f1 : g.f0;
@@ -1501,10 +1682,10 @@ hipError_t launch_backward(const Group<T>& g, hipStream_t s, int* launches, int 
       const dim3 block(32 * stage8_tile<T>());
       if (lc == LP) {
         hipLaunchKernelGGL((k_bwd_stage8_p<T, kS8Columns>), grid, block, 0, s, n, i, src, ss, dst, g.fs, g.st,
-                           g.frz);
+                           g.frz, g);
       } else if (lc == 0) {
         hipLaunchKernelGGL((k_bwd_stage8_p<T, kS8Roots>), grid, block, 0, s, n, i, src, ss, dst, g.fs, g.st,
-                           g.frz);
+                           g.frz, g);
       } else switch (lc) {
         case 1: hipLaunchKernelGGL((k_bwd_stage8<T, 1>), grid, block, 0, s, n, i, src, ss, dst, g.fs, g.st); break;
         case 2: hipLaunchKernelGGL((k_bwd_stage8<T, 2>), grid, block, 0, s, n, i, src, ss, dst, g.fs, g.st); break;
@@ -1618,13 +1799,14 @@ hipError_t launch_backward8_sym_v(const Group<T>& g, hipStream_t s, T* dst) {
   const uint32_t slots = stage8_slots(i - 1, LP) + 1u;  // + the empty row
   const dim3 grid((slots + 7u) & ~7u, 1, g.nb);
   hipLaunchKernelGGL((k_bwd_stage8_p<T, kS8SymRoots>), grid, dim3(32 * stage8_tile<T>()), 0, s, n, i, g.v, g.ys,
-                     dst, g.fs, g.st, g.frz);
+                     dst, g.fs, g.st, g.frz, g);
   return hipGetLastError();
 }
 template hipError_t launch_backward8_sym_v<float>(const Group<float>&, hipStream_t, float*);
 template hipError_t launch_backward8_sym_v<double>(const Group<double>&, hipStream_t, double*);
 
 int backward_launches(int n, int fuse) {
+  if (fuse >= 6 && n == kStage12N) return 2;
   if (fuse >= 3 && n >= 4) {
     const int four = n / 4, eight = (four - 1) / 2;  // the last launch keeps four positions
     return four - eight + (n % 4 + 1) / 2;

@@ -220,18 +220,22 @@ __device__ __forceinline__ Part gather_parts(const double* src, int nblk) {
 
 // Reduce the block's records and store the result as record rec of an instance
 // whose records start at `part`.  Only thread 0 combines the per-wave records and
-// writes (blockDim.x == kBlock).
-__device__ __forceinline__ void store_block_part(double* part, int rec, Part p) {
-  __shared__ Part sp[kBlock / kWave];
+// writes (blockDim.x == NT, kBlock for store_block_part).
+template <int NT>
+__device__ __forceinline__ void store_block_part_nt(double* part, int rec, Part p) {
+  __shared__ Part sp[NT / kWave];
   p = wave_reduce(p);
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   if (lane == 0) sp[wave] = p;
   __syncthreads();
   if (threadIdx.x == 0) {
     Part r = sp[0];
-    for (int w = 1; w < kBlock / kWave; ++w) r = combine(r, sp[w]);
+    for (int w = 1; w < NT / kWave; ++w) r = combine(r, sp[w]);
     store_part(part + (size_t)rec * kPartStride, r);
   }
+}
+__device__ __forceinline__ void store_block_part(double* part, int rec, Part p) {
+  store_block_part_nt<kBlock>(part, rec, p);
 }
 
 }  // namespace ba

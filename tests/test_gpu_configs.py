@@ -282,6 +282,7 @@ def test_stage8_columns_are_bitwise(ba, n, prec):
     ds = [0.64, 0.95]
     c = ba.Context(ns, ds, prec=p)
     c.set_tuning(ba.TUNE_PERSISTENT, 0)
+    c.set_tuning(ba.TUNE_FACTORED_FUSE, 5)  # the plan whose backward has eight-position launches at every n
     start = torch.tensor(np.concatenate([np.full(1 << m, -m * LN2) for m in ns]))
     out = []
     top = 4 if prec == "fp32" else 3

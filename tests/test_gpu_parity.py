@@ -387,15 +387,17 @@ def test_graph_needs_a_stream(ba):
     c.close()
 
 
-@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6, 7, 8, 12, 13, 16, 17])
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6, 7, 8, 12, 13, 16, 17, 20])
 def test_factored_fusion_settings_agree(ba, n):
-    """One, two, four and eight input positions per launch, and the last four and
-    the first eight forward positions in one launch, give the same evaluation (all
-    against the oracle for n <= 8)."""
+    """One, two, four and eight input positions per launch, the last four and the
+    first eight forward positions in one launch, and (n = 20) the backward sweep as
+    twelve positions then eight, give the same evaluation (all against the oracle
+    for n <= 8)."""
     d = 0.6
     lp = inp.random_logp(n, seed=40 + n, spread=2.0)
+    say("fusion settings n=%d" % n)
     out = []
-    for fuse in (0, 1, 2, 3, 4, 5):
+    for fuse in (0, 1, 2, 3, 4, 5, 6):
         c = ba.Context(n, d)
         c.set_tuning(ba.TUNE_FACTORED_FUSE, fuse)
         got = c.eval(torch.from_numpy(lp))
@@ -409,7 +411,7 @@ def test_factored_fusion_settings_agree(ba, n):
     # the same order: bitwise equal
     c = ba.Context(n, d)
     same = []
-    for fuse in (2, 3, 4, 5):
+    for fuse in (2, 3, 4, 5, 6):
         c.set_tuning(ba.TUNE_FACTORED_FUSE, fuse)
         got = c.eval(torch.from_numpy(lp))
         same.append((got["L"], got["U"], got["r"].cpu().numpy(), got["D"].cpu().numpy()))
@@ -417,6 +419,8 @@ def test_factored_fusion_settings_agree(ba, n):
     assert np.array_equal(same[0][3], same[1][3]) and same[0][0] == same[1][0] and same[0][1] == same[1][1]
     # the first eight forward positions in one launch are two four-position steps
     assert np.array_equal(same[2][2], same[3][2]) and np.array_equal(same[2][3], same[3][3])
+    # twelve backward positions in one launch are three four-position steps
+    assert np.array_equal(same[3][3], same[4][3]) and same[3][0] == same[4][0] and same[3][1] == same[4][1]
     if n <= 8:
         ev = bdc.evaluate(bdc.channel_dense(n, d), lp)
         assert abs(out[1][0] - ev.L / LN2) < 1e-11
@@ -458,6 +462,31 @@ def test_eight_position_backward_is_bitwise_four(ba, n, prec):
     assert out[0][0].shape == (X,)
     assert np.array_equal(out[0][0], out[1][0])
     assert out[0][1] == out[1][1]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_twelve_position_backward_iterates(ba, prec):
+    """At n = 20 the backward sweep as twelve positions then eight with D (launch
+    plan level 6) gives the iterates and bounds of level 5 (eight, eight, four with
+    D): the same G; only the grouping of the D records' sums differs."""
+    n = 20
+    p = ba.PREC_FP64 if prec == "fp64" else ba.PREC_FP32_LOG
+    ns = [n] * 3 if prec == "fp32" else [n]
+    ds = [0.64, 0.8, 0.95] if prec == "fp32" else [0.7]
+    say("twelve-position backward %s" % prec)
+    c = chain(ba.Context(ns, ds, prec=p))
+    start = torch.tensor(np.concatenate([np.full(1 << m, -m * LN2) for m in ns]))
+    out = []
+    for fuse in (5, 6):
+        c.set_logp(start)
+        c.set_tuning(ba.TUNE_FACTORED_FUSE, fuse)
+        c.step(4)
+        out.append((c.get_logp().cpu().numpy(), c.bounds()))
+    c.close()
+    tol = 1e-12 if prec == "fp64" else 1e-5
+    assert np.max(np.abs(out[0][0] - out[1][0])) < tol
+    for k in range(len(ns)):
+        assert abs(out[0][1][0][k] - out[1][1][0][k]) < tol and abs(out[0][1][1][k] - out[1][1][1][k]) < tol
 
 
 @pytest.mark.parametrize("n,prec", [(12, "fp64"), (17, "fp64"), (20, "fp32"), (20, "fp64")])
