@@ -401,7 +401,7 @@ int sweeps(ba_ctx* c, const GroupHost& gh, const Group<T>& G, int use_sw_g, T* g
       HIPCHK(c, launch_logr<T>(G, use_sw_g, 0, n1, n2, s));
     }
     {
-      Timer t(c, BA_K_SWEEP2, backward_launches(n, c->fuse));
+      Timer t(c, BA_K_SWEEP2, backward_launches(n, c->fuse, int(sizeof(T))));
       Group<T> G2 = G;
       G2.g = g_out;
       G2.s8lc = c->s8lc;

@@ -1236,6 +1236,20 @@ __global__ __launch_bounds__(32 * stage8_tile<T>()) void k_bwd_stage8_p(int n, i
     for (int k = 0; k < kPer; ++k)
       if (li[k] != ~0u) stv<T, VW>(buf + li[k], v[k]);
   }
+  // DP: the inputs x = w S8 + s0 + (vector j) of output column group w = f / 4 of
+  // 256, vector j = f mod 4; their H and log p are loaded now and held through the
+  // two steps
+  constexpr int KD = int((256u * 4u) / NT);
+  uint32_t xs[KD];
+  Vec<T, VW> hd[KD], lq[KD];
+  if constexpr (DP) {
+#pragma unroll
+    for (int k = 0; k < KD; ++k) {
+      const uint32_t f = t + uint32_t(k) * NT;
+      xs[k] = ((f >> 2) << sh) + s0 + (f & 3u) * uint32_t(VW);
+    }
+    d_loads<T, VW, KD>(g, b, xs, hd, lq);
+  }
   __syncthreads();
   // step 1: thread (z = 1-based node a of the depth-4 subtree, lane c1); a = 0 idles
   Vec<T, 1> Dv[16];
@@ -1319,21 +1333,16 @@ __global__ __launch_bounds__(32 * stage8_tile<T>()) void k_bwd_stage8_p(int n, i
       if (rho < nr) stv<T, 4>(o + (rho << 8) + 4u * j, ld<T, 4>(buf + rho * kOutPitch + 4u * j));
     }
   } else if constexpr (DP) {
-    // D at the inputs x = w S8 + s0 + (vector j) of output column group w = f / 4
-    // of 256, vector j = f mod 4, and the block's record
-    constexpr int K = int((256u * 4u) / NT);
+    // D at the inputs xs from G of column group w, vector j, and the block's record
     const double M = g.st[b].M;
-    uint32_t xs[K];
-    Vec<T, VW> gv[K];
+    Vec<T, VW> gv[KD];
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
+    for (int k = 0; k < KD; ++k) {
       const uint32_t f = t + uint32_t(k) * NT;
-      const uint32_t w = f >> 2, j = f & 3u;
-      xs[k] = (w << sh) + s0 + j * uint32_t(VW);
-      gv[k] = ld<T, VW>(buf + (w << LP) + j * uint32_t(VW));
+      gv[k] = ld<T, VW>(buf + ((f >> 2) << LP) + (f & 3u) * uint32_t(VW));
     }
     Part p = part_empty();
-    d_records<T, VW, K>(g, b, M, xs, gv, p);
+    d_records_pre<T, VW, KD>(g, b, M, xs, gv, hd, lq, p);
     store_block_part_nt<int(NT)>(g.part + (size_t)b * g.ps, int(lin & ((1u << lcb) - 1u)), p);
   } else {
     // copy-out: output column group w = f / 4 of 256, vector j = f mod 4
@@ -1348,38 +1357,44 @@ __global__ __launch_bounds__(32 * stage8_tile<T>()) void k_bwd_stage8_p(int n, i
 }
 
 // Twelve backward positions from v in one launch (i = n - 12 .. n - 1, for n =
-// kStage12N), one root row y of B_i per block.  The depth-12 subtree of y in v (depth
-// k is one run of 2^k consecutive ranks) is copied to LDS; three four-position steps
-// then form B_{i+8} at the 511 nodes of depth <= 8 (16 columns each), B_{i+4} at the
-// 31 nodes of depth <= 4 (256 columns) and the row B_i[y] (4096 columns), every value
-// as bwd4_tree on 31 values: the same sums in the same order as three four-position
-// launches.  Column u3 2^8 + u2 2^4 + u1 of B_i: u3 holds the input bits of
-// positions i .. i+3, u2 of i+4 .. i+7, u1 of i+8 .. i+11 (the first one highest).
+// kStage12N, FP32), one root row y of B_i per block.  The depth-12 subtree of y in v
+// (depth k is one run of 2^k consecutive ranks) is copied to LDS; three
+// four-position steps then form B_{i+8} at the 511 nodes of depth <= 8 (16 columns
+// each), B_{i+4} at the 31 nodes of depth <= 4 (256 columns) and the row B_i[y]
+// (4096 columns), every value as bwd4_tree on 31 values: the same sums in the same
+// order as three four-position launches.  Column u3 2^8 + u2 2^4 + u1 of B_i: u3
+// holds the input bits of positions i .. i+3, u2 of i+4 .. i+7, u1 of i+8 .. i+11
+// (the first one highest).
 // Root order: XCD x (blockIdx.x mod 8) takes the roots in the subtree of node x of
 // level 3, deepest level first, then root x of the 7 above level 3 (x < 7).  The
 // subtrees of the roots an XCD takes lie in that node's eighth of v, except for
 // those 7.
-// LDS, 32 banks of 4 bytes: node q (1-based heap index in y's subtree) at
-// stage12_slot(q) = q ^ ((q >> 5) & 15): for 32 consecutive nodes a of one level
-// (32-aligned) and any descendant offset (d <= 4, m < 2^d), the nodes a 2^d + m have
-// distinct slots mod 32.  B_{i+8} as [column][node] under the same permutation
-// (written by consecutive nodes, read by 32 consecutive nodes z < 32 at one column);
-// B_{i+4} as [node z][column ^ z] (written by 32 nodes z at one column, read at
-// consecutive columns of one node).
+// LDS, 32 banks of 4 bytes, one padding word per 32: node q (1-based heap index in
+// y's subtree) at stage12_slot(q) = q + q / 32.  For 32 consecutive nodes a of one
+// level (32-aligned) and any descendant offset (d <= 4, m < 2^d) the slots of
+// a 2^d + m are distinct mod 32, and slot(a 2^d + m) = slot(a 2^d) + m, so a step
+// reads its 31 values at five per-thread bases plus instruction offsets.  B_{i+8} as
+// [column][node] with the same slots (column pitch kS12P1); B_{i+4} as [node z]
+// [column] with the odd pitch kS12P2 (written by 32 nodes z at one column, read at
+// consecutive columns of one node).  (A block taking two roots, with the second
+// one's loads in flight through the first one's steps, ran at three blocks per CU
+// instead of four and was slower: 16.6 against 15.6 us at n = 20, 3 x FP32.)
 constexpr int kStage12N = 20;
 constexpr uint32_t kStage12Threads = 512;
+constexpr uint32_t kS12Words = 8192u + 256u;      // LDS words: 8192 slots and their padding
+constexpr uint32_t kS12P1 = 512u + 16u, kS12P2 = 257u;
 
-__device__ __forceinline__ uint32_t stage12_slot(uint32_t q) { return q ^ ((q >> 5) & 15u); }
+__device__ __forceinline__ uint32_t stage12_slot(uint32_t q) { return q + (q >> 5); }
 
-template <typename T>
-__global__ __launch_bounds__(kStage12Threads) void k_bwd_stage12(int n, const T* __restrict__ src, size_t sstride,
-                                                                 T* __restrict__ dst, size_t dstride, const State* st,
-                                                                 int frz) {
+__global__ __launch_bounds__(kStage12Threads) __attribute__((amdgpu_waves_per_eu(8))) void k_bwd_stage12(
+    int n, const float* __restrict__ src, size_t sstride, float* __restrict__ dst, size_t dstride, const State* st,
+    int frz) {
+  using T = float;
   const int b = blockIdx.y;
   if (frz && st[b].converged) return;
   const int i = n - 12;
   // slot k of XCD x: the 2^(L+1) - 1 roots of level-3 node x's subtree (L = i - 3
-  // levels below it), then top root x
+  // levels below it), deepest level first, then top root x
   const uint32_t x = blockIdx.x & 7u, k = blockIdx.x >> 3;
   const int L = i - 3;
   uint32_t root;
@@ -1393,36 +1408,29 @@ __global__ __launch_bounds__(kStage12Threads) void k_bwd_stage12(int n, const T*
   }
   src += (size_t)b * sstride;
   dst += (size_t)b * dstride;
-  __shared__ __attribute__((aligned(16))) T buf[8192];
+  __shared__ __attribute__((aligned(16))) T buf[kS12Words];
   const uint32_t t = threadIdx.x;
   {
     // copy-in, every load of a thread before its LDS stores: depths 0..8 one node
-    // q = t + 1 per thread, depth k >= 9 2^(k-9) per thread
+    // q = t + 1 per thread, depth k >= 9 2^(k-9) values t + 512 j, whose slots are
+    // (1 << k) + (1 << (k - 5)) + 528 j + slot(t)
     T v[16];
-    uint32_t li[16];
-    {
-      const uint32_t q = t + 1u;
-      const int kq = 31 - __clz(q);
-      li[0] = ~0u;
-      if (q < 512u) {
-        v[0] = src[((root + 1u) << kq) - 1u + (q - (1u << kq))];
-        li[0] = stage12_slot(q);
-      }
-    }
+    const uint32_t q = t + 1u;
+    const int kq = 31 - __clz(q);
+    if (q < 512u) v[0] = src[((root + 1u) << kq) - 1u + (q - (1u << kq))];
 #pragma unroll
     for (int kk = 9; kk <= 12; ++kk) {
-      const uint32_t base = ((root + 1u) << kk) - 1u;
+      const T* base = src + (((root + 1u) << kk) - 1u);
 #pragma unroll
-      for (int j = 0; j < (1 << (kk - 9)); ++j) {
-        const uint32_t m = t + uint32_t(j) * kStage12Threads;
-        const int sl = (1 << (kk - 9)) + j;  // 1, 2-3, 4-7, 8-15
-        v[sl] = src[base + m];
-        li[sl] = stage12_slot((1u << kk) + m);
-      }
+      for (int j = 0; j < (1 << (kk - 9)); ++j) v[(1 << (kk - 9)) + j] = base[t + uint32_t(j) * kStage12Threads];
     }
+    if (q < 512u) buf[stage12_slot(q)] = v[0];
+    const uint32_t st0 = stage12_slot(t);
 #pragma unroll
-    for (int j = 0; j < 16; ++j)
-      if (li[j] != ~0u) buf[li[j]] = v[j];
+    for (int kk = 9; kk <= 12; ++kk)
+#pragma unroll
+      for (int j = 0; j < (1 << (kk - 9)); ++j)
+        buf[st0 + (1u << kk) + (1u << (kk - 5)) + uint32_t(j) * 528u] = v[(1 << (kk - 9)) + j];
   }
   __syncthreads();
   // step 1: thread a = node of depth <= 8 (a = 0 idles): B_{i+8}[a][u1]
@@ -1431,45 +1439,45 @@ __global__ __launch_bounds__(kStage12Threads) void k_bwd_stage12(int n, const T*
   if (a != 0u) {
     Vec<T, 1> S[31];
 #pragma unroll
-    for (int d = 0; d <= 4; ++d)
+    for (int d = 0; d <= 4; ++d) {
+      const T* row = buf + stage12_slot(a << d);
 #pragma unroll
-      for (int m = 0; m < (1 << d); ++m) S[(1 << d) - 1 + m].v[0] = buf[stage12_slot((a << d) + uint32_t(m))];
+      for (int m = 0; m < (1 << d); ++m) S[(1 << d) - 1 + m].v[0] = row[m];
+    }
     bwd4_tree<T, 1>(S, Dv);
   }
   __syncthreads();
   if (a != 0u) {
-    const uint32_t sa = stage12_slot(a);
+    T* col = buf + stage12_slot(a);
 #pragma unroll
-    for (int u = 0; u < 16; ++u) buf[uint32_t(u) * 512u + sa] = Dv[u].v[0];
+    for (int u = 0; u < 16; ++u) col[uint32_t(u) * kS12P1] = Dv[u].v[0];
   }
   __syncthreads();
   // step 2: thread (column c = u1, node z of depth <= 4; z = 0 idles): B_{i+4}[z][u2 16 + c]
   const uint32_t c = t >> 5, z = t & 31u;
   if (z != 0u) {
     Vec<T, 1> S[31];
-    const T* col = buf + c * 512u;
+    const T* col = buf + c * kS12P1;
 #pragma unroll
-    for (int d = 0; d <= 4; ++d)
+    for (int d = 0; d <= 4; ++d) {
+      const T* row = col + stage12_slot(z << d);
 #pragma unroll
-      for (int m = 0; m < (1 << d); ++m) S[(1 << d) - 1 + m].v[0] = col[stage12_slot((z << d) + uint32_t(m))];
+      for (int m = 0; m < (1 << d); ++m) S[(1 << d) - 1 + m].v[0] = row[m];
+    }
     bwd4_tree<T, 1>(S, Dv);
   }
   __syncthreads();
   if (z != 0u) {
+    T* row = buf + z * kS12P2 + c;
 #pragma unroll
-    for (int u = 0; u < 16; ++u) buf[z * 256u + ((uint32_t(u) * 16u + c) ^ z)] = Dv[u].v[0];
+    for (int u = 0; u < 16; ++u) row[uint32_t(u) * 16u] = Dv[u].v[0];
   }
   __syncthreads();
   // step 3: thread c2 < 256 (column u2 16 + u1): B_i[root][u3 256 + c2], written out
   if (t < 256u) {
     Vec<T, 1> S[31];
 #pragma unroll
-    for (int d = 0; d <= 4; ++d)
-#pragma unroll
-      for (int m = 0; m < (1 << d); ++m) {
-        const uint32_t q = (1u << d) + uint32_t(m);
-        S[(1 << d) - 1 + m].v[0] = buf[q * 256u + (t ^ q)];
-      }
+    for (int qq = 1; qq < 32; ++qq) S[qq - 1].v[0] = buf[uint32_t(qq) * kS12P2 + t];
     bwd4_tree<T, 1>(S, Dv);
     T* o = dst + ((size_t)root << 12) + t;
 #pragma unroll
@@ -1642,20 +1650,22 @@ hipError_t launch_backward(const Group<T>& g, hipStream_t s, int* launches, int 
   // fuse = 3: the same with eight positions per launch while four remain after
   const int lead = (fuse >= 2 && n >= 4) ? n % 4 : -1;
   for (int top = n; top > 0; k++) {           // B_top -> B_{top-step}
-    // fuse >= 6 at n = kStage12N: the last twelve positions in one launch, then the
-    // first eight in one (with D and its records when dpart)
-    if (fuse >= 6 && n == kStage12N && top == n) {
-      const int i = n - 12;
-      T* dst = (k & 1) ? g.f1 : g.f0;
-      hipLaunchKernelGGL((k_bwd_stage12<T>), dim3(8u << (i - 2), g.nb), dim3(kStage12Threads), 0, s, n, src, ss,
-                         dst, g.fs, g.st, g.frz);
-      if (launches) ++*launches;
-      src = dst;
-      ss = g.fs;
-      top = i;
-      continue;
+    // fuse >= 6 at n = kStage12N, FP32: the last twelve positions in one launch, then
+    // the first eight in one (with D and its records when dpart)
+    if constexpr (sizeof(T) == 4) {
+      if (fuse >= 6 && n == kStage12N && top == n) {
+        const int i = n - 12;
+        T* dst = (k & 1) ? g.f1 : g.f0;
+        hipLaunchKernelGGL(k_bwd_stage12, dim3(2u << i, g.nb), dim3(kStage12Threads), 0, s, n, src, ss, dst, g.fs,
+                           g.st, g.frz);
+        if (launches) ++*launches;
+        src = dst;
+        ss = g.fs;
+        top = i;
+        continue;
+      }
     }
-    if (fuse >= 6 && n == kStage12N && top == 8) {
+    if (fuse >= 6 && sizeof(T) == 4 && n == kStage12N && top == 8) {
       constexpr int LP = stage8_tile<T>() == 16 ? 4 : 3;
       const dim3 grid(1u << (n - 8 - LP), 1, g.nb);  // column blocks of P columns
       const dim3 block(32 * stage8_tile<T>());
@@ -1805,8 +1815,8 @@ hipError_t launch_backward8_sym_v(const Group<T>& g, hipStream_t s, T* dst) {
 template hipError_t launch_backward8_sym_v<float>(const Group<float>&, hipStream_t, float*);
 template hipError_t launch_backward8_sym_v<double>(const Group<double>&, hipStream_t, double*);
 
-int backward_launches(int n, int fuse) {
-  if (fuse >= 6 && n == kStage12N) return 2;
+int backward_launches(int n, int fuse, int esz) {
+  if (fuse >= 6 && n == kStage12N && esz == 4) return 2;
   if (fuse >= 3 && n >= 4) {
     const int four = n / 4, eight = (four - 1) / 2;  // the last launch keeps four positions
     return four - eight + (n % 4 + 1) / 2;

@@ -232,27 +232,32 @@ __device__ __forceinline__ bool order_slot(const Order& o, uint32_t& row, uint32
   return order_slot_q(o, logical_block() * kBlock + threadIdx.x, row, chunk);
 }
 
-// D(x) = H(x) - G(x) - M for N groups of V consecutive inputs (group u starts at
-// input x[u]): D is stored and the inputs' terms are added to the record p.  The
-// maxima of log p + D (and of log p + eta D) and of D over the groups, then the sums
-// of exponentials relative to those maxima and of p D, are formed in the iterate's
-// precision T with no branch per input, and folded into p once.  wt: the number of
-// inputs each value stands for (2 when only one of each complement pair is
-// evaluated).
+// The loads of H and log p for d_records_pre (issued early by callers that hold
+// them while other work runs).
 template <typename T, int V, int N>
-__device__ __forceinline__ void d_records(const Group<T>& g, int b, double M, const uint32_t (&x)[N],
-                                          const Vec<T, V> (&G)[N], Part& p, double wt = 1.0) {
+__device__ __forceinline__ void d_loads(const Group<T>& g, int b, const uint32_t (&x)[N], Vec<T, V> (&h)[N],
+                                        Vec<T, V> (&l)[N]) {
   const T* hf = g.hf + (size_t)b * g.xs;
   const T* lp = g.lp + (size_t)b * g.xs;
-  T* D = g.D + (size_t)b * g.xs;
-  // every load before the first store: D could alias H or log p as far as the
-  // compiler knows, so a store between them would serialise each load behind it
-  Vec<T, V> l[N], d[N];
 #pragma unroll
   for (int u = 0; u < N; ++u) {
-    d[u] = ld<T, V>(hf + x[u]);
+    h[u] = ld<T, V>(hf + x[u]);
     l[u] = ld<T, V>(lp + x[u]);
   }
+}
+
+// D(x) = H(x) - G(x) - M for N groups of V consecutive inputs (group u starts at
+// input x[u]), with H (in d, replaced by D) and log p (l) already loaded: D is
+// stored and the inputs' terms are added to the record p.  The maxima of log p + D
+// (and of log p + eta D) and of D over the groups, then the sums of exponentials
+// relative to those maxima and of p D, are formed in the iterate's precision T with
+// no branch per input, and folded into p once.  wt: the number of inputs each value
+// stands for (2 when only one of each complement pair is evaluated).
+template <typename T, int V, int N>
+__device__ __forceinline__ void d_records_pre(const Group<T>& g, int b, double M, const uint32_t (&x)[N],
+                                              const Vec<T, V> (&G)[N], Vec<T, V> (&d)[N], const Vec<T, V> (&l)[N],
+                                              Part& p, double wt = 1.0) {
+  T* D = g.D + (size_t)b * g.xs;
   T am = T(-INFINITY), dm = T(-INFINITY);
 #pragma unroll
   for (int u = 0; u < N; ++u)
@@ -288,6 +293,17 @@ __device__ __forceinline__ void d_records(const Group<T>& g, int b, double M, co
     q.s2 = wt * double(s2);
   }
   p = part_is_empty(p) ? q : combine(p, q);
+}
+
+// d_records_pre with its own loads.
+template <typename T, int V, int N>
+__device__ __forceinline__ void d_records(const Group<T>& g, int b, double M, const uint32_t (&x)[N],
+                                          const Vec<T, V> (&G)[N], Part& p, double wt = 1.0) {
+  // every load before the first store: D could alias H or log p as far as the
+  // compiler knows, so a store between them would serialise each load behind it
+  Vec<T, V> l[N], d[N];
+  d_loads<T, V, N>(g, b, x, d, l);
+  d_records_pre<T, V, N>(g, b, M, x, G, d, l, p, wt);
 }
 
 // Register part of the four-position forward step for one (y, column), from the

@@ -250,7 +250,7 @@ template <typename T>
 hipError_t launch_backward(const Group<T>& g, hipStream_t s, int* launches, int fuse, int dpart,
                            int* dpart_blocks);                                                   // v -> G
 int factored_launches(int n, int fuse);   // forward launches (two positions each when fuse != 0)
-int backward_launches(int n, int fuse);   // launches of launch_backward
+int backward_launches(int n, int fuse, int esz = 4);  // launches of launch_backward (esz: element bytes)
 int forward_launches(int n, int fuse);    // launches of launch_forward
 // Complement-symmetric iteration (iterate invariant under complement): the two
 // products on the canonical half, v and D fused as above; v is stored at compact

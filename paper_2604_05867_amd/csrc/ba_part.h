@@ -129,18 +129,21 @@ __device__ __forceinline__ Part wave_reduce(Part p) {
   return Part{m, s, dmax, i, id, m2, s2};
 }
 
-// Block reduction (blockDim.x == kBlock); the result is valid in every thread.
-__device__ __forceinline__ Part block_reduce(Part p) {
-  __shared__ Part sp[kBlock / kWave];
+// Block reduction (blockDim.x == NT): every wave reduces its lanes, then every wave
+// reduces the per-wave records (one per lane, lanes past NT / kWave empty), so the
+// result is valid in every thread.  Empty lanes leave every sum and maximum exactly
+// as it is, so the result does not depend on NT beyond the waves that hold records.
+template <int NT>
+__device__ __forceinline__ Part block_reduce_nt(Part p) {
+  __shared__ Part sp[NT / kWave];
   p = wave_reduce(p);
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   __syncthreads();
   if (lane == 0) sp[wave] = p;
   __syncthreads();
-  Part r = sp[0];
-  for (int w = 1; w < kBlock / kWave; ++w) r = combine(r, sp[w]);
-  return r;
+  return wave_reduce(lane < NT / kWave ? sp[lane] : part_empty());
 }
+__device__ __forceinline__ Part block_reduce(Part p) { return block_reduce_nt<kBlock>(p); }
 
 // The update of one iteration from the final record of its D kernel (at kFinalRec):
 // L = log sum p e^D, U = max D; with a step eta != 1 the normaliser Le of
@@ -211,16 +214,20 @@ __device__ __forceinline__ Part load_part(const double* q) {
   return Part{q[0], q[1], q[2], q[3], q[4], q[5], q[6]};
 }
 
-// Combine the nblk records at src (every block that calls this does it in full).
-__device__ __forceinline__ Part gather_parts(const double* src, int nblk) {
+// Combine the nblk records at src (every block that calls this does it in full, with
+// NT threads; the result, valid in every thread, is the same for every NT >= nblk).
+template <int NT>
+__device__ __forceinline__ Part gather_parts_nt(const double* src, int nblk) {
   Part p = part_empty();
-  for (int j = threadIdx.x; j < nblk; j += kBlock) p = combine(p, load_part(src + (size_t)j * kPartStride));
-  return block_reduce(p);
+  for (int j = threadIdx.x; j < nblk; j += NT) p = combine(p, load_part(src + (size_t)j * kPartStride));
+  return block_reduce_nt<NT>(p);
 }
+__device__ __forceinline__ Part gather_parts(const double* src, int nblk) { return gather_parts_nt<kBlock>(src, nblk); }
 
 // Reduce the block's records and store the result as record rec of an instance
-// whose records start at `part`.  Only thread 0 combines the per-wave records and
-// writes (blockDim.x == NT, kBlock for store_block_part).
+// whose records start at `part`: the first wave combines the per-wave records as
+// block_reduce_nt does and its lane 0 writes (blockDim.x == NT, kBlock for
+// store_block_part).
 template <int NT>
 __device__ __forceinline__ void store_block_part_nt(double* part, int rec, Part p) {
   __shared__ Part sp[NT / kWave];
@@ -228,10 +235,9 @@ __device__ __forceinline__ void store_block_part_nt(double* part, int rec, Part 
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   if (lane == 0) sp[wave] = p;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    Part r = sp[0];
-    for (int w = 1; w < NT / kWave; ++w) r = combine(r, sp[w]);
-    store_part(part + (size_t)rec * kPartStride, r);
+  if (wave == 0) {
+    const Part r = wave_reduce(lane < NT / kWave ? sp[lane] : part_empty());
+    if (lane == 0) store_part(part + (size_t)rec * kPartStride, r);
   }
 }
 __device__ __forceinline__ void store_block_part(double* part, int rec, Part p) {
