@@ -1341,9 +1341,17 @@ __global__ __launch_bounds__(32 * stage8_tile<T>()) void k_bwd_stage8_p(int n, i
       const uint32_t f = t + uint32_t(k) * NT;
       gv[k] = ld<T, VW>(buf + ((f >> 2) << LP) + (f & 3u) * uint32_t(VW));
     }
-    Part p = part_empty();
-    d_records_pre<T, VW, KD>(g, b, M, xs, gv, hd, lq, p);
-    store_block_part_nt<int(NT)>(g.part + (size_t)b * g.ps, int(lin & ((1u << lcb) - 1u)), p);
+    const int rec = int(lin & ((1u << lcb) - 1u));
+    if constexpr (sizeof(T) == 4) {
+      // FP32 iterates: the lanes' records reduced in single precision within each wave
+      PartF q;
+      d_records_pre_f(g, b, M, xs, gv, hd, lq, q);
+      store_block_part_f32<int(NT)>(g.part + (size_t)b * g.ps, rec, q, g.eta != 1.0);
+    } else {
+      Part p = part_empty();
+      d_records_pre<T, VW, KD>(g, b, M, xs, gv, hd, lq, p);
+      store_block_part_nt<int(NT)>(g.part + (size_t)b * g.ps, rec, p);
+    }
   } else {
     // copy-out: output column group w = f / 4 of 256, vector j = f mod 4
     T* o = dst + ((size_t)r0 << (sh + 8)) + s0;

@@ -295,6 +295,52 @@ __device__ __forceinline__ void d_records_pre(const Group<T>& g, int b, double M
   p = part_is_empty(p) ? q : combine(p, q);
 }
 
+// d_records_pre for FP32 iterates with the thread's record left in single precision
+// (q, for store_block_part_f32); D is that of d_records_pre, the record's sums use
+// the hardware exponential (2^(x log2 e), relative error below |x| 2^-23), which the
+// single-precision record of an FP32 iterate does not need better than that.
+__device__ __forceinline__ void d_records_pre_f(const Group<float>& g, int b, double M, const uint32_t (&x)[2],
+                                                const Vec<float, 4> (&G)[2], Vec<float, 4> (&d)[2],
+                                                const Vec<float, 4> (&l)[2], PartF& q) {
+  using T = float;
+  constexpr int N = 2, V = 4;
+  T* D = g.D + (size_t)b * g.xs;
+  T am = T(-INFINITY), dm = T(-INFINITY);
+#pragma unroll
+  for (int u = 0; u < N; ++u)
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+      d[u].v[k] = d[u].v[k] - G[u].v[k] - T(M);
+      am = fmax(am, l[u].v[k] + d[u].v[k]);
+      dm = fmax(dm, d[u].v[k]);
+    }
+#pragma unroll
+  for (int u = 0; u < N; ++u) stv<T, V>(D + x[u], d[u]);
+  T s = T(0), i = T(0);
+#pragma unroll
+  for (int u = 0; u < N; ++u)
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+      s += __expf((l[u].v[k] + d[u].v[k]) - am);
+      i += __expf(l[u].v[k]) * d[u].v[k];
+    }
+  q = PartF{am, s, dm, i, T(-INFINITY), T(0)};
+  if (g.eta != 1.0) {
+    const T eta = T(g.eta);
+    T m2 = T(-INFINITY), s2 = T(0);
+#pragma unroll
+    for (int u = 0; u < N; ++u)
+#pragma unroll
+      for (int k = 0; k < V; ++k) m2 = fmax(m2, l[u].v[k] + eta * d[u].v[k]);
+#pragma unroll
+    for (int u = 0; u < N; ++u)
+#pragma unroll
+      for (int k = 0; k < V; ++k) s2 += __expf((l[u].v[k] + eta * d[u].v[k]) - m2);
+    q.m2 = m2;
+    q.s2 = s2;
+  }
+}
+
 // d_records_pre with its own loads.
 template <typename T, int V, int N>
 __device__ __forceinline__ void d_records(const Group<T>& g, int b, double M, const uint32_t (&x)[N],

@@ -129,6 +129,43 @@ __device__ __forceinline__ Part wave_reduce(Part p) {
   return Part{m, s, dmax, i, id, m2, s2};
 }
 
+// A thread's record in single precision (the D launch of FP32 iterates): max of
+// a = log p + D, sum exp(a - m), max D, sum p D, and for a step eta != 1 the max and
+// sum for log p + eta D.
+struct PartF {
+  float m, s, dmax, i, m2, s2;
+};
+
+// The wavefront's records of single-precision lanes reduced as wave_reduce does, in
+// single precision (max first, one hardware exponential per lane, then plain sums),
+// the result in every lane widened to a double record.
+__device__ __forceinline__ Part wave_reduce_f(const PartF& p, bool step) {
+  float m = p.m, dmax = p.dmax;
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    m = fmaxf(m, __shfl_xor(m, off));
+    dmax = fmaxf(dmax, __shfl_xor(dmax, off));
+  }
+  float s = (p.s != 0.0f) ? p.s * __expf(p.m - m) : 0.0f, i = p.i;
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    s += __shfl_xor(s, off);
+    i += __shfl_xor(i, off);
+  }
+  Part r{double(m), double(s), double(dmax), double(i), 0.0, -INFINITY, 0.0};
+  if (step) {
+    float m2 = p.m2;
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) m2 = fmaxf(m2, __shfl_xor(m2, off));
+    float s2 = (p.s2 != 0.0f) ? p.s2 * __expf(p.m2 - m2) : 0.0f;
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) s2 += __shfl_xor(s2, off);
+    r.m2 = double(m2);
+    r.s2 = double(s2);
+  }
+  return r;
+}
+
 // Block reduction (blockDim.x == NT): every wave reduces its lanes, then every wave
 // reduces the per-wave records (one per lane, lanes past NT / kWave empty), so the
 // result is valid in every thread.  Empty lanes leave every sum and maximum exactly
@@ -242,6 +279,21 @@ __device__ __forceinline__ void store_block_part_nt(double* part, int rec, Part 
 }
 __device__ __forceinline__ void store_block_part(double* part, int rec, Part p) {
   store_block_part_nt<kBlock>(part, rec, p);
+}
+
+// The same from single-precision lane records: within each wave in single precision
+// (wave_reduce_f), across the waves in double.
+template <int NT>
+__device__ __forceinline__ void store_block_part_f32(double* part, int rec, const PartF& p, bool step) {
+  __shared__ Part sp[NT / kWave];
+  const Part w = wave_reduce_f(p, step);
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  if (lane == 0) sp[wave] = w;
+  __syncthreads();
+  if (wave == 0) {
+    const Part r = wave_reduce(lane < NT / kWave ? sp[lane] : part_empty());
+    if (lane == 0) store_part(part + (size_t)rec * kPartStride, r);
+  }
 }
 
 }  // namespace ba

@@ -107,11 +107,14 @@ def test_symmetric_exact_channel(ba):
 
 
 def test_symmetric_n20_fp32(ba):
-    """The benchmark shape: n = 20, three instances, FP32 iterates."""
+    """The benchmark shape: n = 20, three instances, FP32 iterates.  The two kernel
+    sets sum in different orders and the full set forms its D records in single
+    precision, so the FP32 iterates agree to rounding (log p of magnitude ~14 has an
+    ulp of ~1e-6) and their FP64-certified bounds within 1e-6 bits."""
     ds = [0.64, 0.8, 0.95]
     (lp_f, lo_f, hi_f), (lp_s, lo_s, hi_s) = run_pair(ba, [20] * 3, ds, ba.PREC_FP32_LOG, 6)
     assert np.max(np.abs(lp_f - lp_s)) < 1e-4
-    assert np.max(np.abs(lo_f - lo_s)) < 1e-7 and np.max(np.abs(hi_f - hi_s)) < 1e-7
+    assert np.max(np.abs(lo_f - lo_s)) < 1e-6 and np.max(np.abs(hi_f - hi_s)) < 1e-6
     X = 1 << 20
     for b in range(3):
         seg = lp_s[b * X:(b + 1) * X]
