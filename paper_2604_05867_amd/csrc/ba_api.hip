@@ -427,6 +427,7 @@ template <typename T>
 int iterate_group(ba_ctx* c, const GroupHost& gh, const Group<T>& G0, bool fused_in, bool leave_pending) {
   Group<T> G = G0;
   G.eta = c->eta;
+  G.dsum = c->eta == 1.0 ? 1 : 0;  // the D array carries log p + D to the update
   // The kernels that write log p, p and the state always test the frozen flag, so
   // a frozen instance's iterate and state stay untouched whether or not the sweeps
   // test it too; skipping the test there (frz = 0) only sweeps a frozen instance

@@ -176,13 +176,13 @@ __global__ __launch_bounds__(kBlock) void k_fwd_first4_upd(int n, T* __restrict_
   T nl[16], dv[16];
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
-    nl[u] = lp[(uint32_t(u) << sh) + s];
+    if (!g.dsum) nl[u] = lp[(uint32_t(u) << sh) + s];  // dsum: D holds log p + D
     dv[u] = D[(uint32_t(u) << sh) + s];
   }
   T R[16];
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
-    nl[u] = update_value<T>(up, eta, lo, nl[u], dv[u]);
+    nl[u] = g.dsum ? update_value_sum<T>(up, lo, dv[u]) : update_value<T>(up, eta, lo, nl[u], dv[u]);
     lp[(uint32_t(u) << sh) + s] = nl[u];
     R[u] = exp_t<T>(nl[u] - T(up.Mn));
   }
@@ -255,12 +255,12 @@ __global__ __launch_bounds__(kFirst8Threads) void k_fwd_first8(int n, const T* _
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       const uint32_t x = ((8u * h + uint32_t(k)) << (n - 4)) + x0;
-      nl[k] = lp[x];
+      if (!g.dsum) nl[k] = lp[x];  // dsum: D holds log p + D
       dv[k] = D[x];
     }
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-      nl[k] = update_value<T>(up, eta, lo, nl[k], dv[k]);
+      nl[k] = g.dsum ? update_value_sum<T>(up, lo, dv[k]) : update_value<T>(up, eta, lo, nl[k], dv[k]);
       lp[((8u * h + uint32_t(k)) << (n - 4)) + x0] = nl[k];
       R[k] = exp_t<T>(nl[k] - T(up.Mn));
     }

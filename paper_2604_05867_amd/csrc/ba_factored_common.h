@@ -247,8 +247,8 @@ __device__ __forceinline__ void d_loads(const Group<T>& g, int b, const uint32_t
 }
 
 // D(x) = H(x) - G(x) - M for N groups of V consecutive inputs (group u starts at
-// input x[u]), with H (in d, replaced by D) and log p (l) already loaded: D is
-// stored and the inputs' terms are added to the record p.  The maxima of log p + D
+// input x[u]), with H (in d, replaced by D) and log p (l) already loaded: D (or log p
+// + D, Group::dsum) is stored and the inputs' terms are added to the record p.  The maxima of log p + D
 // (and of log p + eta D) and of D over the groups, then the sums of exponentials
 // relative to those maxima and of p D, are formed in the iterate's precision T with
 // no branch per input, and folded into p once.  wt: the number of inputs each value
@@ -259,16 +259,23 @@ __device__ __forceinline__ void d_records_pre(const Group<T>& g, int b, double M
                                               Part& p, double wt = 1.0) {
   T* D = g.D + (size_t)b * g.xs;
   T am = T(-INFINITY), dm = T(-INFINITY);
+  Vec<T, V> a[N];  // log p + D
 #pragma unroll
   for (int u = 0; u < N; ++u)
 #pragma unroll
     for (int k = 0; k < V; ++k) {
       d[u].v[k] = d[u].v[k] - G[u].v[k] - T(M);
-      am = fmax(am, l[u].v[k] + d[u].v[k]);
+      a[u].v[k] = l[u].v[k] + d[u].v[k];
+      am = fmax(am, a[u].v[k]);
       dm = fmax(dm, d[u].v[k]);
     }
+  if (g.dsum) {  // uniform: one store loop or the other (a selected struct would go to scratch)
 #pragma unroll
-  for (int u = 0; u < N; ++u) stv<T, V>(D + x[u], d[u]);
+    for (int u = 0; u < N; ++u) stv<T, V>(D + x[u], a[u]);
+  } else {
+#pragma unroll
+    for (int u = 0; u < N; ++u) stv<T, V>(D + x[u], d[u]);
+  }
   T s = T(0), i = T(0);
 #pragma unroll
   for (int u = 0; u < N; ++u)
@@ -306,16 +313,23 @@ __device__ __forceinline__ void d_records_pre_f(const Group<float>& g, int b, do
   constexpr int N = 2, V = 4;
   T* D = g.D + (size_t)b * g.xs;
   T am = T(-INFINITY), dm = T(-INFINITY);
+  Vec<T, V> a[N];  // log p + D
 #pragma unroll
   for (int u = 0; u < N; ++u)
 #pragma unroll
     for (int k = 0; k < V; ++k) {
       d[u].v[k] = d[u].v[k] - G[u].v[k] - T(M);
-      am = fmax(am, l[u].v[k] + d[u].v[k]);
+      a[u].v[k] = l[u].v[k] + d[u].v[k];
+      am = fmax(am, a[u].v[k]);
       dm = fmax(dm, d[u].v[k]);
     }
+  if (g.dsum) {  // uniform: one store loop or the other (a selected struct would go to scratch)
 #pragma unroll
-  for (int u = 0; u < N; ++u) stv<T, V>(D + x[u], d[u]);
+    for (int u = 0; u < N; ++u) stv<T, V>(D + x[u], a[u]);
+  } else {
+#pragma unroll
+    for (int u = 0; u < N; ++u) stv<T, V>(D + x[u], d[u]);
+  }
   T s = T(0), i = T(0);
 #pragma unroll
   for (int u = 0; u < N; ++u)

@@ -134,6 +134,9 @@ struct Group {
                       // frozen flag, which the update kernels always test
   int s8lc;           // eight-position backward launches: log2 of the columns per block
                       // (0: as many as the rows hold, up to the value lanes of a node)
+  int dsum;           // iterations with eta = 1: the D launch stores log p + D in D (the
+                      // update then reads one array: log p <- (log p + D) - L, the same
+                      // rounding as before); 0: D itself (certification, a step eta != 1)
 };
 
 enum StreamOp { kOpScatter = 0, kOpGather = 1, kOpInit = 2, kOpRow = 3, kOpVerify = 4, kOpScatterOrbit = 5 };

@@ -242,6 +242,14 @@ __device__ __forceinline__ T update_value(const UpdateParams& u, T eta, T lo, T 
   return nl > lo ? nl : lo;
 }
 
+// The same from a = log p + D as the D launch stored it (Group::dsum, eta = 1): the
+// sum and then the difference, rounded as update_value rounds them.
+template <typename T>
+__device__ __forceinline__ T update_value_sum(const UpdateParams& u, T lo, T a) {
+  const T nl = a - T(u.L);
+  return nl > lo ? nl : lo;
+}
+
 __device__ __forceinline__ void store_part(double* dst, const Part& p) {
   dst[0] = p.m; dst[1] = p.s; dst[2] = p.dmax; dst[3] = p.i; dst[4] = p.id; dst[5] = p.m2; dst[6] = p.s2;
 }

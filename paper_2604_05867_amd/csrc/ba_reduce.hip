@@ -69,9 +69,10 @@ __global__ __launch_bounds__(kBlock) void k_dpart(Group<T> g, int nblk, int use_
   T* D = g.D + (size_t)b * g.xs;
   Part p = part_empty();
   for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < X; x += gridDim.x * blockDim.x) {
+    const T lpx = lp[x];
     const T dv = h[x] - gg[x] - T(M);
-    D[x] = dv;
-    const double l = double(lp[x]);
+    D[x] = g.dsum ? T(lpx + dv) : dv;  // log p + D for the update (eta = 1), else D
+    const double l = double(lpx);
     const double px = exp_in(l, T());
     const double pdd = use_hd ? px * (g.hd[(size_t)b * g.xs + x] - double(gd[(size_t)b * g.xs + x])) : 0.0;
     part_add<T>(p, l + double(dv), double(dv), px, pdd, 1.0, g.eta != 1.0, l + g.eta * double(dv));
@@ -106,7 +107,7 @@ __global__ __launch_bounds__(kBlock) void k_update(Group<T> g, int nblk, double 
   // sym: D holds the inputs x < 2^(n-1) only; their complements get the same values
   const uint32_t count = sym ? X / 2u : X;
   for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < count; x += gridDim.x * blockDim.x) {
-    const T nl = update_value<T>(u, eta, lo, lp[x], D[x]);
+    const T nl = g.dsum ? update_value_sum<T>(u, lo, D[x]) : update_value<T>(u, eta, lo, lp[x], D[x]);
     const T px = exp_t<T>(nl - T(u.Mn));
     lp[x] = nl;
     p[x] = px;

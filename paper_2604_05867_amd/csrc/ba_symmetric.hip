@@ -543,7 +543,7 @@ __global__ __launch_bounds__(kBlock) void k_fwd_first4_upd_sym(int n, T* __restr
   T nl[16], dv[16];
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
-    nl[u] = lp[xs[u]];
+    if (!g.dsum) nl[u] = lp[xs[u]];  // dsum: D holds log p + D
     dv[u] = D[xs[u]];
   }
   T F0[4][16], H4[8];
@@ -555,7 +555,7 @@ __global__ __launch_bounds__(kBlock) void k_fwd_first4_upd_sym(int n, T* __restr
   for (int u = 0; u < 8; ++u) H4[u] = T(0);
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
-    nl[u] = update_value<T>(up, eta, lo, nl[u], dv[u]);
+    nl[u] = g.dsum ? update_value_sum<T>(up, lo, dv[u]) : update_value<T>(up, eta, lo, nl[u], dv[u]);
     lp[xs[u]] = nl[u];
     lp[X - 1u - xs[u]] = nl[u];
     F0[0][u] = exp_t<T>(nl[u] - T(up.Mn));
