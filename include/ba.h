@@ -253,7 +253,11 @@ int ba_bind_static(ba_ctx *c, void *hip_stream);
  * normalisation) for every instance that has not converged.  Asynchronous: no
  * host synchronisation.  An instance whose current-iterate gap U - L (in the
  * iteration precision) falls below its tolerance (see ba_run) stops updating.
- * BA_ESTATE before ba_bind. */
+ * FP32 iterates with eta = 1 at n = 20 (factored engine, default launch plan)
+ * are scaled to max 1 instead of normalised between the iterations of one call
+ * (the sweeps do not depend on the scale; the last update of the call normalises),
+ * so their in-call L, U and I are not formed; the iterate a call leaves is
+ * normalised.  BA_ESTATE before ba_bind. */
 int ba_step(ba_ctx *c, int iters);
 
 /* Iterate until the FP64-certified gap U - L is below gap_bits for every instance

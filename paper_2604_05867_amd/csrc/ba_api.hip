@@ -420,11 +420,22 @@ bool update_fusable(const ba_ctx* c, const GroupHost& gh) {
   return forward_update_fusable(gh.n, c->fuse);
 }
 
+// FP32 BA iterations at n = 20 (default plan): an update left pending to the next
+// eight-position first launch can shift by the max of log p + D instead of
+// normalising (k_fwd_first8), from the block maxima the D launch wrote, with no
+// final-record launch.
+bool update_by_max(const ba_ctx* c, const GroupHost& gh) {
+  return c->engine == BA_ENGINE_FACTORED && c->prec == BA_PREC_FP32_LOG && c->eta == 1.0 && !sym_active(c, gh.n) &&
+         forward_first8(gh.n, c->fuse) && backward_writes_maxima(gh.n, c->fuse, 4);
+}
+
 // One iteration.  fused_in: the previous iteration's update is pending and done by
-// this iteration's first forward launch; leave_pending: this iteration's update is
-// left to the next iteration's first forward launch.
+// this iteration's first forward launch (by the max from nmax_in block maxima when
+// nmax_in > 0); leave_pending: this iteration's update is left to the next
+// iteration's first forward launch, and *nmax_out > 0 when that one shifts by the max.
 template <typename T>
-int iterate_group(ba_ctx* c, const GroupHost& gh, const Group<T>& G0, bool fused_in, bool leave_pending) {
+int iterate_group(ba_ctx* c, const GroupHost& gh, const Group<T>& G0, bool fused_in, int nmax_in,
+                  bool leave_pending, int* nmax_out) {
   Group<T> G = G0;
   G.eta = c->eta;
   G.dsum = c->eta == 1.0 ? 1 : 0;  // the D array carries log p + D to the update
@@ -437,11 +448,13 @@ int iterate_group(ba_ctx* c, const GroupHost& gh, const Group<T>& G0, bool fused
   G.frz = c->frz_override >= 0 ? c->frz_override : (c->armed ? 1 : 0);
   const double floor = iterate_floor(c);
   const int check_tol = c->prec == BA_PREC_FP64 ? 1 : 0;
-  const FusedUpdate fu{floor, check_tol};
+  const FusedUpdate fu{floor, check_tol, nmax_in};
   int nblk = 0;  // block records written by the fused D launch, if any
   int rc = sweeps<T>(c, gh, G, 0, G.g, 1, &nblk, fused_in ? &fu : nullptr);
   if (rc) return rc;
-  {
+  const bool by_max = leave_pending && nblk > 0 && update_by_max(c, gh);
+  if (nmax_out) *nmax_out = by_max ? nblk : 0;
+  if (!by_max) {
     Timer t(c, BA_K_REDUCE, nblk ? 1 : 2);
     if (!nblk) {
       nblk = reduce_blocks(gh.n);
@@ -792,10 +805,12 @@ int step_group(ba_ctx* c, GroupHost& gh, int iters) {
     return BA_OK;
   }
   const bool fu = update_fusable(c, gh);
+  int nmax = 0;
   for (int it = 0; it < iters; ++it) {
     const bool in = fu && it > 0, out = fu && it + 1 < iters;
-    const int rc = (c->prec == BA_PREC_FP32_LOG) ? iterate_group<float>(c, gh, gh.gf, in, out)
-                                                 : iterate_group<double>(c, gh, gh.gd, in, out);
+    const int nin = in ? nmax : 0;
+    const int rc = (c->prec == BA_PREC_FP32_LOG) ? iterate_group<float>(c, gh, gh.gf, in, nin, out, &nmax)
+                                                 : iterate_group<double>(c, gh, gh.gd, in, nin, out, &nmax);
     if (rc) return rc;
   }
   return BA_OK;

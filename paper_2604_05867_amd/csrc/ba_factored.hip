@@ -227,12 +227,40 @@ constexpr uint32_t kF4Pitch = 16u * 16u + 16u;  // F_4 row in LDS: 16 u2 x 16 co
 template <typename T, bool UPD>
 __global__ __launch_bounds__(kFirst8Threads) void k_fwd_first8(int n, const T* __restrict__ src, size_t sstride,
                                                                T* __restrict__ dst, size_t dstride, Group<T> g,
-                                                               double floor, int check_tol) {
+                                                               double floor, int check_tol, int nmax) {
   const int b = blockIdx.y;
   if ((UPD || g.frz) && g.st[b].converged) return;
   UpdateParams up{};
   if constexpr (UPD) {
-    up = update_params<T>(g, b, check_tol, blockIdx.x == 0 && threadIdx.x == 0);
+    if (nmax > 0) {
+      // shift by the max (FP32 iterates between two normalisations, eta = 1, the D
+      // array holding log p + D): log p <- max(a - m, -floor) with m = max a over the
+      // instance, from the D launch's nmax block maxima (each wave takes their max
+      // itself), i.e. the new iterate scaled so that its max is 1.  Its exact
+      // normalisation is a constant shift of log p that the sweeps, the floor and the
+      // next D launch do not depend on; the update that ends a ba_step call (or a
+      // ba_run chunk) normalises with L as usual.  No L, U or I is formed here.
+      const float* bm = reinterpret_cast<const float*>(g.part + (size_t)b * g.ps + kBlockMaxima);
+      float mv = -INFINITY;
+      for (int j = int(threadIdx.x & (kWave - 1)); j < nmax; j += kWave) mv = fmaxf(mv, bm[j]);
+#pragma unroll
+      for (int off = kWave / 2; off > 0; off >>= 1) mv = fmaxf(mv, __shfl_xor(mv, off));
+      const bool finite = isfinite(mv);
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        State* st = g.st + b;
+        if (!finite) {
+          st->bad = 1;
+          st->converged = 1;
+        } else {
+          st->M = 0.0;
+          st->iters += 1;
+        }
+      }
+      if (!finite) return;
+      up = UpdateParams{double(mv), double(mv), 0.0, false, false};  // L <- m: the new max is 0
+    } else {
+      up = update_params<T>(g, b, check_tol, blockIdx.x == 0 && threadIdx.x == 0);
+    }
     if (up.stop) return;
   }
   src += (size_t)b * sstride;
@@ -1346,7 +1374,8 @@ __global__ __launch_bounds__(32 * stage8_tile<T>()) void k_bwd_stage8_p(int n, i
       // FP32 iterates: the lanes' records reduced in single precision within each wave
       PartF q;
       d_records_pre_f(g, b, M, xs, gv, hd, lq, q);
-      store_block_part_f32<int(NT)>(g.part + (size_t)b * g.ps, rec, q, g.eta != 1.0);
+      double* part = g.part + (size_t)b * g.ps;
+      store_block_part_f32<int(NT)>(part, rec, q, g.eta != 1.0, reinterpret_cast<float*>(part + kBlockMaxima));
     } else {
       Part p = part_empty();
       d_records_pre<T, VW, KD>(g, b, M, xs, gv, hd, lq, p);
@@ -1539,10 +1568,10 @@ hipError_t launch_forward(const Group<T>& g, hipStream_t s, int* launches, int f
       const dim3 grid(1u << (n - 12), g.nb);  // 16 columns of F_8 per block
       if (upd)
         hipLaunchKernelGGL((k_fwd_first8<T, true>), grid, dim3(kFirst8Threads), 0, s, n, src, ss, dst, g.fs, g,
-                           upd->floor, upd->check_tol);
+                           upd->floor, upd->check_tol, upd->nmax);
       else
         hipLaunchKernelGGL((k_fwd_first8<T, false>), grid, dim3(kFirst8Threads), 0, s, n, src, ss, dst, g.fs, g,
-                           0.0, 0);
+                           0.0, 0, 0);
       if (launches) ++*launches;
       src = dst;
       ss = g.fs;
@@ -1847,6 +1876,8 @@ int forward_launches(int n, int fuse) {
 }
 
 bool forward_update_fusable(int n, int fuse) { return fuse >= 2 && n > 4; }
+bool forward_first8(int n, int fuse) { return fuse >= 5 && n >= kFirst8MinN; }
+bool backward_writes_maxima(int n, int fuse, int esz) { return fuse >= 6 && n == kStage12N && esz == 4; }
 
 template hipError_t launch_forward<float>(const Group<float>&, hipStream_t, int*, int, int, const FusedUpdate*);
 template hipError_t launch_forward<double>(const Group<double>&, hipStream_t, int*, int, int,

@@ -243,9 +243,18 @@ hipError_t launch_pull(const Group<T>& g, T* partial, hipStream_t s);
 struct FusedUpdate {
   double floor;
   int check_tol;
+  int nmax;  // > 0: shift by the max (see k_fwd_first8): the D launch left nmax block
+             // maxima of log p + D and no final record; 0: the update from the final record
 };
+// Offset (doubles) of the block maxima of log p + D (floats) in an iterate group's
+// record buffer: the second record set, which only ba_set_logp's passes use.
+constexpr size_t kBlockMaxima = size_t(kMaxRedBlocks) * kPartStride;
 // True when launch_forward's first launch is the four-position one at i = 0.
 bool forward_update_fusable(int n, int fuse);
+// True when launch_forward's first launch is the eight-position one (k_fwd_first8).
+bool forward_first8(int n, int fuse);
+// True when launch_backward's D launch (FP32) also writes the block maxima of log p + D.
+bool backward_writes_maxima(int n, int fuse, int esz);
 template <typename T>
 hipError_t launch_forward(const Group<T>& g, hipStream_t s, int* launches, int fuse, int logv,
                           const FusedUpdate* upd = nullptr);  // p -> r

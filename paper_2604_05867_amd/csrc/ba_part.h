@@ -291,8 +291,11 @@ __device__ __forceinline__ void store_block_part(double* part, int rec, Part p) 
 
 // The same from single-precision lane records: within each wave in single precision
 // (wave_reduce_f), across the waves in double.
+// maxima (may be null): also store the block's max of log p + D there, as a float
+// at index rec.
 template <int NT>
-__device__ __forceinline__ void store_block_part_f32(double* part, int rec, const PartF& p, bool step) {
+__device__ __forceinline__ void store_block_part_f32(double* part, int rec, const PartF& p, bool step,
+                                                     float* maxima) {
   __shared__ Part sp[NT / kWave];
   const Part w = wave_reduce_f(p, step);
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
@@ -300,7 +303,10 @@ __device__ __forceinline__ void store_block_part_f32(double* part, int rec, cons
   __syncthreads();
   if (wave == 0) {
     const Part r = wave_reduce(lane < NT / kWave ? sp[lane] : part_empty());
-    if (lane == 0) store_part(part + (size_t)rec * kPartStride, r);
+    if (lane == 0) {
+      store_part(part + (size_t)rec * kPartStride, r);
+      if (maxima) maxima[rec] = float(r.m);  // exact: the max of floats
+    }
   }
 }
 

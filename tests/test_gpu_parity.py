@@ -560,9 +560,10 @@ def test_fused_update_is_bitwise_separate(ba, prec):
     """Within one step call the update of each iteration but the last runs inside
     the next iteration's first forward launch; the iterates and bounds equal those
     of one-iteration calls (separate update launches) bit for bit, with and without
-    a step eta."""
+    a step eta.  (FP32 iterates at n = 20 shift by the max in between instead:
+    test_fp32_update_by_max_matches_normalised.)"""
     p = ba.PREC_FP64 if prec == "fp64" else ba.PREC_FP32_LOG
-    ns, ds = ([12, 14], [0.6, 0.9]) if prec == "fp64" else ([16, 20], [0.7, 0.95])
+    ns, ds = ([12, 14], [0.6, 0.9]) if prec == "fp64" else ([16, 17], [0.7, 0.95])
     # one context, reset between runs
     c = chain(ba.Context(ns, ds, prec=p))
     start = torch.tensor(np.concatenate([np.full(1 << m, -m * LN2) for m in ns]))
@@ -577,6 +578,32 @@ def test_fused_update_is_bitwise_separate(ba, prec):
         assert np.array_equal(out[0][0], out[1][0])
         assert out[0][1] == out[1][1]
     c.close()
+
+
+@pytest.mark.parametrize("d", [0.64, 0.8])
+def test_fp32_update_by_max_matches_normalised(ba, d):
+    """FP32 BA iterations at n = 20 within one step call shift log p by the max of
+    log p + D (from the D launch's block maxima, no final-record launch) instead of
+    normalising; the call's last update normalises.  The result equals that of
+    one-iteration calls (every update normalised) to FP32 rounding: log p (magnitude
+    ~14, ulp ~1e-6) within 4e-5 after 7 iterations, the FP64-certified bounds within
+    1e-6 bits; and one final-record launch ran for the 7 iterations."""
+    n = 20
+    say("fp32 update by max d=%g" % d)
+    c = chain(ba.Context([n], [d], prec=ba.PREC_FP32_LOG))
+    start = torch.tensor(np.full(1 << n, -n * LN2))
+    out = []
+    for per_call in (1, 7):
+        c.set_logp(start)
+        for _ in range(7 // per_call):
+            c.step(per_call)
+        out.append((c.get_logp().cpu().numpy(), c.bounds()))
+    c.set_logp(start)
+    t = c.time_kernels(7)
+    c.close()
+    assert t["reduce"][1] == 1
+    assert np.max(np.abs(out[0][0] - out[1][0])) < 4e-5
+    assert abs(out[0][1][0][0] - out[1][1][0][0]) < 1e-6 and abs(out[0][1][1][0] - out[1][1][1][0]) < 1e-6
 
 
 @pytest.mark.parametrize("path", ["chain", "persistent"])
