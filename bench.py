@@ -49,11 +49,11 @@ FUSE = 6  # the library default (positions per launch of the factored engine)
 MEASURED_TRAFFIC = {
     "sources": ["paper_2604_05867_amd/csrc/ba_factored.hip", "paper_2604_05867_amd/csrc/ba_factored_common.h"],
     # of the sources concatenated
-    "sha256": "181e503da10d9152f13247f1f339fd4a89b32d3bc33078ab06d7fd10cb589761",
+    "sha256": "e208dda9a011f96543574e014154112afd86542d82aff697c886b770c417cdbc",
     # forward: k_fwd_first8, k_fwd_stage4 x2, k_fwd_last4; backward: k_bwd_stage12,
     # k_bwd_stage8_p with D fused
-    "sweep1": 53678000,
-    "sweep2": 55172000,
+    "sweep1": 50543000,
+    "sweep2": 57012000,
 }
 
 
@@ -83,9 +83,9 @@ def sweep_launch_bytes(n, esz, nb, fuse, backward, fused_update=0.0):
     """Algorithmic HBM bytes of each launch of one sweep of the factored engine, in
     launch order: a launch covering positions i..i+t-1 reads its source stage once
     and writes its destination stage once; the last backward launch also reads
-    H and log p (D is formed there); the first forward launch, when it makes the
-    previous iteration's update (a fraction fused_update of the iterations), reads
-    log p and D instead of p and writes log p.  Launch sequence as in the library: fuse 2 =
+    H and log p (D is formed there, stored as log p + D for BA); the first forward
+    launch, when it makes the previous iteration's update (a fraction fused_update of
+    the iterations), reads log p + D instead of p and writes log p.  Launch sequence as in the library: fuse 2 =
     four positions per launch (forward: the last 1-4 positions two at a time;
     backward: the first n mod 4 positions two or one at a time), fuse 3 = as 2 with
     eight positions per backward launch while four remain after it, fuse 4 = as 3
@@ -125,7 +125,7 @@ def sweep_launch_bytes(n, esz, nb, fuse, backward, fused_update=0.0):
     if backward:
         out[-1] += 2 * (1 << n) * esz * nb
     else:
-        out[0] += fused_update * 2 * (1 << n) * esz * nb
+        out[0] += fused_update * (1 << n) * esz * nb
     return out
 
 
