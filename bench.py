@@ -38,7 +38,7 @@ sys.path.insert(0, ROOT)
 N = 20
 DS = [0.64, 0.80, 0.95]
 UNIT_EQUIV = "W-nonzero-equivalent terms/s (factored engine: nonzeros accounted, not visited)"
-FUSE = 6  # the library default (positions per launch of the factored engine)
+FUSE = 7  # the library default (positions per launch of the factored engine)
 
 
 # HBM bytes per launch of this workload's sweeps, from rocprofv3 FETCH_SIZE and
@@ -50,7 +50,7 @@ MEASURED_TRAFFIC = {
     "sources": ["paper_2604_05867_amd/csrc/ba_factored.hip", "paper_2604_05867_amd/csrc/ba_factored_common.h"],
     # of the sources concatenated
     "sha256": "e208dda9a011f96543574e014154112afd86542d82aff697c886b770c417cdbc",
-    # forward: k_fwd_first8, k_fwd_stage4 x2, k_fwd_last4; backward: k_bwd_stage12,
+    # forward: k_fwd_first8, k_fwd_stage12; backward: k_bwd_stage12,
     # k_bwd_stage8_p with D fused
     "sweep1": 50543000,
     "sweep2": 57012000,
@@ -91,10 +91,13 @@ def sweep_launch_bytes(n, esz, nb, fuse, backward, fused_update=0.0):
     eight positions per backward launch while four remain after it, fuse 4 = as 3
     with the forward's last four positions in one launch (n >= 12), fuse 5 = as 4
     with the forward's first eight positions in one launch (n >= 12), fuse 6 = as 5
-    with the backward at n = 20 as twelve positions then eight, fuse 1 = two."""
+    with the backward at n = 20 as twelve positions then eight, fuse 7 = as 6 with
+    the forward at n = 20 as eight positions then twelve, fuse 1 = two."""
     s = stage_sizes(n)
     steps = []
-    if not backward:
+    if not backward and fuse >= 7 and n == 20:
+        steps = [(0, 8), (8, 20)]
+    elif not backward:
         i = 0
         last4 = fuse >= 4 and n >= 12
         while i < n:
@@ -463,7 +466,7 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
                 "frac": round(achieved / 8000.0, 4),
                 "traffic": measured_traffic(dom),
-                "kernel": ("forward sweep (k_fwd_first8, k_fwd_stage4 x2, k_fwd_last4)" if dom == "sweep1"
+                "kernel": ("forward sweep (k_fwd_first8, k_fwd_stage12)" if dom == "sweep1"
                            else "backward sweep (k_bwd_stage12, k_bwd_stage8_p with D fused)"),
                 "bytes_per_launch": int(bytes_launch), "avg_launch_us": round(per_launch_ms * 1e3, 2)}
 

@@ -175,10 +175,15 @@ int ba_set_graphs(ba_ctx *c, int enable);
  *  before going to device memory.  Capped by the device's per-block limit. */
 enum {
   BA_TUNE_SCATTER_LDS_KB = 0,
-  /* BA_TUNE_FACTORED_FUSE: positions per launch of the factored engine: 6 (default)
-   * as 5, and at n = 20 the backward sweep in two launches: its last twelve
-   * positions (three four-position steps through LDS) and its first eight (with D),
-   * the same sums in the same order as four positions per launch; 5
+  /* BA_TUNE_FACTORED_FUSE: positions per launch of the factored engine: 7 (default)
+   * as 6, and at n = 20 (FP32 iterates) the forward sweep in two launches: its
+   * first eight positions and its last twelve (one block per row of the eighth
+   * stage of output length 8, which recomputes that row's ancestors; three
+   * four-position steps through LDS), the same sums in the same order as four
+   * positions per launch; 6 as 5, and at n = 20 (FP32) the backward sweep in two
+   * launches: its last twelve positions (three four-position steps through LDS) and
+   * its first eight (with D), the same sums in the same order as four positions per
+   * launch; 5
    * as 4, with the forward's first eight positions in one launch (two four-position
    * steps through LDS, the same sums in the same order; n >= 12); 4 as 3, with the
    * forward's last four positions in one launch whose outputs are staged in LDS

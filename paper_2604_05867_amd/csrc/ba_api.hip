@@ -76,7 +76,7 @@ struct ba_ctx {
   std::string err;
   // tuning
   int scatter_lds_kb = 64;
-  int fuse = 6;  // factored engine: positions per launch (see BA_TUNE_FACTORED_FUSE)
+  int fuse = 7;  // factored engine: positions per launch (see BA_TUNE_FACTORED_FUSE)
   int stop_rule = BA_STOP_ITERATE;
   int sym = 0;   // complement-symmetric iteration requested
   double eta = 1.0;  // update step (1 = BA)
@@ -393,7 +393,7 @@ int sweeps(ba_ctx* c, const GroupHost& gh, const Group<T>& G, int use_sw_g, T* g
   } else {
     const int fuse_tail = (tail && !use_sw_g) ? 1 : 0;
     {
-      Timer t(c, BA_K_SWEEP1, forward_launches(n, c->fuse));
+      Timer t(c, BA_K_SWEEP1, forward_launches(n, c->fuse, int(sizeof(T))));
       HIPCHK(c, launch_forward<T>(G, s, nullptr, c->fuse, fuse_tail, upd));
     }
     if (!fuse_tail) {
@@ -645,7 +645,7 @@ int ba_set_tuning(ba_ctx* c, int key, int value) {
     return BA_OK;
   }
   if (key == BA_TUNE_FACTORED_FUSE) {
-    if (value < 0 || value > 6) return fail(c, BA_EINVAL, "fuse must be 0 .. 6");
+    if (value < 0 || value > 7) return fail(c, BA_EINVAL, "fuse must be 0 .. 7");
     c->fuse = value;
     drop_graph(c);
     return BA_OK;

@@ -1522,6 +1522,313 @@ __global__ __launch_bounds__(kStage12Threads) __attribute__((amdgpu_waves_per_eu
   }
 }
 
+// Twelve forward positions in one launch (i = n - 12 .. n - 1 for n = kStage12N,
+// FP32): F_i to r (LOGV: v = w_k log r), one block per leaf z of F_i (level i).
+// The outputs in z's subtree (levels i .. n) depend on F_i of z and of its i
+// ancestors A_1 .. A_i (A_k = k levels up), so each block recomputes that chain:
+//   step 1, thread c2 < 256 (column u2 2^4 + u1 of F_{i+4}): F_{i+4} of the chain
+//     from the root down (each row's four stages take the half of its parent's
+//     values at the same stages that its last bit selects) and of the 30 rows below
+//     z, the 16 column groups u3 of every row loaded from HBM or L2;
+//   step 2, from those 40 rows (one all-zero row stands for the rows above the root):
+//     thread (node q2 of depth 4 below z, u1) the four-position step of q2 with its
+//     30 rows below, and items (row, u1) F_{i+8} of the 15 nodes of depth <= 3 below
+//     z and of the chain rows A_1 .. A_{c+4} (c below);
+//   step 3, from F_{i+8}: thread q3 (depth 8 below z) the step of q3 and its 30 rows
+//     below, and items for the 255 nodes of depth <= 7 below z and for the chain rows
+//     A_1 .. A_c, where c is the number of trailing zero bits of z (8 for the
+//     first leaf): z is the first leaf below A_k exactly for k <= c, so every row above
+//     level i is written by one block.
+// Every value is the same sum in the same order as in k_fwd_stage4 and k_fwd_last4
+// (each stage of a row adds its own two halves, then its parent's half), so the
+// outputs equal those of the three launches bit for bit.  The subtree's outputs are
+// staged in LDS at stage12_slot of their heap index below z and written as one run
+// of ranks per level, as k_bwd_stage12 reads them.  Leaf order: XCD x (blockIdx.x mod
+// 8) takes the run of 2^(i-3) leaves below node x of level 3, whose chains share
+// their rows down to level 3 in that XCD's L2.
+// LDS (one array, each step's output overwriting the previous step's input after a
+// barrier): F_{i+4} as [row][c2] with pitch kF12P1 = 16 mod 32 (rows 1..31: heap index
+// below z, 31 + k: A_k, 0: zeros), so that the two nodes of a half-wavefront read
+// disjoint banks; F_{i+8} as [u1][stage12_slot(q)] with the odd pitch kF12P2 (q < 512
+// below z, 511 + k: A_k, 0: zeros).
+constexpr uint32_t kF12P1 = 256u + 16u;
+constexpr uint32_t kF12P2 = 537u;
+constexpr uint32_t kF12Words = 40u * kF12P1;
+static_assert(kF12Words >= 16u * kF12P2 && kF12Words >= kS12Words, "step buffers fit the array");
+
+// The four-position step of a row from LDS rows of its path P_0 .. P_4 (16 column
+// groups at stride CS from each row pointer; rows above the root point at zeros), in
+// rolling form: P_4 gives its F_i half, P_3 its F_{i+1}, P_2 up to F_{i+2}, P_1 up to
+// F_{i+3}, each row adding to its own halves the half of its parent's values that
+// its last bit selects (the sums of fwd4_thread, with fewer values live).  Returns
+// F_{i+4}[P_0] and leaves P_0's F_i row (R) and its F_{i+1} .. F_{i+3} for
+// fwd4_subtree.
+template <typename T, uint32_t CS>
+__device__ __forceinline__ T fwd4_roll(const T* const (&row)[5], const uint32_t (&lastb)[4], T (&R)[16],
+                                       T (&F1)[8], T (&F2)[4], T (&F3)[2]) {
+  T H0[8], H1[4], H2[2], H3 = T(0);
+  {
+    const T* h = row[4] + (lastb[3] ? 8u * CS : 0u);
+#pragma unroll
+    for (int g = 0; g < 8; ++g) H0[g] = h[uint32_t(g) * CS];
+  }
+#pragma unroll
+  for (int j = 3; j >= 0; --j) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) R[u] = row[j][uint32_t(u) * CS];
+#pragma unroll
+    for (int g = 0; g < 8; ++g) F1[g] = (R[g] + R[8 + g]) + H0[g];
+    if (j <= 2) {
+#pragma unroll
+      for (int g = 0; g < 4; ++g) F2[g] = (F1[g] + F1[4 + g]) + H1[g];
+    }
+    if (j <= 1) {
+#pragma unroll
+      for (int g = 0; g < 2; ++g) F3[g] = (F2[g] + F2[2 + g]) + H2[g];
+    }
+    if (j == 0) return (F3[0] + F3[1]) + H3;
+    const bool lb = lastb[j - 1];
+#pragma unroll
+    for (int g = 0; g < 8; ++g) H0[g] = lb ? R[8 + g] : R[g];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) H1[g] = lb ? F1[4 + g] : F1[g];
+    if (j <= 2) {
+#pragma unroll
+      for (int g = 0; g < 2; ++g) H2[g] = lb ? F2[2 + g] : F2[g];
+    }
+    if (j <= 1) H3 = lb ? F3[1] : F3[0];
+  }
+  return T(0);  // not reached
+}
+
+// fwd4_roll with the 30 rows below P_0 (as fwd4_subtree).
+template <typename T, uint32_t CS>
+__device__ __forceinline__ T fwd4_roll_tree(const T* const (&row)[5], const uint32_t (&lastb)[4], T (&F4)[30]) {
+  T R[16], F1[8], F2[4], F3[2], F1s[2][8];
+  const T v = fwd4_roll<T, CS>(row, lastb, R, F1, F2, F3);
+#pragma unroll
+  for (int cc = 0; cc < 2; ++cc)
+#pragma unroll
+    for (int g = 0; g < 8; ++g) F1s[cc][g] = R[cc * 8 + g];
+  fwd4_subtree<T>(F1, F2, F3, F1s, F4);
+  return v;
+}
+
+// fwd4_roll for the row alone.
+template <typename T, uint32_t CS>
+__device__ __forceinline__ T fwd4_roll_row(const T* const (&row)[5], const uint32_t (&lastb)[4]) {
+  T R[16], F1[8], F2[4], F3[2];
+  return fwd4_roll<T, CS>(row, lastb, R, F1, F2, F3);
+}
+
+// Path of an item of steps 2 and 3 that is not a leaf step: node q (1..) below z at
+// depth dq, or chain row A_k (q = 0); row indices: nodes q >> j, then A_1, A_2, ...
+// (chain index k, 0 past the root).  lastb: a node's last bit, z's (bit 0 of the
+// leaf index l), or A_k's (bit k of l).
+__device__ __forceinline__ void fwd12_path(uint32_t q, uint32_t k0, uint32_t l, uint32_t (&node)[5],
+                                           uint32_t (&chain)[5], uint32_t (&lastb)[4]) {
+  constexpr uint32_t I = kStage12N - 12;
+  const int dq = q ? 31 - __clz(q) : -1;
+#pragma unroll
+  for (int j = 0; j < 5; ++j) {
+    const uint32_t qq = q >> j;
+    const uint32_t k = (j <= dq) ? 0u : (q ? uint32_t(j - dq) : k0 + uint32_t(j));
+    node[j] = (j <= dq) ? qq : 0u;
+    chain[j] = k <= I ? k : 0u;
+    if (j < 4) lastb[j] = (j <= dq) ? (qq >= 2u ? (qq & 1u) : (l & 1u)) : ((l >> k) & 1u);
+  }
+}
+
+template <bool LOGV>
+__global__ __launch_bounds__(kStage12Threads) __attribute__((amdgpu_waves_per_eu(6))) void k_fwd_stage12(
+    int n, const float* __restrict__ src, size_t sstride, float* __restrict__ dst, size_t dstride, const State* st,
+    const Consts* cs, int frz) {
+  using T = float;
+  constexpr int I = kStage12N - 12;
+  const int b = blockIdx.y;
+  if (n != kStage12N || (frz && st[b].converged)) return;
+  const uint32_t l = ((blockIdx.x & 7u) << (I - 3)) + (blockIdx.x >> 3);  // leaf index
+  const uint32_t z1 = (1u << I) + l;                                        // rank of z, plus 1
+  const uint32_t c = l ? uint32_t(__ffs(l) - 1) : uint32_t(I);              // chain rows written here
+  src += (size_t)b * sstride;
+  dst += (size_t)b * dstride;
+  __shared__ __attribute__((aligned(16))) T buf[kF12Words];
+  const uint32_t t = threadIdx.x;
+  // waves 0-3 take the leaf steps, waves 4-7 the other items (a wave-uniform branch)
+  const bool leafw = __builtin_amdgcn_readfirstlane(t) < 256u;
+  // step 1: F_{i+4} of the chain and of z's subtree, column t
+  if (leafw) {
+    T H0[8], H1[4], H2[2], H3 = T(0);
+#pragma unroll
+    for (int g = 0; g < 8; ++g) H0[g] = T(0);
+#pragma unroll
+    for (int g = 0; g < 4; ++g) H1[g] = T(0);
+#pragma unroll
+    for (int g = 0; g < 2; ++g) H2[g] = T(0);
+#pragma unroll
+    for (int j = I; j >= 0; --j) {
+      const T* row = src + ((size_t)((z1 >> j) - 1u) << (kStage12N - I)) + t;  // A_j (A_0 = z)
+      T R[16], F1[8], F2[4], F3[2];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) R[u] = row[uint32_t(u) << 8];
+#pragma unroll
+      for (int g = 0; g < 8; ++g) F1[g] = (R[g] + R[8 + g]) + H0[g];
+#pragma unroll
+      for (int g = 0; g < 4; ++g) F2[g] = (F1[g] + F1[4 + g]) + H1[g];
+#pragma unroll
+      for (int g = 0; g < 2; ++g) F3[g] = (F2[g] + F2[2 + g]) + H2[g];
+      buf[(j ? 31u + uint32_t(j) : 1u) * kF12P1 + t] = (F3[0] + F3[1]) + H3;
+      if (j > 0) {
+        const bool lb = (l >> (j - 1)) & 1u;  // last bit of A_{j-1}
+#pragma unroll
+        for (int g = 0; g < 8; ++g) H0[g] = lb ? R[8 + g] : R[g];
+#pragma unroll
+        for (int g = 0; g < 4; ++g) H1[g] = lb ? F1[4 + g] : F1[g];
+#pragma unroll
+        for (int g = 0; g < 2; ++g) H2[g] = lb ? F2[2 + g] : F2[g];
+        H3 = lb ? F3[1] : F3[0];
+      } else {
+        T F1s[2][8], F4[30];
+#pragma unroll
+        for (int cc = 0; cc < 2; ++cc)
+#pragma unroll
+          for (int g = 0; g < 8; ++g) F1s[cc][g] = R[cc * 8 + g];
+        fwd4_subtree<T>(F1, F2, F3, F1s, F4);
+#pragma unroll
+        for (int q = 2; q < 32; ++q) buf[uint32_t(q) * kF12P1 + t] = F4[q - 2];
+      }
+    }
+    buf[t] = T(0);
+  }
+  __syncthreads();
+  // step 2: F_{i+8}
+  T o[31];
+  const uint32_t nch = c + 4u < uint32_t(I) ? c + 4u : uint32_t(I);
+  const uint32_t items2 = (15u + nch) * 16u;
+  if (leafw) {
+    const uint32_t q2 = 16u + (t >> 4), u1 = t & 15u;
+    const T* row[5];
+    uint32_t lastb[4];
+#pragma unroll
+    for (int j = 0; j < 5; ++j) row[j] = buf + (q2 >> j) * kF12P1 + u1;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) lastb[j] = (q2 >> j) & 1u;
+    T F4[30];
+    o[0] = fwd4_roll_tree<T, 16u>(row, lastb, F4);
+#pragma unroll
+    for (int q = 0; q < 30; ++q) o[1 + q] = F4[q];
+  } else {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const uint32_t e = t - 256u + uint32_t(h) * 256u;
+      if (e < items2) {
+        const uint32_t rb = e >> 4, u1 = e & 15u;
+        const uint32_t q = rb < 15u ? rb + 1u : 0u, k0 = rb < 15u ? 0u : rb - 14u;
+        uint32_t node[5], chain[5], lastb[4];
+        fwd12_path(q, k0, l, node, chain, lastb);
+        const T* row[5];
+#pragma unroll
+        for (int j = 0; j < 5; ++j) row[j] = buf + (node[j] ? node[j] : (chain[j] ? 31u + chain[j] : 0u)) * kF12P1 + u1;
+        o[h] = fwd4_roll_row<T, 16u>(row, lastb);
+      }
+    }
+  }
+  __syncthreads();
+  if (leafw) {
+    const uint32_t q2 = 16u + (t >> 4), u1 = t & 15u;
+    T* col = buf + u1 * kF12P2;
+    col[stage12_slot(q2)] = o[0];
+#pragma unroll
+    for (int d = 1; d <= 4; ++d) {
+      T* r = col + stage12_slot(q2 << d);
+#pragma unroll
+      for (int m = 0; m < (1 << d); ++m) r[m] = o[(1 << d) - 1 + m];
+    }
+    if (t < 16u) buf[t * kF12P2] = T(0);
+  } else {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const uint32_t e = t - 256u + uint32_t(h) * 256u;
+      if (e < items2) {
+        const uint32_t rb = e >> 4, u1 = e & 15u;
+        buf[u1 * kF12P2 + stage12_slot(rb < 15u ? rb + 1u : 511u + (rb - 14u))] = o[h];
+      }
+    }
+  }
+  __syncthreads();
+  // step 3: F_n = r, staged at stage12_slot of the heap index below z
+  const uint32_t items3 = 255u + c;
+  T w[5];
+  if (leafw) {
+    const uint32_t q3 = 256u + t;
+    const T* row[5];
+    uint32_t lastb[4];
+#pragma unroll
+    for (int j = 0; j < 5; ++j) row[j] = buf + stage12_slot(q3 >> j);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) lastb[j] = (q3 >> j) & 1u;
+    T F4[30];
+    o[0] = fwd4_roll_tree<T, kF12P2>(row, lastb, F4);
+#pragma unroll
+    for (int q = 0; q < 30; ++q) o[1 + q] = F4[q];
+#pragma unroll
+    for (int d = 0; d <= 4; ++d) w[d] = T(cs[b].w[2 * I + d]);
+  } else {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const uint32_t e = t - 256u + uint32_t(h) * 256u;
+      if (e < items3) {
+        const uint32_t q = e < 255u ? e + 1u : 0u, k0 = e < 255u ? 0u : e - 254u;
+        uint32_t node[5], chain[5], lastb[4];
+        fwd12_path(q, k0, l, node, chain, lastb);
+        const T* row[5];
+#pragma unroll
+        for (int j = 0; j < 5; ++j)
+          row[j] = buf + stage12_slot(node[j] ? node[j] : (chain[j] ? 511u + chain[j] : 0u));
+        o[h] = fwd4_roll_row<T, kF12P2>(row, lastb);
+        w[h] = T(cs[b].w[q ? I + 31 - __clz(q) : I - int(k0)]);
+      }
+    }
+  }
+  auto outv = [](T wk, T r) -> T {
+    if constexpr (LOGV) return (wk == T(0)) ? T(0) : wk * log_t<T>(r);
+    else return r;
+  };
+  __syncthreads();
+  if (leafw) {
+    const uint32_t q3 = 256u + t;
+    buf[stage12_slot(q3)] = outv(w[0], o[0]);
+#pragma unroll
+    for (int d = 1; d <= 4; ++d) {
+      T* r = buf + stage12_slot(q3 << d);
+#pragma unroll
+      for (int m = 0; m < (1 << d); ++m) r[m] = outv(w[d], o[(1 << d) - 1 + m]);
+    }
+  } else {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const uint32_t e = t - 256u + uint32_t(h) * 256u;
+      if (e < 255u) buf[stage12_slot(e + 1u)] = outv(w[h], o[h]);
+      else if (e < items3) dst[(z1 >> (e - 254u)) - 1u] = outv(w[h], o[h]);  // A_k, k = e - 254
+    }
+  }
+  __syncthreads();
+  // copy-out: depth k of z's subtree is the run of ranks (z + 1) 2^k - 1 + m
+  {
+    const uint32_t q = t + 1u;
+    const int kq = 31 - __clz(q);
+    if (q < 512u) dst[(z1 << kq) - 1u + (q - (1u << kq))] = buf[stage12_slot(q)];
+    const uint32_t st0 = stage12_slot(t);
+#pragma unroll
+    for (int kk = 9; kk <= 12; ++kk) {
+      T* base = dst + ((z1 << kk) - 1u);
+#pragma unroll
+      for (int j = 0; j < (1 << (kk - 9)); ++j)
+        base[t + uint32_t(j) * kStage12Threads] = buf[st0 + (1u << kk) + (1u << (kk - 5)) + uint32_t(j) * 528u];
+    }
+  }
+}
+
 // The same for source rows of width 1 (the first backward launch, from v): one
 // thread per output row r, which is 4 consecutive values.
 template <typename T>
@@ -1577,6 +1884,21 @@ hipError_t launch_forward(const Group<T>& g, hipStream_t s, int* launches, int f
       ss = g.fs;
       i = 8;
       continue;
+    }
+    if constexpr (sizeof(T) == 4) {
+      // fuse >= 7 at n = kStage12N: positions 8 .. n-1 in one launch
+      if (fuse >= 7 && n == kStage12N && i == n - 12) {
+        T* dst = logv ? g.v : g.r;
+        const dim3 grid(1u << (n - 12), g.nb);  // one block per leaf of F_8
+        if (logv)
+          hipLaunchKernelGGL((k_fwd_stage12<true>), grid, dim3(kStage12Threads), 0, s, n, src, ss, dst, g.ys, g.st,
+                             g.cs, g.frz);
+        else
+          hipLaunchKernelGGL((k_fwd_stage12<false>), grid, dim3(kStage12Threads), 0, s, n, src, ss, dst, g.ys,
+                             g.st, g.cs, g.frz);
+        if (launches) ++*launches;
+        break;
+      }
     }
     if (last4 && n - i == 4) {
       T* dst = logv ? g.v : g.r;
@@ -1862,7 +2184,8 @@ int backward_launches(int n, int fuse, int esz) {
   return factored_launches(n, fuse);
 }
 
-int forward_launches(int n, int fuse) {
+int forward_launches(int n, int fuse, int esz) {
+  if (fuse >= 7 && n == kStage12N && esz == 4) return 2;
   if (fuse >= 5 && n >= kFirst8MinN) return forward_launches(n, 4) - 1;
   if (fuse >= 4 && n >= kLast4MinN) {
     const int four = (n - 4) / 4, rest = (n - 4) % 4;  // then 0-3 positions two or one at a time

@@ -367,39 +367,29 @@ __device__ __forceinline__ void d_records(const Group<T>& g, int b, double M, co
 }
 
 // Register part of the four-position forward step for one (y, column), from the
-// first stage on: F1p holds F_{i+1} of the path P_0 = y .. P_3 (8 groups), F1s
-// that of the two children of y; lastb[j] = last bit of P_j.  Returns F_{i+4}[y]
-// and, in F4, the 30 rows below y (breadth-first: depth d, index m at
-// (1 << d) - 2 + m).
+// The 30 rows below a row y after four stages, from y's values at the first three
+// of them (F1z = F_{i+1}[y], 8 column groups; F2z, F3z) and F1s, the two children of
+// y at stage i+1 (the halves of F_i[y]): breadth-first, depth d index m at
+// (1 << d) - 2 + m.
 template <typename T>
-__device__ __forceinline__ T fwd4_after_stage1(const T (&F1p)[4][8], const T (&F1s)[2][8],
-                                               const uint32_t (&lastb)[4], T (&F4)[30]) {
-  // stage 2: path P_0..P_2 (4 groups), subtree depth 1..2 (breadth-first 0..5)
-  T F2p[3][4], F2s[6][4];
-#pragma unroll
-  for (int j = 0; j < 3; ++j)
-#pragma unroll
-    for (int g = 0; g < 4; ++g)
-      F2p[j][g] = (F1p[j][g] + F1p[j][4 + g]) + (lastb[j] ? F1p[j + 1][4 + g] : F1p[j + 1][g]);
+__device__ __forceinline__ void fwd4_subtree(const T (&F1z)[8], const T (&F2z)[4], const T (&F3z)[2],
+                                             const T (&F1s)[2][8], T (&F4)[30]) {
+  // stage 2: subtree depth 1..2 (breadth-first 0..5)
+  T F2s[6][4];
 #pragma unroll
   for (int c = 0; c < 2; ++c)
 #pragma unroll
-    for (int g = 0; g < 4; ++g) F2s[c][g] = (F1s[c][g] + F1s[c][4 + g]) + F1p[0][c * 4 + g];
+    for (int g = 0; g < 4; ++g) F2s[c][g] = (F1s[c][g] + F1s[c][4 + g]) + F1z[c * 4 + g];
 #pragma unroll
   for (int c = 0; c < 4; ++c)  // depth 2: child c/2 of y, then bit c&1
 #pragma unroll
     for (int g = 0; g < 4; ++g) F2s[2 + c][g] = F1s[c >> 1][(c & 1) * 4 + g];
-  // stage 3: path P_0..P_1 (2 groups), subtree depth 1..3 (breadth-first 0..13)
-  T F3p[2][2], F3s[14][2];
-#pragma unroll
-  for (int j = 0; j < 2; ++j)
-#pragma unroll
-    for (int g = 0; g < 2; ++g)
-      F3p[j][g] = (F2p[j][g] + F2p[j][2 + g]) + (lastb[j] ? F2p[j + 1][2 + g] : F2p[j + 1][g]);
+  // stage 3: subtree depth 1..3 (breadth-first 0..13)
+  T F3s[14][2];
 #pragma unroll
   for (int c = 0; c < 2; ++c)
 #pragma unroll
-    for (int g = 0; g < 2; ++g) F3s[c][g] = (F2s[c][g] + F2s[c][2 + g]) + F2p[0][c * 2 + g];
+    for (int g = 0; g < 2; ++g) F3s[c][g] = (F2s[c][g] + F2s[c][2 + g]) + F2z[c * 2 + g];
 #pragma unroll
   for (int c = 0; c < 4; ++c)
 #pragma unroll
@@ -408,15 +398,39 @@ __device__ __forceinline__ T fwd4_after_stage1(const T (&F1p)[4][8], const T (&F
   for (int c = 0; c < 8; ++c)
 #pragma unroll
     for (int g = 0; g < 2; ++g) F3s[6 + c][g] = F2s[2 + (c >> 1)][(c & 1) * 2 + g];
-  // stage 4: y (1 group), subtree depth 1..4
+  // stage 4: subtree depth 1..4
 #pragma unroll
-  for (int c = 0; c < 2; ++c) F4[c] = (F3s[c][0] + F3s[c][1]) + F3p[0][c];
+  for (int c = 0; c < 2; ++c) F4[c] = (F3s[c][0] + F3s[c][1]) + F3z[c];
 #pragma unroll
   for (int c = 0; c < 4; ++c) F4[2 + c] = (F3s[2 + c][0] + F3s[2 + c][1]) + F3s[c >> 1][c & 1];
 #pragma unroll
   for (int c = 0; c < 8; ++c) F4[6 + c] = (F3s[6 + c][0] + F3s[6 + c][1]) + F3s[2 + (c >> 1)][c & 1];
 #pragma unroll
   for (int c = 0; c < 16; ++c) F4[14 + c] = F3s[6 + (c >> 1)][c & 1];
+}
+
+// first stage on: F1p holds F_{i+1} of the path P_0 = y .. P_3 (8 groups), F1s
+// that of the two children of y; lastb[j] = last bit of P_j.  Returns F_{i+4}[y]
+// and, in F4, the 30 rows below y (as fwd4_subtree).
+template <typename T>
+__device__ __forceinline__ T fwd4_after_stage1(const T (&F1p)[4][8], const T (&F1s)[2][8],
+                                               const uint32_t (&lastb)[4], T (&F4)[30]) {
+  // stage 2: path P_0..P_2 (4 groups)
+  T F2p[3][4];
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+      F2p[j][g] = (F1p[j][g] + F1p[j][4 + g]) + (lastb[j] ? F1p[j + 1][4 + g] : F1p[j + 1][g]);
+  // stage 3: path P_0..P_1 (2 groups)
+  T F3p[2][2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j)
+#pragma unroll
+    for (int g = 0; g < 2; ++g)
+      F3p[j][g] = (F2p[j][g] + F2p[j][2 + g]) + (lastb[j] ? F2p[j + 1][2 + g] : F2p[j + 1][g]);
+  fwd4_subtree<T>(F1p[0], F2p[0], F3p[0], F1s, F4);
+  // stage 4: y (1 group)
   return (F3p[0][0] + F3p[0][1]) + (lastb[0] ? F3p[1][1] : F3p[1][0]);
 }
 

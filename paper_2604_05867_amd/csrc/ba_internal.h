@@ -231,7 +231,11 @@ hipError_t launch_pull(const Group<T>& g, T* partial, hipStream_t s);
 // two (or one) at a time: the last 1-4 in the forward, the first n mod 4 in the
 // backward; fuse = 3: as 2 with eight positions per backward launch
 // (k_bwd_stage8) while four remain for the last; fuse = 4: as 3 with the last four
-// forward positions in one launch (k_fwd_last4, n >= 12).
+// forward positions in one launch (k_fwd_last4, n >= 12); fuse = 5: as 4 with the
+// first eight forward positions in one launch (k_fwd_first8); fuse = 6: as 5 with
+// the backward sweep at n = 20 (FP32) in two launches (k_bwd_stage12, then
+// k_bwd_stage8_p with D); fuse = 7: as 6 with the forward positions 8 .. 19 at
+// n = 20 (FP32) in one launch (k_fwd_stage12).
 // logv = 1: the last forward launch writes v = w_k log r instead of r.
 // dpart = 1: the last backward launch also forms D = H - G - M and the block
 // records of k_dpart, writing D instead of G; *dpart_blocks returns the number of
@@ -263,7 +267,7 @@ hipError_t launch_backward(const Group<T>& g, hipStream_t s, int* launches, int 
                            int* dpart_blocks);                                                   // v -> G
 int factored_launches(int n, int fuse);   // forward launches (two positions each when fuse != 0)
 int backward_launches(int n, int fuse, int esz = 4);  // launches of launch_backward (esz: element bytes)
-int forward_launches(int n, int fuse);    // launches of launch_forward
+int forward_launches(int n, int fuse, int esz = 4);  // launches of launch_forward
 // Complement-symmetric iteration (iterate invariant under complement): the two
 // products on the canonical half, v and D fused as above; v is stored at compact
 // indices (2^n entries) and D, G for x < 2^(n-1).  Supported for even n >= 4 with

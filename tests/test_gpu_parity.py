@@ -397,7 +397,7 @@ def test_factored_fusion_settings_agree(ba, n):
     lp = inp.random_logp(n, seed=40 + n, spread=2.0)
     say("fusion settings n=%d" % n)
     out = []
-    for fuse in (0, 1, 2, 3, 4, 5, 6):
+    for fuse in (0, 1, 2, 3, 4, 5, 6, 7):
         c = ba.Context(n, d)
         c.set_tuning(ba.TUNE_FACTORED_FUSE, fuse)
         got = c.eval(torch.from_numpy(lp))
@@ -487,6 +487,29 @@ def test_twelve_position_backward_iterates(ba, prec):
     assert np.max(np.abs(out[0][0] - out[1][0])) < tol
     for k in range(len(ns)):
         assert abs(out[0][1][0][k] - out[1][1][0][k]) < tol and abs(out[0][1][1][k] - out[1][1][1][k]) < tol
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_twelve_position_forward_is_bitwise(ba, seed):
+    """At n = 20 (FP32) the forward positions 8-19 in one launch per leaf of F_8
+    (launch plan level 7: the leaf's ancestor rows recomputed in its block) give
+    bitwise the iterates and bounds of level 6 (positions 8-11, 12-15 and 16-19 in
+    three launches): every value is the same sum in the same order."""
+    n = 20
+    ns, ds = [n] * 3, [0.64, 0.8, 0.95]
+    say("twelve-position forward seed=%d" % seed)
+    c = chain(ba.Context(ns, ds, prec=ba.PREC_FP32_LOG))
+    start = torch.tensor(np.concatenate([inp.random_logp(n, seed=70 + 3 * seed + k, spread=3.0)
+                                         for k in range(3)]))
+    out = []
+    for fuse in (6, 7):
+        c.set_logp(start)
+        c.set_tuning(ba.TUNE_FACTORED_FUSE, fuse)
+        c.step(3)
+        out.append((c.get_logp().cpu().numpy(), c.bounds()))
+    c.close()
+    assert np.array_equal(out[0][0], out[1][0])
+    assert out[0][1] == out[1][1]
 
 
 @pytest.mark.parametrize("n,prec", [(12, "fp64"), (17, "fp64"), (20, "fp32"), (20, "fp64")])
