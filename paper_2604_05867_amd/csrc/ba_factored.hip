@@ -570,7 +570,7 @@ __global__ __launch_bounds__(kLast2Threads) void k_fwd_last2(int n, const T* __r
   const T w0 = T(cs[b].w[L]), w1 = T(cs[b].w[L + 1]), w2 = T(cs[b].w[L + 2]), w3 = T(cs[b].w[L + 3]),
           w4 = T(cs[b].w[L + 4]);
   auto outv = [](T w, T r) -> T {
-    if constexpr (LOGV) return (w == T(0)) ? T(0) : w * log_t<T>(r);
+    if constexpr (LOGV) return wlog_t<T>(w, r);
     else return r;
   };
   if (blockIdx.x >= ndeep) {
@@ -685,7 +685,7 @@ __global__ __launch_bounds__(kLast4Threads) void k_fwd_last4(int n, const T* __r
     const T w0 = T(cs[b].w[L]), w1 = T(cs[b].w[L + 1]), w2 = T(cs[b].w[L + 2]), w3 = T(cs[b].w[L + 3]),
             w4 = T(cs[b].w[L + 4]);
     auto outv = [](T w, T r) -> T {
-      if constexpr (LOGV) return (w == T(0)) ? T(0) : w * log_t<T>(r);
+      if constexpr (LOGV) return wlog_t<T>(w, r);
       else return r;
     };
     dst[y] = outv(w0, va);
@@ -1791,7 +1791,7 @@ __global__ __launch_bounds__(kStage12Threads) __attribute__((amdgpu_waves_per_eu
     }
   }
   auto outv = [](T wk, T r) -> T {
-    if constexpr (LOGV) return (wk == T(0)) ? T(0) : wk * log_t<T>(r);
+    if constexpr (LOGV) return wlog_t<T>(wk, r);
     else return r;
   };
   __syncthreads();

@@ -80,8 +80,7 @@ __device__ __forceinline__ Vec<T, V> zero_vec() {
 // v(y) = w_k log r(y) for the output of rank y (0 where w_k = 0).
 template <typename T>
 __device__ __forceinline__ T log_weighted(const Consts& cs, uint32_t y, T r) {
-  const T wk = T(cs.w[length_of_rank(y)]);
-  return (wk == T(0)) ? T(0) : wk * log_t<T>(r);
+  return wlog_t<T>(T(cs.w[length_of_rank(y)]), r);
 }
 
 // ---------------------------------------------------------------------------

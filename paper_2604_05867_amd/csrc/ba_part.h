@@ -20,6 +20,19 @@ template <>
 __device__ __forceinline__ float log_t<float>(float v) { return logf(v); }
 template <>
 __device__ __forceinline__ double log_t<double>(double v) { return log(v); }
+// w log r for a value r of the output law (v = w_k log r), 0 where w = 0.  FP32: the
+// hardware base-2 logarithm times w ln 2; r is a normal number here (every iterate
+// value is at least e^-87, the largest FP32 floor, and r sums such values).
+template <typename T>
+__device__ __forceinline__ T wlog_t(T w, T r);
+template <>
+__device__ __forceinline__ float wlog_t<float>(float w, float r) {
+  return (w == 0.0f) ? 0.0f : (w * 0.693147180559945309f) * __builtin_amdgcn_logf(r);
+}
+template <>
+__device__ __forceinline__ double wlog_t<double>(double w, double r) {
+  return (w == 0.0) ? 0.0 : w * log(r);
+}
 template <typename T>
 __device__ __forceinline__ T exp_t(T v);
 template <>

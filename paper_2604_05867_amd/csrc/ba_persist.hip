@@ -152,7 +152,7 @@ __global__ __launch_bounds__(NT) void k_persist(Group<T> g, int iters, double fl
     // v(y) = w_k log r(y), in place (B_n)
     for (uint32_t y = t; y < Y; y += kPersistThreads) {
       const T wk = T(cs.w[rank_length(y)]);
-      src[y] = (wk == T(0)) ? T(0) : wk * log_t<T>(src[y]);
+      src[y] = wlog_t<T>(wk, src[y]);
     }
     __syncthreads();
     // backward: B_i (2^(i+1) - 1 rows of 2^w columns, w = n - i) from B_{i+1}: column

@@ -29,7 +29,7 @@ __global__ __launch_bounds__(kBlock) void k_logr(Group<T> g, int use_sw) {
   T* v = g.v + (size_t)b * g.ys;
   for (uint32_t y = blockIdx.x * blockDim.x + threadIdx.x; y < Y; y += gridDim.x * blockDim.x) {
     const T wk = T(w[length_of_rank(y)]);
-    v[y] = (wk == T(0)) ? T(0) : wk * log_t<T>(r[y]);
+    v[y] = wlog_t<T>(wk, r[y]);
   }
 }
 
@@ -51,7 +51,7 @@ __global__ __launch_bounds__(kBlock) void k_logr_split(Group<T> g, int use_sw, i
     const uint32_t y1 = R1 + 1u - (1u << k1), y2 = R2 + 1u - (1u << k2);
     const uint32_t rank = ((y1 | (1u << k1)) << k2) + y2 - 1u;
     const T wk = T(w[k1 + k2]);
-    v2[idx] = (wk == T(0)) ? T(0) : wk * log_t<T>(r[rank]);
+    v2[idx] = wlog_t<T>(wk, r[rank]);
   }
 }
 
