@@ -38,7 +38,7 @@ sys.path.insert(0, ROOT)
 N = 20
 DS = [0.64, 0.80, 0.95]
 UNIT_EQUIV = "W-nonzero-equivalent terms/s (factored engine: nonzeros accounted, not visited)"
-FUSE = 7  # the library default (positions per launch of the factored engine)
+FUSE = 8  # the library default (positions per launch of the factored engine)
 
 
 # HBM bytes per launch of this workload's sweeps, from rocprofv3 FETCH_SIZE and
@@ -129,6 +129,33 @@ def sweep_launch_bytes(n, esz, nb, fuse, backward, fused_update=0.0):
         out[-1] += 2 * (1 << n) * esz * nb
     else:
         out[0] += fused_update * (1 << n) * esz * nb
+    return out
+
+
+def call_launch_bytes(n, esz, nb, fuse, iters, backward):
+    """Algorithmic HBM bytes of every launch of one sweep over a ba_step call of
+    `iters` iterations, in launch order: sweep_launch_bytes per iteration (the first
+    iteration without the fused update), and at fuse 8 (n = 20) the D launch of
+    iterations 1 .. iters-2 fused with the next iteration's update and first eight
+    forward positions: it reads B_8, H and log p and writes log p and F_8 (no D), and
+    the next forward sweep is the one launch of positions 8-19."""
+    s = stage_sizes(n)
+    x = (1 << n) * esz * nb
+    out = []
+    for it in range(iters):
+        if fuse >= 8 and n == 20:
+            fused_prev = 2 <= it
+            fused_here = 1 <= it < iters - 1
+            if not backward:
+                out += [(s[8] + s[20]) * esz * nb] if fused_prev else \
+                    sweep_launch_bytes(n, esz, nb, 7, False, fused_update=1.0 if it else 0.0)
+            else:
+                b = sweep_launch_bytes(n, esz, nb, 7, True)
+                if fused_here:
+                    b[-1] = 2 * s[8] * esz * nb + 3 * x
+                out += b
+        else:
+            out += sweep_launch_bytes(n, esz, nb, fuse, backward, fused_update=1.0 if it else 0.0)
     return out
 
 
@@ -457,17 +484,16 @@ def main():
     dom = max(("sweep1", "sweep2"), key=lambda k: kt[k][0])
     dom_ms, dom_launches = kt[dom]
     per_launch_ms = dom_ms / max(dom_launches, 1)
-    # within one step call every iteration but the first makes the previous update
-    per_launch = sweep_launch_bytes(N, 4, nb, FUSE, backward=(dom == "sweep2"),
-                                    fused_update=(args.steps - 1) / args.steps)
-    assert len(per_launch) == dom_launches // args.steps, (len(per_launch), dom_launches)
+    per_launch = call_launch_bytes(N, 4, nb, FUSE, args.steps, backward=(dom == "sweep2"))
+    assert len(per_launch) == dom_launches, (len(per_launch), dom_launches)
     bytes_launch = sum(per_launch) / len(per_launch)
     achieved = bytes_launch / (per_launch_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
                 "frac": round(achieved / 8000.0, 4),
                 "traffic": measured_traffic(dom),
                 "kernel": ("forward sweep (k_fwd_first8, k_fwd_stage12)" if dom == "sweep1"
-                           else "backward sweep (k_bwd_stage12, k_bwd_stage8_p with D fused)"),
+                           else "backward sweep (k_bwd_stage12, k_bwd_stage8_p with D and the next "
+                                "iteration's update and first eight forward positions)"),
                 "bytes_per_launch": int(bytes_launch), "avg_launch_us": round(per_launch_ms * 1e3, 2)}
 
     lo, hi = ctx.bounds()

@@ -175,7 +175,12 @@ int ba_set_graphs(ba_ctx *c, int enable);
  *  before going to device memory.  Capped by the device's per-block limit. */
 enum {
   BA_TUNE_SCATTER_LDS_KB = 0,
-  /* BA_TUNE_FACTORED_FUSE: positions per launch of the factored engine: 7 (default)
+  /* BA_TUNE_FACTORED_FUSE: positions per launch of the factored engine: 8 (default)
+   * as 7, and at n = 20 (FP32 iterates, step 1, full kernels) inside one ba_step call
+   * from its second iteration on, the D launch of every iteration but the last also
+   * makes the next iteration's update and first eight forward positions on the same
+   * inputs (the new log p shifted by the previous iteration's max of log p + D instead
+   * of the current one: iterates equal to FP32 rounding); 7
    * as 6, and at n = 20 (FP32 iterates) the forward sweep in two launches: its
    * first eight positions and its last twelve (one block per row of the eighth
    * stage of output length 8, which recomputes that row's ancestors; three
@@ -259,10 +264,12 @@ int ba_bind_static(ba_ctx *c, void *hip_stream);
  * host synchronisation.  An instance whose current-iterate gap U - L (in the
  * iteration precision) falls below its tolerance (see ba_run) stops updating.
  * FP32 iterates with eta = 1 at n = 20 (factored engine, default launch plan)
- * are scaled to max 1 instead of normalised between the iterations of one call
- * (the sweeps do not depend on the scale; the last update of the call normalises),
- * so their in-call L, U and I are not formed; the iterate a call leaves is
- * normalised.  BA_ESTATE before ba_bind. */
+ * are scaled by a max shift instead of normalised between the iterations of one
+ * call (the sweeps do not depend on the scale; the last update of the call
+ * normalises): after the first iteration the shift is the max of log p + D, from
+ * the third on that of the iteration before (the new log p then lies at most n ln 2
+ * above 0), so their in-call L, U and I are not formed; the iterate a call leaves
+ * is normalised.  BA_ESTATE before ba_bind. */
 int ba_step(ba_ctx *c, int iters);
 
 /* Iterate until the FP64-certified gap U - L is below gap_bits for every instance

@@ -10,7 +10,7 @@ change the work decomposition, never the results beyond rounding order.
 
 Knobs:
   engine factored:
-    TUNE_FACTORED_FUSE     positions per launch (launch plan level 7 .. 0)
+    TUNE_FACTORED_FUSE     positions per launch (launch plan level 8 .. 0)
     TUNE_STAGE8_COLUMNS    columns per block of the eight-position backward
                            launches, log2 (0 = widest, 1 .. 4), i.e. the tile of
                            (subtree roots x columns) a block stages in LDS
@@ -31,7 +31,7 @@ from . import (ENGINE_FACTORED, ENGINE_STREAM, TUNE_FACTORED_FUSE, TUNE_PERSIST_
 
 # knob -> candidate values, the library default first
 KNOBS = {
-    ENGINE_FACTORED: [(TUNE_FACTORED_FUSE, [7, 6, 5, 4, 3, 2, 1, 0]),
+    ENGINE_FACTORED: [(TUNE_FACTORED_FUSE, [8, 7, 6, 5, 4, 3, 2, 1, 0]),
                       (TUNE_STAGE8_COLUMNS, [0, 1, 2, 3, 4]),
                       (TUNE_PERSISTENT, [1, 0, 2]),
                       (TUNE_PERSIST_THREADS, [1024, 512, 256])],

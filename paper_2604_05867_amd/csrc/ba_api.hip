@@ -76,7 +76,7 @@ struct ba_ctx {
   std::string err;
   // tuning
   int scatter_lds_kb = 64;
-  int fuse = 7;  // factored engine: positions per launch (see BA_TUNE_FACTORED_FUSE)
+  int fuse = 8;  // factored engine: positions per launch (see BA_TUNE_FACTORED_FUSE)
   int stop_rule = BA_STOP_ITERATE;
   int sym = 0;   // complement-symmetric iteration requested
   double eta = 1.0;  // update step (1 = BA)
@@ -333,7 +333,8 @@ bool sym_active(const ba_ctx* c, int n) {
 // launches k_dpart).
 template <typename T>
 int sweeps(ba_ctx* c, const GroupHost& gh, const Group<T>& G, int use_sw_g, T* g_out, int tail = 0,
-           int* tail_done = nullptr, const FusedUpdate* upd = nullptr) {
+           int* tail_done = nullptr, const FusedUpdate* upd = nullptr, bool first8_done = false,
+           const FusedNext* next = nullptr) {
   if (tail_done) *tail_done = 0;
   hipStream_t s = c->stream;
   const int n = gh.n, n1 = (n + 1) / 2, n2 = n / 2;
@@ -393,8 +394,8 @@ int sweeps(ba_ctx* c, const GroupHost& gh, const Group<T>& G, int use_sw_g, T* g
   } else {
     const int fuse_tail = (tail && !use_sw_g) ? 1 : 0;
     {
-      Timer t(c, BA_K_SWEEP1, forward_launches(n, c->fuse, int(sizeof(T))));
-      HIPCHK(c, launch_forward<T>(G, s, nullptr, c->fuse, fuse_tail, upd));
+      Timer t(c, BA_K_SWEEP1, forward_launches(n, c->fuse, int(sizeof(T))) - (first8_done ? 1 : 0));
+      HIPCHK(c, launch_forward<T>(G, s, nullptr, c->fuse, fuse_tail, upd, first8_done ? 1 : 0));
     }
     if (!fuse_tail) {
       Timer t(c, BA_K_LOGR, 1);
@@ -405,7 +406,7 @@ int sweeps(ba_ctx* c, const GroupHost& gh, const Group<T>& G, int use_sw_g, T* g
       Group<T> G2 = G;
       G2.g = g_out;
       G2.s8lc = c->s8lc;
-      HIPCHK(c, launch_backward<T>(G2, s, nullptr, c->fuse, fuse_tail, tail_done));
+      HIPCHK(c, launch_backward<T>(G2, s, nullptr, c->fuse, fuse_tail, tail_done, next));
     }
   }
   return BA_OK;
@@ -433,9 +434,12 @@ bool update_by_max(const ba_ctx* c, const GroupHost& gh) {
 // this iteration's first forward launch (by the max from nmax_in block maxima when
 // nmax_in > 0); leave_pending: this iteration's update is left to the next
 // iteration's first forward launch, and *nmax_out > 0 when that one shifts by the max.
+// first8_done: the previous iteration's D launch made this iteration's update and
+// first eight forward positions; next: this iteration's D launch makes the next one's
+// (then no record, reduction or update launch follows here).
 template <typename T>
 int iterate_group(ba_ctx* c, const GroupHost& gh, const Group<T>& G0, bool fused_in, int nmax_in,
-                  bool leave_pending, int* nmax_out) {
+                  bool leave_pending, int* nmax_out, bool first8_done = false, const FusedNext* next = nullptr) {
   Group<T> G = G0;
   G.eta = c->eta;
   G.dsum = c->eta == 1.0 ? 1 : 0;  // the D array carries log p + D to the update
@@ -450,8 +454,12 @@ int iterate_group(ba_ctx* c, const GroupHost& gh, const Group<T>& G0, bool fused
   const int check_tol = c->prec == BA_PREC_FP64 ? 1 : 0;
   const FusedUpdate fu{floor, check_tol, nmax_in};
   int nblk = 0;  // block records written by the fused D launch, if any
-  int rc = sweeps<T>(c, gh, G, 0, G.g, 1, &nblk, fused_in ? &fu : nullptr);
+  int rc = sweeps<T>(c, gh, G, 0, G.g, 1, &nblk, fused_in ? &fu : nullptr, first8_done, next);
   if (rc) return rc;
+  if (next) {
+    if (nmax_out) *nmax_out = 0;
+    return BA_OK;
+  }
   const bool by_max = leave_pending && nblk > 0 && update_by_max(c, gh);
   if (nmax_out) *nmax_out = by_max ? nblk : 0;
   if (!by_max) {
@@ -645,7 +653,7 @@ int ba_set_tuning(ba_ctx* c, int key, int value) {
     return BA_OK;
   }
   if (key == BA_TUNE_FACTORED_FUSE) {
-    if (value < 0 || value > 7) return fail(c, BA_EINVAL, "fuse must be 0 .. 7");
+    if (value < 0 || value > 8) return fail(c, BA_EINVAL, "fuse must be 0 .. 8");
     c->fuse = value;
     drop_graph(c);
     return BA_OK;
@@ -805,13 +813,22 @@ int step_group(ba_ctx* c, GroupHost& gh, int iters) {
     return BA_OK;
   }
   const bool fu = update_fusable(c, gh);
+  // launch plan level 8: from the second iteration of the call on (the iterate then
+  // carries a max shift), every D launch but the last also makes the next iteration's
+  // update and first eight forward positions
+  const bool fnext = fu && update_by_max(c, gh) && backward_fuses_next(gh.n, c->fuse, 4);
   int nmax = 0;
+  bool done8 = false;
   for (int it = 0; it < iters; ++it) {
-    const bool in = fu && it > 0, out = fu && it + 1 < iters;
+    const bool in = fu && it > 0 && !done8, out = fu && it + 1 < iters;
     const int nin = in ? nmax : 0;
-    const int rc = (c->prec == BA_PREC_FP32_LOG) ? iterate_group<float>(c, gh, gh.gf, in, nin, out, &nmax)
-                                                 : iterate_group<double>(c, gh, gh.gd, in, nin, out, &nmax);
+    const bool nx = fnext && it >= 1 && it + 1 < iters;
+    const FusedNext fn{iterate_floor(c), it & 1};
+    const int rc = (c->prec == BA_PREC_FP32_LOG)
+                       ? iterate_group<float>(c, gh, gh.gf, in, nin, out, &nmax, done8, nx ? &fn : nullptr)
+                       : iterate_group<double>(c, gh, gh.gd, in, nin, out, &nmax);
     if (rc) return rc;
+    done8 = nx;
   }
   return BA_OK;
 }

@@ -224,6 +224,93 @@ constexpr int kFirst8MinN = 12;
 constexpr uint32_t kFirst8Threads = 512;
 constexpr uint32_t kF4Pitch = 16u * 16u + 16u;  // F_4 row in LDS: 16 u2 x 16 columns, padded
 
+// Positions 0-7 of the forward sweep for the columns s0 .. s0+15 of F_8, from the
+// inputs held in R by threads t < 256 (R[u1] = p(x) for x = u1 2^(n-4) + u2 2^(n-8) +
+// s0 + c1, pair t = u2 16 + c1, u1 < 16; the block synchronised after R was formed,
+// buf free): the four-position step of the one row of F_0 for each pair leaves F_4
+// (31 rows x 16 u2 x 16 columns) in buf, then thread (z, c), z < 31, runs the
+// four-position step of row z of F_4 on the LDS rows of its path and writes F_8 of
+// row z and, for a leaf, of the 30 rows below it.
+template <typename T>
+__device__ __forceinline__ void first8_steps(T* buf, const T (&R)[16], uint32_t t, T* __restrict__ dst, int n,
+                                             uint32_t s0) {
+  const int sh8 = n - 8;
+  // step 1b: the four-position step of the one row of F_0 for pair pr
+  if (t < 256u) {
+    const uint32_t u2 = t >> 4, c1 = t & 15u;
+    // the first stage of fwd4_thread for the row without ancestors
+    uint32_t P[5], lastb[4];
+    fwd4_path(0u, P, lastb);
+    T F1p[4][8], F1s[2][8];
+#pragma unroll
+    for (int j = 1; j < 4; ++j)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) F1p[j][q] = (T(0) + T(0)) + T(0);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) F1p[0][q] = (R[q] + R[8 + q]) + T(0);
+#pragma unroll
+    for (int cc = 0; cc < 2; ++cc)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) F1s[cc][q] = R[cc * 8 + q];
+    T F4[30];
+    const T v0 = fwd4_after_stage1<T>(F1p, F1s, lastb, F4);
+    T* col = buf + u2 * 16u + c1;
+    col[0] = v0;
+#pragma unroll
+    for (int z = 1; z < 31; ++z) col[uint32_t(z) * kF4Pitch] = F4[z - 1];
+  }
+  __syncthreads();
+  // step 2: thread (z, c), z < 31: fwd4_thread on the LDS rows of z's path
+  const uint32_t z = t >> 4, c = t & 15u;
+  const int lz = length_of_rank(z);
+  if (z < 31u) {
+    T F4[30];
+    uint32_t P[5], lastb[4];
+    fwd4_path(z, P, lastb);
+    T F1p[4][8], F1s[2][8], Hc[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) Hc[u] = T(0);
+    if (4 <= lz) {
+      const T* row = buf + P[4] * kF4Pitch + (lastb[3] << 7) + c;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) Hc[u] = row[uint32_t(u) << 4];
+    }
+#pragma unroll
+    for (int j = 3; j >= 0; --j) {
+      T R[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) R[u] = T(0);
+      if (j <= lz) {
+        const T* row = buf + P[j] * kF4Pitch + c;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) R[u] = row[uint32_t(u) << 4];
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) F1p[j][q] = (R[q] + R[8 + q]) + Hc[q];
+      if (j > 0) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) Hc[q] = lastb[j - 1] ? R[8 + q] : R[q];
+      } else {
+#pragma unroll
+        for (int cc = 0; cc < 2; ++cc)
+#pragma unroll
+          for (int q = 0; q < 8; ++q) F1s[cc][q] = R[cc * 8 + q];
+      }
+    }
+    const T vz = fwd4_after_stage1<T>(F1p, F1s, lastb, F4);
+    // F_8 of row z and, for a leaf, of the 30 rows below it: 16 consecutive columns of
+    // each row per 16 lanes
+    at(dst, (z << sh8) + s0 + c) = vz;
+    if (lz == 4) {
+#pragma unroll
+      for (int d = 1; d <= 4; ++d)
+#pragma unroll
+        for (int m = 0; m < (1 << d); ++m)
+          at(dst, ((((z + 1u) << d) - 1u + uint32_t(m)) << sh8) + s0 + c) = F4[(1 << d) - 2 + m];
+    }
+  }
+}
+
 template <typename T, bool UPD>
 __global__ __launch_bounds__(kFirst8Threads) void k_fwd_first8(int n, const T* __restrict__ src, size_t sstride,
                                                                T* __restrict__ dst, size_t dstride, Group<T> g,
@@ -306,79 +393,7 @@ __global__ __launch_bounds__(kFirst8Threads) void k_fwd_first8(int n, const T* _
     for (int k = 0; k < 8; ++k) R[8 + k] = buf[uint32_t(k) * 256u + pr];
   }
   __syncthreads();
-  // step 1b: the four-position step of the one row of F_0 for pair pr
-  if (!h) {
-    // the first stage of fwd4_thread for the row without ancestors
-    uint32_t P[5], lastb[4];
-    fwd4_path(0u, P, lastb);
-    T F1p[4][8], F1s[2][8];
-#pragma unroll
-    for (int j = 1; j < 4; ++j)
-#pragma unroll
-      for (int q = 0; q < 8; ++q) F1p[j][q] = (T(0) + T(0)) + T(0);
-#pragma unroll
-    for (int q = 0; q < 8; ++q) F1p[0][q] = (R[q] + R[8 + q]) + T(0);
-#pragma unroll
-    for (int cc = 0; cc < 2; ++cc)
-#pragma unroll
-      for (int q = 0; q < 8; ++q) F1s[cc][q] = R[cc * 8 + q];
-    T F4[30];
-    const T v0 = fwd4_after_stage1<T>(F1p, F1s, lastb, F4);
-    T* col = buf + u2 * 16u + c1;
-    col[0] = v0;
-#pragma unroll
-    for (int z = 1; z < 31; ++z) col[uint32_t(z) * kF4Pitch] = F4[z - 1];
-  }
-  __syncthreads();
-  // step 2: thread (z, c), z < 31: fwd4_thread on the LDS rows of z's path
-  const uint32_t z = t >> 4, c = t & 15u;
-  const int lz = length_of_rank(z);
-  if (z < 31u) {
-    T F4[30];
-    uint32_t P[5], lastb[4];
-    fwd4_path(z, P, lastb);
-    T F1p[4][8], F1s[2][8], Hc[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) Hc[u] = T(0);
-    if (4 <= lz) {
-      const T* row = buf + P[4] * kF4Pitch + (lastb[3] << 7) + c;
-#pragma unroll
-      for (int u = 0; u < 8; ++u) Hc[u] = row[uint32_t(u) << 4];
-    }
-#pragma unroll
-    for (int j = 3; j >= 0; --j) {
-      T R[16];
-#pragma unroll
-      for (int u = 0; u < 16; ++u) R[u] = T(0);
-      if (j <= lz) {
-        const T* row = buf + P[j] * kF4Pitch + c;
-#pragma unroll
-        for (int u = 0; u < 16; ++u) R[u] = row[uint32_t(u) << 4];
-      }
-#pragma unroll
-      for (int q = 0; q < 8; ++q) F1p[j][q] = (R[q] + R[8 + q]) + Hc[q];
-      if (j > 0) {
-#pragma unroll
-        for (int q = 0; q < 8; ++q) Hc[q] = lastb[j - 1] ? R[8 + q] : R[q];
-      } else {
-#pragma unroll
-        for (int cc = 0; cc < 2; ++cc)
-#pragma unroll
-          for (int q = 0; q < 8; ++q) F1s[cc][q] = R[cc * 8 + q];
-      }
-    }
-    const T vz = fwd4_after_stage1<T>(F1p, F1s, lastb, F4);
-    // F_8 of row z and, for a leaf, of the 30 rows below it: 16 consecutive columns of
-    // each row per 16 lanes
-    at(dst, (z << sh8) + s0 + c) = vz;
-    if (lz == 4) {
-#pragma unroll
-      for (int d = 1; d <= 4; ++d)
-#pragma unroll
-        for (int m = 0; m < (1 << d); ++m)
-          at(dst, ((((z + 1u) << d) - 1u + uint32_t(m)) << sh8) + s0 + c) = F4[(1 << d) - 2 + m];
-    }
-  }
+  first8_steps<T>(buf, R, t, dst, n, s0);
 }
 
 // One backward stage; each thread produces V consecutive columns of one row
@@ -1139,7 +1154,25 @@ __global__ __launch_bounds__(32 * stage8_tile<T>()) void k_bwd_stage8(int n, int
 // kS8ColumnsD: kS8Columns at i = 0 (the one root is the empty row, B_0 = G) with
 // D(x) = H(x) - G(x) - M and the block's record formed instead of writing G; the
 // record index is the block's column block.
-enum Stage8Mode { kS8Columns = 0, kS8Roots = 1, kS8SymRoots = 2, kS8ColumnsD = 3 };
+// kS8ColumnsDU (FP32, eta = 1): kS8ColumnsD without the record, the D launch of an
+// iteration fused with the next iteration's update and first eight forward positions
+// on the same inputs: a = log p + D, the new iterate log p <- max(a - m', -floor),
+// p = e^{log p} into LDS at G's slots, the block's max of a (for the next such launch),
+// then first8_steps from p to F_8 (dst).  m' is the max of a of the iteration before
+// (the block maxima that launch left, each wave taking their max itself), or 0: a is
+// the same for any scale of p (D falls by what log p gains), and for the law it
+// represents a <= 0 (D(x) <= -log p(x)) with max a >= -n ln 2, so either shift leaves
+// the new log p at most n ln 2 above 0.  The shift only moves the floor, by m' - max
+// a, which vanishes as the iteration converges.
+enum Stage8Mode { kS8Columns = 0, kS8Roots = 1, kS8SymRoots = 2, kS8ColumnsD = 3, kS8ColumnsDU = 4 };
+
+// The fused update of kS8ColumnsDU: the maxima it reads (nullptr: shift 0) and writes,
+// and the floor.
+struct S8Update {
+  const float* mprev;  // per instance, at stride ps doubles
+  float* mout;
+  float floor;
+};
 
 __host__ __device__ constexpr uint32_t stage8_sigma_bits(uint32_t q) {
   return ((uint32_t(__builtin_popcount(q & 0xAAAAAAAAu)) & 1u) << 1) | (uint32_t(__builtin_popcount(q)) & 1u);
@@ -1149,16 +1182,18 @@ template <typename T, int MODE>
 __global__ __launch_bounds__(32 * stage8_tile<T>()) void k_bwd_stage8_p(int n, int i, const T* __restrict__ src,
                                                                       size_t sstride, T* __restrict__ dst,
                                                                       size_t dstride, const State* st, int frz,
-                                                                      Group<T> g) {
+                                                                      Group<T> g, S8Update fu) {
   constexpr bool ROOTS = MODE == kS8Roots || MODE == kS8SymRoots, SYM = MODE == kS8SymRoots;
-  constexpr bool DP = MODE == kS8ColumnsD;
+  constexpr bool DU = MODE == kS8ColumnsDU;
+  constexpr bool DP = MODE == kS8ColumnsD || DU;
+  static_assert(!DU || sizeof(T) == 4, "the fused update is for FP32 iterates");
   constexpr uint32_t P = uint32_t(stage8_tile<T>());  // value lanes per node
   constexpr int LP = P == 16 ? 4 : 3;
   constexpr uint32_t NT = 32u * P;                     // threads
   constexpr int VW = 16 / int(sizeof(T));              // P / VW = 4 vectors per node row
   constexpr uint32_t kOutPitch = 260u;                 // ROOTS: output row pitch
   const int b = blockIdx.z;
-  if (frz && st[b].converged) return;
+  if ((DU || frz) && st[b].converged) return;  // DU writes log p: frozen instances always stay
   src += (size_t)b * sstride;
   dst += (size_t)b * dstride;
   const int sh = n - i - 8;                  // log2 of S8 (0 for ROOTS)
@@ -1197,7 +1232,8 @@ __global__ __launch_bounds__(32 * stage8_tile<T>()) void k_bwd_stage8_p(int n, i
   const uint32_t r0 = (1u << lev) - 1u + g0;  // rank of the first root
   const uint32_t s0 = (lin & ((1u << lcb) - 1u)) * P;
   const uint32_t t = threadIdx.x;
-  __shared__ __attribute__((aligned(16))) T buf[512u * P];
+  // DU: the buffer also holds first8_steps' F_4
+  __shared__ __attribute__((aligned(16))) T buf[DU ? 31u * kF4Pitch : 512u * P];
   if constexpr (ROOTS) {
     // copy-in: depth k of the roots' subtrees is one run of nr 2^k consecutive ranks;
     // value m of the run is root m >> k, node 2^k + (m mod 2^k).  Full groups: the
@@ -1277,6 +1313,24 @@ __global__ __launch_bounds__(32 * stage8_tile<T>()) void k_bwd_stage8_p(int n, i
       xs[k] = ((f >> 2) << sh) + s0 + (f & 3u) * uint32_t(VW);
     }
     d_loads<T, VW, KD>(g, b, xs, hd, lq);
+  }
+  // DU: the shift m' from the previous launch's block maxima (every wave reduces them)
+  float mprev = 0.0f;
+  if constexpr (DU) {
+    if (fu.mprev) {
+      const float* bm = fu.mprev + (size_t)b * g.ps * 2u;
+      mprev = -INFINITY;
+      for (uint32_t j = t & (kWave - 1u); j < (1u << (n - 8 - LP)); j += kWave) mprev = fmaxf(mprev, bm[j]);
+#pragma unroll
+      for (int off = kWave / 2; off > 0; off >>= 1) mprev = fmaxf(mprev, __shfl_xor(mprev, off));
+      if (!isfinite(mprev)) {
+        if (lin == 0u && t == 0u) {
+          g.st[b].bad = 1;
+          g.st[b].converged = 1;
+        }
+        return;  // the whole block (mprev is the same in every wave)
+      }
+    }
   }
   __syncthreads();
   // step 1: thread (z = 1-based node a of the depth-4 subtree, lane c1); a = 0 idles
@@ -1360,6 +1414,53 @@ __global__ __launch_bounds__(32 * stage8_tile<T>()) void k_bwd_stage8_p(int n, i
       const uint32_t rho = f >> 6, j = f & 63u;
       if (rho < nr) stv<T, 4>(o + (rho << 8) + 4u * j, ld<T, 4>(buf + rho * kOutPitch + 4u * j));
     }
+  } else if constexpr (DU) {
+    // a = log p + D at the inputs xs (G of column group w, vector j), the new log p and
+    // p = e^{log p}, which replaces G at the same slots (each thread reads and writes
+    // only its own); with w = u1 16 + u2 and the block's 16 columns, p(x) of input
+    // u1 2^(n-4) + u2 2^(n-8) + s0 + c1 sits at u1 256 + u2 16 + c1 as first8_steps wants
+    const double M = g.st[b].M;
+    float* lp = g.lp + (size_t)b * g.xs;
+    const float lo = -fu.floor;
+    float am = -INFINITY;
+#pragma unroll
+    for (int k = 0; k < KD; ++k) {
+      const uint32_t f = t + uint32_t(k) * NT;
+      float* slot = buf + ((f >> 2) << LP) + (f & 3u) * uint32_t(VW);
+      const Vec<float, VW> gv = ld<float, VW>(slot);
+      Vec<float, VW> nl, pv;
+#pragma unroll
+      for (int e = 0; e < VW; ++e) {
+        const float d = hd[k].v[e] - gv.v[e] - float(M);
+        const float a = lq[k].v[e] + d;
+        am = fmaxf(am, a);
+        const float x = a - mprev;
+        nl.v[e] = x > lo ? x : lo;
+        pv.v[e] = exp_t<float>(nl.v[e]);
+      }
+      stv<float, VW>(lp + xs[k], nl);
+      stv<float, VW>(slot, pv);
+    }
+    // the block's max of a: waves, then the first wave over their maxima
+    __shared__ float wmax[NT / kWave];
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) am = fmaxf(am, __shfl_xor(am, off));
+    if ((t & (kWave - 1u)) == 0u) wmax[t / kWave] = am;
+    __syncthreads();
+    if (t == 0u) {
+      float m = wmax[0];
+#pragma unroll
+      for (uint32_t w = 1; w < NT / kWave; ++w) m = fmaxf(m, wmax[w]);
+      fu.mout[(size_t)b * g.ps * 2u + (lin & ((1u << lcb) - 1u))] = m;
+      if (lin == 0u) g.st[b].iters += 1;
+    }
+    float R[16];
+    if (t < 256u) {
+#pragma unroll
+      for (int u1 = 0; u1 < 16; ++u1) R[u1] = buf[uint32_t(u1) * 256u + t];
+    }
+    __syncthreads();
+    first8_steps<float>(buf, R, t, dst, n, s0);
   } else if constexpr (DP) {
     // D at the inputs xs from G of column group w, vector j, and the block's record
     const double M = g.st[b].M;
@@ -1858,18 +1959,28 @@ using namespace fac;
 
 template <typename T>
 hipError_t launch_forward(const Group<T>& g, hipStream_t s, int* launches, int fuse, int logv,
-                          const FusedUpdate* upd) {
+                          const FusedUpdate* upd, int first8_done) {
   const int n = g.n;
   constexpr int V = 16 / sizeof(T);
   const T* src = g.p;
   size_t ss = g.xs;
   int k = 0;
   if (upd && !forward_update_fusable(n, fuse)) return hipErrorInvalidValue;
+  int i = 0;
+  if (first8_done) {
+    // F_8 was formed by the previous iteration's fused D launch (into f1); only the
+    // one launch of positions 8 .. n-1 follows
+    if (upd || !backward_fuses_next(n, fuse, int(sizeof(T)))) return hipErrorInvalidValue;
+    src = g.f1;
+    ss = g.fs;
+    i = 8;
+    k = 1;
+  }
   // fuse >= 4: the last four positions in one launch with LDS-staged outputs;
   // fuse >= 5: the first eight positions in one launch
   const bool last4 = fuse >= 4 && n >= kLast4MinN;
   const bool first8 = fuse >= 5 && n >= kFirst8MinN;
-  for (int i = 0; i < n; k++) {
+  for (; i < n; k++) {
     if (first8 && i == 0) {
       T* dst = (k & 1) ? g.f1 : g.f0;
       const dim3 grid(1u << (n - 12), g.nb);  // 16 columns of F_8 per block
@@ -1998,7 +2109,8 @@ hipError_t launch_forward(const Group<T>& g, hipStream_t s, int* launches, int f
 
 template <typename T>
 hipError_t launch_backward(const Group<T>& g, hipStream_t s, int* launches, int fuse, int dpart,
-                           int* dpart_blocks) {
+                           int* dpart_blocks, const FusedNext* next) {
+  if (next && !backward_fuses_next(g.n, fuse, int(sizeof(T)))) return hipErrorInvalidValue;
   const int n = g.n;
   constexpr int V = 16 / sizeof(T);
   const T* src = g.v;
@@ -2028,13 +2140,22 @@ hipError_t launch_backward(const Group<T>& g, hipStream_t s, int* launches, int 
       constexpr int LP = stage8_tile<T>() == 16 ? 4 : 3;
       const dim3 grid(1u << (n - 8 - LP), 1, g.nb);  // column blocks of P columns
       const dim3 block(32 * stage8_tile<T>());
-      if (dpart) {
+      if (next) {
+        // D with the next iteration's update and first eight forward positions: F_8 to f1
+        if constexpr (sizeof(T) == 4) {
+          float* m0 = reinterpret_cast<float*>(g.part + kBlockMaxima);  // maxima set 0 of instance 0
+          const uint32_t nset = grid.x;
+          const S8Update u{m0 + (next->par ? 0u : nset), m0 + (next->par ? nset : 0u), float(next->floor)};
+          hipLaunchKernelGGL((k_bwd_stage8_p<T, kS8ColumnsDU>), grid, block, 0, s, n, 0, src, ss, g.f1, g.fs,
+                             g.st, g.frz, g, u);
+        }
+      } else if (dpart) {
         hipLaunchKernelGGL((k_bwd_stage8_p<T, kS8ColumnsD>), grid, block, 0, s, n, 0, src, ss, g.g, g.xs, g.st,
-                           g.frz, g);
+                           g.frz, g, S8Update{});
         if (dpart_blocks) *dpart_blocks = int(grid.x);
       } else {
         hipLaunchKernelGGL((k_bwd_stage8_p<T, kS8Columns>), grid, block, 0, s, n, 0, src, ss, g.g, g.xs, g.st,
-                           g.frz, g);
+                           g.frz, g, S8Update{});
       }
       if (launches) ++*launches;
       top = 0;
@@ -2051,10 +2172,10 @@ hipError_t launch_backward(const Group<T>& g, hipStream_t s, int* launches, int 
       const dim3 block(32 * stage8_tile<T>());
       if (lc == LP) {
         hipLaunchKernelGGL((k_bwd_stage8_p<T, kS8Columns>), grid, block, 0, s, n, i, src, ss, dst, g.fs, g.st,
-                           g.frz, g);
+                           g.frz, g, S8Update{});
       } else if (lc == 0) {
         hipLaunchKernelGGL((k_bwd_stage8_p<T, kS8Roots>), grid, block, 0, s, n, i, src, ss, dst, g.fs, g.st,
-                           g.frz, g);
+                           g.frz, g, S8Update{});
       } else switch (lc) {
         case 1: hipLaunchKernelGGL((k_bwd_stage8<T, 1>), grid, block, 0, s, n, i, src, ss, dst, g.fs, g.st); break;
         case 2: hipLaunchKernelGGL((k_bwd_stage8<T, 2>), grid, block, 0, s, n, i, src, ss, dst, g.fs, g.st); break;
@@ -2168,7 +2289,7 @@ hipError_t launch_backward8_sym_v(const Group<T>& g, hipStream_t s, T* dst) {
   const uint32_t slots = stage8_slots(i - 1, LP) + 1u;  // + the empty row
   const dim3 grid((slots + 7u) & ~7u, 1, g.nb);
   hipLaunchKernelGGL((k_bwd_stage8_p<T, kS8SymRoots>), grid, dim3(32 * stage8_tile<T>()), 0, s, n, i, g.v, g.ys,
-                     dst, g.fs, g.st, g.frz, g);
+                     dst, g.fs, g.st, g.frz, g, S8Update{});
   return hipGetLastError();
 }
 template hipError_t launch_backward8_sym_v<float>(const Group<float>&, hipStream_t, float*);
@@ -2201,11 +2322,15 @@ int forward_launches(int n, int fuse, int esz) {
 bool forward_update_fusable(int n, int fuse) { return fuse >= 2 && n > 4; }
 bool forward_first8(int n, int fuse) { return fuse >= 5 && n >= kFirst8MinN; }
 bool backward_writes_maxima(int n, int fuse, int esz) { return fuse >= 6 && n == kStage12N && esz == 4; }
+bool backward_fuses_next(int n, int fuse, int esz) { return fuse >= 8 && n == kStage12N && esz == 4; }
 
-template hipError_t launch_forward<float>(const Group<float>&, hipStream_t, int*, int, int, const FusedUpdate*);
+template hipError_t launch_forward<float>(const Group<float>&, hipStream_t, int*, int, int, const FusedUpdate*,
+                                          int);
 template hipError_t launch_forward<double>(const Group<double>&, hipStream_t, int*, int, int,
-                                           const FusedUpdate*);
-template hipError_t launch_backward<float>(const Group<float>&, hipStream_t, int*, int, int, int*);
-template hipError_t launch_backward<double>(const Group<double>&, hipStream_t, int*, int, int, int*);
+                                           const FusedUpdate*, int);
+template hipError_t launch_backward<float>(const Group<float>&, hipStream_t, int*, int, int, int*,
+                                           const FusedNext*);
+template hipError_t launch_backward<double>(const Group<double>&, hipStream_t, int*, int, int, int*,
+                                            const FusedNext*);
 
 }  // namespace ba

@@ -235,7 +235,9 @@ hipError_t launch_pull(const Group<T>& g, T* partial, hipStream_t s);
 // first eight forward positions in one launch (k_fwd_first8); fuse = 6: as 5 with
 // the backward sweep at n = 20 (FP32) in two launches (k_bwd_stage12, then
 // k_bwd_stage8_p with D); fuse = 7: as 6 with the forward positions 8 .. 19 at
-// n = 20 (FP32) in one launch (k_fwd_stage12).
+// n = 20 (FP32) in one launch (k_fwd_stage12); fuse = 8: as 7 with the D launch of
+// an iteration inside a ba_step call fused with the next iteration's update and first
+// eight forward positions (FusedNext).
 // logv = 1: the last forward launch writes v = w_k log r instead of r.
 // dpart = 1: the last backward launch also forms D = H - G - M and the block
 // records of k_dpart, writing D instead of G; *dpart_blocks returns the number of
@@ -259,12 +261,24 @@ bool forward_update_fusable(int n, int fuse);
 bool forward_first8(int n, int fuse);
 // True when launch_backward's D launch (FP32) also writes the block maxima of log p + D.
 bool backward_writes_maxima(int n, int fuse, int esz);
+// The D launch of an iteration fused with the next iteration's update and first eight
+// forward positions (fuse = 8: FP32 iterates, eta = 1, n = 20, the iterate scaled by a
+// max shift, i.e. not the first iteration of a ba_step call): it writes its block
+// maxima of log p + D to set par of two sets in the record buffer's second set and
+// shifts by the max of set 1 - par (the D launch before it); the next forward sweep
+// then starts from its F_8 (launch_forward with first8_done).
+struct FusedNext {
+  double floor;
+  int par;
+};
+// True when launch_backward can take a FusedNext (element bytes esz).
+bool backward_fuses_next(int n, int fuse, int esz);
 template <typename T>
 hipError_t launch_forward(const Group<T>& g, hipStream_t s, int* launches, int fuse, int logv,
-                          const FusedUpdate* upd = nullptr);  // p -> r
+                          const FusedUpdate* upd = nullptr, int first8_done = 0);  // p -> r
 template <typename T>
 hipError_t launch_backward(const Group<T>& g, hipStream_t s, int* launches, int fuse, int dpart,
-                           int* dpart_blocks);                                                   // v -> G
+                           int* dpart_blocks, const FusedNext* next = nullptr);  // v -> G
 int factored_launches(int n, int fuse);   // forward launches (two positions each when fuse != 0)
 int backward_launches(int n, int fuse, int esz = 4);  // launches of launch_backward (esz: element bytes)
 int forward_launches(int n, int fuse, int esz = 4);  // launches of launch_forward

@@ -629,6 +629,42 @@ def test_fp32_update_by_max_matches_normalised(ba, d):
     assert abs(out[0][1][0][0] - out[1][1][0][0]) < 1e-6 and abs(out[0][1][1][0] - out[1][1][1][0]) < 1e-6
 
 
+@pytest.mark.parametrize("per_call", [1, 2, 3, 7])
+def test_fused_next_iteration_matches_plan7(ba, per_call):
+    """Launch plan level 8 (n = 20, FP32): inside a step call, from the second
+    iteration on, each D launch but the last also makes the next iteration's update
+    (a shift by the previous iteration's max of log p + D) and first eight forward
+    positions.  The iterates equal those of level 7 (shift by the current max) to FP32
+    rounding: log p within 4e-5 and the FP64-certified bounds within 1e-6 bits after 7
+    iterations in calls of 1, 2, 3 or 7; with 7 per call, 9 forward launches (first8 and
+    k_fwd_stage12 in iterations 0 and 1, then k_fwd_stage12 alone) and one record
+    reduction ran."""
+    n = 20
+    ns, ds = [n] * 3, [0.64, 0.8, 0.95]
+    say("fused next iteration per_call=%d" % per_call)
+    c = chain(ba.Context(ns, ds, prec=ba.PREC_FP32_LOG))
+    start = torch.tensor(np.concatenate([inp.random_logp(n, seed=90 + k, spread=3.0) for k in range(3)]))
+    out = []
+    for fuse in (7, 8):
+        c.set_logp(start)
+        c.set_tuning(ba.TUNE_FACTORED_FUSE, fuse)
+        done = 0
+        while done < 7:
+            k = min(per_call, 7 - done)
+            c.step(k)
+            done += k
+        out.append((c.get_logp().cpu().numpy(), c.bounds()))
+    if per_call == 7:
+        c.set_logp(start)
+        t = c.time_kernels(7)
+        assert t["sweep1"][1] == 9 and t["sweep2"][1] == 14 and t["reduce"][1] == 1
+    c.close()
+    assert np.all(np.isfinite(out[1][0]))
+    assert np.max(np.abs(out[0][0] - out[1][0])) < 4e-5
+    for k in range(3):
+        assert abs(out[0][1][0][k] - out[1][1][0][k]) < 1e-6 and abs(out[0][1][1][k] - out[1][1][1][k]) < 1e-6
+
+
 @pytest.mark.parametrize("path", ["chain", "persistent"])
 def test_fused_update_stops_at_tolerance(ba, path):
     """FP64 iterates stop at the first iterate whose gap is below the tolerance,
