@@ -41,19 +41,18 @@ UNIT_EQUIV = "W-nonzero-equivalent terms/s (factored engine: nonzeros accounted,
 FUSE = 8  # the library default (positions per launch of the factored engine)
 
 
-# HBM bytes per launch of this workload's sweeps, from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE (scaled by a device copy's reading of the same counters: x2.0 and x1.0),
-# averaged over the launches of one sweep of a fused iteration (the first forward
-# launch also making the previous iteration's update); valid only for the kernel
-# sources they were measured on (summary: profiles/factored_sweeps_n20_fp32_x3.md).
+# HBM bytes per launch of each kernel of this workload's default plan (3 instances),
+# from rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by a device copy's reading of the
+# same counters (x2.0 and x1.0); a sweep's figure is their average over the launches
+# of one ba_step call, weighted as the algorithmic bytes are.  Valid only for the
+# kernel sources they were measured on (summary: profiles/factored_sweeps_n20_fp32_x3.md).
 MEASURED_TRAFFIC = {
-    "sources": ["paper_2604_05867_amd/csrc/ba_factored.hip", "paper_2604_05867_amd/csrc/ba_factored_common.h"],
+    "sources": ["paper_2604_05867_amd/csrc/ba_factored.hip", "paper_2604_05867_amd/csrc/ba_factored_common.h",
+                "paper_2604_05867_amd/csrc/ba_part.h"],
     # of the sources concatenated
-    "sha256": "e208dda9a011f96543574e014154112afd86542d82aff697c886b770c417cdbc",
-    # forward: k_fwd_first8, k_fwd_stage12; backward: k_bwd_stage12,
-    # k_bwd_stage8_p with D fused
-    "sweep1": 50543000,
-    "sweep2": 57012000,
+    "sha256": "5c527c30e840004aa5bb2fbc2480fc545860d1a42864cf5b6b8d2be211554cf1",
+    "bytes": {"first8": 37790000, "first8_upd": 50450000, "fwd12": 51450000,
+              "bwd12": 50960000, "d8": 63070000, "dfused": 88170000},
 }
 
 
@@ -66,12 +65,15 @@ def kernel_source_sha():
     return h.hexdigest()
 
 
-def measured_traffic(sweep):
-    """The PMC traffic figure of a sweep if the kernel sources are unchanged since it
-    was taken, else None."""
+def measured_traffic(fuse, iters, backward):
+    """The PMC traffic per launch of a sweep over a ba_step call of `iters` iterations
+    if the kernel sources are unchanged since it was taken, else None."""
     if MEASURED_TRAFFIC["sha256"] is None or kernel_source_sha() != MEASURED_TRAFFIC["sha256"]:
         return None
-    return MEASURED_TRAFFIC[sweep]
+    kinds = call_launch_kinds(N, fuse, iters, backward)
+    if kinds is None:
+        return None
+    return int(sum(MEASURED_TRAFFIC["bytes"][k] for k in kinds) / len(kinds))
 
 
 def stage_sizes(n):
@@ -132,31 +134,42 @@ def sweep_launch_bytes(n, esz, nb, fuse, backward, fused_update=0.0):
     return out
 
 
-def call_launch_bytes(n, esz, nb, fuse, iters, backward):
-    """Algorithmic HBM bytes of every launch of one sweep over a ba_step call of
-    `iters` iterations, in launch order: sweep_launch_bytes per iteration (the first
-    iteration without the fused update), and at fuse 8 (n = 20) the D launch of
-    iterations 1 .. iters-2 fused with the next iteration's update and first eight
-    forward positions: it reads B_8, H and log p and writes log p and F_8 (no D), and
-    the next forward sweep is the one launch of positions 8-19."""
-    s = stage_sizes(n)
-    x = (1 << n) * esz * nb
+def call_launch_kinds(n, fuse, iters, backward):
+    """Kinds of the launches of one sweep over a ba_step call of `iters` iterations at
+    launch plan level 8, n = 20 (FP32), in order, else None: forward first8 (iteration
+    0), first8_upd (iteration 1: the update by the max shift), then fwd12 (positions
+    8-19) alone, its first eight positions made by the fused D launch before it;
+    backward bwd12, then d8 (D with its record) in the first and last iterations and
+    dfused (D, the next iteration's update and first eight forward positions) between."""
+    if not (fuse >= 8 and n == 20):
+        return None
     out = []
     for it in range(iters):
-        if fuse >= 8 and n == 20:
-            fused_prev = 2 <= it
-            fused_here = 1 <= it < iters - 1
-            if not backward:
-                out += [(s[8] + s[20]) * esz * nb] if fused_prev else \
-                    sweep_launch_bytes(n, esz, nb, 7, False, fused_update=1.0 if it else 0.0)
-            else:
-                b = sweep_launch_bytes(n, esz, nb, 7, True)
-                if fused_here:
-                    b[-1] = 2 * s[8] * esz * nb + 3 * x
-                out += b
+        if not backward:
+            out += (["first8_upd" if it == 1 else "first8"] if it < 2 else []) + ["fwd12"]
         else:
-            out += sweep_launch_bytes(n, esz, nb, fuse, backward, fused_update=1.0 if it else 0.0)
+            out += ["bwd12", "dfused" if 1 <= it < iters - 1 else "d8"]
     return out
+
+
+def call_launch_bytes(n, esz, nb, fuse, iters, backward):
+    """Algorithmic HBM bytes of every launch of one sweep over a ba_step call of
+    `iters` iterations, in launch order: every launch reads its source stage once and
+    writes its destination stage once; first8_upd reads log p + D instead of p and
+    writes log p; a D launch (d8) reads B_8, H and log p and writes log p + D; the
+    fused D launch (dfused) reads B_8, H and log p and writes log p and F_8.  Below
+    level 8, sweep_launch_bytes per iteration (the first one without the update)."""
+    s = stage_sizes(n)
+    x = 1 << n
+    kinds = call_launch_kinds(n, fuse, iters, backward)
+    if kinds is None:
+        out = []
+        for it in range(iters):
+            out += sweep_launch_bytes(n, esz, nb, fuse, backward, fused_update=1.0 if it else 0.0)
+        return out
+    size = {"first8": s[0] + s[8], "first8_upd": s[0] + s[8] + x, "fwd12": s[8] + s[20],
+            "bwd12": s[20] + s[8], "d8": s[8] + s[0] + 2 * x, "dfused": 2 * s[8] + 3 * x}
+    return [size[k] * esz * nb for k in kinds]
 
 
 def cpu_baseline(logps, gpu_bounds):
@@ -490,7 +503,7 @@ def main():
     achieved = bytes_launch / (per_launch_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
                 "frac": round(achieved / 8000.0, 4),
-                "traffic": measured_traffic(dom),
+                "traffic": measured_traffic(FUSE, args.steps, dom == "sweep2"),
                 "kernel": ("forward sweep (k_fwd_first8, k_fwd_stage12)" if dom == "sweep1"
                            else "backward sweep (k_bwd_stage12, k_bwd_stage8_p with D and the next "
                                 "iteration's update and first eight forward positions)"),

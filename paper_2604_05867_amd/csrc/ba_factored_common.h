@@ -365,7 +365,8 @@ __device__ __forceinline__ void d_records(const Group<T>& g, int b, double M, co
   d_records_pre<T, V, N>(g, b, M, x, G, d, l, p, wt);
 }
 
-// Register part of the four-position forward step for one (y, column), from the
+// Register parts of the four-position forward step for one (y, column).
+//
 // The 30 rows below a row y after four stages, from y's values at the first three
 // of them (F1z = F_{i+1}[y], 8 column groups; F2z, F3z) and F1s, the two children of
 // y at stage i+1 (the halves of F_i[y]): breadth-first, depth d index m at
