@@ -327,6 +327,13 @@ bool sym_active(const ba_ctx* c, int n) {
   return c->sym && c->engine == BA_ENGINE_FACTORED && symmetric_supported(n, c->fuse);
 }
 
+// A complement-symmetric iterate at n = 20 with FP32 iterates, eta = 1 and launch plan
+// level 8 runs the full plan's kernels on half the rows and column tiles
+// (Group::half) instead of the complement-symmetric kernels.
+bool half_plan(const ba_ctx* c, int n) {
+  return sym_active(c, n) && c->prec == BA_PREC_FP32_LOG && c->eta == 1.0 && backward_fuses_next(n, c->fuse, 4);
+}
+
 // tail = 1 (factored engine, iteration only): the last forward launch writes v
 // and the last backward launch forms D and its block records; *tail_done is the
 // number of those records, 0 if the backward part was not fused (then the caller
@@ -380,7 +387,7 @@ int sweeps(ba_ctx* c, const GroupHost& gh, const Group<T>& G, int use_sw_g, T* g
       HIPCHK(c, launch_fill_zero(g_out, size_t(G.nb) * G.xs * sizeof(T), s));
       HIPCHK(c, launch_stream<T>(kOpGather, gh.tb, G2, k0, ex, s));
     }
-  } else if (tail && !use_sw_g && sym_active(c, n)) {
+  } else if (tail && !use_sw_g && sym_active(c, n) && !G.half) {
     {
       Timer t(c, BA_K_SWEEP1, forward_launches(n, sym_fuse_fwd(c)));
       HIPCHK(c, launch_forward_sym<T>(G, s, nullptr, sym_fuse_fwd(c), upd));
@@ -417,7 +424,7 @@ int sweeps(ba_ctx* c, const GroupHost& gh, const Group<T>& G, int use_sw_g, T* g
 // kernels with four positions per launch).
 bool update_fusable(const ba_ctx* c, const GroupHost& gh) {
   if (c->engine != BA_ENGINE_FACTORED) return false;
-  if (sym_active(c, gh.n)) return forward_update_fusable(gh.n, sym_fuse_fwd(c));
+  if (sym_active(c, gh.n) && !half_plan(c, gh.n)) return forward_update_fusable(gh.n, sym_fuse_fwd(c));
   return forward_update_fusable(gh.n, c->fuse);
 }
 
@@ -426,8 +433,9 @@ bool update_fusable(const ba_ctx* c, const GroupHost& gh) {
 // normalising (k_fwd_first8), from the block maxima the D launch wrote, with no
 // final-record launch.
 bool update_by_max(const ba_ctx* c, const GroupHost& gh) {
-  return c->engine == BA_ENGINE_FACTORED && c->prec == BA_PREC_FP32_LOG && c->eta == 1.0 && !sym_active(c, gh.n) &&
-         forward_first8(gh.n, c->fuse) && backward_writes_maxima(gh.n, c->fuse, 4);
+  return c->engine == BA_ENGINE_FACTORED && c->prec == BA_PREC_FP32_LOG && c->eta == 1.0 &&
+         (!sym_active(c, gh.n) || half_plan(c, gh.n)) && forward_first8(gh.n, c->fuse) &&
+         backward_writes_maxima(gh.n, c->fuse, 4);
 }
 
 // One iteration.  fused_in: the previous iteration's update is pending and done by
@@ -443,6 +451,7 @@ int iterate_group(ba_ctx* c, const GroupHost& gh, const Group<T>& G0, bool fused
   Group<T> G = G0;
   G.eta = c->eta;
   G.dsum = c->eta == 1.0 ? 1 : 0;  // the D array carries log p + D to the update
+  G.half = half_plan(c, gh.n) ? 1 : 0;
   // The kernels that write log p, p and the state always test the frozen flag, so
   // a frozen instance's iterate and state stay untouched whether or not the sweeps
   // test it too; skipping the test there (frz = 0) only sweeps a frozen instance
@@ -472,7 +481,7 @@ int iterate_group(ba_ctx* c, const GroupHost& gh, const Group<T>& G0, bool fused
   }
   if (!leave_pending) {
     Timer t(c, BA_K_UPDATE, 1);
-    HIPCHK(c, launch_update<T>(G, reduce_blocks(gh.n), floor, check_tol, sym_active(c, gh.n) ? 1 : 0,
+    HIPCHK(c, launch_update<T>(G, reduce_blocks(gh.n), floor, check_tol, sym_active(c, gh.n) && !G.half ? 1 : 0,
                                c->stream));
   }
   return BA_OK;

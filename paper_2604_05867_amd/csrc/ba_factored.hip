@@ -231,10 +231,30 @@ constexpr uint32_t kF4Pitch = 16u * 16u + 16u;  // F_4 row in LDS: 16 u2 x 16 co
 // (31 rows x 16 u2 x 16 columns) in buf, then thread (z, c), z < 31, runs the
 // four-position step of row z of F_4 on the LDS rows of its path and writes F_8 of
 // row z and, for a leaf, of the 30 rows below it.
-template <typename T>
+// HALF (complement-symmetric iterate, the column block's first bit 0): F_8 keeps the
+// rows that start with 0 and the empty row at every column; a value of a row that
+// starts with 1 goes to its complement's row at the complementary column, one of the
+// empty row to both columns.
+template <typename T, bool HALF = false>
 __device__ __forceinline__ void first8_steps(T* buf, const T (&R)[16], uint32_t t, T* __restrict__ dst, int n,
                                              uint32_t s0) {
   const int sh8 = n - 8;
+  auto put = [&](uint32_t R, uint32_t col, T v) {
+    if constexpr (HALF) {
+      const int k = length_of_rank(R);
+      const uint32_t cc = (1u << sh8) - 1u - col;
+      if (R == 0u) {
+        at(dst, col) = v;
+        at(dst, cc) = v;
+      } else if (R + 1u - (1u << k) >= (1u << (k - 1))) {
+        at(dst, (mirror_rank(R) << sh8) + cc) = v;
+      } else {
+        at(dst, (R << sh8) + col) = v;
+      }
+    } else {
+      at(dst, (R << sh8) + col) = v;
+    }
+  };
   // step 1b: the four-position step of the one row of F_0 for pair pr
   if (t < 256u) {
     const uint32_t u2 = t >> 4, c1 = t & 15u;
@@ -300,13 +320,12 @@ __device__ __forceinline__ void first8_steps(T* buf, const T (&R)[16], uint32_t 
     const T vz = fwd4_after_stage1<T>(F1p, F1s, lastb, F4);
     // F_8 of row z and, for a leaf, of the 30 rows below it: 16 consecutive columns of
     // each row per 16 lanes
-    at(dst, (z << sh8) + s0 + c) = vz;
+    put(z, s0 + c, vz);
     if (lz == 4) {
 #pragma unroll
       for (int d = 1; d <= 4; ++d)
 #pragma unroll
-        for (int m = 0; m < (1 << d); ++m)
-          at(dst, ((((z + 1u) << d) - 1u + uint32_t(m)) << sh8) + s0 + c) = F4[(1 << d) - 2 + m];
+        for (int m = 0; m < (1 << d); ++m) put(((z + 1u) << d) - 1u + uint32_t(m), s0 + c, F4[(1 << d) - 2 + m]);
     }
   }
 }
@@ -1164,7 +1183,16 @@ __global__ __launch_bounds__(32 * stage8_tile<T>()) void k_bwd_stage8(int n, int
 // represents a <= 0 (D(x) <= -log p(x)) with max a >= -n ln 2, so either shift leaves
 // the new log p at most n ln 2 above 0.  The shift only moves the floor, by m' - max
 // a, which vanishes as the iteration converges.
-enum Stage8Mode { kS8Columns = 0, kS8Roots = 1, kS8SymRoots = 2, kS8ColumnsD = 3, kS8ColumnsDU = 4 };
+// kS8ColumnsDH, kS8ColumnsDUH: kS8ColumnsD and kS8ColumnsDU for a complement-symmetric
+// iterate (Group::half): B_i keeps the rows that start with 0 and the empty row, so a
+// row that starts with 1 is read from its complement's row at the complementary
+// columns, reversed; only the column blocks whose first bit is 0 run (x and cpl x
+// then cover every input once), each record counts its inputs twice, and log p + D,
+// log p and F_8 are written at x and at cpl x (F_8 at the rows that start with 0).
+enum Stage8Mode {
+  kS8Columns = 0, kS8Roots = 1, kS8SymRoots = 2, kS8ColumnsD = 3, kS8ColumnsDU = 4, kS8ColumnsDH = 5,
+  kS8ColumnsDUH = 6
+};
 
 // The fused update of kS8ColumnsDU: the maxima it reads (nullptr: shift 0) and writes,
 // and the floor.
@@ -1184,9 +1212,10 @@ __global__ __launch_bounds__(32 * stage8_tile<T>()) void k_bwd_stage8_p(int n, i
                                                                       size_t dstride, const State* st, int frz,
                                                                       Group<T> g, S8Update fu) {
   constexpr bool ROOTS = MODE == kS8Roots || MODE == kS8SymRoots, SYM = MODE == kS8SymRoots;
-  constexpr bool DU = MODE == kS8ColumnsDU;
-  constexpr bool DP = MODE == kS8ColumnsD || DU;
-  static_assert(!DU || sizeof(T) == 4, "the fused update is for FP32 iterates");
+  constexpr bool DU = MODE == kS8ColumnsDU || MODE == kS8ColumnsDUH;
+  constexpr bool HC = MODE == kS8ColumnsDH || MODE == kS8ColumnsDUH;  // complement half
+  constexpr bool DP = MODE == kS8ColumnsD || MODE == kS8ColumnsDH || DU;
+  static_assert(!(DU || HC) || sizeof(T) == 4, "the fused update and the half plan are for FP32 iterates");
   constexpr uint32_t P = uint32_t(stage8_tile<T>());  // value lanes per node
   constexpr int LP = P == 16 ? 4 : 3;
   constexpr uint32_t NT = 32u * P;                     // threads
@@ -1199,7 +1228,7 @@ __global__ __launch_bounds__(32 * stage8_tile<T>()) void k_bwd_stage8_p(int n, i
   const int sh = n - i - 8;                  // log2 of S8 (0 for ROOTS)
   // logical block (root group, column block), column blocks innermost; with 8 or
   // more column blocks XCD x takes its eighth of the column blocks of every root
-  const int lcb = ROOTS ? 0 : sh - LP;
+  const int lcb = ROOTS ? 0 : sh - LP - (HC ? 1 : 0);
   uint32_t lin = 0;
   if constexpr (ROOTS) {
     lin = logical_block();
@@ -1291,8 +1320,18 @@ __global__ __launch_bounds__(32 * stage8_tile<T>()) void k_bwd_stage8_p(int n, i
       li[k] = ~0u;
       if (q < 512u) {
         const int dq = 31 - __clz(q);
-        const uint32_t rank = ((r0 + 1u) << dq) - 1u + (q - (1u << dq));
-        v[k] = ld<T, VW>(src + ((size_t)rank << sh) + s0 + j * uint32_t(VW));
+        const uint32_t m = q - (1u << dq);
+        const uint32_t rank = ((r0 + 1u) << dq) - 1u + m;
+        if (HC && dq > 0 && m >= (1u << (dq - 1))) {
+          // a row that starts with 1 (the root is the empty row): its complement's row
+          // (mirrored within the level) at the complementary columns, reversed
+          const uint32_t mr = (1u << dq) - 1u + ((1u << dq) - 1u - m);
+          const Vec<T, VW> w = ld<T, VW>(src + ((size_t)mr << sh) + ((1u << sh) - uint32_t(VW) - s0 - j * uint32_t(VW)));
+#pragma unroll
+          for (int e = 0; e < VW; ++e) v[k].v[e] = w.v[VW - 1 - e];
+        } else {
+          v[k] = ld<T, VW>(src + ((size_t)rank << sh) + s0 + j * uint32_t(VW));
+        }
         li[k] = (((q & ~3u) | stage8_sigma_bits(q)) << LP) + j * uint32_t(VW);
       }
     }
@@ -1320,7 +1359,7 @@ __global__ __launch_bounds__(32 * stage8_tile<T>()) void k_bwd_stage8_p(int n, i
     if (fu.mprev) {
       const float* bm = fu.mprev + (size_t)b * g.ps * 2u;
       mprev = -INFINITY;
-      for (uint32_t j = t & (kWave - 1u); j < (1u << (n - 8 - LP)); j += kWave) mprev = fmaxf(mprev, bm[j]);
+      for (uint32_t j = t & (kWave - 1u); j < (1u << lcb); j += kWave) mprev = fmaxf(mprev, bm[j]);
 #pragma unroll
       for (int off = kWave / 2; off > 0; off >>= 1) mprev = fmaxf(mprev, __shfl_xor(mprev, off));
       if (!isfinite(mprev)) {
@@ -1439,6 +1478,12 @@ __global__ __launch_bounds__(32 * stage8_tile<T>()) void k_bwd_stage8_p(int n, i
         pv.v[e] = exp_t<float>(nl.v[e]);
       }
       stv<float, VW>(lp + xs[k], nl);
+      if constexpr (HC) {  // cpl x = 2^n - 1 - x
+        Vec<float, VW> rv;
+#pragma unroll
+        for (int e = 0; e < VW; ++e) rv.v[e] = nl.v[VW - 1 - e];
+        stv<float, VW>(lp + ((1u << n) - uint32_t(VW) - xs[k]), rv);
+      }
       stv<float, VW>(slot, pv);
     }
     // the block's max of a: waves, then the first wave over their maxima
@@ -1460,7 +1505,7 @@ __global__ __launch_bounds__(32 * stage8_tile<T>()) void k_bwd_stage8_p(int n, i
       for (int u1 = 0; u1 < 16; ++u1) R[u1] = buf[uint32_t(u1) * 256u + t];
     }
     __syncthreads();
-    first8_steps<float>(buf, R, t, dst, n, s0);
+    first8_steps<float, HC>(buf, R, t, dst, n, s0);
   } else if constexpr (DP) {
     // D at the inputs xs from G of column group w, vector j, and the block's record
     const double M = g.st[b].M;
@@ -1474,7 +1519,7 @@ __global__ __launch_bounds__(32 * stage8_tile<T>()) void k_bwd_stage8_p(int n, i
     if constexpr (sizeof(T) == 4) {
       // FP32 iterates: the lanes' records reduced in single precision within each wave
       PartF q;
-      d_records_pre_f(g, b, M, xs, gv, hd, lq, q);
+      d_records_pre_f(g, b, M, xs, gv, hd, lq, q, HC);
       double* part = g.part + (size_t)b * g.ps;
       store_block_part_f32<int(NT)>(part, rec, q, g.eta != 1.0, reinterpret_cast<float*>(part + kBlockMaxima));
     } else {
@@ -1524,6 +1569,11 @@ constexpr uint32_t kS12P1 = 512u + 16u, kS12P2 = 257u;
 
 __device__ __forceinline__ uint32_t stage12_slot(uint32_t q) { return q + (q >> 5); }
 
+// HALF (complement-symmetric iterate, the twelve-position plan): v holds the rows that
+// start with 0 (and the empty row), B_i is formed for those roots only (256 blocks);
+// the empty root reads a row that starts with 1 at its complement, whose rank mirrors
+// it within its level (the run of a level reversed).
+template <bool HALF>
 __global__ __launch_bounds__(kStage12Threads) __attribute__((amdgpu_waves_per_eu(8))) void k_bwd_stage12(
     int n, const float* __restrict__ src, size_t sstride, float* __restrict__ dst, size_t dstride, const State* st,
     int frz) {
@@ -1531,18 +1581,32 @@ __global__ __launch_bounds__(kStage12Threads) __attribute__((amdgpu_waves_per_eu
   const int b = blockIdx.y;
   if (frz && st[b].converged) return;
   const int i = n - 12;
-  // slot k of XCD x: the 2^(L+1) - 1 roots of level-3 node x's subtree (L = i - 3
-  // levels below it), deepest level first, then top root x
   const uint32_t x = blockIdx.x & 7u, k = blockIdx.x >> 3;
-  const int L = i - 3;
   uint32_t root;
-  if (k + 1u == (2u << L)) {
-    if (x >= 7u) return;
-    root = x;
+  if constexpr (HALF) {
+    // slot k of XCD x: the 2^(L+1) - 1 roots of the subtree of level-4 node 0x (x as
+    // three bits; L = i - 4 levels below it), deepest level first, then top root x of
+    // the 8 above level 4 that are empty or start with 0 (ranks 0, 1, 3, 4, 7 .. 10)
+    const int L = i - 4;
+    if (k + 1u == (2u << L)) {
+      root = x < 2u ? x : (x < 4u ? x + 1u : x + 3u);
+    } else {
+      const uint32_t r = (2u << L) - 1u - k;  // 1 .. 2^(L+1) - 1
+      const int l = 31 - __clz(r);            // level l below level 4
+      root = ((16u + x) << l) - 1u + ((2u << l) - 1u - r);
+    }
   } else {
-    const uint32_t r = (2u << L) - 1u - k;  // 1 .. 2^(L+1) - 1
-    const int l = 31 - __clz(r);            // level l below level 3
-    root = ((8u + x) << l) - 1u + ((2u << l) - 1u - r);
+    // slot k of XCD x: the 2^(L+1) - 1 roots of level-3 node x's subtree (L = i - 3
+    // levels below it), deepest level first, then top root x
+    const int L = i - 3;
+    if (k + 1u == (2u << L)) {
+      if (x >= 7u) return;
+      root = x;
+    } else {
+      const uint32_t r = (2u << L) - 1u - k;  // 1 .. 2^(L+1) - 1
+      const int l = 31 - __clz(r);            // level l below level 3
+      root = ((8u + x) << l) - 1u + ((2u << l) - 1u - r);
+    }
   }
   src += (size_t)b * sstride;
   dst += (size_t)b * dstride;
@@ -1555,12 +1619,30 @@ __global__ __launch_bounds__(kStage12Threads) __attribute__((amdgpu_waves_per_eu
     T v[16];
     const uint32_t q = t + 1u;
     const int kq = 31 - __clz(q);
-    if (q < 512u) v[0] = src[((root + 1u) << kq) - 1u + (q - (1u << kq))];
+    if (HALF && root == 0u) {
+      // element m of level k: m or, from 2^(k-1) on (a row starting with 1), 2^k - 1 - m
+      if (q < 512u) {
+        const uint32_t m = q - (1u << kq);
+        const uint32_t mm = (kq > 0 && m >= (1u << (kq - 1))) ? (1u << kq) - 1u - m : m;
+        v[0] = src[(1u << kq) - 1u + mm];
+      }
 #pragma unroll
-    for (int kk = 9; kk <= 12; ++kk) {
-      const T* base = src + (((root + 1u) << kk) - 1u);
+      for (int kk = 9; kk <= 12; ++kk) {
+        const T* base = src + ((1u << kk) - 1u);
 #pragma unroll
-      for (int j = 0; j < (1 << (kk - 9)); ++j) v[(1 << (kk - 9)) + j] = base[t + uint32_t(j) * kStage12Threads];
+        for (int j = 0; j < (1 << (kk - 9)); ++j) {
+          const uint32_t m = t + uint32_t(j) * kStage12Threads;
+          v[(1 << (kk - 9)) + j] = base[m >= (1u << (kk - 1)) ? (1u << kk) - 1u - m : m];
+        }
+      }
+    } else {
+      if (q < 512u) v[0] = src[((root + 1u) << kq) - 1u + (q - (1u << kq))];
+#pragma unroll
+      for (int kk = 9; kk <= 12; ++kk) {
+        const T* base = src + (((root + 1u) << kk) - 1u);
+#pragma unroll
+        for (int j = 0; j < (1 << (kk - 9)); ++j) v[(1 << (kk - 9)) + j] = base[t + uint32_t(j) * kStage12Threads];
+      }
     }
     if (q < 512u) buf[stage12_slot(q)] = v[0];
     const uint32_t st0 = stage12_slot(t);
@@ -1740,7 +1822,9 @@ __device__ __forceinline__ void fwd12_path(uint32_t q, uint32_t k0, uint32_t l, 
   }
 }
 
-template <bool LOGV>
+// HALF (complement-symmetric iterate): the leaves that start with 0 only (128 blocks),
+// which form v on the rows that start with 0 and the empty row.
+template <bool LOGV, bool HALF>
 __global__ __launch_bounds__(kStage12Threads) __attribute__((amdgpu_waves_per_eu(6))) void k_fwd_stage12(
     int n, const float* __restrict__ src, size_t sstride, float* __restrict__ dst, size_t dstride, const State* st,
     const Consts* cs, int frz) {
@@ -1748,7 +1832,8 @@ __global__ __launch_bounds__(kStage12Threads) __attribute__((amdgpu_waves_per_eu
   constexpr int I = kStage12N - 12;
   const int b = blockIdx.y;
   if (n != kStage12N || (frz && st[b].converged)) return;
-  const uint32_t l = ((blockIdx.x & 7u) << (I - 3)) + (blockIdx.x >> 3);  // leaf index
+  constexpr int LX = HALF ? I - 4 : I - 3;  // log2 of the leaves per XCD
+  const uint32_t l = ((blockIdx.x & 7u) << LX) + (blockIdx.x >> 3);  // leaf index
   const uint32_t z1 = (1u << I) + l;                                        // rank of z, plus 1
   const uint32_t c = l ? uint32_t(__ffs(l) - 1) : uint32_t(I);              // chain rows written here
   src += (size_t)b * sstride;
@@ -2000,13 +2085,21 @@ hipError_t launch_forward(const Group<T>& g, hipStream_t s, int* launches, int f
       // fuse >= 7 at n = kStage12N: positions 8 .. n-1 in one launch
       if (fuse >= 7 && n == kStage12N && i == n - 12) {
         T* dst = logv ? g.v : g.r;
-        const dim3 grid(1u << (n - 12), g.nb);  // one block per leaf of F_8
-        if (logv)
-          hipLaunchKernelGGL((k_fwd_stage12<true>), grid, dim3(kStage12Threads), 0, s, n, src, ss, dst, g.ys, g.st,
-                             g.cs, g.frz);
-        else
-          hipLaunchKernelGGL((k_fwd_stage12<false>), grid, dim3(kStage12Threads), 0, s, n, src, ss, dst, g.ys,
+        const dim3 grid((1u << (n - 12)) >> (g.half ? 1 : 0), g.nb);  // one block per leaf of F_8
+        if (g.half) {
+          if (logv)
+            hipLaunchKernelGGL((k_fwd_stage12<true, true>), grid, dim3(kStage12Threads), 0, s, n, src, ss, dst, g.ys,
+                               g.st, g.cs, g.frz);
+          else
+            hipLaunchKernelGGL((k_fwd_stage12<false, true>), grid, dim3(kStage12Threads), 0, s, n, src, ss, dst,
+                               g.ys, g.st, g.cs, g.frz);
+        } else if (logv) {
+          hipLaunchKernelGGL((k_fwd_stage12<true, false>), grid, dim3(kStage12Threads), 0, s, n, src, ss, dst, g.ys,
                              g.st, g.cs, g.frz);
+        } else {
+          hipLaunchKernelGGL((k_fwd_stage12<false, false>), grid, dim3(kStage12Threads), 0, s, n, src, ss, dst,
+                             g.ys, g.st, g.cs, g.frz);
+        }
         if (launches) ++*launches;
         break;
       }
@@ -2127,8 +2220,12 @@ hipError_t launch_backward(const Group<T>& g, hipStream_t s, int* launches, int 
       if (fuse >= 6 && n == kStage12N && top == n) {
         const int i = n - 12;
         T* dst = (k & 1) ? g.f1 : g.f0;
-        hipLaunchKernelGGL(k_bwd_stage12, dim3(2u << i, g.nb), dim3(kStage12Threads), 0, s, n, src, ss, dst, g.fs,
-                           g.st, g.frz);
+        if (g.half)
+          hipLaunchKernelGGL(k_bwd_stage12<true>, dim3(1u << i, g.nb), dim3(kStage12Threads), 0, s, n, src, ss, dst,
+                             g.fs, g.st, g.frz);
+        else
+          hipLaunchKernelGGL(k_bwd_stage12<false>, dim3(2u << i, g.nb), dim3(kStage12Threads), 0, s, n, src, ss, dst,
+                             g.fs, g.st, g.frz);
         if (launches) ++*launches;
         src = dst;
         ss = g.fs;
@@ -2138,20 +2235,32 @@ hipError_t launch_backward(const Group<T>& g, hipStream_t s, int* launches, int 
     }
     if (fuse >= 6 && sizeof(T) == 4 && n == kStage12N && top == 8) {
       constexpr int LP = stage8_tile<T>() == 16 ? 4 : 3;
-      const dim3 grid(1u << (n - 8 - LP), 1, g.nb);  // column blocks of P columns
+      // column blocks of P columns (half: those whose first column bit is 0)
+      const dim3 grid((1u << (n - 8 - LP)) >> (g.half ? 1 : 0), 1, g.nb);
       const dim3 block(32 * stage8_tile<T>());
+      if (g.half && !(dpart || next)) return hipErrorInvalidValue;
       if (next) {
         // D with the next iteration's update and first eight forward positions: F_8 to f1
         if constexpr (sizeof(T) == 4) {
           float* m0 = reinterpret_cast<float*>(g.part + kBlockMaxima);  // maxima set 0 of instance 0
           const uint32_t nset = grid.x;
           const S8Update u{m0 + (next->par ? 0u : nset), m0 + (next->par ? nset : 0u), float(next->floor)};
-          hipLaunchKernelGGL((k_bwd_stage8_p<T, kS8ColumnsDU>), grid, block, 0, s, n, 0, src, ss, g.f1, g.fs,
-                             g.st, g.frz, g, u);
+          if (g.half)
+            hipLaunchKernelGGL((k_bwd_stage8_p<T, kS8ColumnsDUH>), grid, block, 0, s, n, 0, src, ss, g.f1, g.fs,
+                               g.st, g.frz, g, u);
+          else
+            hipLaunchKernelGGL((k_bwd_stage8_p<T, kS8ColumnsDU>), grid, block, 0, s, n, 0, src, ss, g.f1, g.fs,
+                               g.st, g.frz, g, u);
         }
       } else if (dpart) {
-        hipLaunchKernelGGL((k_bwd_stage8_p<T, kS8ColumnsD>), grid, block, 0, s, n, 0, src, ss, g.g, g.xs, g.st,
-                           g.frz, g, S8Update{});
+        if constexpr (sizeof(T) == 4) {
+          if (g.half)
+            hipLaunchKernelGGL((k_bwd_stage8_p<T, kS8ColumnsDH>), grid, block, 0, s, n, 0, src, ss, g.g, g.xs, g.st,
+                               g.frz, g, S8Update{});
+          else
+            hipLaunchKernelGGL((k_bwd_stage8_p<T, kS8ColumnsD>), grid, block, 0, s, n, 0, src, ss, g.g, g.xs, g.st,
+                               g.frz, g, S8Update{});
+        }
         if (dpart_blocks) *dpart_blocks = int(grid.x);
       } else {
         hipLaunchKernelGGL((k_bwd_stage8_p<T, kS8Columns>), grid, block, 0, s, n, 0, src, ss, g.g, g.xs, g.st,

@@ -305,9 +305,12 @@ __device__ __forceinline__ void d_records_pre(const Group<T>& g, int b, double M
 // (q, for store_block_part_f32); D is that of d_records_pre, the record's sums use
 // the hardware exponential (2^(x log2 e), relative error below |x| 2^-23), which the
 // single-precision record of an FP32 iterate does not need better than that.
+// half: the inputs stand for themselves and their complements (complement-symmetric
+// iterate): log p + D (or D) is written at x and at cpl x = 2^n - 1 - x, and the
+// record's sums count every input twice.
 __device__ __forceinline__ void d_records_pre_f(const Group<float>& g, int b, double M, const uint32_t (&x)[2],
                                                 const Vec<float, 4> (&G)[2], Vec<float, 4> (&d)[2],
-                                                const Vec<float, 4> (&l)[2], PartF& q) {
+                                                const Vec<float, 4> (&l)[2], PartF& q, bool half = false) {
   using T = float;
   constexpr int N = 2, V = 4;
   T* D = g.D + (size_t)b * g.xs;
@@ -329,6 +332,16 @@ __device__ __forceinline__ void d_records_pre_f(const Group<float>& g, int b, do
 #pragma unroll
     for (int u = 0; u < N; ++u) stv<T, V>(D + x[u], d[u]);
   }
+  if (half) {
+    const uint32_t X = 1u << g.n;
+#pragma unroll
+    for (int u = 0; u < N; ++u) {
+      Vec<T, V> r;
+#pragma unroll
+      for (int k = 0; k < V; ++k) r.v[k] = g.dsum ? a[u].v[V - 1 - k] : d[u].v[V - 1 - k];
+      stv<T, V>(D + (X - uint32_t(V) - x[u]), r);
+    }
+  }
   T s = T(0), i = T(0);
 #pragma unroll
   for (int u = 0; u < N; ++u)
@@ -337,6 +350,10 @@ __device__ __forceinline__ void d_records_pre_f(const Group<float>& g, int b, do
       s += __expf((l[u].v[k] + d[u].v[k]) - am);
       i += __expf(l[u].v[k]) * d[u].v[k];
     }
+  if (half) {
+    s += s;
+    i += i;
+  }
   q = PartF{am, s, dm, i, T(-INFINITY), T(0)};
   if (g.eta != 1.0) {
     const T eta = T(g.eta);
@@ -350,7 +367,7 @@ __device__ __forceinline__ void d_records_pre_f(const Group<float>& g, int b, do
 #pragma unroll
       for (int k = 0; k < V; ++k) s2 += __expf((l[u].v[k] + eta * d[u].v[k]) - m2);
     q.m2 = m2;
-    q.s2 = s2;
+    q.s2 = half ? s2 + s2 : s2;
   }
 }
 

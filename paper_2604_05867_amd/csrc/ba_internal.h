@@ -137,6 +137,10 @@ struct Group {
   int dsum;           // iterations with eta = 1: the D launch stores log p + D in D (the
                       // update then reads one array: log p <- (log p + D) - L, the same
                       // rounding as before); 0: D itself (certification, a step eta != 1)
+  int half;           // complement-symmetric iterate, launch plan level 8 at n = 20 (FP32):
+                      // the stages keep the rows that start with 0 (and the empty row),
+                      // the D launches take the column tiles whose first bit is 0 and
+                      // write log p (and log p + D) at x and at its complement
 };
 
 enum StreamOp { kOpScatter = 0, kOpGather = 1, kOpInit = 2, kOpRow = 3, kOpVerify = 4, kOpScatterOrbit = 5 };

@@ -61,6 +61,26 @@ def test_symmetric_fp64_equals_full(ba, n, fuse):
     assert np.array_equal(lp_s, lp_s[::-1])
 
 
+def test_full_kernels_keep_complement_symmetry_bitwise(ba):
+    """Theorem 4 on the full kernels of the n = 20 FP32 plan (first eight positions,
+    twelve-position launches, fused D launch): from the uniform law every iterate is
+    complement-invariant, and these kernels keep it bit for bit (the sum at (cpl y,
+    cpl s) adds the same terms as at (y, s), two operands swapped), over 7 iterations in
+    one call and 3 more in another.  (The four- and eight-position kernels of the other
+    plans group some sums differently at mirrored positions, so there the invariance
+    holds to rounding.)"""
+    n = 20
+    say("full kernels complement symmetry n=20 fp32")
+    ns, ds = [n] * 3, [0.64, 0.8, 0.95]
+    c = ba.Context(ns, ds, prec=ba.PREC_FP32_LOG)
+    c.step(7)
+    c.step(3)
+    lp = c.get_logp().cpu().numpy().reshape(len(ns), 1 << n)
+    c.close()
+    for k in range(len(ns)):
+        assert np.array_equal(lp[k], lp[k][::-1])
+
+
 @pytest.mark.parametrize("n", [8, 14])
 def test_symmetric_fp64_matches_oracle(ba, n):
     """Against the oracle's dense or sparse BA from the uniform law (Section 2.3)."""
@@ -106,14 +126,55 @@ def test_symmetric_exact_channel(ba):
     assert np.max(np.abs(lo_f - lo_s)) < 1e-12 and np.max(np.abs(hi_f - hi_s)) < 1e-12
 
 
-def test_symmetric_n20_fp32(ba):
-    """The benchmark shape: n = 20, three instances, FP32 iterates.  The two kernel
-    sets sum in different orders and the full set forms its D records in single
-    precision, so the FP32 iterates agree to rounding (log p of magnitude ~14 has an
-    ulp of ~1e-6) and their FP64-certified bounds within 1e-6 bits."""
+@pytest.mark.parametrize("fuse", [4, 8])
+def test_symmetric_n20_fp32(ba, fuse):
+    """The benchmark shape: n = 20, three instances, FP32 iterates, with the
+    complement-symmetric kernels (launch plan 4) or the full plan on half the rows and
+    column tiles (plan 8).  The two sets sum in different orders (or group the records
+    differently) and the full set forms its D records in single precision, so the FP32
+    iterates agree to rounding (log p of magnitude ~14 has an ulp of ~1e-6) and their
+    FP64-certified bounds within 1e-6 bits."""
+    say("symmetric n=20 fp32 fuse=%d" % fuse)
     ds = [0.64, 0.8, 0.95]
-    (lp_f, lo_f, hi_f), (lp_s, lo_s, hi_s) = run_pair(ba, [20] * 3, ds, ba.PREC_FP32_LOG, 6)
+    (lp_f, lo_f, hi_f), (lp_s, lo_s, hi_s) = run_pair(ba, [20] * 3, ds, ba.PREC_FP32_LOG, 6, fuse=fuse)
     assert np.max(np.abs(lp_f - lp_s)) < 1e-4
+    assert np.max(np.abs(lo_f - lo_s)) < 1e-6 and np.max(np.abs(hi_f - hi_s)) < 1e-6
+    X = 1 << 20
+    for b in range(3):
+        seg = lp_s[b * X:(b + 1) * X]
+        assert np.array_equal(seg, seg[::-1])
+
+
+@pytest.mark.parametrize("per_call", [1, 2, 3, 7])
+def test_half_plan_n20_fp32_calls(ba, per_call):
+    """The half plan (complement-symmetric iterate, n = 20, FP32, plan 8: the full
+    plan's kernels on the rows that start with 0 and the column tiles whose first bit
+    is 0) against the full plan from the uniform law, 7 iterations in calls of 1, 2, 3
+    or 7: log p within 4e-5 and the certified bounds within 1e-6 bits (the D records
+    count each input of a pair twice, so L rounds differently); the half iterate is
+    exactly complement-invariant; with 7 per call the same launches ran (9 forward, 14
+    backward, one record reduction)."""
+    say("half plan n=20 per_call=%d" % per_call)
+    ds = [0.64, 0.8, 0.95]
+    out = []
+    for sym in (False, True):
+        c = ba.Context([20] * 3, ds, prec=ba.PREC_FP32_LOG)
+        if sym:
+            c.set_symmetry(True)
+        done = 0
+        while done < 7:
+            k = min(per_call, 7 - done)
+            c.step(k)
+            done += k
+        lo, hi = c.bounds()
+        out.append((c.get_logp().cpu().numpy(), np.array(lo), np.array(hi)))
+        if per_call == 7 and sym:
+            c.set_logp(torch.full((3 << 20,), -20 * LN2, dtype=torch.float64))
+            t = c.time_kernels(7)
+            assert t["sweep1"][1] == 9 and t["sweep2"][1] == 14 and t["reduce"][1] == 1
+        c.close()
+    (lp_f, lo_f, hi_f), (lp_s, lo_s, hi_s) = out
+    assert np.max(np.abs(lp_f - lp_s)) < 4e-5
     assert np.max(np.abs(lo_f - lo_s)) < 1e-6 and np.max(np.abs(hi_f - hi_s)) < 1e-6
     X = 1 << 20
     for b in range(3):
