@@ -534,7 +534,8 @@ def test_first_eight_forward_is_bitwise_four(ba, n, prec):
     assert out[0][1] == out[1][1]
 
 
-@pytest.mark.parametrize("n,prec,sym", [(16, "fp32", False), (13, "fp64", False), (16, "fp32", True)])
+@pytest.mark.parametrize("n,prec,sym", [(16, "fp32", False), (13, "fp64", False), (16, "fp32", True),
+                                        (20, "fp32", False), (20, "fp32", True)])
 def test_freeze_flag_skip_is_bitwise(ba, n, prec, sym):
     """Until a gap tolerance is set (ba_run) no instance can be frozen by one, and the
     sweep kernels skip reading the frozen flag: the iterates of step() then equal,
