@@ -50,7 +50,7 @@ MEASURED_TRAFFIC = {
     "sources": ["paper_2604_05867_amd/csrc/ba_factored.hip", "paper_2604_05867_amd/csrc/ba_factored_common.h",
                 "paper_2604_05867_amd/csrc/ba_part.h"],
     # of the sources concatenated
-    "sha256": "5c527c30e840004aa5bb2fbc2480fc545860d1a42864cf5b6b8d2be211554cf1",
+    "sha256": "501a5f8965064f376ce2360ed7e3503846b70584f6c8a529a813cb46e998bcdb",
     "bytes": {"first8": 37790000, "first8_upd": 50450000, "fwd12": 51450000,
               "bwd12": 50960000, "d8": 63070000, "dfused": 88170000},
 }
