@@ -126,7 +126,10 @@ int ba_set_stop_rule(ba_ctx *c, int rule);
  * inputs x < 2^(n-1) and the stage entries whose first column bit is 0, reading the
  * other half from the complement (about half the memory traffic; same results up
  * to rounding).  Applies to groups with even n >= 4 and BA_TUNE_FACTORED_FUSE >= 1
- * (its kernels take two positions per launch).
+ * (its kernels take two positions per launch).  At n = 20 with FP32 iterates, step
+ * 1 and BA_TUNE_FACTORED_FUSE = 8 the iterations instead run the default plan's
+ * kernels on half their rows and column tiles (the rows that start with 0, the
+ * tiles whose first column bit is 0), writing log p at x and at cpl x.
  * enable = 2: complement and reversal.  As 1 for the factored engine; in addition
  * the iterations of the stream engine compute q = W^T p by Algorithm 7: only inputs
  * that are the smallest member of their orbit {x, cpl x, rev x, cpl rev x} are
