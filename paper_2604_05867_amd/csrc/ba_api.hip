@@ -466,7 +466,7 @@ int iterate_group(ba_ctx* c, const GroupHost& gh, const Group<T>& G0, bool fused
   int rc = sweeps<T>(c, gh, G, 0, G.g, 1, &nblk, fused_in ? &fu : nullptr, first8_done, next);
   if (rc) return rc;
   if (next) {
-    if (nmax_out) *nmax_out = 0;
+    if (nmax_out) *nmax_out = nblk;  // the block maxima it wrote
     return BA_OK;
   }
   const bool by_max = leave_pending && nblk > 0 && update_by_max(c, gh);
@@ -832,7 +832,7 @@ int step_group(ba_ctx* c, GroupHost& gh, int iters) {
     const bool in = fu && it > 0 && !done8, out = fu && it + 1 < iters;
     const int nin = in ? nmax : 0;
     const bool nx = fnext && it >= 1 && it + 1 < iters;
-    const FusedNext fn{iterate_floor(c), it & 1};
+    const FusedNext fn{iterate_floor(c), it & 1, nmax};
     const int rc = (c->prec == BA_PREC_FP32_LOG)
                        ? iterate_group<float>(c, gh, gh.gf, in, nin, out, &nmax, done8, nx ? &fn : nullptr)
                        : iterate_group<double>(c, gh, gh.gd, in, nin, out, &nmax);

@@ -222,7 +222,6 @@ __global__ __launch_bounds__(kBlock) void k_fwd_first4_upd(int n, T* __restrict_
 // the same order, as with k_fwd_first4_upd (or k_fwd_stage4) and k_fwd_stage4.
 constexpr int kFirst8MinN = 12;
 constexpr uint32_t kFirst8Threads = 512;
-constexpr uint32_t kF4Pitch = 16u * 16u + 16u;  // F_4 row in LDS: 16 u2 x 16 columns, padded
 
 // Positions 0-7 of the forward sweep for the columns s0 .. s0+15 of F_8, from the
 // inputs held in R by threads t < 256 (R[u1] = p(x) for x = u1 2^(n-4) + u2 2^(n-8) +
@@ -235,9 +234,16 @@ constexpr uint32_t kF4Pitch = 16u * 16u + 16u;  // F_4 row in LDS: 16 u2 x 16 co
 // rows that start with 0 and the empty row at every column; a value of a row that
 // starts with 1 goes to its complement's row at the complementary column, one of the
 // empty row to both columns.
-template <typename T, bool HALF = false>
+template <int C>
+constexpr uint32_t f4_pitch() { return 16u * uint32_t(C) + 16u; }  // F_4 row in LDS: 16 u2 x C columns, padded
+
+// C: the columns of the block (16, or 8 with 128 pairs and 248 step-2 threads).
+template <typename T, bool HALF = false, int C = 16>
 __device__ __forceinline__ void first8_steps(T* buf, const T (&R)[16], uint32_t t, T* __restrict__ dst, int n,
                                              uint32_t s0) {
+  static_assert(C == 16 || C == 8, "16 or 8 columns");
+  constexpr uint32_t PC = f4_pitch<C>();
+  constexpr int LC = C == 16 ? 4 : 3;
   const int sh8 = n - 8;
   auto put = [&](uint32_t R, uint32_t col, T v) {
     if constexpr (HALF) {
@@ -256,8 +262,8 @@ __device__ __forceinline__ void first8_steps(T* buf, const T (&R)[16], uint32_t 
     }
   };
   // step 1b: the four-position step of the one row of F_0 for pair pr
-  if (t < 256u) {
-    const uint32_t u2 = t >> 4, c1 = t & 15u;
+  if (t < 16u * C) {
+    const uint32_t u2 = t >> LC, c1 = t & uint32_t(C - 1);
     // the first stage of fwd4_thread for the row without ancestors
     uint32_t P[5], lastb[4];
     fwd4_path(0u, P, lastb);
@@ -274,14 +280,14 @@ __device__ __forceinline__ void first8_steps(T* buf, const T (&R)[16], uint32_t 
       for (int q = 0; q < 8; ++q) F1s[cc][q] = R[cc * 8 + q];
     T F4[30];
     const T v0 = fwd4_after_stage1<T>(F1p, F1s, lastb, F4);
-    T* col = buf + u2 * 16u + c1;
+    T* col = buf + u2 * uint32_t(C) + c1;
     col[0] = v0;
 #pragma unroll
-    for (int z = 1; z < 31; ++z) col[uint32_t(z) * kF4Pitch] = F4[z - 1];
+    for (int z = 1; z < 31; ++z) col[uint32_t(z) * PC] = F4[z - 1];
   }
   __syncthreads();
   // step 2: thread (z, c), z < 31: fwd4_thread on the LDS rows of z's path
-  const uint32_t z = t >> 4, c = t & 15u;
+  const uint32_t z = t >> LC, c = t & uint32_t(C - 1);
   const int lz = length_of_rank(z);
   if (z < 31u) {
     T F4[30];
@@ -291,9 +297,9 @@ __device__ __forceinline__ void first8_steps(T* buf, const T (&R)[16], uint32_t 
 #pragma unroll
     for (int u = 0; u < 8; ++u) Hc[u] = T(0);
     if (4 <= lz) {
-      const T* row = buf + P[4] * kF4Pitch + (lastb[3] << 7) + c;
+      const T* row = buf + P[4] * PC + (lastb[3] ? 8u * C : 0u) + c;
 #pragma unroll
-      for (int u = 0; u < 8; ++u) Hc[u] = row[uint32_t(u) << 4];
+      for (int u = 0; u < 8; ++u) Hc[u] = row[uint32_t(u) * C];
     }
 #pragma unroll
     for (int j = 3; j >= 0; --j) {
@@ -301,9 +307,9 @@ __device__ __forceinline__ void first8_steps(T* buf, const T (&R)[16], uint32_t 
 #pragma unroll
       for (int u = 0; u < 16; ++u) R[u] = T(0);
       if (j <= lz) {
-        const T* row = buf + P[j] * kF4Pitch + c;
+        const T* row = buf + P[j] * PC + c;
 #pragma unroll
-        for (int u = 0; u < 16; ++u) R[u] = row[uint32_t(u) << 4];
+        for (int u = 0; u < 16; ++u) R[u] = row[uint32_t(u) * C];
       }
 #pragma unroll
       for (int q = 0; q < 8; ++q) F1p[j][q] = (R[q] + R[8 + q]) + Hc[q];
@@ -374,7 +380,7 @@ __global__ __launch_bounds__(kFirst8Threads) void k_fwd_first8(int n, const T* _
   const int sh8 = n - 8;                      // log2 of the F_8 width
   // neighbouring column blocks share 128-byte lines: consecutive logical blocks on one XCD
   const uint32_t s0 = logical_block() * 16u, t = threadIdx.x;
-  __shared__ T buf[31u * kF4Pitch];
+  __shared__ T buf[31u * f4_pitch<16>()];
   // step 1a: all threads load (and update) 8 of the 16 inputs of pair pr = (u2, c):
   // u1 = 8 h .. 8 h + 7; the upper halves pass through LDS (the start of buf)
   const uint32_t h = t >> 8, pr = t & 255u;
@@ -1194,32 +1200,35 @@ enum Stage8Mode {
   kS8ColumnsDUH = 6
 };
 
-// The fused update of kS8ColumnsDU: the maxima it reads (nullptr: shift 0) and writes,
-// and the floor.
+// The fused update of kS8ColumnsDU: the maxima it reads (nprev of them; nullptr: shift
+// 0) and writes, and the floor.
 struct S8Update {
   const float* mprev;  // per instance, at stride ps doubles
   float* mout;
   float floor;
+  int nprev;
 };
 
 __host__ __device__ constexpr uint32_t stage8_sigma_bits(uint32_t q) {
   return ((uint32_t(__builtin_popcount(q & 0xAAAAAAAAu)) & 1u) << 1) | (uint32_t(__builtin_popcount(q)) & 1u);
 }
 
-template <typename T, int MODE>
-__global__ __launch_bounds__(32 * stage8_tile<T>()) void k_bwd_stage8_p(int n, int i, const T* __restrict__ src,
-                                                                      size_t sstride, T* __restrict__ dst,
-                                                                      size_t dstride, const State* st, int frz,
-                                                                      Group<T> g, S8Update fu) {
+// PT: value lanes per node (columns per block in the column modes), 0 for the
+// precision's default (stage8_tile); the fused update of the half plan takes 8.
+template <typename T, int MODE, int PT = 0>
+__global__ __launch_bounds__(32 * (PT ? PT : stage8_tile<T>())) void k_bwd_stage8_p(
+    int n, int i, const T* __restrict__ src, size_t sstride, T* __restrict__ dst, size_t dstride, const State* st,
+    int frz, Group<T> g, S8Update fu) {
   constexpr bool ROOTS = MODE == kS8Roots || MODE == kS8SymRoots, SYM = MODE == kS8SymRoots;
   constexpr bool DU = MODE == kS8ColumnsDU || MODE == kS8ColumnsDUH;
   constexpr bool HC = MODE == kS8ColumnsDH || MODE == kS8ColumnsDUH;  // complement half
   constexpr bool DP = MODE == kS8ColumnsD || MODE == kS8ColumnsDH || DU;
   static_assert(!(DU || HC) || sizeof(T) == 4, "the fused update and the half plan are for FP32 iterates");
-  constexpr uint32_t P = uint32_t(stage8_tile<T>());  // value lanes per node
+  constexpr uint32_t P = uint32_t(PT ? PT : stage8_tile<T>());  // value lanes per node
   constexpr int LP = P == 16 ? 4 : 3;
   constexpr uint32_t NT = 32u * P;                     // threads
-  constexpr int VW = 16 / int(sizeof(T));              // P / VW = 4 vectors per node row
+  constexpr int VW = int(P) / 4;                       // P / VW = 4 vectors per node row
+  static_assert(PT == 0 || MODE == kS8ColumnsDUH, "other tiles only for the half plan's fused update");
   constexpr uint32_t kOutPitch = 260u;                 // ROOTS: output row pitch
   const int b = blockIdx.z;
   if ((DU || frz) && st[b].converged) return;  // DU writes log p: frozen instances always stay
@@ -1262,7 +1271,7 @@ __global__ __launch_bounds__(32 * stage8_tile<T>()) void k_bwd_stage8_p(int n, i
   const uint32_t s0 = (lin & ((1u << lcb) - 1u)) * P;
   const uint32_t t = threadIdx.x;
   // DU: the buffer also holds first8_steps' F_4
-  __shared__ __attribute__((aligned(16))) T buf[DU ? 31u * kF4Pitch : 512u * P];
+  __shared__ __attribute__((aligned(16))) T buf[DU ? 31u * f4_pitch<int(P)>() : 512u * P];
   if constexpr (ROOTS) {
     // copy-in: depth k of the roots' subtrees is one run of nr 2^k consecutive ranks;
     // value m of the run is root m >> k, node 2^k + (m mod 2^k).  Full groups: the
@@ -1359,7 +1368,7 @@ __global__ __launch_bounds__(32 * stage8_tile<T>()) void k_bwd_stage8_p(int n, i
     if (fu.mprev) {
       const float* bm = fu.mprev + (size_t)b * g.ps * 2u;
       mprev = -INFINITY;
-      for (uint32_t j = t & (kWave - 1u); j < (1u << lcb); j += kWave) mprev = fmaxf(mprev, bm[j]);
+      for (uint32_t j = t & (kWave - 1u); j < uint32_t(fu.nprev); j += kWave) mprev = fmaxf(mprev, bm[j]);
 #pragma unroll
       for (int off = kWave / 2; off > 0; off >>= 1) mprev = fmaxf(mprev, __shfl_xor(mprev, off));
       if (!isfinite(mprev)) {
@@ -1500,12 +1509,12 @@ __global__ __launch_bounds__(32 * stage8_tile<T>()) void k_bwd_stage8_p(int n, i
       if (lin == 0u) g.st[b].iters += 1;
     }
     float R[16];
-    if (t < 256u) {
+    if (t < 16u * P) {
 #pragma unroll
-      for (int u1 = 0; u1 < 16; ++u1) R[u1] = buf[uint32_t(u1) * 256u + t];
+      for (int u1 = 0; u1 < 16; ++u1) R[u1] = buf[uint32_t(u1) * 16u * P + t];
     }
     __syncthreads();
-    first8_steps<float, HC>(buf, R, t, dst, n, s0);
+    first8_steps<float, HC, int(P)>(buf, R, t, dst, n, s0);
   } else if constexpr (DP) {
     // D at the inputs xs from G of column group w, vector j, and the block's record
     const double M = g.st[b].M;
@@ -2242,15 +2251,23 @@ hipError_t launch_backward(const Group<T>& g, hipStream_t s, int* launches, int 
       if (next) {
         // D with the next iteration's update and first eight forward positions: F_8 to f1
         if constexpr (sizeof(T) == 4) {
-          float* m0 = reinterpret_cast<float*>(g.part + kBlockMaxima);  // maxima set 0 of instance 0
-          const uint32_t nset = grid.x;
-          const S8Update u{m0 + (next->par ? 0u : nset), m0 + (next->par ? nset : 0u), float(next->floor)};
-          if (g.half)
-            hipLaunchKernelGGL((k_bwd_stage8_p<T, kS8ColumnsDUH>), grid, block, 0, s, n, 0, src, ss, g.f1, g.fs,
-                               g.st, g.frz, g, u);
-          else
+          // maxima set k of instance 0 at kBlockMaxima + k kMaxRedBlocks floats (set 0 is
+          // also the D launch's with records)
+          float* m0 = reinterpret_cast<float*>(g.part + kBlockMaxima);
+          const uint32_t ks = uint32_t(kMaxRedBlocks);
+          const S8Update u{m0 + (next->par ? 0u : ks), m0 + (next->par ? ks : 0u), float(next->floor), next->nprev};
+          if (g.half) {
+            // 8 columns per block: twice the blocks of half the work (the half plan's
+            // 16-column launch runs fewer blocks than CUs)
+            const dim3 grid8((1u << (n - 8 - 3)) >> 1, 1, g.nb);
+            hipLaunchKernelGGL((k_bwd_stage8_p<T, kS8ColumnsDUH, 8>), grid8, dim3(32 * 8), 0, s, n, 0, src, ss, g.f1,
+                               g.fs, g.st, g.frz, g, u);
+            if (dpart_blocks) *dpart_blocks = int(grid8.x);
+          } else {
             hipLaunchKernelGGL((k_bwd_stage8_p<T, kS8ColumnsDU>), grid, block, 0, s, n, 0, src, ss, g.f1, g.fs,
                                g.st, g.frz, g, u);
+            if (dpart_blocks) *dpart_blocks = int(grid.x);
+          }
         }
       } else if (dpart) {
         if constexpr (sizeof(T) == 4) {

@@ -274,6 +274,7 @@ bool backward_writes_maxima(int n, int fuse, int esz);
 struct FusedNext {
   double floor;
   int par;
+  int nprev;  // block maxima the D launch before it wrote
 };
 // True when launch_backward can take a FusedNext (element bytes esz).
 bool backward_fuses_next(int n, int fuse, int esz);
