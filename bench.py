@@ -50,9 +50,9 @@ MEASURED_TRAFFIC = {
     "sources": ["paper_2604_05867_amd/csrc/ba_factored.hip", "paper_2604_05867_amd/csrc/ba_factored_common.h",
                 "paper_2604_05867_amd/csrc/ba_part.h"],
     # of the sources concatenated
-    "sha256": "501a5f8965064f376ce2360ed7e3503846b70584f6c8a529a813cb46e998bcdb",
-    "bytes": {"first8": 37790000, "first8_upd": 50450000, "fwd12": 51450000,
-              "bwd12": 50960000, "d8": 63070000, "dfused": 88170000},
+    "sha256": "fadc141d2966f71d7c6acb56c997d54b600c1619a75c1121b370e7a6552da530",
+    "bytes": {"first8": 37780000, "first8_upd": 50450000, "fwd12": 51450000,
+              "bwd12": 50960000, "d8": 63060000, "dfused": 88180000},
 }
 
 
