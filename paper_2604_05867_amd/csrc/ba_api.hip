@@ -331,7 +331,7 @@ bool sym_active(const ba_ctx* c, int n) {
 // level 8 runs the full plan's kernels on half the rows and column tiles
 // (Group::half) instead of the complement-symmetric kernels.
 bool half_plan(const ba_ctx* c, int n) {
-  return sym_active(c, n) && c->prec == BA_PREC_FP32_LOG && c->eta == 1.0 && backward_fuses_next(n, c->fuse, 4);
+  return sym_active(c, n) && c->prec == BA_PREC_FP32_LOG && c->eta == 1.0 && half_plan_fits(n, c->fuse);
 }
 
 // tail = 1 (factored engine, iteration only): the last forward launch writes v
@@ -428,8 +428,8 @@ bool update_fusable(const ba_ctx* c, const GroupHost& gh) {
   return forward_update_fusable(gh.n, c->fuse);
 }
 
-// FP32 BA iterations at n = 20 (default plan): an update left pending to the next
-// eight-position first launch can shift by the max of log p + D instead of
+// FP32 BA iterations at n >= 12 (launch plan levels 6-8): an update left pending to
+// the next eight-position first launch can shift by the max of log p + D instead of
 // normalising (k_fwd_first8), from the block maxima the D launch wrote, with no
 // final-record launch.
 bool update_by_max(const ba_ctx* c, const GroupHost& gh) {

@@ -2051,6 +2051,14 @@ __global__ __launch_bounds__(kBlock) void k_bwd_stage2_w1(const T* __restrict__ 
 
 using namespace fac;
 
+// Launch plan levels 6-8 with FP32 iterates for n >= kD8MinN: the backward sweep
+// ends with one eight-position launch from B_8 that forms D (with the block records
+// and maxima, or fused with the next iteration's update and first eight forward
+// positions at level 8).  At n = kStage12N one twelve-position launch reaches B_8;
+// at other n two-, four- and eight-position launches stop at position 8.
+constexpr int kD8MinN = 12;
+bool d8_plan(int n, int fuse, int esz) { return fuse >= 6 && esz == 4 && n >= kD8MinN; }
+
 template <typename T>
 hipError_t launch_forward(const Group<T>& g, hipStream_t s, int* launches, int fuse, int logv,
                           const FusedUpdate* upd, int first8_done) {
@@ -2062,13 +2070,13 @@ hipError_t launch_forward(const Group<T>& g, hipStream_t s, int* launches, int f
   if (upd && !forward_update_fusable(n, fuse)) return hipErrorInvalidValue;
   int i = 0;
   if (first8_done) {
-    // F_8 was formed by the previous iteration's fused D launch (into f1); only the
-    // one launch of positions 8 .. n-1 follows
+    // F_8 was formed by the previous iteration's fused D launch (into f1); the
+    // launches of positions 8 .. n-1 follow (the next one writes f0)
     if (upd || !backward_fuses_next(n, fuse, int(sizeof(T)))) return hipErrorInvalidValue;
     src = g.f1;
     ss = g.fs;
     i = 8;
-    k = 1;
+    k = 0;
   }
   // fuse >= 4: the last four positions in one launch with LDS-staged outputs;
   // fuse >= 5: the first eight positions in one launch
@@ -2217,7 +2225,11 @@ hipError_t launch_backward(const Group<T>& g, hipStream_t s, int* launches, int 
   constexpr int V = 16 / sizeof(T);
   const T* src = g.v;
   size_t ss = g.ys;
-  int k = 0;
+  // levels 6-8 at n other than kStage12N: the launches stop at position 8, and the
+  // first one takes the parity that leaves B_8 in f0 (the fused D launch writes F_8
+  // to f1)
+  const bool to8 = sizeof(T) == 4 && d8_plan(n, fuse, int(sizeof(T))) && n != kStage12N;
+  int k = to8 ? (backward_launches(n, fuse, int(sizeof(T))) - 2) & 1 : 0;
   if (dpart_blocks) *dpart_blocks = 0;
   // fuse = 2: four positions per launch, the n mod 4 leftover positions first;
   // fuse = 3: the same with eight positions per launch while four remain after
@@ -2242,7 +2254,7 @@ hipError_t launch_backward(const Group<T>& g, hipStream_t s, int* launches, int 
         continue;
       }
     }
-    if (fuse >= 6 && sizeof(T) == 4 && n == kStage12N && top == 8) {
+    if (sizeof(T) == 4 && d8_plan(n, fuse, int(sizeof(T))) && top == 8) {
       constexpr int LP = stage8_tile<T>() == 16 ? 4 : 3;
       // column blocks of P columns (half: those whose first column bit is 0)
       const dim3 grid((1u << (n - 8 - LP)) >> (g.half ? 1 : 0), 1, g.nb);
@@ -2250,6 +2262,7 @@ hipError_t launch_backward(const Group<T>& g, hipStream_t s, int* launches, int 
       if (g.half && !(dpart || next)) return hipErrorInvalidValue;
       if (next) {
         // D with the next iteration's update and first eight forward positions: F_8 to f1
+        if (src == g.f1) return hipErrorInvalidValue;
         if constexpr (sizeof(T) == 4) {
           // maxima set k of instance 0 at kBlockMaxima + k kMaxRedBlocks floats (set 0 is
           // also the D launch's with records)
@@ -2287,7 +2300,7 @@ hipError_t launch_backward(const Group<T>& g, hipStream_t s, int* launches, int 
       top = 0;
       continue;
     }
-    if (fuse >= 3 && lead >= 0 && n - top >= lead && top - 8 >= 4) {
+    if (fuse >= 3 && lead >= 0 && n - top >= lead && top - 8 >= (to8 ? 8 : 4)) {
       const int i = top - 8;
       T* dst = (k & 1) ? g.f1 : g.f0;
       constexpr int LP = stage8_tile<T>() == 16 ? 4 : stage8_tile<T>() == 8 ? 3 : 2;
@@ -2423,6 +2436,12 @@ template hipError_t launch_backward8_sym_v<double>(const Group<double>&, hipStre
 
 int backward_launches(int n, int fuse, int esz) {
   if (fuse >= 6 && n == kStage12N && esz == 4) return 2;
+  if (d8_plan(n, fuse, esz)) {
+    // the n mod 4 leading positions two or one at a time, eight-position launches
+    // while they end at 8 or above, a four-position one if four are left, the D launch
+    const int lead = n % 4, m = (n - lead - 8) / 4;
+    return (lead + 1) / 2 + m / 2 + m % 2 + 1;
+  }
   if (fuse >= 3 && n >= 4) {
     const int four = n / 4, eight = (four - 1) / 2;  // the last launch keeps four positions
     return four - eight + (n % 4 + 1) / 2;
@@ -2447,8 +2466,9 @@ int forward_launches(int n, int fuse, int esz) {
 
 bool forward_update_fusable(int n, int fuse) { return fuse >= 2 && n > 4; }
 bool forward_first8(int n, int fuse) { return fuse >= 5 && n >= kFirst8MinN; }
-bool backward_writes_maxima(int n, int fuse, int esz) { return fuse >= 6 && n == kStage12N && esz == 4; }
-bool backward_fuses_next(int n, int fuse, int esz) { return fuse >= 8 && n == kStage12N && esz == 4; }
+bool backward_writes_maxima(int n, int fuse, int esz) { return d8_plan(n, fuse, esz); }
+bool backward_fuses_next(int n, int fuse, int esz) { return fuse >= 8 && d8_plan(n, fuse, esz); }
+bool half_plan_fits(int n, int fuse) { return fuse >= 8 && n == kStage12N; }
 
 template hipError_t launch_forward<float>(const Group<float>&, hipStream_t, int*, int, int, const FusedUpdate*,
                                           int);

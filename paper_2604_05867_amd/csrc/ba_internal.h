@@ -266,8 +266,8 @@ bool forward_first8(int n, int fuse);
 // True when launch_backward's D launch (FP32) also writes the block maxima of log p + D.
 bool backward_writes_maxima(int n, int fuse, int esz);
 // The D launch of an iteration fused with the next iteration's update and first eight
-// forward positions (fuse = 8: FP32 iterates, eta = 1, n = 20, the iterate scaled by a
-// max shift, i.e. not the first iteration of a ba_step call): it writes its block
+// forward positions (fuse = 8: FP32 iterates, eta = 1, n >= 12, the iterate scaled by
+// a max shift, i.e. not the first iteration of a ba_step call): it writes its block
 // maxima of log p + D to set par of two sets in the record buffer's second set and
 // shifts by the max of set 1 - par (the D launch before it); the next forward sweep
 // then starts from its F_8 (launch_forward with first8_done).
@@ -278,6 +278,9 @@ struct FusedNext {
 };
 // True when launch_backward can take a FusedNext (element bytes esz).
 bool backward_fuses_next(int n, int fuse, int esz);
+// True when a complement-symmetric FP32 iterate can run the full plan's kernels on half
+// the rows and column tiles (Group::half: the twelve-position plan of n = 20).
+bool half_plan_fits(int n, int fuse);
 template <typename T>
 hipError_t launch_forward(const Group<T>& g, hipStream_t s, int* launches, int fuse, int logv,
                           const FusedUpdate* upd = nullptr, int first8_done = 0);  // p -> r

@@ -584,12 +584,15 @@ def test_fused_update_is_bitwise_separate(ba, prec):
     """Within one step call the update of each iteration but the last runs inside
     the next iteration's first forward launch; the iterates and bounds equal those
     of one-iteration calls (separate update launches) bit for bit, with and without
-    a step eta.  (FP32 iterates at n = 20 shift by the max in between instead:
-    test_fp32_update_by_max_matches_normalised.)"""
+    a step eta.  (FP32 iterates at launch plan levels 6-8 shift by the max in
+    between instead: test_fp32_update_by_max_matches_normalised, so FP32 runs at
+    level 5 here.)"""
     p = ba.PREC_FP64 if prec == "fp64" else ba.PREC_FP32_LOG
     ns, ds = ([12, 14], [0.6, 0.9]) if prec == "fp64" else ([16, 17], [0.7, 0.95])
     # one context, reset between runs
     c = chain(ba.Context(ns, ds, prec=p))
+    if prec == "fp32":
+        c.set_tuning(ba.TUNE_FACTORED_FUSE, 5)
     start = torch.tensor(np.concatenate([np.full(1 << m, -m * LN2) for m in ns]))
     for eta in (1.0, 1.8):
         out = []
@@ -604,16 +607,15 @@ def test_fused_update_is_bitwise_separate(ba, prec):
     c.close()
 
 
-@pytest.mark.parametrize("d", [0.64, 0.8])
-def test_fp32_update_by_max_matches_normalised(ba, d):
-    """FP32 BA iterations at n = 20 within one step call shift log p by the max of
-    log p + D (from the D launch's block maxima, no final-record launch) instead of
+@pytest.mark.parametrize("n,d", [(20, 0.64), (20, 0.8), (16, 0.8)])
+def test_fp32_update_by_max_matches_normalised(ba, n, d):
+    """FP32 BA iterations (n = 20 and 16) within one step call shift log p by the max
+    of log p + D (from the D launch's block maxima, no final-record launch) instead of
     normalising; the call's last update normalises.  The result equals that of
     one-iteration calls (every update normalised) to FP32 rounding: log p (magnitude
     ~14, ulp ~1e-6) within 4e-5 after 7 iterations, the FP64-certified bounds within
     1e-6 bits; and one final-record launch ran for the 7 iterations."""
-    n = 20
-    say("fp32 update by max d=%g" % d)
+    say("fp32 update by max n=%d d=%g" % (n, d))
     c = chain(ba.Context([n], [d], prec=ba.PREC_FP32_LOG))
     start = torch.tensor(np.full(1 << n, -n * LN2))
     out = []
@@ -664,6 +666,70 @@ def test_fused_next_iteration_matches_plan7(ba, per_call):
     assert np.max(np.abs(out[0][0] - out[1][0])) < 4e-5
     for k in range(3):
         assert abs(out[0][1][0][k] - out[1][1][0][k]) < 1e-6 and abs(out[0][1][1][k] - out[1][1][1][k]) < 1e-6
+
+
+# launch plans 6-8 at lengths other than 20 (FP32): forward launches at level 5 per
+# iteration (first8 and the rest), backward launches at level 8 per iteration
+PLAN8_LAUNCHES = {12: (2, 2), 13: (3, 3), 14: (3, 3), 16: (3, 2), 17: (4, 3), 19: (5, 4)}
+
+
+@pytest.mark.parametrize("n", sorted(PLAN8_LAUNCHES))
+def test_fused_next_iteration_other_n(ba, n):
+    """Launch plan levels 6-8 at lengths other than 20 (FP32, three instances): the
+    backward launches stop at position 8 for one eight-position D launch, which writes
+    the block maxima of log p + D (the next update shifts by the max; no final-record
+    launch) and at level 8 also makes the next iteration's update and first eight
+    forward positions.  The iterates equal those of level 5 (every update normalised)
+    to FP32 rounding after 7 iterations in calls of 1, 3 or 7 (log p within 4e-5, the
+    FP64-certified bounds within 1e-6 bits); with 7 per call, level 8 runs the first
+    eight forward positions as their own launch in iterations 0 and 1 only, its
+    backward launches per iteration, and one record reduction."""
+    ns, ds = [n] * 3, [0.64, 0.8, 0.95]
+    say("plan 8 at n=%d" % n)
+    c = chain(ba.Context(ns, ds, prec=ba.PREC_FP32_LOG))
+    start = torch.tensor(np.concatenate([inp.random_logp(n, seed=120 + k, spread=3.0) for k in range(3)]))
+    ref = None
+    for fuse in (5, 6, 8):
+        c.set_tuning(ba.TUNE_FACTORED_FUSE, fuse)
+        for per_call in ((1,) if fuse == 5 else (1, 3, 7)):
+            c.set_logp(start)
+            done = 0
+            while done < 7:
+                k = min(per_call, 7 - done)
+                c.step(k)
+                done += k
+            got = (c.get_logp().cpu().numpy(), c.bounds())
+            if ref is None:
+                ref = got
+                continue
+            assert np.all(np.isfinite(got[0]))
+            assert np.max(np.abs(got[0] - ref[0])) < 4e-5, (fuse, per_call)
+            for j in range(3):
+                assert abs(got[1][0][j] - ref[1][0][j]) < 1e-6 and abs(got[1][1][j] - ref[1][1][j]) < 1e-6
+    c.set_logp(start)
+    t = c.time_kernels(7)
+    c.close()
+    f5, b8 = PLAN8_LAUNCHES[n]
+    assert t["sweep1"][1] == 7 * f5 - 5 and t["sweep2"][1] == 7 * b8 and t["reduce"][1] == 1
+
+
+def test_symmetric_other_n_keeps_symmetric_kernels(ba):
+    """With ba_set_symmetry at n = 16 (FP32, launch plan 8) the complement-symmetric
+    kernels run (the half plan is the twelve-position plan of n = 20 only): the
+    iterate stays exactly complement-invariant and agrees with the full plan to FP32
+    rounding."""
+    n, ds = 16, [0.64, 0.9]
+    out = []
+    for sym in (False, True):
+        c = chain(ba.Context([n] * 2, ds, prec=ba.PREC_FP32_LOG))
+        if sym:
+            c.set_symmetry(True)
+        c.step(7)
+        out.append(c.get_logp().cpu().numpy().reshape(2, 1 << n))
+        c.close()
+    for k in range(2):
+        assert np.array_equal(out[1][k], out[1][k][::-1])
+    assert np.max(np.abs(out[0] - out[1])) < 4e-5
 
 
 @pytest.mark.parametrize("path", ["chain", "persistent"])
