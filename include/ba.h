@@ -179,19 +179,22 @@ int ba_set_graphs(ba_ctx *c, int enable);
 enum {
   BA_TUNE_SCATTER_LDS_KB = 0,
   /* BA_TUNE_FACTORED_FUSE: positions per launch of the factored engine: 8 (default)
-   * as 7, and at n = 20 (FP32 iterates, step 1, full kernels) inside one ba_step call
-   * from its second iteration on, the D launch of every iteration but the last also
-   * makes the next iteration's update and first eight forward positions on the same
-   * inputs (the new log p shifted by the previous iteration's max of log p + D instead
-   * of the current one: iterates equal to FP32 rounding); 7
+   * as 7, and at n >= 12 (FP32 iterates, step 1, full kernels) inside one ba_step
+   * call from its second iteration on, the D launch of every iteration but the last
+   * also makes the next iteration's update and first eight forward positions on the
+   * same inputs (the new log p shifted by the previous iteration's max of log p + D
+   * instead of the current one: iterates equal to FP32 rounding); 7
    * as 6, and at n = 20 (FP32 iterates) the forward sweep in two launches: its
    * first eight positions and its last twelve (one block per row of the eighth
    * stage of output length 8, which recomputes that row's ancestors; three
    * four-position steps through LDS), the same sums in the same order as four
-   * positions per launch; 6 as 5, and at n = 20 (FP32) the backward sweep in two
-   * launches: its last twelve positions (three four-position steps through LDS) and
-   * its first eight (with D), the same sums in the same order as four positions per
-   * launch; 5
+   * positions per launch; 6 as 5, and at n >= 12 with FP32 iterates the backward
+   * sweep's first eight positions in one launch with D and the block maxima of
+   * log p + D, so that an update left to the next iteration's first launch shifts by
+   * that max instead of normalising (no final-record launch; iterates equal to FP32
+   * rounding), the launches before it stopping at position 8 (at n = 20 one launch
+   * of the last twelve positions, three four-position steps through LDS; the same
+   * sums in the same order as four positions per launch); 5
    * as 4, with the forward's first eight positions in one launch (two four-position
    * steps through LDS, the same sums in the same order; n >= 12); 4 as 3, with the
    * forward's last four positions in one launch whose outputs are staged in LDS
