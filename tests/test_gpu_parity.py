@@ -670,7 +670,7 @@ def test_fused_next_iteration_matches_plan7(ba, per_call):
 
 # launch plans 6-8 at lengths other than 20 (FP32): forward launches at level 5 per
 # iteration (first8 and the rest), backward launches at level 8 per iteration
-PLAN8_LAUNCHES = {12: (2, 2), 13: (3, 3), 14: (3, 3), 16: (3, 2), 17: (4, 3), 19: (5, 4)}
+PLAN8_LAUNCHES = {12: (2, 2), 13: (3, 3), 14: (3, 3), 15: (4, 4), 16: (3, 2), 17: (4, 3), 18: (4, 3), 19: (5, 4)}
 
 
 @pytest.mark.parametrize("n", sorted(PLAN8_LAUNCHES))
