@@ -50,9 +50,9 @@ MEASURED_TRAFFIC = {
     "sources": ["paper_2604_05867_amd/csrc/ba_factored.hip", "paper_2604_05867_amd/csrc/ba_factored_common.h",
                 "paper_2604_05867_amd/csrc/ba_part.h"],
     # of the sources concatenated
-    "sha256": "fadc141d2966f71d7c6acb56c997d54b600c1619a75c1121b370e7a6552da530",
+    "sha256": "23ae63e094e7c86a19d6455a3a87c9f233c711e6a15a16c20cb56df4dcd3a69c",
     "bytes": {"first8": 37780000, "first8_upd": 50450000, "fwd12": 51450000,
-              "bwd12": 50960000, "d8": 63060000, "dfused": 88180000},
+              "bwd12": 50960000, "d8": 63070000, "dfused": 88170000},
 }
 
 
