@@ -6,6 +6,9 @@ Workload: three instances n = 20, d in {0.64, 0.80, 0.95}, p_0 uniform, FP32
 log-domain iterates (FP64 certification reported after the timed steps).  One
 step = one BA iteration of all three instances: q = W^T p, D(x), the Blahut
 reductions and the update, over all 2*3^20 - 2^20 nonzeros of W per instance.
+The steps run as ba_step calls of --per-call iterations (50: ba_run's chunk between
+FP64 certifications, whose first and last iterations carry the call's own launches)
+after --warmup iterations that bring the device to its steady clocks.
 
 metric: BA iterations per second, and W-nonzero terms per second =
 iterations/s x nnz(W) x instances.  The default engine evaluates the two products
@@ -65,15 +68,38 @@ def kernel_source_sha():
     return h.hexdigest()
 
 
-def measured_traffic(fuse, iters, backward):
-    """The PMC traffic per launch of a sweep over a ba_step call of `iters` iterations
-    if the kernel sources are unchanged since it was taken, else None."""
+def measured_traffic(fuse, calls, backward):
+    """The PMC traffic per launch of a sweep over ba_step calls of the given lengths
+    (iterations) if the kernel sources are unchanged since it was taken, else None."""
     if MEASURED_TRAFFIC["sha256"] is None or kernel_source_sha() != MEASURED_TRAFFIC["sha256"]:
         return None
-    kinds = call_launch_kinds(N, fuse, iters, backward)
-    if kinds is None:
-        return None
+    kinds = []
+    for iters in calls:
+        k = call_launch_kinds(N, fuse, iters, backward)
+        if k is None:
+            return None
+        kinds += k
     return int(sum(MEASURED_TRAFFIC["bytes"][k] for k in kinds) / len(kinds))
+
+
+def call_lengths(iters, per_call):
+    """iters iterations as ba_step calls of per_call (the last one shorter)."""
+    return [min(per_call, iters - i) for i in range(0, iters, per_call)]
+
+
+def step_calls(ctx, iters, per_call):
+    for k in call_lengths(iters, per_call):
+        ctx.step(k)
+
+
+def time_kernel_calls(ctx, iters, per_call):
+    """ba_time_kernels over the same calls: {kernel class: (ms, launches)} summed."""
+    tot = {}
+    for k in call_lengths(iters, per_call):
+        for name, (ms, nl) in ctx.time_kernels(k).items():
+            a = tot.get(name, (0.0, 0))
+            tot[name] = (a[0] + ms, a[1] + nl)
+    return tot
 
 
 def stage_sizes(n):
@@ -426,8 +452,10 @@ def step_compare(cap, gap_bits, etas):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--per-call", type=int, default=50,
+                    help="iterations per ba_step call (ba_run's chunk between FP64 certifications)")
     ap.add_argument("--stream-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stream", action="store_true")
@@ -480,30 +508,36 @@ def main():
     nb = len(DS)
     ctx = ba.Context([N] * nb, DS, prec=ba.PREC_FP32_LOG, engine=ba.ENGINE_FACTORED, cert_every=50,
                      device=dev)
+    # every step is one BA iteration; they run as ba_step calls of per_call iterations
+    # (ba_run's chunk between FP64 certifications), the warm-up long enough for the
+    # device to reach its steady clocks
+    pc = max(1, args.per_call)
     print("bench: warmup %d" % args.warmup, file=sys.stderr, flush=True)
-    ctx.step(args.warmup)
+    step_calls(ctx, args.warmup, pc)
     torch.cuda.synchronize()
     print("bench: timing %d steps" % args.steps, file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    ctx.step(args.steps)
+    step_calls(ctx, args.steps, pc)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     ms_step = el / args.steps * 1e3
     iters_s = args.steps / el
     value = iters_s * nnz * nb
 
-    # per-kernel-class device time (HIP events on the bound stream) over the same number of steps
-    kt = ctx.time_kernels(args.steps)
+    # per-kernel-class device time (HIP events on the bound stream) over the same calls
+    kt = time_kernel_calls(ctx, args.steps, pc)
     dom = max(("sweep1", "sweep2"), key=lambda k: kt[k][0])
     dom_ms, dom_launches = kt[dom]
     per_launch_ms = dom_ms / max(dom_launches, 1)
-    per_launch = call_launch_bytes(N, 4, nb, FUSE, args.steps, backward=(dom == "sweep2"))
+    per_launch = []
+    for k in call_lengths(args.steps, pc):
+        per_launch += call_launch_bytes(N, 4, nb, FUSE, k, backward=(dom == "sweep2"))
     assert len(per_launch) == dom_launches, (len(per_launch), dom_launches)
     bytes_launch = sum(per_launch) / len(per_launch)
     achieved = bytes_launch / (per_launch_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
                 "frac": round(achieved / 8000.0, 4),
-                "traffic": measured_traffic(FUSE, args.steps, dom == "sweep2"),
+                "traffic": measured_traffic(FUSE, call_lengths(args.steps, pc), dom == "sweep2"),
                 "kernel": ("forward sweep (k_fwd_first8, k_fwd_stage12)" if dom == "sweep1"
                            else "backward sweep (k_bwd_stage12, k_bwd_stage8_p with D and the next "
                                 "iteration's update and first eight forward positions)"),
@@ -520,13 +554,13 @@ def main():
     print("bench: symmetric kernels", file=sys.stderr, flush=True)
     csym = ba.Context([N] * nb, DS, prec=ba.PREC_FP32_LOG, engine=ba.ENGINE_FACTORED, cert_every=50, device=dev)
     csym.set_symmetry(True)
-    csym.step(args.warmup)
+    step_calls(csym, args.warmup, pc)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    csym.step(args.steps)
+    step_calls(csym, args.steps, pc)
     torch.cuda.synchronize()
     esym = time.perf_counter() - t0
-    ktsym = csym.time_kernels(args.steps)
+    ktsym = time_kernel_calls(csym, args.steps, pc)
     lo_s, hi_s = csym.bounds()
     extra["symmetric"] = {"value": args.steps / esym * nnz * nb, "unit": UNIT_EQUIV,
                           "iters_per_s": args.steps / esym, "ms_per_step": esym / args.steps * 1e3,
@@ -581,11 +615,11 @@ def main():
         cp.close()
     print("bench: fp64 plain", file=sys.stderr, flush=True)
     c64 = ba.Context(N, 0.80, prec=ba.PREC_FP64, engine=ba.ENGINE_FACTORED, device=dev)
-    c64.step(2)
+    step_calls(c64, max(2, args.warmup // 5), pc)
     torch.cuda.synchronize()
     k64 = max(5, args.steps // 5)
     t0 = time.perf_counter()
-    c64.step(k64)
+    step_calls(c64, k64, pc)
     torch.cuda.synchronize()
     e64 = time.perf_counter() - t0
     extra["fp64_single"] = {"iters_per_s": k64 / e64, "value": k64 / e64 * nnz, "unit": UNIT_EQUIV,
@@ -617,7 +651,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "BA iteration, binary deletion channel n=20, d in {0.64,0.80,0.95} "
                                "(3 instances), p0 uniform, FP32 log-domain iterates, factored engine",
-                   "n": N, "d": DS, "instances": nb, "nnz_per_instance": nnz},
+                   "n": N, "d": DS, "instances": nb, "nnz_per_instance": nnz, "iterations_per_call": pc},
         "kernel_ms_per_step": kernel_ms,
         "roofline": roofline,
         "certified": cert,
