@@ -713,6 +713,40 @@ def test_fused_next_iteration_other_n(ba, n):
     assert t["sweep1"][1] == 7 * f5 - 5 and t["sweep2"][1] == 7 * b8 and t["reduce"][1] == 1
 
 
+@pytest.mark.parametrize("n", [16, 20])
+def test_fp32_default_plan_tracks_fp64_iterates(ba, n):
+    """The default plan's FP32-only launches (first eight positions, the
+    twelve-position launches at n = 20, the D launch fused with the next update)
+    against the FP64 launch chain, which the oracle pins: three instances from a
+    random full-support law, 30 iterations in calls of 10, both at the 80-nat floor.
+    log p agrees to FP32 accuracy on the inputs within 30 nats of the maximum (the
+    mass the bounds depend on): within 2e-4 nats (measured 2-3e-5 after 30
+    iterations of ~1e-7 relative rounding on values up to ~40); the FP64-certified
+    bounds of the two iterates: L within 1e-6 bits, U = max D, which moves with the
+    iterate's rounding at its maximising input, within 2e-6 bits (measured up to
+    7e-7)."""
+    ns, ds = [n] * 3, [0.64, 0.8, 0.95]
+    say("fp32 default plan against fp64 n=%d" % n)
+    start = torch.tensor(np.concatenate([inp.random_logp(n, seed=150 + k, spread=3.0) for k in range(3)]))
+    out = []
+    for p in (ba.PREC_FP32_LOG, ba.PREC_FP64):
+        c = chain(ba.Context(ns, ds, prec=p))
+        c.set_floor(80.0)
+        c.set_logp(start)
+        for _ in range(3):
+            c.step(10)
+        out.append((c.get_logp().cpu().numpy().reshape(3, 1 << n), c.bounds()))
+        c.close()
+    for k in range(3):
+        lp32, lp64 = out[0][0][k], out[1][0][k]
+        top = lp64 > lp64.max() - 30.0
+        err = float(np.max(np.abs(lp32 - lp64)[top]))
+        say("n=%d d=%.2f: max |log p32 - log p64| = %.2e, bounds %.2e %.2e" % (
+            n, ds[k], err, out[0][1][0][k] - out[1][1][0][k], out[0][1][1][k] - out[1][1][1][k]))
+        assert err < 2e-4
+        assert abs(out[0][1][0][k] - out[1][1][0][k]) < 1e-6 and abs(out[0][1][1][k] - out[1][1][1][k]) < 2e-6
+
+
 def test_symmetric_other_n_keeps_symmetric_kernels(ba):
     """With ba_set_symmetry at n = 16 (FP32, launch plan 8) the complement-symmetric
     kernels run (the half plan is the twelve-position plan of n = 20 only): the
