@@ -53,9 +53,9 @@ MEASURED_TRAFFIC = {
     "sources": ["paper_2604_05867_amd/csrc/ba_factored.hip", "paper_2604_05867_amd/csrc/ba_factored_common.h",
                 "paper_2604_05867_amd/csrc/ba_part.h"],
     # of the sources concatenated
-    "sha256": "23ae63e094e7c86a19d6455a3a87c9f233c711e6a15a16c20cb56df4dcd3a69c",
+    "sha256": "49340f8670fce8520761f69ff22d7ed91b77b5fe0766735f3b28e6ed348187cb",
     "bytes": {"first8": 37780000, "first8_upd": 50450000, "fwd12": 51450000,
-              "bwd12": 50960000, "d8": 63070000, "dfused": 88170000},
+              "bwd12": 50960000, "d8": 63060000, "dfused": 88200000},
 }
 
 

@@ -1350,7 +1350,7 @@ __global__ __launch_bounds__(32 * (PT ? PT : stage8_tile<T>())) void k_bwd_stage
   }
   // DP: the inputs x = w S8 + s0 + (vector j) of output column group w = f / 4 of
   // 256, vector j = f mod 4; their H and log p are loaded now and held through the
-  // two steps
+  // two steps (DU without HC forms D from step 2's registers instead, below)
   constexpr int KD = int((256u * 4u) / NT);
   uint32_t xs[KD];
   Vec<T, VW> hd[KD], lq[KD];
@@ -1360,7 +1360,7 @@ __global__ __launch_bounds__(32 * (PT ? PT : stage8_tile<T>())) void k_bwd_stage
       const uint32_t f = t + uint32_t(k) * NT;
       xs[k] = ((f >> 2) << sh) + s0 + (f & 3u) * uint32_t(VW);
     }
-    d_loads<T, VW, KD>(g, b, xs, hd, lq);
+    if constexpr (!(DU && !HC)) d_loads<T, VW, KD>(g, b, xs, hd, lq);
   }
   // DU: the shift m' from the previous launch's block maxima (every wave reduces them)
   float mprev = 0.0f;
@@ -1426,6 +1426,59 @@ __global__ __launch_bounds__(32 * (PT ? PT : stage8_tile<T>())) void k_bwd_stage
     bwd4_tree<T, 1>(S, Dv);
   }
   __syncthreads();
+  if constexpr (DU && !HC) {
+    // thread (u2, c2) holds G at the inputs x = u1 2^(n-4) + u2 2^(n-8) + s0 + c2,
+    // u1 < 16, which are the inputs first8_steps takes from thread u2 P + c2: a = log
+    // p + D, the new log p = max(a - m', -floor) and p = e^{log p} stay in registers
+    // (H and log p loaded eight inputs at a time; no pass of G and p through LDS),
+    // and the block's max of a goes to its maxima set.  (The half plan's 8-column
+    // tiles keep the vector mapping of the branch below, which spreads the D work
+    // over twice the threads and measured faster there.)
+    const double M = g.st[b].M;
+    float* lp = g.lp + (size_t)b * g.xs;
+    const float* hf = g.hf + (size_t)b * g.xs;
+    const float lo = -fu.floor;
+    float am = -INFINITY;
+    float R[16];
+    if (u2 < 16u) {
+      const uint32_t x0 = (u2 << (n - 8)) + s0 + c2;
+#pragma unroll
+      for (int h = 0; h < 16; h += 8) {
+        float hv[8], lv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          hv[u] = hf[x0 + (uint32_t(h + u) << (n - 4))];
+          lv[u] = lp[x0 + (uint32_t(h + u) << (n - 4))];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const uint32_t x = x0 + (uint32_t(h + u) << (n - 4));
+          const float d = hv[u] - Dv[h + u].v[0] - float(M);
+          const float a = lv[u] + d;
+          am = fmaxf(am, a);
+          const float y = a - mprev;
+          const float nl = y > lo ? y : lo;
+          lp[x] = nl;
+          R[h + u] = exp_t<float>(nl);
+        }
+      }
+    }
+    // the block's max of a: waves, then the first wave over their maxima
+    __shared__ float wmax[NT / kWave];
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) am = fmaxf(am, __shfl_xor(am, off));
+    if ((t & (kWave - 1u)) == 0u) wmax[t / kWave] = am;
+    __syncthreads();
+    if (t == 0u) {
+      float m = wmax[0];
+#pragma unroll
+      for (uint32_t w = 1; w < NT / kWave; ++w) m = fmaxf(m, wmax[w]);
+      fu.mout[(size_t)b * g.ps * 2u + (lin & ((1u << lcb) - 1u))] = m;
+      if (lin == 0u) g.st[b].iters += 1;
+    }
+    first8_steps<float, false, int(P)>(buf, R, t, dst, n, s0);
+    return;
+  }
   if (u2 < 16u) {
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
@@ -1462,7 +1515,7 @@ __global__ __launch_bounds__(32 * (PT ? PT : stage8_tile<T>())) void k_bwd_stage
       const uint32_t rho = f >> 6, j = f & 63u;
       if (rho < nr) stv<T, 4>(o + (rho << 8) + 4u * j, ld<T, 4>(buf + rho * kOutPitch + 4u * j));
     }
-  } else if constexpr (DU) {
+  } else if constexpr (DU && HC) {
     // a = log p + D at the inputs xs (G of column group w, vector j), the new log p and
     // p = e^{log p}, which replaces G at the same slots (each thread reads and writes
     // only its own); with w = u1 16 + u2 and the block's 16 columns, p(x) of input
@@ -1515,7 +1568,7 @@ __global__ __launch_bounds__(32 * (PT ? PT : stage8_tile<T>())) void k_bwd_stage
     }
     __syncthreads();
     first8_steps<float, HC, int(P)>(buf, R, t, dst, n, s0);
-  } else if constexpr (DP) {
+  } else if constexpr (DP && !DU) {
     // D at the inputs xs from G of column group w, vector j, and the block's record
     const double M = g.st[b].M;
     Vec<T, VW> gv[KD];
@@ -1536,7 +1589,7 @@ __global__ __launch_bounds__(32 * (PT ? PT : stage8_tile<T>())) void k_bwd_stage
       d_records_pre<T, VW, KD>(g, b, M, xs, gv, hd, lq, p);
       store_block_part_nt<int(NT)>(g.part + (size_t)b * g.ps, rec, p);
     }
-  } else {
+  } else if constexpr (!DU) {
     // copy-out: output column group w = f / 4 of 256, vector j = f mod 4
     T* o = dst + ((size_t)r0 << (sh + 8)) + s0;
 #pragma unroll
