@@ -327,6 +327,32 @@ def run_segments(ctx, gap_bits, cap, seg, tag, current=False):
     return done
 
 
+def config3_groups(steps, warmup, per_call):
+    """The iteration of each group of config 3 on its own: 32 instances of one length
+    n in {10, 12, 14, 16}, d = linspace(0.64, 0.96, 32), FP32 iterates, the default
+    plan (n <= 11 as one persistent launch per call); one JSON line per group with
+    its sustained time per iteration (calls of per_call iterations after warmup)."""
+    import numpy as np
+    import torch
+
+    import paper_2604_05867_amd as ba
+    ds = [float(d) for d in np.linspace(0.64, 0.96, 32)]
+    for n in (10, 12, 14, 16):
+        c = ba.Context([n] * 32, ds, prec=ba.PREC_FP32_LOG, engine=ba.ENGINE_FACTORED, cert_every=per_call)
+        step_calls(c, warmup, per_call)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        step_calls(c, steps, per_call)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        kt = time_kernel_calls(c, steps, per_call)
+        c.close()
+        print(json.dumps({"group": "n=%d x 32 instances, FP32, default plan" % n, "n": n, "instances": 32,
+                          "steps": steps, "ms_per_step": el / steps * 1e3, "iters_per_s": steps / el,
+                          "kernel_ms_per_step": {k: round(v[0] / steps, 4) for k, v in kt.items()},
+                          "launches_per_step": {k: v[1] / steps for k, v in kt.items()}}), flush=True)
+
+
 def config3(cap, gap_bits, plain_limit_s, plain_graphs=False, symmetric=False, plain_floor=None):
     """Batched FP32 (one graph, 128 instances) against plain FP64 one instance at a
     time, both to a certified gap < gap_bits or the iteration cap.  Prints one JSON
@@ -462,6 +488,8 @@ def main():
     ap.add_argument("--no-config5", action="store_true",
                     help="skip the stopping-rule run of the workload (and the CPU baseline on its laws)")
     ap.add_argument("--config5-cap", type=int, default=200000)
+    ap.add_argument("--config3-groups", action="store_true",
+                    help="the iteration of each config-3 group (32 instances of one n) on its own")
     ap.add_argument("--config3", action="store_true",
                     help="batched FP32 vs plain FP64 at equal certified gap (several minutes)")
     ap.add_argument("--config3-symmetric", action="store_true",
@@ -486,6 +514,9 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": a.numel() * 4}))
+        return
+    if args.config3_groups:
+        config3_groups(args.steps, args.warmup, max(1, args.per_call))
         return
     if args.config3:
         config3(args.cap, args.gap, args.plain_limit_s, args.plain_graphs, args.config3_symmetric,
